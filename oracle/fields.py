@@ -1,0 +1,133 @@
+"""Gauge fields on the extended lattice, clover field tensors, Pauli term.
+
+Orbifold (Sec. 2.1, eq. "orbi:gauge"): on the mirror lattice the gauge field
+is the charge conjugate of the physical one, U(x + L1 e1, mu) = U(x, mu)^*
+and A(x + L1 e1, mu) = -A(x, mu).
+
+Hopping links (Sec. 2.3): the covariant derivatives carry
+W(x, mu) = U(x, mu) z(x, mu)^qhat with z = exp(iA) and the integer charge
+qhat = q / q_el.
+
+Clover (Sec. 2.3): the SU(3) field tensor is the clover average of the
+Luscher-Sint-Sommer-Weisz paper cited there,
+    F(x) = (Q_munu(x) - Q_numu(x)) / 8,
+with Q_munu the sum of the four plaquette leaves in the (mu, nu) plane that
+start and end at x, all with the same orientation (no trace subtraction).  The
+U(1) tensor is the paper's explicit formula
+    Ahat_munu(x) = i/(4 q_el) Im{ z_munu(x) + z_munu(x-mu) + z_munu(x-nu)
+                                  + z_munu(x-mu-nu) }.
+With open time boundaries, links crossing x0 = T-1 -> 0 do not exist and the
+leaves that contain one are dropped.
+
+Pauli term: P(x) = (4 + m0) + c_sw sum_{mu,nu} (i/4) sigma_munu F_munu
+                   + q c_sw^U(1) sum_{mu,nu} (i/4) sigma_munu Ahat_munu,
+with m0 = 1/(2 kappa) - 4 and sigma_munu = (i/2)[gamma_mu, gamma_nu].
+"""
+
+import numpy as np
+
+from .dirac import sigma_munu
+
+PLANES = [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
+
+
+def dagger(m):
+    return np.conj(np.swapaxes(m, -1, -2))
+
+
+def extend_gauge(lat, u_phs, a_phs=None):
+    """Extended-lattice fields from physical ones via the orbifold constraint."""
+    u = np.empty((lat.V, 4, 3, 3), dtype=np.complex128)
+    a = np.zeros((lat.V, 4), dtype=np.float64)
+    ph = lat.phys_index()
+    u[ph] = u_phs
+    if a_phs is not None:
+        a[ph] = a_phs
+    if lat.cstar:
+        mi = lat.mirror(ph)
+        u[mi] = np.conj(u_phs)
+        if a_phs is not None:
+            a[mi] = -a_phs
+    return u, a
+
+
+def charge_hat(q, q_el):
+    qh = q / q_el
+    r = round(qh)
+    if abs(qh - r) > 1e-9:
+        raise ValueError("q / q_el must be an integer")
+    return int(r)
+
+
+def hopping_links(lat, u, a, qhat):
+    """W(x, mu) = U(x, mu) exp(i qhat A(x, mu))."""
+    return u * np.exp(1j * qhat * a)[:, :, None, None]
+
+
+def _existing(lat):
+    """1 for links that exist, 0 for the links cut by open time boundaries."""
+    return np.abs(lat.sign)  # [4, V]
+
+
+def su3_field_tensor(lat, u):
+    """F[plane, x, 3, 3] for the six planes mu < nu (anti-Hermitian)."""
+    ex = _existing(lat)
+    uu = u * ex.T[:, :, None, None]
+    ud = dagger(uu)
+    f = np.empty((6, lat.V, 3, 3), dtype=np.complex128)
+    for p, (mu, nu) in enumerate(PLANES):
+        xpm = lat.fwd[mu]
+        xpn = lat.fwd[nu]
+        xmm = lat.bwd[mu]
+        xmn = lat.bwd[nu]
+        xmm_pn = lat.fwd[nu][xmm]     # x - mu + nu
+        xmm_mn = lat.bwd[nu][xmm]     # x - mu - nu
+        xpm_mn = lat.fwd[mu][xmn]     # x + mu - nu
+        m = lambda *ms: _chain(ms)
+        q = (m(uu[:, mu], uu[xpm, nu], ud[xpn, mu], ud[:, nu])
+             + m(uu[:, nu], ud[xmm_pn, mu], ud[xmm, nu], uu[xmm, mu])
+             + m(ud[xmm, mu], ud[xmm_mn, nu], uu[xmm_mn, mu], uu[xmn, nu])
+             + m(ud[xmn, nu], uu[xmn, mu], uu[xpm_mn, nu], ud[:, mu]))
+        f[p] = (q - dagger(q)) / 8.0
+    return f
+
+
+def _chain(ms):
+    r = ms[0]
+    for m in ms[1:]:
+        r = r @ m
+    return r
+
+
+def u1_field_tensor(lat, a, q_el):
+    """Ahat[plane, x] for mu < nu, the paper's formula (purely imaginary)."""
+    ex = _existing(lat)
+    z = np.exp(1j * a) * ex.T
+    ah = np.empty((6, lat.V), dtype=np.complex128)
+    for p, (mu, nu) in enumerate(PLANES):
+        zmn = z[:, mu] * z[lat.fwd[mu], nu] * np.conj(z[lat.fwd[nu], mu]) * np.conj(z[:, nu])
+        xmm = lat.bwd[mu]
+        xmn = lat.bwd[nu]
+        s = zmn + zmn[xmm] + zmn[xmn] + zmn[lat.bwd[nu][xmm]]
+        ah[p] = 1j / (4.0 * q_el) * np.imag(s)
+    return ah
+
+
+def pauli_term(lat, u, a, kappa, q, csw, csw_u1, q_el):
+    """P[x, 12, 12] on spin (x) colour, index s*3 + c."""
+    m0 = 1.0 / (2.0 * kappa) - 4.0
+    f = su3_field_tensor(lat, u)
+    p = np.zeros((lat.V, 12, 12), dtype=np.complex128)
+    p += (4.0 + m0) * np.eye(12)
+    eye3 = np.eye(3)
+    if a is not None and q != 0.0:
+        ah = u1_field_tensor(lat, a, q_el)
+    else:
+        ah = None
+    for k, (mu, nu) in enumerate(PLANES):
+        # sum over both orders (mu,nu), (nu,mu) of (i/4) sigma F = (i/2) sigma F for mu<nu
+        s = 0.5j * sigma_munu(mu, nu)
+        p += csw * np.einsum("st,xab->xsatb", s, f[k]).reshape(lat.V, 12, 12)
+        if ah is not None:
+            p += q * csw_u1 * np.einsum("st,x,ab->xsatb", s, ah[k], eye3).reshape(lat.V, 12, 12)
+    return p
