@@ -1,0 +1,228 @@
+/*
+ * qxd.h -- C ABI of libqxd: the O(a)-improved Wilson-clover Dirac operator on
+ * an SU(3) x U(1) gauge field with C* spatial boundaries, and its even-odd /
+ * SAP-preconditioned GCR solvers, on one AMD MI355X (gfx950).
+ *
+ * The operations follow Campos et al., "openQ*D simulation code for QCD+QED"
+ * (Lattice 2017, arXiv:1710.08839):
+ *   - extended lattice, orbifold constraint, shifted boundaries: Sec. 2.1
+ *   - D = m0 + Dw + dD_sw, charges qhat = q / q_el, clover tensors: Sec. 2.3
+ *   - even-odd blocks and the Schur complement D^: Sec. 2.4
+ *   - SAP-preconditioned GCR: named in the abstract and Sec. 2.
+ *
+ * Conventions shared by every entry point
+ *   Axes: mu = 0 is time, 1..3 are space.  C* needs direction 1; under C* the
+ *   extended lattice is T x 2L1 x L2 x L3 and sites with x1 >= L1 form the
+ *   mirror lattice.
+ *   Site order ("API order"): ((x0*N1 + x1)*L2 + x2)*L3 + x3, N1 = 2L1 under
+ *   C*, else L1.  x3 runs fastest.
+ *   Gamma matrices: chiral basis, gamma_0 = [[0,-1],[-1,0]],
+ *   gamma_k = [[0,-i s_k],[i s_k,0]], gamma_5 = diag(1,1,-1,-1).
+ *   Spinors in API layout: double [nrhs][V_ext][4 spin][3 colour][re,im].
+ *   D = (4 + m0) + dD_sw - 1/2 sum_mu [(1-g_mu) W(x,mu) psi(x+mu)
+ *       + (1+g_mu) W(x-mu,mu)^dag psi(x-mu)],  W = U exp(i qhat A),
+ *   m0 = 1/(2 kappa) - 4.  Fermions are antiperiodic in time (time_bc = 0)
+ *   or the time hop is absent (time_bc = 1, open, boundary coefficient 1).
+ *   Clover: F = (Q_munu - Q_munu^dag)/8 from the four plaquette leaves;
+ *   Ahat = i/(4 q_el) Im(sum of the four U(1) plaquettes).
+ *
+ * Memory: pointers named *_host are host memory, *_dev device memory on the
+ * context's GPU.  The caller owns every buffer it passes; the library owns
+ * field and context handles and their workspaces.  Calls return a
+ * qxd_status; on error nothing has been written unless stated, and
+ * qxd_last_error() gives a message (thread-local).  Arguments are checked on
+ * the host before any device work.  Device work is queued on the stream
+ * passed as `stream` (a hipStream_t, NULL = the default stream); entry points
+ * that return results to the host synchronise that stream.
+ *
+ * Native layout: for speed, spinors can be kept in the library's private
+ * device layout and precision (qxd_spinor_bytes / qxd_spinor_pack /
+ * qxd_spinor_unpack); pass QXD_NATIVE to qxd_dirac_apply to use it.
+ */
+#ifndef QXD_H
+#define QXD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QXD_ABI_VERSION 1
+
+typedef enum {
+  QXD_OK = 0,
+  QXD_EINVAL = -1,   /* invalid argument (checked before any device work)   */
+  QXD_ENOMEM = -2,   /* device or host allocation failed                     */
+  QXD_ENOCONV = -3,  /* solver hit maxiter; best iterate and info written    */
+  QXD_EFLOAT = -4,   /* NaN/Inf in the input or the iteration                */
+  QXD_EDEVICE = -5,  /* HIP runtime error                                     */
+  QXD_EBUSY = -6,    /* serve request still pending                           */
+  QXD_ENOTFOUND = -7 /* unknown serve ticket                                  */
+} qxd_status;
+
+/* Storage precision of spinors, links and Pauli terms.  F64 computes in FP64;
+ * the others compute in FP32.  F16S stores spinors as FP16 with one FP32
+ * scale per site (the site's largest component magnitude). */
+typedef enum { QXD_F64 = 0, QXD_F32 = 1, QXD_F16S = 2, QXD_BF16 = 3 } qxd_prec;
+
+typedef enum {
+  QXD_OP_D = 0,      /* full D on all of the extended lattice (Sec. 2.3)      */
+  QXD_OP_DHAT = 1,   /* D^ = D_ee - D_eo D_oo^-1 D_oe on even sites; odd
+                        sites of the output are set to 0 (Sec. 2.4)           */
+  QXD_OP_HOP = 2,    /* hopping part of D only (D minus its diagonal)         */
+  QXD_OP_PAULI = 3,  /* diagonal part P(x) = 4 + m0 + dD_sw only              */
+  QXD_OP_OOINV = 4   /* D_oo^-1 on odd sites, even sites set to 0             */
+} qxd_op;
+
+#define QXD_NATIVE 1u  /* in/out are native-layout buffers of precision prec */
+
+typedef struct {
+  int dims[4];    /* physical T, L1, L2, L3; all even                        */
+  int time_bc;    /* 0: periodic gauge, antiperiodic fermions; 1: open      */
+  int cstar;      /* 0: periodic space; k = 1..3: directions 1..k are C*    */
+  double q_el;    /* elementary charge (Sec. 2.2); 1/6 is required with C*
+                     for charged hadrons; 0 means 1/6                         */
+  int block[4];   /* block size of the device layout and of SAP; each even,
+                     dividing the extended extent (and L1); 0 means 4          */
+} qxd_lattice;
+
+typedef struct {
+  double kappa;   /* hopping parameter, m0 = 1/(2 kappa) - 4               */
+  double q;       /* charge in units of e; q / q_el must be an integer       */
+  double csw;     /* SU(3) clover coefficient                                */
+  double csw_u1;  /* U(1) clover coefficient                                 */
+} qxd_quark;
+
+typedef enum { QXD_SOLVER_EO_GCR = 0, QXD_SOLVER_SAP_GCR = 1 } qxd_solver_kind;
+
+typedef struct {
+  int kind;           /* qxd_solver_kind                                       */
+  double tol;         /* target |eta - D psi| / |eta| in FP64 (e.g. 1e-10)     */
+  int maxiter;        /* EO_GCR: GCR iterations; SAP_GCR: inner iterations     */
+  int nkv;            /* Krylov vectors per restart cycle                      */
+  int ncy;            /* SAP cycles per preconditioner application             */
+  int nmr;            /* MR steps per SAP block solve                          */
+  int inner_prec;     /* qxd_prec of the SAP-GCR inner solver                  */
+  double inner_tol;   /* relative residual reduction per inner solve           */
+  int max_outer;      /* outer defect-correction steps (SAP_GCR)              */
+} qxd_solver;
+
+typedef struct {
+  int status;         /* qxd_status of this right-hand side                    */
+  int outer_iters;    /* defect-correction steps                               */
+  int inner_iters;    /* GCR iterations (sum over outer steps)                 */
+  double true_resid;  /* |eta - D psi| / |eta| computed in FP64 at the end     */
+  double seconds;     /* wall time of this solve                               */
+} qxd_solve_info;
+
+typedef struct qxd_ctx qxd_ctx;
+typedef struct qxd_field qxd_field;
+
+/* Version of this ABI (QXD_ABI_VERSION). */
+int qxd_abi_version(void);
+
+/* Thread-local message describing the last error of this thread. */
+const char *qxd_last_error(void);
+
+/* Open a context on HIP device `device`.  *ctx receives the handle. */
+qxd_status qxd_init(int device, qxd_ctx **ctx);
+
+/* Release a context.  All its fields must have been released. */
+qxd_status qxd_finalize(qxd_ctx *ctx);
+
+/* Upload a gauge field (Sec. 2.1, 2.3).  U_host: double
+ * [V_phs][4 mu][3][3][re,im], U(x,mu) row-major, physical sites in API order
+ * with extent L1 in direction 1.  A_host: double [V_phs][4] U(1) potential
+ * with z = exp(iA), or NULL for an SU(3)-only field.  Under C* the library
+ * builds the mirror half by the orbifold constraint U(x+L1 e1) = U(x)^*,
+ * A(x+L1 e1) = -A(x).  The host arrays may be freed after return. */
+qxd_status qxd_field_upload(qxd_ctx *ctx, const qxd_lattice *lat,
+                            const double *U_host, const double *A_host,
+                            qxd_field **field);
+
+/* Release a field and every operator (Pauli term) cached on it. */
+qxd_status qxd_field_release(qxd_field *field);
+
+/* Number of extended-lattice sites V_ext of the field. */
+qxd_status qxd_field_volume(const qxd_field *field, int64_t *v_ext);
+
+/* Bytes of one native-layout spinor of precision prec (nrhs = 1). */
+qxd_status qxd_spinor_bytes(const qxd_field *field, qxd_prec prec, size_t *bytes);
+
+/* API-layout FP64 spinors (device) -> native layout of precision prec. */
+qxd_status qxd_spinor_pack(qxd_field *field, qxd_prec prec, const double *in_dev,
+                           void *out_dev, int nrhs, void *stream);
+
+/* Native layout of precision prec -> API-layout FP64 spinors (device). */
+qxd_status qxd_spinor_unpack(qxd_field *field, qxd_prec prec, const void *in_dev,
+                             double *out_dev, int nrhs, void *stream);
+
+/* out = op(in) for nrhs spinors.  quarks: nquark entries; right-hand side r
+ * uses quarks[r * nquark / nrhs] (nrhs must be a multiple of nquark).  With
+ * flags & QXD_NATIVE, in_dev/out_dev are nrhs consecutive native spinors of
+ * precision prec; otherwise they are API-layout FP64 buffers and the operator
+ * is applied in precision prec.  in and out must not overlap.  Asynchronous
+ * on `stream`. */
+qxd_status qxd_dirac_apply(qxd_field *field, const qxd_quark *quarks, int nquark,
+                           qxd_op op, qxd_prec prec, const void *in_dev, void *out_dev,
+                           int nrhs, unsigned flags, void *stream);
+
+/* Solve D psi = eta for nrhs right-hand sides (API-layout FP64, device), each
+ * to |eta - D psi| / |eta| <= s->tol with the residual computed in FP64.
+ * quarks as in qxd_dirac_apply.  psi_dev is the initial guess if use_guess,
+ * else it is overwritten.  info: nrhs entries (may be NULL).  Returns
+ * QXD_ENOCONV if any right-hand side missed tol (best iterate written),
+ * QXD_EFLOAT on NaN/Inf.  Synchronises `stream`. */
+qxd_status qxd_solve(qxd_field *field, const qxd_quark *quarks, int nquark,
+                     const qxd_solver *s, const double *eta_dev, double *psi_dev,
+                     int nrhs, int use_guess, qxd_solve_info *info, void *stream);
+
+/* Apply the SAP preconditioner M_SAP of the SAP_GCR solver (ncy cycles of
+ * black and white block solves, each by nmr minimal-residual steps on the
+ * even-odd block operator with Dirichlet faces) to nrhs API-layout FP64
+ * spinors, computing in precision prec with the field's blocks.  out = M in.
+ * Asynchronous on `stream`. */
+qxd_status qxd_sap_apply(qxd_field *field, const qxd_quark *quark, qxd_prec prec, int ncy,
+                         int nmr, const double *in_dev, double *out_dev, int nrhs, void *stream);
+
+/* ---- serving: continuous batching of solve requests ------------------- */
+
+typedef struct {
+  qxd_field *field;        /* resident gauge field                           */
+  qxd_quark quark;         /* operator of every right-hand side              */
+  qxd_solver solver;       /* solver parameters                              */
+  const double *eta_dev;   /* nrhs API-layout FP64 sources (device)          */
+  double *psi_dev;         /* nrhs API-layout FP64 solutions (device)        */
+  int nrhs;
+} qxd_request;
+
+typedef struct {
+  int status;              /* qxd_status of the request                      */
+  int nrhs;
+  double latency_s;        /* submit -> completion                            */
+  double queue_s;          /* submit -> admission                             */
+  int inner_iters;         /* max over right-hand sides                       */
+  double true_resid;       /* max over right-hand sides                       */
+} qxd_result;
+
+/* Start the serving scheduler of ctx with a device-memory budget (bytes) for
+ * request workspaces; 0 means 80% of the free device memory. */
+qxd_status qxd_serve_start(qxd_ctx *ctx, size_t budget_bytes, int max_active);
+
+/* Queue a request; *ticket identifies it.  Buffers must stay valid until
+ * qxd_serve_poll reports completion. */
+qxd_status qxd_serve_submit(qxd_ctx *ctx, const qxd_request *req, uint64_t *ticket);
+
+/* QXD_EBUSY while pending; otherwise fills *out (status of the solve) and
+ * forgets the ticket.  QXD_ENOTFOUND for unknown tickets. */
+qxd_status qxd_serve_poll(qxd_ctx *ctx, uint64_t ticket, qxd_result *out);
+
+/* Stop the scheduler after finishing admitted requests. */
+qxd_status qxd_serve_stop(qxd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QXD_H */

@@ -132,6 +132,27 @@ def build_operator(lat, u_ext, a_ext, kappa, q=0.0, csw=0.0, csw_u1=1.0, q_el=1.
     return DiracOperator(lat, w, p)
 
 
+def apply_at_sites(lat, u_ext, a_ext, psi, sites, kappa, q=0.0, csw=0.0, csw_u1=1.0, q_el=1.0 / 6.0):
+    """(D psi)(x) at the listed sites only, by the same site formula, for
+    lattices too large to build the whole operator."""
+    from .fields import charge_hat, pauli_term
+    sites = np.asarray(sites)
+    qhat = charge_hat(q, q_el) if a_ext is not None else 0
+    p = pauli_term(lat, u_ext, a_ext, kappa, q if a_ext is not None else 0.0, csw, csw_u1, q_el, sites)
+    out = np.einsum("xij,xj->xi", p, psi[sites].reshape(-1, 12)).reshape(-1, 4, 3)
+    acc = np.zeros_like(out)
+    for mu in range(4):
+        yf = lat.fwd[mu][sites]
+        yb = lat.bwd[mu][sites]
+        wf = u_ext[sites, mu] * (np.exp(1j * qhat * a_ext[sites, mu])[:, None, None] if qhat else 1.0)
+        wb = u_ext[yb, mu] * (np.exp(1j * qhat * a_ext[yb, mu])[:, None, None] if qhat else 1.0)
+        fw = np.einsum("xab,xsb->xsa", wf, psi[yf]) * lat.sign[mu][sites][:, None, None]
+        bw = np.einsum("xba,xsb->xsa", np.conj(wb), psi[yb]) * lat.bsign[mu][sites][:, None, None]
+        acc += np.einsum("st,xtc->xsc", EYE4 - GAMMA[mu], fw)
+        acc += np.einsum("st,xtc->xsc", EYE4 + GAMMA[mu], bw)
+    return out - 0.5 * acc
+
+
 def dot(a, b):
     """(a, b) = sum conj(a) b over everything."""
     return np.vdot(a, b)

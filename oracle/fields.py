@@ -69,25 +69,31 @@ def _existing(lat):
     return np.abs(lat.sign)  # [4, V]
 
 
-def su3_field_tensor(lat, u):
-    """F[plane, x, 3, 3] for the six planes mu < nu (anti-Hermitian)."""
+def su3_field_tensor(lat, u, sites=None):
+    """F[plane, x, 3, 3] for the six planes mu < nu (anti-Hermitian), at all
+    sites or at the listed ones."""
     ex = _existing(lat)
-    uu = u * ex.T[:, :, None, None]
-    ud = dagger(uu)
-    f = np.empty((6, lat.V, 3, 3), dtype=np.complex128)
+    x = np.arange(lat.V) if sites is None else np.asarray(sites)
+
+    def U(y, mu):
+        return u[y, mu] * ex[mu][y][:, None, None]
+
+    def Ud(y, mu):
+        return dagger(U(y, mu))
+
+    f = np.empty((6, len(x), 3, 3), dtype=np.complex128)
     for p, (mu, nu) in enumerate(PLANES):
-        xpm = lat.fwd[mu]
-        xpn = lat.fwd[nu]
-        xmm = lat.bwd[mu]
-        xmn = lat.bwd[nu]
+        xpm = lat.fwd[mu][x]
+        xpn = lat.fwd[nu][x]
+        xmm = lat.bwd[mu][x]
+        xmn = lat.bwd[nu][x]
         xmm_pn = lat.fwd[nu][xmm]     # x - mu + nu
         xmm_mn = lat.bwd[nu][xmm]     # x - mu - nu
         xpm_mn = lat.fwd[mu][xmn]     # x + mu - nu
-        m = lambda *ms: _chain(ms)
-        q = (m(uu[:, mu], uu[xpm, nu], ud[xpn, mu], ud[:, nu])
-             + m(uu[:, nu], ud[xmm_pn, mu], ud[xmm, nu], uu[xmm, mu])
-             + m(ud[xmm, mu], ud[xmm_mn, nu], uu[xmm_mn, mu], uu[xmn, nu])
-             + m(ud[xmn, nu], uu[xmn, mu], uu[xpm_mn, nu], ud[:, mu]))
+        q = (_chain([U(x, mu), U(xpm, nu), Ud(xpn, mu), Ud(x, nu)])
+             + _chain([U(x, nu), Ud(xmm_pn, mu), Ud(xmm, nu), U(xmm, mu)])
+             + _chain([Ud(xmm, mu), Ud(xmm_mn, nu), U(xmm_mn, mu), U(xmn, nu)])
+             + _chain([Ud(xmn, nu), U(xmn, mu), U(xpm_mn, nu), Ud(x, mu)]))
         f[p] = (q - dagger(q)) / 8.0
     return f
 
@@ -99,35 +105,42 @@ def _chain(ms):
     return r
 
 
-def u1_field_tensor(lat, a, q_el):
+def u1_field_tensor(lat, a, q_el, sites=None):
     """Ahat[plane, x] for mu < nu, the paper's formula (purely imaginary)."""
     ex = _existing(lat)
-    z = np.exp(1j * a) * ex.T
-    ah = np.empty((6, lat.V), dtype=np.complex128)
+    x = np.arange(lat.V) if sites is None else np.asarray(sites)
+
+    def z(y, mu):
+        return np.exp(1j * a[y, mu]) * ex[mu][y]
+
+    def zmn(y, mu, nu):
+        return z(y, mu) * z(lat.fwd[mu][y], nu) * np.conj(z(lat.fwd[nu][y], mu)) * np.conj(z(y, nu))
+
+    ah = np.empty((6, len(x)), dtype=np.complex128)
     for p, (mu, nu) in enumerate(PLANES):
-        zmn = z[:, mu] * z[lat.fwd[mu], nu] * np.conj(z[lat.fwd[nu], mu]) * np.conj(z[:, nu])
-        xmm = lat.bwd[mu]
-        xmn = lat.bwd[nu]
-        s = zmn + zmn[xmm] + zmn[xmn] + zmn[lat.bwd[nu][xmm]]
+        xmm = lat.bwd[mu][x]
+        xmn = lat.bwd[nu][x]
+        s = zmn(x, mu, nu) + zmn(xmm, mu, nu) + zmn(xmn, mu, nu) + zmn(lat.bwd[nu][xmm], mu, nu)
         ah[p] = 1j / (4.0 * q_el) * np.imag(s)
     return ah
 
 
-def pauli_term(lat, u, a, kappa, q, csw, csw_u1, q_el):
-    """P[x, 12, 12] on spin (x) colour, index s*3 + c."""
+def pauli_term(lat, u, a, kappa, q, csw, csw_u1, q_el, sites=None):
+    """P[x, 12, 12] on spin (x) colour, index s*3 + c (all or listed sites)."""
     m0 = 1.0 / (2.0 * kappa) - 4.0
-    f = su3_field_tensor(lat, u)
-    p = np.zeros((lat.V, 12, 12), dtype=np.complex128)
+    f = su3_field_tensor(lat, u, sites)
+    n = f.shape[1]
+    p = np.zeros((n, 12, 12), dtype=np.complex128)
     p += (4.0 + m0) * np.eye(12)
     eye3 = np.eye(3)
     if a is not None and q != 0.0:
-        ah = u1_field_tensor(lat, a, q_el)
+        ah = u1_field_tensor(lat, a, q_el, sites)
     else:
         ah = None
     for k, (mu, nu) in enumerate(PLANES):
         # sum over both orders (mu,nu), (nu,mu) of (i/4) sigma F = (i/2) sigma F for mu<nu
         s = 0.5j * sigma_munu(mu, nu)
-        p += csw * np.einsum("st,xab->xsatb", s, f[k]).reshape(lat.V, 12, 12)
+        p += csw * np.einsum("st,xab->xsatb", s, f[k]).reshape(n, 12, 12)
         if ah is not None:
-            p += q * csw_u1 * np.einsum("st,x,ab->xsatb", s, ah[k], eye3).reshape(lat.V, 12, 12)
+            p += q * csw_u1 * np.einsum("st,x,ab->xsatb", s, ah[k], eye3).reshape(n, 12, 12)
     return p

@@ -1,0 +1,447 @@
+// The C ABI of libqxd (include/qxd.h): argument checks, gauge-field upload,
+// operator cache, Dirac-operator application and layout conversion.  Solvers
+// live in solver.cpp and the serving scheduler in serve.cpp.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <cstring>
+
+#include "host.h"
+#include "solver.h"
+
+namespace qxd {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+int qhat_of(double q, double q_el, bool *ok) {
+  double qh = q / q_el;
+  double r = nearbyint(qh);
+  *ok = fabs(qh - r) < 1e-9 && fabs(r) < 1e6;
+  return (int)r;
+}
+
+// Validate the lattice (Sec. 2.1 geometry) and fill the device geometry.
+static qxd_status make_geom(const qxd_lattice *lat, Geom *g) {
+  if (!lat) {
+    set_error("lattice is NULL");
+    return QXD_EINVAL;
+  }
+  if (lat->cstar < 0 || lat->cstar > 3) {
+    set_error("cstar must be 0..3 (got %d)", lat->cstar);
+    return QXD_EINVAL;
+  }
+  if (lat->time_bc != 0 && lat->time_bc != 1) {
+    set_error("time_bc must be 0 (antiperiodic) or 1 (open)");
+    return QXD_EINVAL;
+  }
+  int N[4] = {lat->dims[0], lat->cstar ? 2 * lat->dims[1] : lat->dims[1], lat->dims[2], lat->dims[3]};
+  int64_t V = 1;
+  for (int m = 0; m < 4; m++) {
+    if (lat->dims[m] < 2 || lat->dims[m] % 2) {
+      set_error("lattice extent %d of direction %d must be even and >= 2", lat->dims[m], m);
+      return QXD_EINVAL;
+    }
+    int b = lat->block[m] ? lat->block[m] : 4;
+    if (b < 2 || b % 2 || N[m] % b) {
+      set_error("block extent %d must be even and divide the extended extent %d (direction %d)", b, N[m], m);
+      return QXD_EINVAL;
+    }
+    g->N[m] = N[m];
+    g->b[m] = b;
+    g->nb[m] = N[m] / b;
+    V *= N[m];
+  }
+  if (V > (int64_t)1 << 30) {
+    set_error("extended volume %lld exceeds 2^30 sites", (long long)V);
+    return QXD_EINVAL;
+  }
+  g->L1 = lat->dims[1];
+  if (lat->cstar && g->L1 % g->b[1]) {
+    set_error("under C* the block extent in direction 1 must divide L1");
+    return QXD_EINVAL;
+  }
+  g->L1b = g->L1 / g->b[1];
+  g->shift_mask = 0;
+  for (int k = 2; k <= lat->cstar; k++) g->shift_mask |= 1 << k;
+  g->time_bc = lat->time_bc;
+  g->V = (int)V;
+  g->Vh = (int)(V / 2);
+  g->Vb = g->b[0] * g->b[1] * g->b[2] * g->b[3];
+  g->Vbh = g->Vb / 2;
+  g->hb3 = g->b[3] / 2;
+  g->nblocks = g->nb[0] * g->nb[1] * g->nb[2] * g->nb[3];
+  return QXD_OK;
+}
+
+void *Field::workspace(const std::string &name, size_t bytes, hipError_t *err) {
+  auto &slot = work[name];
+  if (!slot) slot.reset(new DevBuf());
+  *err = slot->ensure(bytes);
+  return *err == hipSuccess ? slot->p : nullptr;
+}
+
+qxd_status Field::ensure_links(int prec, hipStream_t st) {
+  if (links_ready[prec]) return QXD_OK;
+  int64_t n_pairs = (int64_t)36 * g.V;
+  QXD_HIP_CHECK(links[prec].ensure(n_pairs * pair_bytes(prec)));
+  QXD_HIP_CHECK(launch_convert_pairs(prec, links[QXD_F64].as<double2>(), links[prec].p, n_pairs, st));
+  QXD_HIP_CHECK(angles[prec].ensure((size_t)4 * g.V * sizeof(float)));
+  QXD_HIP_CHECK(launch_convert_reals(angles[QXD_F64].as<double>(), angles[prec].as<float>(), (int64_t)4 * g.V, st));
+  links_ready[prec] = true;
+  return QXD_OK;
+}
+
+qxd_status Field::get_op(const qxd_quark &q, int prec, Operator **out, hipStream_t st) {
+  if (!(q.kappa > 0.0) || !isfinite(q.kappa) || !isfinite(q.csw) || !isfinite(q.csw_u1) || !isfinite(q.q)) {
+    set_error("quark parameters must be finite with kappa > 0");
+    return QXD_EINVAL;
+  }
+  int qhat = 0;
+  if (has_u1) {
+    bool ok;
+    qhat = qhat_of(q.q, q_el, &ok);
+    if (!ok) {
+      set_error("charge q = %g is not an integer multiple of q_el = %g", q.q, q_el);
+      return QXD_EINVAL;
+    }
+  }
+  auto key = std::make_tuple(q.kappa, has_u1 ? q.q : 0.0, q.csw, has_u1 ? q.csw_u1 : 0.0);
+  auto it = ops.find(key);
+  Operator *op;
+  if (it == ops.end()) {
+    std::unique_ptr<Operator> nop(new Operator());
+    nop->quark = q;
+    nop->qhat = qhat;
+    QXD_HIP_CHECK(nop->pauli[QXD_F64].ensure((size_t)36 * g.V * 16));
+    QXD_HIP_CHECK(nop->pinv[QXD_F64].ensure((size_t)36 * g.Vh * 16));
+    QXD_HIP_CHECK(launch_pauli_build(g, links[QXD_F64].as<double2>(), angles[QXD_F64].as<double>(), has_u1,
+                                     q.kappa, q.csw, has_u1 ? qhat * q.csw_u1 : 0.0,
+                                     nop->pauli[QXD_F64].as<double2>(), st));
+    hipError_t e;
+    int *bad = (int *)workspace("bad_count", sizeof(int), &e);
+    QXD_HIP_CHECK(e);
+    QXD_HIP_CHECK(hipMemsetAsync(bad, 0, sizeof(int), st));
+    QXD_HIP_CHECK(launch_pauli_invert(g, nop->pauli[QXD_F64].as<double2>(), nop->pinv[QXD_F64].as<double2>(), bad, st));
+    int nbad = 0;
+    QXD_HIP_CHECK(hipMemcpyAsync(&nbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    QXD_HIP_CHECK(hipStreamSynchronize(st));
+    if (nbad) {
+      set_error("%d odd-site Pauli blocks are not positive definite (kappa=%g, csw=%g)", nbad, q.kappa, q.csw);
+      return QXD_EFLOAT;
+    }
+    QXD_HIP_CHECK(nop->wl[QXD_F64].ensure((size_t)36 * g.V * 16));
+    QXD_HIP_CHECK(launch_fold_phase(g, links[QXD_F64].as<double2>(), angles[QXD_F64].as<double>(), qhat,
+                                    nop->wl[QXD_F64].as<double2>(), st));
+    nop->ready[QXD_F64] = true;
+    op = nop.get();
+    ops[key] = std::move(nop);
+  } else {
+    op = it->second.get();
+  }
+  if (!op->ready[prec]) {
+    QXD_HIP_CHECK(op->pauli[prec].ensure((size_t)36 * g.V * pair_bytes(prec)));
+    QXD_HIP_CHECK(op->pinv[prec].ensure((size_t)36 * g.Vh * pair_bytes(prec)));
+    QXD_HIP_CHECK(launch_convert_pairs(prec, op->pauli[QXD_F64].as<double2>(), op->pauli[prec].p, (int64_t)36 * g.V, st));
+    QXD_HIP_CHECK(launch_convert_pairs(prec, op->pinv[QXD_F64].as<double2>(), op->pinv[prec].p, (int64_t)36 * g.Vh, st));
+    QXD_HIP_CHECK(op->wl[prec].ensure((size_t)36 * g.V * pair_bytes(prec)));
+    QXD_HIP_CHECK(launch_convert_pairs(prec, op->wl[QXD_F64].as<double2>(), op->wl[prec].p, (int64_t)36 * g.V, st));
+    op->ready[prec] = true;
+  }
+  qxd_status s = ensure_links(prec, st);
+  if (s != QXD_OK) return s;
+  *out = op;
+  return QXD_OK;
+}
+
+OpFields Field::op_fields(const Operator &op, int prec) const {
+  OpFields f;
+  f.links = op.wl[prec].p;
+  f.angles = nullptr;
+  f.pauli = op.pauli[prec].p;
+  f.pinv = op.pinv[prec].p;
+  f.qhat = 0;
+  return f;
+}
+
+OpFields Field::op_fields_u(const Operator &op, int prec) const {
+  OpFields f;
+  f.links = links[prec].p;
+  f.angles = angles[prec].p;
+  f.pauli = op.pauli[prec].p;
+  f.pinv = op.pinv[prec].p;
+  f.qhat = op.qhat;
+  return f;
+}
+
+// Apply `op` to one native spinor (full-lattice buffers).
+qxd_status apply_native(Field *fd, const Operator &op, qxd_op which, int prec, void *in, void *out,
+                        hipStream_t st) {
+  const Geom &g = fd->g;
+  OpFields f = fd->op_fields(op, prec);
+  SpinorArg full_in{in, g.V, 0}, full_out{out, g.V, 0}, none{nullptr, 0, 0};
+  switch (which) {
+    case QXD_OP_D:
+      QXD_HIP_CHECK(launch_dirac(prec, DK_FULL, g, f, full_in, full_in, full_out, -0.5, st));
+      break;
+    case QXD_OP_HOP:
+      QXD_HIP_CHECK(launch_dirac(prec, DK_HOP, g, f, full_in, none, full_out, -0.5, st));
+      break;
+    case QXD_OP_PAULI:
+      QXD_HIP_CHECK(launch_dirac(prec, DK_PAULI, g, f, full_in, full_in, full_out, 0.0, st));
+      break;
+    case QXD_OP_DHAT: {
+      hipError_t e;
+      void *tmp = fd->workspace("dhat_tmp", spinor_bytes(prec, g.Vh), &e);
+      QXD_HIP_CHECK(e);
+      SpinorArg t_o{tmp, g.Vh, g.Vh};
+      QXD_HIP_CHECK(launch_dirac(prec, DK_ODD, g, f, full_in, none, t_o, -0.5, st));
+      QXD_HIP_CHECK(launch_dirac(prec, DK_EVEN, g, f, t_o, full_in, full_out, 0.5, st));
+      QXD_HIP_CHECK(launch_zero_sites(prec, full_out, g.Vh, g.Vh, st));
+      break;
+    }
+    case QXD_OP_OOINV:
+      QXD_HIP_CHECK(launch_dirac(prec, DK_ODD, g, f, full_in, full_in, full_out, 0.0, st));
+      QXD_HIP_CHECK(launch_zero_sites(prec, full_out, 0, g.Vh, st));
+      break;
+    default:
+      set_error("unknown operator %d", (int)which);
+      return QXD_EINVAL;
+  }
+  return QXD_OK;
+}
+
+}  // namespace qxd
+
+using namespace qxd;
+
+static bool valid_prec(int p) { return p >= QXD_F64 && p <= QXD_BF16; }
+
+extern "C" {
+
+int qxd_abi_version(void) { return QXD_ABI_VERSION; }
+
+const char *qxd_last_error(void) { return g_err; }
+
+qxd_status qxd_init(int device, qxd_ctx **ctx) {
+  if (!ctx) {
+    set_error("ctx is NULL");
+    return QXD_EINVAL;
+  }
+  int n = 0;
+  QXD_HIP_CHECK(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) {
+    set_error("device %d out of range (%d devices)", device, n);
+    return QXD_EINVAL;
+  }
+  QXD_HIP_CHECK(hipSetDevice(device));
+  qxd_ctx *c = new qxd_ctx();
+  c->device = device;
+  *ctx = c;
+  return QXD_OK;
+}
+
+qxd_status qxd_finalize(qxd_ctx *ctx) {
+  if (!ctx) {
+    set_error("ctx is NULL");
+    return QXD_EINVAL;
+  }
+  if (ctx->serve) qxd_serve_stop(ctx);
+  if (ctx->n_fields) {
+    set_error("%d fields of this context are still alive", ctx->n_fields);
+    return QXD_EINVAL;
+  }
+  delete ctx;
+  return QXD_OK;
+}
+
+qxd_status qxd_field_upload(qxd_ctx *ctx, const qxd_lattice *lat, const double *U_host,
+                            const double *A_host, qxd_field **field) {
+  if (!ctx || !field || !U_host) {
+    set_error("ctx, U_host and field must be non-NULL");
+    return QXD_EINVAL;
+  }
+  Geom g;
+  qxd_status s = make_geom(lat, &g);
+  if (s != QXD_OK) return s;
+  double q_el = lat->q_el == 0.0 ? 1.0 / 6.0 : lat->q_el;
+  if (!(q_el > 0.0) || !isfinite(q_el)) {
+    set_error("q_el must be positive");
+    return QXD_EINVAL;
+  }
+  QXD_HIP_CHECK(hipSetDevice(ctx->device));
+  std::unique_ptr<qxd_field> f(new qxd_field());
+  f->ctx = ctx;
+  f->lat = *lat;
+  f->g = g;
+  f->q_el = q_el;
+  f->has_u1 = A_host != nullptr;
+  int64_t vph = (int64_t)lat->dims[0] * lat->dims[1] * lat->dims[2] * lat->dims[3];
+  DevBuf u_st, a_st;
+  QXD_HIP_CHECK(u_st.ensure(vph * 4 * 18 * sizeof(double)));
+  QXD_HIP_CHECK(hipMemcpy(u_st.p, U_host, vph * 4 * 18 * sizeof(double), hipMemcpyHostToDevice));
+  if (A_host) {
+    QXD_HIP_CHECK(a_st.ensure(vph * 4 * sizeof(double)));
+    QXD_HIP_CHECK(hipMemcpy(a_st.p, A_host, vph * 4 * sizeof(double), hipMemcpyHostToDevice));
+  }
+  QXD_HIP_CHECK(f->links[QXD_F64].ensure((size_t)36 * g.V * 16));
+  QXD_HIP_CHECK(f->angles[QXD_F64].ensure((size_t)4 * g.V * 8));
+  QXD_HIP_CHECK(launch_orbifold(g, u_st.as<double>(), a_st.as<double>(), f->links[QXD_F64].as<double2>(),
+                                f->angles[QXD_F64].as<double>(), 0));
+  QXD_HIP_CHECK(hipDeviceSynchronize());
+  f->links_ready[QXD_F64] = true;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->n_fields++;
+  }
+  *field = f.release();
+  return QXD_OK;
+}
+
+qxd_status qxd_field_release(qxd_field *field) {
+  if (!field) {
+    set_error("field is NULL");
+    return QXD_EINVAL;
+  }
+  qxd_ctx *ctx = field->ctx;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  delete field;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->n_fields--;
+  return QXD_OK;
+}
+
+qxd_status qxd_field_volume(const qxd_field *field, int64_t *v_ext) {
+  if (!field || !v_ext) {
+    set_error("field and v_ext must be non-NULL");
+    return QXD_EINVAL;
+  }
+  *v_ext = field->g.V;
+  return QXD_OK;
+}
+
+qxd_status qxd_spinor_bytes(const qxd_field *field, qxd_prec prec, size_t *bytes) {
+  if (!field || !bytes || !valid_prec(prec)) {
+    set_error("invalid arguments to qxd_spinor_bytes");
+    return QXD_EINVAL;
+  }
+  *bytes = field->spinor_bytes(prec);
+  return QXD_OK;
+}
+
+qxd_status qxd_spinor_pack(qxd_field *field, qxd_prec prec, const double *in_dev, void *out_dev,
+                           int nrhs, void *stream) {
+  if (!field || !in_dev || !out_dev || nrhs < 1 || !valid_prec(prec)) {
+    set_error("invalid arguments to qxd_spinor_pack");
+    return QXD_EINVAL;
+  }
+  QXD_HIP_CHECK(hipSetDevice(field->ctx->device));
+  QXD_HIP_CHECK(launch_pack(prec, field->g, in_dev, out_dev, nrhs, (hipStream_t)stream));
+  return QXD_OK;
+}
+
+qxd_status qxd_spinor_unpack(qxd_field *field, qxd_prec prec, const void *in_dev, double *out_dev,
+                             int nrhs, void *stream) {
+  if (!field || !in_dev || !out_dev || nrhs < 1 || !valid_prec(prec)) {
+    set_error("invalid arguments to qxd_spinor_unpack");
+    return QXD_EINVAL;
+  }
+  QXD_HIP_CHECK(hipSetDevice(field->ctx->device));
+  QXD_HIP_CHECK(launch_unpack(prec, field->g, in_dev, out_dev, nrhs, (hipStream_t)stream));
+  return QXD_OK;
+}
+
+qxd_status qxd_dirac_apply(qxd_field *field, const qxd_quark *quarks, int nquark, qxd_op op,
+                           qxd_prec prec, const void *in_dev, void *out_dev, int nrhs, unsigned flags,
+                           void *stream) {
+  if (!field || !quarks || !in_dev || !out_dev || nquark < 1 || nrhs < 1 || nrhs % nquark ||
+      !valid_prec(prec) || op < QXD_OP_D || op > QXD_OP_OOINV || (flags & ~QXD_NATIVE)) {
+    set_error("invalid arguments to qxd_dirac_apply");
+    return QXD_EINVAL;
+  }
+  if (in_dev == out_dev) {
+    set_error("in and out must not overlap");
+    return QXD_EINVAL;
+  }
+  std::lock_guard<std::recursive_mutex> lk(field->mu);
+  hipStream_t st = (hipStream_t)stream;
+  QXD_HIP_CHECK(hipSetDevice(field->ctx->device));
+  size_t nb = field->spinor_bytes(prec);
+  const bool native = flags & QXD_NATIVE;
+  void *nin = nullptr, *nout = nullptr;
+  if (!native) {
+    hipError_t e;
+    nin = field->workspace("apply_in", nb, &e);
+    QXD_HIP_CHECK(e);
+    nout = field->workspace("apply_out", nb, &e);
+    QXD_HIP_CHECK(e);
+  }
+  int per = nrhs / nquark;
+  for (int r = 0; r < nrhs; r++) {
+    Operator *o;
+    qxd_status s = field->get_op(quarks[r / per], prec, &o, st);
+    if (s != QXD_OK) return s;
+    if (native) {
+      s = apply_native(field, *o, op, prec, (char *)in_dev + r * nb, (char *)out_dev + r * nb, st);
+    } else {
+      const double *src = (const double *)in_dev + (int64_t)r * 24 * field->g.V;
+      double *dst = (double *)out_dev + (int64_t)r * 24 * field->g.V;
+      QXD_HIP_CHECK(launch_pack(prec, field->g, src, nin, 1, st));
+      s = apply_native(field, *o, op, prec, nin, nout, st);
+      if (s == QXD_OK) QXD_HIP_CHECK(launch_unpack(prec, field->g, nout, dst, 1, st));
+    }
+    if (s != QXD_OK) return s;
+  }
+  return QXD_OK;
+}
+
+qxd_status qxd_solve(qxd_field *field, const qxd_quark *quarks, int nquark, const qxd_solver *s,
+                     const double *eta_dev, double *psi_dev, int nrhs, int use_guess,
+                     qxd_solve_info *info, void *stream) {
+  if (!field || !quarks || !s || !eta_dev || !psi_dev || nquark < 1 || nrhs < 1 || nrhs % nquark) {
+    set_error("invalid arguments to qxd_solve");
+    return QXD_EINVAL;
+  }
+  std::lock_guard<std::recursive_mutex> lk(field->mu);
+  QXD_HIP_CHECK(hipSetDevice(field->ctx->device));
+  return solve(field, quarks, nquark, *s, eta_dev, psi_dev, nrhs, use_guess, info, (hipStream_t)stream);
+}
+
+qxd_status qxd_sap_apply(qxd_field *field, const qxd_quark *quark, qxd_prec prec, int ncy, int nmr,
+                         const double *in_dev, double *out_dev, int nrhs, void *stream) {
+  if (!field || !quark || !in_dev || !out_dev || nrhs < 1 || ncy < 1 || nmr < 0 || !valid_prec(prec)) {
+    set_error("invalid arguments to qxd_sap_apply");
+    return QXD_EINVAL;
+  }
+  std::lock_guard<std::recursive_mutex> lk(field->mu);
+  hipStream_t st = (hipStream_t)stream;
+  QXD_HIP_CHECK(hipSetDevice(field->ctx->device));
+  qxd_status s = check_sap_blocks(field);
+  if (s != QXD_OK) return s;
+  Operator *o;
+  s = field->get_op(*quark, prec, &o, st);
+  if (s != QXD_OK) return s;
+  size_t nb = field->spinor_bytes(prec);
+  hipError_t e;
+  void *nin = field->workspace("precond_in", nb, &e);
+  QXD_HIP_CHECK(e);
+  void *nout = field->workspace("precond_out", nb, &e);
+  QXD_HIP_CHECK(e);
+  for (int r = 0; r < nrhs; r++) {
+    QXD_HIP_CHECK(launch_pack(prec, field->g, in_dev + (int64_t)r * 24 * field->g.V, nin, 1, st));
+    s = sap_apply(field, *o, prec, ncy, nmr, nin, nout, st);
+    if (s != QXD_OK) return s;
+    QXD_HIP_CHECK(launch_unpack(prec, field->g, nout, out_dev + (int64_t)r * 24 * field->g.V, 1, st));
+  }
+  return QXD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,370 @@
+// Linear algebra on native spinors for the Krylov solvers: multi-dot products,
+// multi-axpys with fused norms, residual updates and precision conversion.
+//
+// Every reduction accumulates in FP64 (GCR orthogonalisation and norms are
+// FP64 whatever the storage precision) and is deterministic: a fixed grid of
+// at most RED_BLOCKS work-groups writes per-group partial sums, and one
+// work-group adds them in a fixed tree order.  Results depend only on the
+// vector length and the data, never on what else runs on the GPU.
+#include "blas.h"
+#include "qxd_impl.h"
+
+namespace qxd {
+
+namespace {
+
+constexpr int BT = 256;
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+  // wavefront reduction then across the 4 wavefronts of the group
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  return r;
+}
+
+inline unsigned red_grid(int64_t n) {
+  int64_t g = (n + BT - 1) / BT;
+  return (unsigned)(g < RED_BLOCKS ? (g < 1 ? 1 : g) : RED_BLOCKS);
+}
+
+template <int P>
+__device__ __forceinline__ void ld(const Spinor<P> &v, int64_t i, cx<double> a[4][3]) {
+  load_spinor<P, double>(v, i, a);
+}
+
+// partial[k][blk] for k < nred
+__global__ void finish_kernel(const double *partial, int nblk, int nred, double *out,
+                              const double *div, int div_stride) {
+  __shared__ double sh[4];
+  for (int k = 0; k < nred; k++) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += BT) v += partial[(int64_t)k * nblk + b];
+    double s = block_sum(v, sh);
+    if (threadIdx.x == 0) {
+      if (div) s /= div[(k / 2) * div_stride];
+      out[k] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// partial[(base + 2l (+1)) * grid + blk] = block sums of (y_l, x), l < N
+template <int P, int N>
+__global__ void mdot_kernel(VecList<P> ys, Spinor<P> x, int64_t first, int64_t count,
+                            double *partial, int base) {
+  __shared__ double sh[4];
+  double acc[2 * N];
+#pragma unroll
+  for (int k = 0; k < 2 * N; k++) acc[k] = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * BT + threadIdx.x; t < count; t += (int64_t)gridDim.x * BT) {
+    int64_t i = first + t;
+    cx<double> xv[4][3];
+    ld<P>(x, i, xv);
+#pragma unroll
+    for (int l = 0; l < N; l++) {
+      cx<double> yv[4][3];
+      ld<P>(ys.v[l], i, yv);
+      double re = 0, im = 0;
+#pragma unroll
+      for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+          cx<double> z = cmulc(yv[a][c], xv[a][c]);
+          re += z.re;
+          im += z.im;
+        }
+      acc[2 * l] += re;
+      acc[2 * l + 1] += im;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 2 * N; k++) {
+    double s = block_sum(acc[k], sh);
+    if (threadIdx.x == 0) partial[(int64_t)(base + k) * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+template <int P>
+struct MaxpyArgs {
+  int ntriples;
+  Spinor<P> src[2];
+  Spinor<P> dst[2];
+  VecList<P> ys[2];
+  const double *coef;   // complex, element l + coef_base
+  const double *div;
+  int div_stride;
+  int coef_base;
+  int want_norms;
+  int has_w;
+  Spinor<P> w;
+};
+
+// z_t = src_t - sum_{l<N} coef[l] / div[l] * ys_t[l] for t < ntriples; then
+// partial sums of (z_0, z_0) and (z_0, w).
+template <int P, int N>
+__global__ void maxpy_kernel(MaxpyArgs<P> a, int64_t first, int64_t count, double *partial) {
+  __shared__ double sh[4];
+  cx<double> cf[N > 0 ? N : 1];
+#pragma unroll
+  for (int l = 0; l < N; l++) {
+    int L = a.coef_base + l;
+    double d = a.div ? a.div[L * a.div_stride] : 1.0;
+    cf[l] = {a.coef[2 * L] / d, a.coef[2 * L + 1] / d};
+  }
+  double nn = 0.0, wr = 0.0, wi = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * BT + threadIdx.x; t < count; t += (int64_t)gridDim.x * BT) {
+    int64_t i = first + t;
+    for (int tr = 0; tr < a.ntriples; tr++) {
+      cx<double> z[4][3];
+      ld<P>(a.src[tr], i, z);
+#pragma unroll
+      for (int l = 0; l < N; l++) {
+        cx<double> y[4][3];
+        ld<P>(a.ys[tr].v[l], i, y);
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+#pragma unroll
+          for (int k = 0; k < 3; k++) z[s][k] = z[s][k] - cf[l] * y[s][k];
+      }
+      store_spinor<P, double>(a.dst[tr], i, z);
+      if (tr == 0 && a.want_norms) {
+        // re-read what was stored so that the norms match the stored vector
+        ld<P>(a.dst[0], i, z);
+        cx<double> w[4][3];
+        if (a.has_w) ld<P>(a.w, i, w);
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+#pragma unroll
+          for (int k = 0; k < 3; k++) {
+            nn += norm2(z[s][k]);
+            if (a.has_w) {
+              cx<double> q = cmulc(z[s][k], w[s][k]);
+              wr += q.re;
+              wi += q.im;
+            }
+          }
+      }
+    }
+  }
+  if (a.want_norms) {
+    double s0 = block_sum(nn, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s0;
+    double s1 = block_sum(wr, sh);
+    if (threadIdx.x == 0) partial[gridDim.x + blockIdx.x] = s1;
+    double s2 = block_sum(wi, sh);
+    if (threadIdx.x == 0) partial[2 * gridDim.x + blockIdx.x] = s2;
+  }
+}
+
+// y -= (num / den) x  with num complex (device), den real (device); then |y|^2.
+template <int P>
+__global__ void update_kernel(Spinor<P> y, Spinor<P> x, const double *num, const double *den,
+                              int negate, int64_t first, int64_t count, double *partial) {
+  __shared__ double sh[4];
+  double d = den ? *den : 1.0;
+  cx<double> c{num[0] / d, num[1] / d};
+  if (negate) c = -c;
+  double nn = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * BT + threadIdx.x; t < count; t += (int64_t)gridDim.x * BT) {
+    int64_t i = first + t;
+    cx<double> yv[4][3], xv[4][3];
+    ld<P>(y, i, yv);
+    ld<P>(x, i, xv);
+#pragma unroll
+    for (int s = 0; s < 4; s++)
+#pragma unroll
+      for (int k = 0; k < 3; k++) yv[s][k] = yv[s][k] - c * xv[s][k];
+    store_spinor<P, double>(y, i, yv);
+    ld<P>(y, i, yv);
+#pragma unroll
+    for (int s = 0; s < 4; s++)
+#pragma unroll
+      for (int k = 0; k < 3; k++) nn += norm2(yv[s][k]);
+  }
+  double s0 = block_sum(nn, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s0;
+}
+
+// y_Q = a * y_Q + b * x_P (a, b real; y may be absent: a = 0 and y not read);
+// optional |y|^2.
+template <int Q, int P>
+__global__ void axpby_kernel(Spinor<Q> y, double a, Spinor<P> x, double b, int64_t first,
+                             int64_t count, double *partial) {
+  __shared__ double sh[4];
+  double nn = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * BT + threadIdx.x; t < count; t += (int64_t)gridDim.x * BT) {
+    int64_t i = first + t;
+    cx<double> yv[4][3], xv[4][3];
+    ld<P>(x, i, xv);
+    if (a != 0.0) {
+      ld<Q>(y, i, yv);
+#pragma unroll
+      for (int s = 0; s < 4; s++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) yv[s][k] = a * yv[s][k] + b * xv[s][k];
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; s++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) yv[s][k] = b * xv[s][k];
+    }
+    store_spinor<Q, double>(y, i, yv);
+    if (partial) {
+      ld<Q>(y, i, yv);
+#pragma unroll
+      for (int s = 0; s < 4; s++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) nn += norm2(yv[s][k]);
+    }
+  }
+  if (partial) {
+    double s0 = block_sum(nn, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s0;
+  }
+}
+
+// |x|^2 and a finiteness check
+template <int P>
+__global__ void norm_kernel(Spinor<P> x, int64_t first, int64_t count, double *partial) {
+  __shared__ double sh[4];
+  double nn = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * BT + threadIdx.x; t < count; t += (int64_t)gridDim.x * BT) {
+    cx<double> xv[4][3];
+    ld<P>(x, first + t, xv);
+#pragma unroll
+    for (int s = 0; s < 4; s++)
+#pragma unroll
+      for (int k = 0; k < 3; k++) nn += norm2(xv[s][k]);
+  }
+  double s0 = block_sum(nn, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s0;
+}
+
+template <int P>
+Spinor<P> view(const SpinorArg &a) {
+  return spinor_view<P>(a.ptr, a.sites, a.off);
+}
+
+}  // namespace
+
+hipError_t finish(const double *partial, int nblk, int nred, double *out, const double *div,
+                  int div_stride, hipStream_t st) {
+  finish_kernel<<<1, BT, 0, st>>>(partial, nblk, nred, out, div, div_stride);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t blas_mdot(const SpinorArg *ys, int n, SpinorArg x, int64_t first, int64_t count,
+                     double *partial, double *out, const double *div, int div_stride, hipStream_t st) {
+  if (n < 1 || n > MAXV) return hipErrorInvalidValue;
+  unsigned g = red_grid(count);
+  Spinor<P> xv = view<P>(x);
+  for (int c0 = 0; c0 < n; c0 += CHUNK) {
+    int m = n - c0 < CHUNK ? n - c0 : CHUNK;
+    VecList<P> l;
+    for (int k = 0; k < m; k++) l.v[k] = view<P>(ys[c0 + k]);
+    int base = 2 * c0;
+    switch (m) {
+#define QXD_CASE(N) case N: mdot_kernel<P, N><<<g, BT, 0, st>>>(l, xv, first, count, partial, base); break;
+      QXD_CASE(1) QXD_CASE(2) QXD_CASE(3) QXD_CASE(4) QXD_CASE(5) QXD_CASE(6) QXD_CASE(7) QXD_CASE(8)
+#undef QXD_CASE
+    }
+  }
+  return finish(partial, g, 2 * n, out, div, div_stride, st);
+}
+
+template <int P>
+hipError_t blas_maxpy(const MaxpyHost &h, int64_t first, int64_t count, double *partial, double *out,
+                      hipStream_t st) {
+  if (h.n < 0 || h.n > MAXV || h.ntriples < 1 || h.ntriples > 2) return hipErrorInvalidValue;
+  unsigned g = red_grid(count);
+  int c0 = 0;
+  do {
+    int m = h.n - c0 < CHUNK ? h.n - c0 : CHUNK;
+    bool last = c0 + m >= h.n;
+    MaxpyArgs<P> a;
+    a.ntriples = h.ntriples;
+    for (int tr = 0; tr < h.ntriples; tr++) {
+      a.src[tr] = view<P>(c0 == 0 ? h.src[tr] : h.dst[tr]);
+      a.dst[tr] = view<P>(h.dst[tr]);
+      for (int k = 0; k < m; k++) a.ys[tr].v[k] = view<P>(h.ys[tr][c0 + k]);
+    }
+    a.coef = h.coef;
+    a.div = h.div;
+    a.div_stride = h.div_stride;
+    a.coef_base = c0;
+    a.want_norms = last && out != nullptr;
+    a.has_w = h.w.ptr != nullptr;
+    a.w = a.has_w ? view<P>(h.w) : Spinor<P>{nullptr, nullptr, 0, 0};
+    switch (m) {
+#define QXD_CASE(N) case N: maxpy_kernel<P, N><<<g, BT, 0, st>>>(a, first, count, partial); break;
+      QXD_CASE(0) QXD_CASE(1) QXD_CASE(2) QXD_CASE(3) QXD_CASE(4) QXD_CASE(5) QXD_CASE(6) QXD_CASE(7) QXD_CASE(8)
+#undef QXD_CASE
+    }
+    c0 += m;
+  } while (c0 < h.n);
+  if (!out) return hipGetLastError();
+  return finish(partial, g, 3, out, nullptr, 0, st);
+}
+
+template <int P>
+hipError_t blas_update(SpinorArg y, SpinorArg x, const double *num, const double *den, int negate,
+                       int64_t first, int64_t count, double *partial, double *out, hipStream_t st) {
+  unsigned g = red_grid(count);
+  update_kernel<P><<<g, BT, 0, st>>>(view<P>(y), view<P>(x), num, den, negate, first, count, partial);
+  return finish(partial, g, 1, out, nullptr, 0, st);
+}
+
+template <int Q, int P>
+hipError_t blas_axpby(SpinorArg y, double a, SpinorArg x, double b, int64_t first, int64_t count,
+                      double *partial, double *out, hipStream_t st) {
+  unsigned g = red_grid(count);
+  axpby_kernel<Q, P><<<g, BT, 0, st>>>(view<Q>(y), a, view<P>(x), b, first, count, out ? partial : nullptr);
+  if (!out) return hipGetLastError();
+  return finish(partial, g, 1, out, nullptr, 0, st);
+}
+
+template <int P>
+hipError_t blas_norm2(SpinorArg x, int64_t first, int64_t count, double *partial, double *out,
+                      hipStream_t st) {
+  unsigned g = red_grid(count);
+  norm_kernel<P><<<g, BT, 0, st>>>(view<P>(x), first, count, partial);
+  return finish(partial, g, 1, out, nullptr, 0, st);
+}
+
+#define QXD_INST(P)                                                                              \
+  template hipError_t blas_mdot<P>(const SpinorArg *, int, SpinorArg, int64_t, int64_t, double *, \
+                                   double *, const double *, int, hipStream_t);                   \
+  template hipError_t blas_maxpy<P>(const MaxpyHost &, int64_t, int64_t, double *, double *,     \
+                                    hipStream_t);                                                \
+  template hipError_t blas_update<P>(SpinorArg, SpinorArg, const double *, const double *, int,  \
+                                     int64_t, int64_t, double *, double *, hipStream_t);          \
+  template hipError_t blas_norm2<P>(SpinorArg, int64_t, int64_t, double *, double *, hipStream_t);
+QXD_INST(QXD_F64)
+QXD_INST(QXD_F32)
+QXD_INST(QXD_F16S)
+QXD_INST(QXD_BF16)
+#undef QXD_INST
+
+#define QXD_INST2(Q, P)                                                                       \
+  template hipError_t blas_axpby<Q, P>(SpinorArg, double, SpinorArg, double, int64_t, int64_t, \
+                                       double *, double *, hipStream_t);
+QXD_INST2(QXD_F64, QXD_F64)
+QXD_INST2(QXD_F64, QXD_F32)
+QXD_INST2(QXD_F64, QXD_F16S)
+QXD_INST2(QXD_F64, QXD_BF16)
+QXD_INST2(QXD_F32, QXD_F64)
+QXD_INST2(QXD_F16S, QXD_F64)
+QXD_INST2(QXD_BF16, QXD_F64)
+QXD_INST2(QXD_F32, QXD_F32)
+QXD_INST2(QXD_F16S, QXD_F16S)
+QXD_INST2(QXD_BF16, QXD_BF16)
+#undef QXD_INST2
+
+}  // namespace qxd

@@ -1,0 +1,364 @@
+// Gauge-field ingest with the C* orbifold, clover/Pauli construction, the
+// inverse of the odd-site Pauli blocks, and layout/precision conversions.
+#include "dirac_site.h"
+#include "launch.h"
+
+namespace qxd {
+
+namespace {
+
+struct M3 {
+  cx<double> m[3][3];
+};
+
+__device__ __forceinline__ M3 ld_u(const double2 *links, int64_t V, int mu, int64_t i) {
+  M3 r;
+  load_link<QXD_F64, double>(links, V, mu, i, r.m);
+  return r;
+}
+__device__ __forceinline__ M3 mul(const M3 &a, const M3 &b) {
+  M3 r;
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      cx<double> s{0, 0};
+      for (int k = 0; k < 3; k++) s = fma_acc(s, a.m[i][k], b.m[k][j]);
+      r.m[i][j] = s;
+    }
+  return r;
+}
+__device__ __forceinline__ M3 dag(const M3 &a) {
+  M3 r;
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) r.m[i][j] = conj(a.m[j][i]);
+  return r;
+}
+
+// ---- orbifold build (Sec. 2.1, eq. orbi:gauge) ------------------------------
+__global__ void orbifold_kernel(Geom g, const double *u_phs, const double *a_phs, double2 *links,
+                                double *angles) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.V) return;
+  Site s = decode(g, i);
+  int x[4];
+  global_coords(g, s, x);
+  bool mirror;
+  int64_t j = phys_lex(g, x, mirror);
+  for (int mu = 0; mu < 4; mu++) {
+    bool cut = g.time_bc == 1 && mu == 0 && x[0] == g.N[0] - 1;
+    const double *u = u_phs + (j * 4 + mu) * 18;
+    for (int k = 0; k < 9; k++) {
+      double re = u[2 * k], im = u[2 * k + 1];
+      if (mirror) im = -im;
+      if (cut) re = im = 0.0;
+      links[(int64_t)(mu * 9 + k) * g.V + i] = make_double2(re, im);
+    }
+    double a = a_phs ? a_phs[j * 4 + mu] : 0.0;
+    angles[(int64_t)mu * g.V + i] = mirror ? -a : a;
+  }
+}
+
+// ---- clover and Pauli term (Sec. 2.3) ---------------------------------------
+__device__ __forceinline__ cx<double> zlink(const Geom &g, const double *angles, int mu,
+                                            int64_t i, const Site &s) {
+  int x0 = s.B[0] * g.b[0] + s.y[0];
+  if (g.time_bc == 1 && mu == 0 && x0 == g.N[0] - 1) return {0.0, 0.0};
+  double sn, cs;
+  sincos(angles[(int64_t)mu * g.V + i], &sn, &cs);
+  return {cs, sn};
+}
+
+__global__ void pauli_build_kernel(Geom g, const double2 *links, const double *angles, int has_u1,
+                                   double kappa, double csw, double u1coef, double2 *pauli) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.V) return;
+  Site s = decode(g, i);
+  // G_p = csw F_p + u1coef * Ahat'_p for the planes (01,02,03,12,13,23)
+  M3 gp[6];
+  int p = 0;
+  for (int mu = 0; mu < 4; mu++)
+    for (int nu = mu + 1; nu < 4; nu++, p++) {
+      int sg;
+      Site xpm = neighbour(g, s, mu, 1, sg), xpn = neighbour(g, s, nu, 1, sg);
+      Site xmm = neighbour(g, s, mu, -1, sg), xmn = neighbour(g, s, nu, -1, sg);
+      Site xmm_pn = neighbour(g, xmm, nu, 1, sg), xmm_mn = neighbour(g, xmm, nu, -1, sg);
+      Site xpm_mn = neighbour(g, xmn, mu, 1, sg);
+      int64_t ixpm = encode(g, xpm), ixpn = encode(g, xpn), ixmm = encode(g, xmm),
+              ixmn = encode(g, xmn), ixmm_pn = encode(g, xmm_pn), ixmm_mn = encode(g, xmm_mn),
+              ixpm_mn = encode(g, xpm_mn);
+      M3 q1 = mul(mul(ld_u(links, g.V, mu, i), ld_u(links, g.V, nu, ixpm)),
+                  mul(dag(ld_u(links, g.V, mu, ixpn)), dag(ld_u(links, g.V, nu, i))));
+      M3 q2 = mul(mul(ld_u(links, g.V, nu, i), dag(ld_u(links, g.V, mu, ixmm_pn))),
+                  mul(dag(ld_u(links, g.V, nu, ixmm)), ld_u(links, g.V, mu, ixmm)));
+      M3 q3 = mul(mul(dag(ld_u(links, g.V, mu, ixmm)), dag(ld_u(links, g.V, nu, ixmm_mn))),
+                  mul(ld_u(links, g.V, mu, ixmm_mn), ld_u(links, g.V, nu, ixmn)));
+      M3 q4 = mul(mul(dag(ld_u(links, g.V, nu, ixmn)), ld_u(links, g.V, mu, ixmn)),
+                  mul(ld_u(links, g.V, nu, ixpm_mn), dag(ld_u(links, g.V, mu, i))));
+      double ah = 0.0;  // Ahat' = i * ah
+      if (has_u1) {
+        auto zp = [&](int64_t y, const Site &sy, int64_t ypm, const Site &sypm, int64_t ypn,
+                      const Site &sypn) {
+          return zlink(g, angles, mu, y, sy) * zlink(g, angles, nu, ypm, sypm) *
+                 conj(zlink(g, angles, mu, ypn, sypn)) * conj(zlink(g, angles, nu, y, sy));
+        };
+        cx<double> zs = zp(i, s, ixpm, xpm, ixpn, xpn) + zp(ixmm, xmm, i, s, ixmm_pn, xmm_pn) +
+                        zp(ixmn, xmn, ixpm_mn, xpm_mn, i, s) +
+                        zp(ixmm_mn, xmm_mn, ixmn, xmn, ixmm, xmm);
+        ah = 0.25 * zs.im;
+      }
+      for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+          cx<double> qs = q1.m[a][b] + q2.m[a][b] + q3.m[a][b] + q4.m[a][b];
+          cx<double> qt = q1.m[b][a] + q2.m[b][a] + q3.m[b][a] + q4.m[b][a];
+          cx<double> f = 0.125 * (qs - conj(qt));
+          gp[p].m[a][b] = csw * f;
+        }
+      for (int a = 0; a < 3; a++) gp[p].m[a][a].im += u1coef * ah;
+    }
+  // chiral blocks: M_l = +-G_0l - B_l, B = (G_23, -G_13, G_12); H_l = (i/2) M_l
+  double d = 0.5 / kappa;
+  for (int blk = 0; blk < 2; blk++) {
+    double sgn = blk == 0 ? 1.0 : -1.0;
+    M3 h[3];
+    for (int a = 0; a < 3; a++)
+      for (int b = 0; b < 3; b++) {
+        cx<double> m1 = sgn * gp[0].m[a][b] - gp[5].m[a][b];
+        cx<double> m2 = sgn * gp[1].m[a][b] + gp[4].m[a][b];
+        cx<double> m3 = sgn * gp[2].m[a][b] - gp[3].m[a][b];
+        h[0].m[a][b] = 0.5 * times_i(m1);
+        h[1].m[a][b] = 0.5 * times_i(m2);
+        h[2].m[a][b] = 0.5 * times_i(m3);
+      }
+    cx<double> A[6][6];
+    for (int a = 0; a < 3; a++)
+      for (int b = 0; b < 3; b++) {
+        cx<double> dd{a == b ? d : 0.0, 0.0};
+        A[a][b] = dd + h[2].m[a][b];
+        A[a][3 + b] = h[0].m[a][b] - times_i(h[1].m[a][b]);
+        A[3 + a][b] = h[0].m[a][b] + times_i(h[1].m[a][b]);
+        A[3 + a][3 + b] = dd - h[2].m[a][b];
+      }
+    int base = 18 * blk;
+    for (int k = 0; k < 3; k++)
+      pauli[(int64_t)(base + k) * g.V + i] = make_double2(A[2 * k][2 * k].re, A[2 * k + 1][2 * k + 1].re);
+    for (int r = 0; r < 6; r++)
+      for (int c = r + 1; c < 6; c++)
+        pauli[(int64_t)(base + 3 + tri_index(r, c)) * g.V + i] = make_double2(A[r][c].re, A[r][c].im);
+  }
+}
+
+// In-place Gauss-Jordan inverse of a Hermitian positive-definite 6x6 block
+// (no pivoting is needed for positive-definite matrices; a non-positive or
+// tiny pivot is reported as singular).
+__global__ void pauli_invert_kernel(Geom g, const double2 *pauli, double2 *pinv, int *bad) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * g.Vh) return;
+  int blk = t / g.Vh;
+  int j = t - blk * g.Vh;      // odd-site half index
+  int64_t i = (int64_t)g.Vh + j;
+  int base = 18 * blk;
+  cx<double> a[6][6];
+  for (int k = 0; k < 3; k++) {
+    double2 v = pauli[(int64_t)(base + k) * g.V + i];
+    a[2 * k][2 * k] = {v.x, 0.0};
+    a[2 * k + 1][2 * k + 1] = {v.y, 0.0};
+  }
+  for (int r = 0; r < 6; r++)
+    for (int c = r + 1; c < 6; c++) {
+      double2 v = pauli[(int64_t)(base + 3 + tri_index(r, c)) * g.V + i];
+      a[r][c] = {v.x, v.y};
+      a[c][r] = {v.x, -v.y};
+    }
+  double scale = 0.0;
+  for (int r = 0; r < 6; r++) scale = fmax(scale, a[r][r].re);
+  bool ok = scale > 0.0;
+  for (int k = 0; k < 6; k++) {
+    cx<double> p = a[k][k];
+    double n2 = norm2(p);
+    if (!(n2 > 1e-28 * scale * scale)) ok = false;
+    cx<double> pi{p.re / n2, -p.im / n2};
+    a[k][k] = {1.0, 0.0};
+    for (int c = 0; c < 6; c++) a[k][c] = a[k][c] * pi;
+    for (int r = 0; r < 6; r++) {
+      if (r == k) continue;
+      cx<double> f = a[r][k];
+      a[r][k] = {0.0, 0.0};
+      for (int c = 0; c < 6; c++) a[r][c] = a[r][c] - f * a[k][c];
+    }
+  }
+  if (!ok) atomicAdd(bad, 1);
+  for (int k = 0; k < 3; k++)
+    pinv[(int64_t)(base + k) * g.Vh + j] = make_double2(a[2 * k][2 * k].re, a[2 * k + 1][2 * k + 1].re);
+  for (int r = 0; r < 6; r++)
+    for (int c = r + 1; c < 6; c++) {
+      // symmetrise the rounding of the two triangles
+      cx<double> v = 0.5 * (a[r][c] + conj(a[c][r]));
+      pinv[(int64_t)(base + 3 + tri_index(r, c)) * g.Vh + j] = make_double2(v.re, v.im);
+    }
+}
+
+template <int P>
+__global__ void convert_pairs_kernel(const double2 *src, typename St<P>::pair_t *dst, int64_t n) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double2 v = src[k];
+  using C = typename St<P>::comp_t;
+  St<P>::st(dst, k, cx<C>{(C)v.x, (C)v.y});
+}
+
+__global__ void convert_reals_kernel(const double *src, float *dst, int64_t n) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) dst[k] = (float)src[k];
+}
+
+// ---- spinor layout conversion ---------------------------------------------
+template <int P>
+__global__ void pack_kernel(Geom g, const double *api, void *native, size_t bytes) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int r = blockIdx.y;
+  if (i >= g.V) return;
+  Site s = decode(g, i);
+  int x[4];
+  global_coords(g, s, x);
+  int64_t l = ext_lex(g, x);
+  const double *src = api + ((int64_t)r * g.V + l) * 24;
+  cx<double> psi[4][3];
+  for (int a = 0; a < 4; a++)
+    for (int c = 0; c < 3; c++) psi[a][c] = {src[(a * 3 + c) * 2], src[(a * 3 + c) * 2 + 1]};
+  Spinor<P> out = spinor_view<P>((char *)native + r * bytes, g.V, 0);
+  store_spinor<P, double>(out, i, psi);
+}
+
+template <int P>
+__global__ void unpack_kernel(Geom g, const void *native, double *api, size_t bytes) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int r = blockIdx.y;
+  if (i >= g.V) return;
+  Site s = decode(g, i);
+  int x[4];
+  global_coords(g, s, x);
+  int64_t l = ext_lex(g, x);
+  Spinor<P> in = spinor_view<P>((char *)const_cast<void *>(native) + r * bytes, g.V, 0);
+  cx<double> psi[4][3];
+  load_spinor<P, double>(in, i, psi);
+  double *dst = api + ((int64_t)r * g.V + l) * 24;
+  for (int a = 0; a < 4; a++)
+    for (int c = 0; c < 3; c++) {
+      dst[(a * 3 + c) * 2] = psi[a][c].re;
+      dst[(a * 3 + c) * 2 + 1] = psi[a][c].im;
+    }
+}
+
+// W(x,mu) = U(x,mu) exp(i qhat A(x,mu)) in FP64
+__global__ void fold_phase_kernel(int64_t V, const double2 *links, const double *angles, int qhat,
+                                  double2 *w) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 4 * V) return;
+  int mu = (int)(t / V);
+  int64_t i = t - mu * V;
+  double sn, cs;
+  sincos(qhat * angles[t], &sn, &cs);
+  cx<double> z{cs, sn};
+  for (int k = 0; k < 9; k++) {
+    double2 u = links[(int64_t)(mu * 9 + k) * V + i];
+    cx<double> r = cx<double>{u.x, u.y} * z;
+    w[(int64_t)(mu * 9 + k) * V + i] = make_double2(r.re, r.im);
+  }
+}
+
+template <int P>
+__global__ void zero_sites_kernel(Spinor<P> v, int64_t first, int64_t count) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  int64_t i = first + k;
+  cx<typename St<P>::comp_t> z[4][3];
+  for (int a = 0; a < 4; a++)
+    for (int c = 0; c < 3; c++) z[a][c] = {0, 0};
+  store_spinor<P, typename St<P>::comp_t>(v, i, z);
+}
+
+}  // namespace
+
+hipError_t launch_zero_sites(int prec, SpinorArg v, int64_t first, int64_t count, hipStream_t st) {
+  unsigned gr = grid_for(count, 256);
+  switch (prec) {
+    case QXD_F64: zero_sites_kernel<QXD_F64><<<gr, 256, 0, st>>>(spinor_view<QXD_F64>(v.ptr, v.sites, v.off), first, count); break;
+    case QXD_F32: zero_sites_kernel<QXD_F32><<<gr, 256, 0, st>>>(spinor_view<QXD_F32>(v.ptr, v.sites, v.off), first, count); break;
+    case QXD_F16S: zero_sites_kernel<QXD_F16S><<<gr, 256, 0, st>>>(spinor_view<QXD_F16S>(v.ptr, v.sites, v.off), first, count); break;
+    case QXD_BF16: zero_sites_kernel<QXD_BF16><<<gr, 256, 0, st>>>(spinor_view<QXD_BF16>(v.ptr, v.sites, v.off), first, count); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_phase(const Geom &g, const double2 *links, const double *angles, int qhat,
+                             double2 *w, hipStream_t st) {
+  fold_phase_kernel<<<grid_for(4 * (int64_t)g.V, 256), 256, 0, st>>>(g.V, links, angles, qhat, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_orbifold(const Geom &g, const double *u_phs, const double *a_phs, double2 *links,
+                           double *angles, hipStream_t st) {
+  orbifold_kernel<<<grid_for(g.V, 256), 256, 0, st>>>(g, u_phs, a_phs, links, angles);
+  return hipGetLastError();
+}
+
+hipError_t launch_pauli_build(const Geom &g, const double2 *links, const double *angles, int has_u1,
+                              double kappa, double csw, double u1coef, double2 *pauli,
+                              hipStream_t st) {
+  pauli_build_kernel<<<grid_for(g.V, 128), 128, 0, st>>>(g, links, angles, has_u1, kappa, csw,
+                                                         u1coef, pauli);
+  return hipGetLastError();
+}
+
+hipError_t launch_pauli_invert(const Geom &g, const double2 *pauli, double2 *pinv, int *bad,
+                               hipStream_t st) {
+  pauli_invert_kernel<<<grid_for(2 * (int64_t)g.Vh, 128), 128, 0, st>>>(g, pauli, pinv, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert_pairs(int prec, const double2 *src, void *dst, int64_t n, hipStream_t st) {
+  unsigned gr = grid_for(n, 256);
+  switch (prec) {
+    case QXD_F64: return hipMemcpyAsync(dst, src, n * 16, hipMemcpyDeviceToDevice, st);
+    case QXD_F32: convert_pairs_kernel<QXD_F32><<<gr, 256, 0, st>>>(src, (float2 *)dst, n); break;
+    case QXD_F16S: convert_pairs_kernel<QXD_F16S><<<gr, 256, 0, st>>>(src, (h2_t *)dst, n); break;
+    case QXD_BF16: convert_pairs_kernel<QXD_BF16><<<gr, 256, 0, st>>>(src, (uint32_t *)dst, n); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_convert_reals(const double *src, float *dst, int64_t n, hipStream_t st) {
+  convert_reals_kernel<<<grid_for(n, 256), 256, 0, st>>>(src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(int prec, const Geom &g, const double *api, void *native, int nrhs,
+                       hipStream_t st) {
+  dim3 gr(grid_for(g.V, 256), nrhs);
+  size_t bytes = spinor_bytes(prec, g.V);
+  switch (prec) {
+    case QXD_F64: pack_kernel<QXD_F64><<<gr, 256, 0, st>>>(g, api, native, bytes); break;
+    case QXD_F32: pack_kernel<QXD_F32><<<gr, 256, 0, st>>>(g, api, native, bytes); break;
+    case QXD_F16S: pack_kernel<QXD_F16S><<<gr, 256, 0, st>>>(g, api, native, bytes); break;
+    case QXD_BF16: pack_kernel<QXD_BF16><<<gr, 256, 0, st>>>(g, api, native, bytes); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(int prec, const Geom &g, const void *native, double *api, int nrhs,
+                         hipStream_t st) {
+  dim3 gr(grid_for(g.V, 256), nrhs);
+  size_t bytes = spinor_bytes(prec, g.V);
+  switch (prec) {
+    case QXD_F64: unpack_kernel<QXD_F64><<<gr, 256, 0, st>>>(g, native, api, bytes); break;
+    case QXD_F32: unpack_kernel<QXD_F32><<<gr, 256, 0, st>>>(g, native, api, bytes); break;
+    case QXD_F16S: unpack_kernel<QXD_F16S><<<gr, 256, 0, st>>>(g, native, api, bytes); break;
+    case QXD_BF16: unpack_kernel<QXD_BF16><<<gr, 256, 0, st>>>(g, native, api, bytes); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace qxd

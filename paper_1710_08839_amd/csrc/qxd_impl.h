@@ -1,0 +1,329 @@
+// Internal types of libqxd: device geometry of the extended lattice, storage
+// precisions, complex arithmetic and the spinor/link/Pauli layouts.
+//
+// Device layout ("native order").  The extended lattice (Sec. 2.1 of the
+// openQ*D paper) is cut into blocks of b0 x b1 x b2 x b3 sites (all even).
+// A site x has parity p = (x0+x1+x2+x3) & 1, block coordinates B_mu =
+// x_mu / b_mu (block index lexicographic, B0 slowest) and local coordinates
+// y_mu = x_mu mod b_mu with local lexicographic index l.  Its native index is
+//     i = p * V/2 + block * Vb/2 + (l >> 1),
+// so even sites come first, and inside one parity every block is contiguous
+// (the SAP block solver reads its block as one contiguous range).
+//
+// Fields are structure-of-arrays over native sites:
+//   spinor   [12 complex (spin*3 + colour)][sites]        (+ [sites] fp32 scale for F16S)
+//   links    [4 mu][9 complex (row*3 + col)][V]           forward links U(x,mu)
+//   angles   [4 mu][V]                                     U(1) potential A(x,mu)
+//   pauli    [36 pairs][V]  two 6x6 Hermitian blocks, 18 pairs each:
+//            pairs 0-2 hold the 6 real diagonal entries, pairs 3-17 the upper
+//            triangle (0,1),(0,2)...(0,5),(1,2)...(4,5) as (re, im).
+//   pauli_inv [36 pairs][V/2]  inverse blocks on odd sites (D_oo^-1)
+// Block 0 acts on spins 0,1 (gamma5 = +1), block 1 on spins 2,3; inside a
+// block the index is s*3 + colour.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/qxd.h"
+
+#define QXD_HD __host__ __device__ __forceinline__
+
+namespace qxd {
+
+// ---------------------------------------------------------------------------
+// complex arithmetic
+// ---------------------------------------------------------------------------
+template <class T>
+struct cx {
+  T re, im;
+};
+template <class T> QXD_HD cx<T> mk(T r, T i) { return cx<T>{r, i}; }
+template <class T> QXD_HD cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <class T> QXD_HD cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <class T> QXD_HD cx<T> operator-(cx<T> a) { return {-a.re, -a.im}; }
+template <class T> QXD_HD cx<T> operator*(cx<T> a, cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class T> QXD_HD cx<T> operator*(T s, cx<T> a) { return {s * a.re, s * a.im}; }
+template <class T> QXD_HD cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
+// conj(a) * b
+template <class T> QXD_HD cx<T> cmulc(cx<T> a, cx<T> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <class T> QXD_HD cx<T> times_i(cx<T> a) { return {-a.im, a.re}; }
+template <class T> QXD_HD cx<T> times_mi(cx<T> a) { return {a.im, -a.re}; }
+template <class T> QXD_HD T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+template <class T> QXD_HD cx<T> fma_acc(cx<T> acc, cx<T> a, cx<T> b) {
+  acc.re += a.re * b.re - a.im * b.im;
+  acc.im += a.re * b.im + a.im * b.re;
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
+// storage precisions
+// ---------------------------------------------------------------------------
+typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+
+template <int P> struct St;
+template <> struct St<QXD_F64> {
+  using pair_t = double2;
+  using real_t = double;   // storage of single reals (angles)
+  using comp_t = double;   // arithmetic
+  static constexpr bool scaled = false;
+  QXD_HD static cx<double> ld(const pair_t *p, int64_t i) {
+    pair_t v = p[i];
+    return {v.x, v.y};
+  }
+  QXD_HD static void st(pair_t *p, int64_t i, cx<double> z) { p[i] = make_double2(z.re, z.im); }
+  QXD_HD static double ldr(const real_t *p, int64_t i) { return p[i]; }
+  QXD_HD static void str(real_t *p, int64_t i, double v) { p[i] = v; }
+};
+template <> struct St<QXD_F32> {
+  using pair_t = float2;
+  using real_t = float;
+  using comp_t = float;
+  static constexpr bool scaled = false;
+  QXD_HD static cx<float> ld(const pair_t *p, int64_t i) {
+    pair_t v = p[i];
+    return {v.x, v.y};
+  }
+  QXD_HD static void st(pair_t *p, int64_t i, cx<float> z) { p[i] = make_float2(z.re, z.im); }
+  QXD_HD static float ldr(const real_t *p, int64_t i) { return p[i]; }
+  QXD_HD static void str(real_t *p, int64_t i, float v) { p[i] = v; }
+};
+template <> struct St<QXD_F16S> {
+  using pair_t = h2_t;
+  using real_t = float;    // angles stay fp32
+  using comp_t = float;
+  static constexpr bool scaled = true;
+  QXD_HD static cx<float> ld(const pair_t *p, int64_t i) {
+    pair_t v = p[i];
+    return {(float)v.x, (float)v.y};
+  }
+  QXD_HD static void st(pair_t *p, int64_t i, cx<float> z) {
+    pair_t v;
+    v.x = (_Float16)z.re;
+    v.y = (_Float16)z.im;
+    p[i] = v;
+  }
+  QXD_HD static float ldr(const real_t *p, int64_t i) { return p[i]; }
+  QXD_HD static void str(real_t *p, int64_t i, float v) { p[i] = v; }
+};
+// bfloat16 pairs stored as one uint32: low half = real part, high half = imag
+template <> struct St<QXD_BF16> {
+  using pair_t = uint32_t;
+  using real_t = float;
+  using comp_t = float;
+  static constexpr bool scaled = false;
+  QXD_HD static float bf2f(uint32_t bits16) { return __builtin_bit_cast(float, bits16 << 16); }
+  QXD_HD static uint32_t f2bf(float f) {
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return u >> 16;
+  }
+  QXD_HD static cx<float> ld(const pair_t *p, int64_t i) {
+    uint32_t v = p[i];
+    return {bf2f(v & 0xffffu), bf2f(v >> 16)};
+  }
+  QXD_HD static void st(pair_t *p, int64_t i, cx<float> z) { p[i] = f2bf(z.re) | (f2bf(z.im) << 16); }
+  QXD_HD static float ldr(const real_t *p, int64_t i) { return p[i]; }
+  QXD_HD static void str(real_t *p, int64_t i, float v) { p[i] = v; }
+};
+
+inline size_t pair_bytes(int prec) {
+  switch (prec) {
+    case QXD_F64: return 16;
+    case QXD_F32: return 8;
+    default: return 4;
+  }
+}
+inline size_t real_bytes(int prec) { return prec == QXD_F64 ? 8 : 4; }
+
+// Bytes of one native spinor over `sites` sites.
+inline size_t spinor_bytes(int prec, int64_t sites) {
+  size_t b = 12 * pair_bytes(prec) * (size_t)sites;
+  if (prec == QXD_F16S) b += 4 * (size_t)sites;
+  return b;
+}
+
+// A spinor view: component c of native site i lives at data[c*stride + i - off].
+template <int P>
+struct Spinor {
+  typename St<P>::pair_t *data;
+  float *scale;   // F16S only: one fp32 scale per site (same indexing)
+  int64_t stride;
+  int64_t off;
+};
+
+template <int P>
+QXD_HD Spinor<P> spinor_view(void *base, int64_t sites, int64_t off) {
+  Spinor<P> s;
+  s.data = (typename St<P>::pair_t *)base;
+  s.scale = St<P>::scaled ? (float *)((char *)base + 12 * sizeof(typename St<P>::pair_t) * sites) : nullptr;
+  s.stride = sites;
+  s.off = off;
+  return s;
+}
+
+template <int P, class T>
+QXD_HD void load_spinor(const Spinor<P> &s, int64_t i, cx<T> psi[4][3]) {
+  int64_t j = i - s.off;
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      cx<typename St<P>::comp_t> z = St<P>::ld(s.data, (a * 3 + c) * s.stride + j);
+      psi[a][c] = {(T)z.re, (T)z.im};
+    }
+  if constexpr (St<P>::scaled) {
+    T f = (T)s.scale[j];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int c = 0; c < 3; c++) psi[a][c] = f * psi[a][c];
+  }
+}
+
+template <int P, class T>
+QXD_HD void store_spinor(const Spinor<P> &s, int64_t i, const cx<T> psi[4][3]) {
+  int64_t j = i - s.off;
+  using C = typename St<P>::comp_t;
+  C f = (C)1;
+  if constexpr (St<P>::scaled) {
+    T m = 0;
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        T r = psi[a][c].re < 0 ? -psi[a][c].re : psi[a][c].re;
+        T q = psi[a][c].im < 0 ? -psi[a][c].im : psi[a][c].im;
+        m = r > m ? r : m;
+        m = q > m ? q : m;
+      }
+    s.scale[j] = (float)m;
+    f = m > 0 ? (C)(1.0f / (float)m) : (C)0;
+  }
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int c = 0; c < 3; c++)
+      St<P>::st(s.data, (a * 3 + c) * s.stride + j, cx<C>{(C)(f * (C)psi[a][c].re), (C)(f * (C)psi[a][c].im)});
+}
+
+// ---------------------------------------------------------------------------
+// geometry of the extended lattice (Sec. 2.1)
+// ---------------------------------------------------------------------------
+struct Geom {
+  int N[4];        // extended extents T, N1, L2, L3
+  int b[4];        // block extents
+  int nb[4];       // blocks per direction
+  int L1;          // physical extent of direction 1
+  int L1b;         // L1 / b1: block shift of the C* shifted boundary
+  int shift_mask;  // bit k (k = 2, 3): direction k has shifted (C*) boundaries
+  int time_bc;     // 0 antiperiodic fermions, 1 open
+  int V, Vh;       // sites, half of them
+  int Vb, Vbh;     // sites per block, half of them
+  int hb3;         // b3 / 2
+  int nblocks;
+};
+
+// Decoded site: block coordinates B, local coordinates y, parity p.
+struct Site {
+  int B[4];
+  int y[4];
+  int p;
+};
+
+QXD_HD Site decode(const Geom &g, int i) {
+  Site s;
+  s.p = i >= g.Vh;
+  int r = i - s.p * g.Vh;
+  int blk = r / g.Vbh;
+  int h = r - blk * g.Vbh;
+  s.B[3] = blk % g.nb[3];
+  blk /= g.nb[3];
+  s.B[2] = blk % g.nb[2];
+  blk /= g.nb[2];
+  s.B[1] = blk % g.nb[1];
+  s.B[0] = blk / g.nb[1];
+  int q = h / g.hb3;
+  int y3h = h - q * g.hb3;
+  s.y[2] = q % g.b[2];
+  q /= g.b[2];
+  s.y[1] = q % g.b[1];
+  s.y[0] = q / g.b[1];
+  int e = (s.p + s.y[0] + s.y[1] + s.y[2]) & 1;
+  s.y[3] = 2 * y3h + e;
+  return s;
+}
+
+QXD_HD int block_index(const Geom &g, const int B[4]) {
+  return ((B[0] * g.nb[1] + B[1]) * g.nb[2] + B[2]) * g.nb[3] + B[3];
+}
+
+QXD_HD int encode(const Geom &g, const Site &s) {
+  int l = ((s.y[0] * g.b[1] + s.y[1]) * g.b[2] + s.y[2]) * g.b[3] + s.y[3];
+  return s.p * g.Vh + block_index(g, s.B) * g.Vbh + (l >> 1);
+}
+
+QXD_HD void global_coords(const Geom &g, const Site &s, int x[4]) {
+#pragma unroll
+  for (int m = 0; m < 4; m++) x[m] = s.B[m] * g.b[m] + s.y[m];
+}
+
+// Neighbour x + mu (dir = +1) or x - mu (dir = -1).  `sign` receives the
+// fermion factor of the hop: -1 across the antiperiodic time boundary, 0 across
+// an open one, else 1.  Shifted C* boundaries move x1 by L1 (mod 2 L1).
+QXD_HD Site neighbour(const Geom &g, const Site &s, int mu, int dir, int &sign) {
+  Site t = s;
+  t.p = s.p ^ 1;
+  sign = 1;
+  int y = s.y[mu] + dir;
+  if (y >= 0 && y < g.b[mu]) {
+    t.y[mu] = y;
+    return t;
+  }
+  t.y[mu] = dir > 0 ? 0 : g.b[mu] - 1;
+  int B = s.B[mu] + dir;
+  bool wrap = false;
+  if (B == g.nb[mu]) {
+    B = 0;
+    wrap = true;
+  } else if (B < 0) {
+    B = g.nb[mu] - 1;
+    wrap = true;
+  }
+  t.B[mu] = B;
+  if (wrap) {
+    if (mu == 0) {
+      sign = g.time_bc == 0 ? -1 : 0;
+    } else if ((g.shift_mask >> mu) & 1) {
+      int b1 = t.B[1] + g.L1b;
+      if (b1 >= g.nb[1]) b1 -= g.nb[1];
+      t.B[1] = b1;
+    }
+  }
+  return t;
+}
+
+// Physical-lattice lexicographic index of the site (mirror sites map to their
+// physical partner); `mirror` tells which half the site lies in.
+QXD_HD int64_t phys_lex(const Geom &g, const int x[4], bool &mirror) {
+  int x1 = x[1];
+  mirror = x1 >= g.L1;
+  if (mirror) x1 -= g.L1;
+  return (((int64_t)x[0] * g.L1 + x1) * g.N[2] + x[2]) * g.N[3] + x[3];
+}
+
+QXD_HD int64_t ext_lex(const Geom &g, const int x[4]) {
+  return (((int64_t)x[0] * g.N[1] + x[1]) * g.N[2] + x[2]) * g.N[3] + x[3];
+}
+
+// ---------------------------------------------------------------------------
+// launch helpers
+// ---------------------------------------------------------------------------
+inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+
+}  // namespace qxd

@@ -1,0 +1,524 @@
+// Solvers for D psi = eta (qxd_solve): the plain even-odd GCR in FP64 and the
+// SAP-preconditioned flexible GCR with FP64 outer defect correction.
+//
+// The paper names these solvers (abstract, Sec. 2) without printing their
+// steps; the steps follow the standard Schwarz-preconditioned GCR:
+//   * EO_GCR: restarted GCR on D^ psi_e = eta^_e with eta^_e = eta_e -
+//     D_eo D_oo^-1 eta_o, then psi_o = D_oo^-1 (eta_o - D_oe psi_e) (Sec. 2.4).
+//   * SAP_GCR: x += s * delta with s = |r|, r = eta - D x in FP64, where delta
+//     solves D delta = r / s approximately by flexible GCR in the inner
+//     precision, right-preconditioned by ncy cycles of the Schwarz alternating
+//     procedure (block solves by nmr minimal-residual steps on the even-odd
+//     block operator).
+// Gram-Schmidt coefficients and norms are FP64 and stay on the device; the host
+// reads one residual norm per iteration.
+#include <math.h>
+
+#include <chrono>
+#include <vector>
+
+#include "blas.h"
+#include "sap.h"
+#include "solver.h"
+
+namespace qxd {
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Ws {
+  Field *f;
+  hipStream_t st;
+  qxd_status err = QXD_OK;
+  void *get(const std::string &name, size_t bytes) {
+    hipError_t e;
+    void *p = f->workspace(name, bytes, &e);
+    if (e != hipSuccess) {
+      set_error("workspace allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+      err = QXD_ENOMEM;
+    }
+    return p;
+  }
+};
+
+#define CK(...)                                                                       \
+  do {                                                                                 \
+    hipError_t _e = (__VA_ARGS__);                                                          \
+    if (_e != hipSuccess) {                                                            \
+      set_error("HIP error %s at %s:%d", hipGetErrorString(_e), __FILE__, __LINE__);  \
+      return QXD_EDEVICE;                                                              \
+    }                                                                                  \
+  } while (0)
+#define CS(...)                         \
+  do {                                   \
+    qxd_status _s = (__VA_ARGS__);            \
+    if (_s != QXD_OK) return _s;         \
+  } while (0)
+
+// read `n` doubles from device (synchronises the stream)
+qxd_status fetch(double *host, const double *dev, int n, hipStream_t st) {
+  CK(hipMemcpyAsync(host, dev, n * sizeof(double), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  return QXD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// D^ on even-half FP64 vectors
+// ---------------------------------------------------------------------------
+struct Schur {
+  Field *f;
+  OpFields of;
+  int prec;
+  void *tmp;  // odd-half temporary
+  qxd_status apply(void *in_e, void *out_e, hipStream_t st) {
+    const Geom &g = f->g;
+    SpinorArg in{in_e, g.Vh, 0}, out{out_e, g.Vh, 0}, t{tmp, g.Vh, g.Vh}, none{nullptr, 0, 0};
+    CK(launch_dirac(prec, DK_ODD, g, of, in, none, t, -0.5, st));
+    CK(launch_dirac(prec, DK_EVEN, g, of, t, in, out, 0.5, st));
+    return QXD_OK;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// plain even-odd GCR, FP64
+// ---------------------------------------------------------------------------
+qxd_status eo_gcr(Field *f, const Operator &op, const qxd_solver &s, void *eta, void *psi, bool guess,
+                  qxd_solve_info *info, hipStream_t st) {
+  const Geom &g = f->g;
+  const int P = QXD_F64;
+  const int nkv = s.nkv > 0 ? s.nkv : 16;
+  if (nkv > MAXV) {
+    set_error("nkv must be <= %d", MAXV);
+    return QXD_EINVAL;
+  }
+  Ws w{f, st};
+  size_t hb = spinor_bytes(P, g.Vh), fb = spinor_bytes(P, g.V);
+  char *pv = (char *)w.get("gcr_p", hb * nkv);
+  char *qv = (char *)w.get("gcr_q", hb * nkv);
+  void *x = w.get("gcr_x", hb), *r = w.get("gcr_r", hb), *b = w.get("gcr_b", hb);
+  void *tmp = w.get("gcr_tmp", hb), *full = w.get("gcr_full", fb);
+  double *partial = (double *)w.get("partial", blas_partial_doubles() * 8);
+  double *scal = (double *)w.get("scalars", (size_t)(2 * MAXV + 3 * MAXV + 16) * 8);
+  if (w.err) return w.err;
+  double *beta = scal, *rec = scal + 2 * MAXV, *rn2 = rec + 3 * MAXV, *misc = rn2 + 4;
+  Schur A{f, f->op_fields(op, P), P, tmp};
+  auto H = [&](void *p) { return SpinorArg{p, g.Vh, 0}; };
+  SpinorArg FULL_eta{eta, g.V, 0}, FULL_psi{psi, g.V, 0}, FULL{full, g.V, 0}, none{nullptr, 0, 0};
+  OpFields of = f->op_fields(op, P);
+
+  // |eta|
+  CK(blas_norm2<P>(FULL_eta, 0, g.V, partial, misc, st));
+  double eta2;
+  CS(fetch(&eta2, misc, 1, st));
+  if (!isfinite(eta2)) {
+    set_error("source contains NaN/Inf");
+    return QXD_EFLOAT;
+  }
+  if (eta2 == 0.0) {
+    CK(hipMemsetAsync(psi, 0, fb, st));
+    if (info) info->true_resid = 0.0;
+    return QXD_OK;
+  }
+  const double eta_n = sqrt(eta2);
+  // b = eta^_e = eta_e + acc(D_oo^-1 eta_o)/2
+  SpinorArg t_o{tmp, g.Vh, g.Vh};
+  CK(launch_dirac(P, DK_ODD, g, of, FULL_eta, FULL_eta, t_o, 0.0, st));
+  CK(launch_dirac(P, DK_EVEN_ID, g, of, t_o, FULL_eta, H(b), 0.5, st));
+  // x = guess_e or 0; r = b - D^ x
+  if (guess) {
+    CK(blas_axpby<P, P>(H(x), 0.0, FULL_psi, 1.0, 0, g.Vh, partial, nullptr, st));
+    CS(A.apply(x, r, st));
+    CK(blas_axpby<P, P>(H(r), -1.0, H(b), 1.0, 0, g.Vh, partial, rn2, st));
+  } else {
+    CK(hipMemsetAsync(x, 0, hb, st));
+    CK(blas_axpby<P, P>(H(r), 0.0, H(b), 1.0, 0, g.Vh, partial, rn2, st));
+  }
+  double r2;
+  CS(fetch(&r2, rn2, 1, st));
+  int it = 0;
+  const int maxiter = s.maxiter > 0 ? s.maxiter : 100000;
+  double target = 0.5 * s.tol * eta_n;
+  double true_res = INFINITY;
+  std::vector<SpinorArg> ps(nkv), qs(nkv);
+  for (int k = 0; k < nkv; k++) {
+    ps[k] = H(pv + k * hb);
+    qs[k] = H(qv + k * hb);
+  }
+  for (int refine = 0; refine < 8; refine++) {
+    while (sqrt(r2) > target && it < maxiter) {
+      for (int k = 0; k < nkv && it < maxiter; k++, it++) {
+        // q_k = D^ r; orthogonalise against q_0..q_{k-1} (and p_k = r - sum beta p_l)
+        CS(A.apply(r, qs[k].ptr, st));
+        if (k > 0) CK(blas_mdot<P>(qs.data(), k, qs[k], 0, g.Vh, partial, beta, rec, 3, st));
+        MaxpyHost m;
+        m.n = k;
+        m.ntriples = 2;
+        m.src[0] = qs[k];
+        m.dst[0] = qs[k];
+        m.ys[0] = qs.data();
+        m.src[1] = H(r);
+        m.dst[1] = ps[k];
+        m.ys[1] = ps.data();
+        m.coef = beta;
+        m.w = H(r);
+        CK(blas_maxpy<P>(m, 0, g.Vh, partial, rec + 3 * k, st));
+        // alpha = (q_k, r) / |q_k|^2: x += alpha p_k, r -= alpha q_k
+        CK(blas_update<P>(H(x), ps[k], rec + 3 * k + 1, rec + 3 * k, 1, 0, g.Vh, partial, misc, st));
+        CK(blas_update<P>(H(r), qs[k], rec + 3 * k + 1, rec + 3 * k, 0, 0, g.Vh, partial, rn2, st));
+        CS(fetch(&r2, rn2, 1, st));
+        if (!isfinite(r2)) {
+          set_error("GCR residual is NaN/Inf");
+          return QXD_EFLOAT;
+        }
+        if (sqrt(r2) <= target) {
+          it++;
+          break;
+        }
+      }
+      // restart: r = b - D^ x
+      CS(A.apply(x, r, st));
+      CK(blas_axpby<P, P>(H(r), -1.0, H(b), 1.0, 0, g.Vh, partial, rn2, st));
+      CS(fetch(&r2, rn2, 1, st));
+    }
+    // psi_e = x, psi_o = D_oo^-1 (eta_o + acc(x)/2); true residual in FP64
+    CK(blas_axpby<P, P>(SpinorArg{psi, g.V, 0}, 0.0, H(x), 1.0, 0, g.Vh, partial, nullptr, st));
+    CK(launch_dirac(P, DK_ODD, g, of, H(x), FULL_eta, FULL_psi, 0.5, st));
+    CK(launch_dirac(P, DK_FULL, g, of, FULL_psi, FULL_psi, FULL, -0.5, st));
+    CK(blas_axpby<P, P>(FULL, -1.0, FULL_eta, 1.0, 0, g.V, partial, misc, st));
+    double res2;
+    CS(fetch(&res2, misc, 1, st));
+    true_res = sqrt(res2) / eta_n;
+    if (true_res <= s.tol || it >= maxiter) break;
+    target *= 0.25;
+  }
+  if (info) {
+    info->outer_iters = 1;
+    info->inner_iters = it;
+    info->true_resid = true_res;
+  }
+  return true_res <= s.tol ? QXD_OK : QXD_ENOCONV;
+}
+
+// ---------------------------------------------------------------------------
+// SAP preconditioner
+// ---------------------------------------------------------------------------
+qxd_status colour_lists(Field *f, const int **lists, int *per_colour) {
+  const Geom &g = f->g;
+  hipError_t e;
+  int *d = (int *)f->workspace("sap_blocks", sizeof(int) * g.nblocks, &e);
+  if (e != hipSuccess) {
+    set_error("workspace allocation failed");
+    return QXD_ENOMEM;
+  }
+  if (!f->work.count("sap_blocks_ready")) {
+    std::vector<int> h;
+    h.reserve(g.nblocks);
+    for (int c = 0; c < 2; c++)
+      for (int B0 = 0; B0 < g.nb[0]; B0++)
+        for (int B1 = 0; B1 < g.nb[1]; B1++)
+          for (int B2 = 0; B2 < g.nb[2]; B2++)
+            for (int B3 = 0; B3 < g.nb[3]; B3++)
+              if (((B0 + B1 + B2 + B3) & 1) == c) h.push_back(((B0 * g.nb[1] + B1) * g.nb[2] + B2) * g.nb[3] + B3);
+    CK(hipMemcpy(d, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice));
+    f->work["sap_blocks_ready"].reset(new DevBuf());
+  }
+  lists[0] = d;
+  lists[1] = d + g.nblocks / 2;
+  *per_colour = g.nblocks / 2;
+  return QXD_OK;
+}
+
+template <int P>
+qxd_status sap_apply_t(Field *f, const Operator &op, int ncy, int nmr, void *rho, void *psi, hipStream_t st) {
+  const Geom &g = f->g;
+  CS(check_sap_blocks(f));
+  const int *lists[2];
+  int nper;
+  CS(colour_lists(f, lists, &nper));
+  Ws w{f, st};
+  size_t fb = spinor_bytes(P, g.V);
+  void *r = w.get("sap_r", fb), *v = w.get("sap_v", fb);
+  if (w.err) return w.err;
+  OpFields of = f->op_fields(op, P);
+  SapArgs<P> a;
+  a.g = g;
+  a.links = (const typename St<P>::pair_t *)of.links;
+  a.angles = (const typename St<P>::real_t *)of.angles;
+  a.qhat = of.qhat;
+  a.pauli = (const typename St<P>::pair_t *)of.pauli;
+  a.pinv = (const typename St<P>::pair_t *)of.pinv;
+  a.rho = spinor_view<P>(rho, g.V, 0);
+  a.r = spinor_view<P>(r, g.V, 0);
+  a.psi = spinor_view<P>(psi, g.V, 0);
+  a.v = spinor_view<P>(v, g.V, 0);
+  a.nmr = nmr;
+  for (int cy = 0; cy < ncy; cy++)
+    for (int c = 0; c < 2; c++) {
+      a.blocks = lists[c];
+      a.first = cy == 0;
+      a.skip_face = cy == 0 && c == 0;
+      CK(launch_sap_colour<P>(a, nper, st));
+    }
+  return QXD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// flexible GCR (inner solver, precision P) with SAP; solves D delta = b
+// approximately to |b - D delta| <= tol |b|.
+// ---------------------------------------------------------------------------
+template <int P>
+qxd_status fgcr(Field *f, const Operator &op, const qxd_solver &s, void *b, void *delta, double tol,
+                int *iters_out, double *res_out, hipStream_t st) {
+  const Geom &g = f->g;
+  const int nkv = s.nkv > 0 ? s.nkv : 16;
+  if (nkv > MAXV) {
+    set_error("nkv must be <= %d", MAXV);
+    return QXD_EINVAL;
+  }
+  Ws w{f, st};
+  size_t fb = spinor_bytes(P, g.V);
+  char *phv = (char *)w.get("fgcr_phi", fb * nkv);
+  char *chv = (char *)w.get("fgcr_chi", fb * nkv);
+  void *rho = w.get("fgcr_rho", fb);
+  double *partial = (double *)w.get("partial", blas_partial_doubles() * 8);
+  double *scal = (double *)w.get("fgcr_scal", (size_t)(2 * MAXV * MAXV + 3 * MAXV + 2 * MAXV + 16) * 8);
+  if (w.err) return w.err;
+  double *amat = scal;                    // a_lk at amat[2*(k*MAXV + l)]
+  double *rec = amat + 2 * MAXV * MAXV;   // per k: |chi_k|^2, (chi_k, rho)
+  double *coef = rec + 3 * MAXV;          // back-substitution coefficients
+  double *rn2 = coef + 2 * MAXV;
+  auto F = [&](void *p) { return SpinorArg{p, g.V, 0}; };
+  std::vector<SpinorArg> phi(nkv), chi(nkv);
+  for (int k = 0; k < nkv; k++) {
+    phi[k] = F(phv + k * fb);
+    chi[k] = F(chv + k * fb);
+  }
+  CK(blas_axpby<P, P>(F(rho), 0.0, F(b), 1.0, 0, g.V, partial, rn2, st));
+  double b2;
+  CS(fetch(&b2, rn2, 1, st));
+  const double bn = sqrt(b2);
+  CK(hipMemsetAsync(delta, 0, fb, st));
+  double r2 = b2;
+  int it = 0;
+  const int maxiter = s.maxiter > 0 ? s.maxiter : 1000;
+  const int ncy = s.ncy > 0 ? s.ncy : 5, nmr = s.nmr > 0 ? s.nmr : 4;
+  OpFields of = f->op_fields(op, P);
+  while (sqrt(r2) > tol * bn && it < maxiter) {
+    int kused = 0;
+    for (int k = 0; k < nkv && it < maxiter; k++) {
+      CS(sap_apply_t<P>(f, op, ncy, nmr, rho, phi[k].ptr, st));
+      CK(launch_dirac(P, DK_FULL, g, of, phi[k], phi[k], chi[k], -0.5, st));
+      double *ak = amat + 2 * k * MAXV;
+      if (k > 0) CK(blas_mdot<P>(chi.data(), k, chi[k], 0, g.V, partial, ak, rec, 3, st));
+      MaxpyHost m;
+      m.n = k;
+      m.src[0] = chi[k];
+      m.dst[0] = chi[k];
+      m.ys[0] = chi.data();
+      m.coef = ak;
+      m.w = F(rho);
+      CK(blas_maxpy<P>(m, 0, g.V, partial, rec + 3 * k, st));
+      CK(blas_update<P>(F(rho), chi[k], rec + 3 * k + 1, rec + 3 * k, 0, 0, g.V, partial, rn2, st));
+      CS(fetch(&r2, rn2, 1, st));
+      it++;
+      kused = k + 1;
+      if (!isfinite(r2)) {
+        set_error("FGCR residual is NaN/Inf");
+        return QXD_EFLOAT;
+      }
+      if (sqrt(r2) <= tol * bn) break;
+    }
+    // back-substitution: R beta = c with R_lk = a_lk (l < k), R_kk = 1,
+    // c_k = (chi_k, rho_k) / |chi_k|^2; then delta += sum beta_k phi_k
+    std::vector<double> hv(2 * MAXV * MAXV + 3 * MAXV);
+    CS(fetch(hv.data(), amat, (int)hv.size(), st));
+    std::vector<double> br(kused), bi(kused);
+    for (int k = kused - 1; k >= 0; k--) {
+      double n = hv[2 * MAXV * MAXV + 3 * k];
+      double cr = hv[2 * MAXV * MAXV + 3 * k + 1] / n, ci = hv[2 * MAXV * MAXV + 3 * k + 2] / n;
+      for (int j = k + 1; j < kused; j++) {
+        double ar = hv[2 * (j * MAXV + k)], ai = hv[2 * (j * MAXV + k) + 1];
+        cr -= ar * br[j] - ai * bi[j];
+        ci -= ar * bi[j] + ai * br[j];
+      }
+      br[k] = cr;
+      bi[k] = ci;
+    }
+    std::vector<double> hc(2 * kused);
+    for (int k = 0; k < kused; k++) {
+      hc[2 * k] = -br[k];
+      hc[2 * k + 1] = -bi[k];
+    }
+    CK(hipMemcpyAsync(coef, hc.data(), hc.size() * 8, hipMemcpyHostToDevice, st));
+    MaxpyHost m;
+    m.n = kused;
+    m.src[0] = F(delta);
+    m.dst[0] = F(delta);
+    m.ys[0] = phi.data();
+    m.coef = coef;
+    CK(blas_maxpy<P>(m, 0, g.V, partial, nullptr, st));
+    CK(hipStreamSynchronize(st));  // hc must stay alive until the copy is done
+    if (sqrt(r2) > tol * bn && it < maxiter) {
+      // restart from the true residual rho = b - D delta
+      CK(launch_dirac(P, DK_FULL, g, of, F(delta), F(delta), chi[0], -0.5, st));
+      CK(blas_axpby<P, P>(F(rho), 0.0, F(b), 1.0, 0, g.V, partial, nullptr, st));
+      CK(blas_axpby<P, P>(F(rho), 1.0, chi[0], -1.0, 0, g.V, partial, rn2, st));
+      CS(fetch(&r2, rn2, 1, st));
+    }
+  }
+  *iters_out = it;
+  *res_out = sqrt(r2) / bn;
+  return QXD_OK;
+}
+
+template <int P>
+qxd_status sap_gcr(Field *f, const Operator &op64, const qxd_quark &q, const qxd_solver &s, void *eta,
+                   void *psi, bool guess, qxd_solve_info *info, hipStream_t st) {
+  const Geom &g = f->g;
+  Operator *op;
+  CS(f->get_op(q, P, &op, st));
+  Ws w{f, st};
+  size_t fb64 = spinor_bytes(QXD_F64, g.V), fb = spinor_bytes(P, g.V);
+  void *r = w.get("dc_r", fb64), *tmp = w.get("dc_tmp", fb64);
+  void *bin = w.get("dc_b", fb), *delta = w.get("dc_delta", fb);
+  double *partial = (double *)w.get("partial", blas_partial_doubles() * 8);
+  double *misc = (double *)w.get("dc_misc", 64);
+  if (w.err) return w.err;
+  auto F64v = [&](void *p) { return SpinorArg{p, g.V, 0}; };
+  OpFields of64 = f->op_fields(op64, QXD_F64);
+  CK(blas_norm2<QXD_F64>(F64v(eta), 0, g.V, partial, misc, st));
+  double eta2;
+  CS(fetch(&eta2, misc, 1, st));
+  if (!isfinite(eta2)) {
+    set_error("source contains NaN/Inf");
+    return QXD_EFLOAT;
+  }
+  if (eta2 == 0.0) {
+    CK(hipMemsetAsync(psi, 0, fb64, st));
+    if (info) info->true_resid = 0.0;
+    return QXD_OK;
+  }
+  const double eta_n = sqrt(eta2);
+  double r2;
+  if (guess) {
+    CK(launch_dirac(QXD_F64, DK_FULL, g, of64, F64v(psi), F64v(psi), F64v(tmp), -0.5, st));
+    CK(blas_axpby<QXD_F64, QXD_F64>(F64v(r), 0.0, F64v(eta), 1.0, 0, g.V, partial, nullptr, st));
+    CK(blas_axpby<QXD_F64, QXD_F64>(F64v(r), 1.0, F64v(tmp), -1.0, 0, g.V, partial, misc, st));
+  } else {
+    CK(hipMemsetAsync(psi, 0, fb64, st));
+    CK(blas_axpby<QXD_F64, QXD_F64>(F64v(r), 0.0, F64v(eta), 1.0, 0, g.V, partial, misc, st));
+  }
+  CS(fetch(&r2, misc, 1, st));
+  int outer = 0, inner = 0;
+  const int max_outer = s.max_outer > 0 ? s.max_outer : 50;
+  double inner_tol = s.inner_tol > 0 ? s.inner_tol : (P == QXD_F64 ? 1e-6 : (P == QXD_F32 ? 1e-5 : 1e-2));
+  while (sqrt(r2) > s.tol * eta_n && outer < max_outer) {
+    double sn = sqrt(r2);
+    // b = r / |r| in the inner precision
+    CK(blas_axpby<P, QXD_F64>(SpinorArg{bin, g.V, 0}, 0.0, F64v(r), 1.0 / sn, 0, g.V, partial, nullptr, st));
+    int it;
+    double res;
+    CS(fgcr<P>(f, *op, s, bin, delta, inner_tol, &it, &res, st));
+    inner += it;
+    // x += |r| delta; r = eta - D x (FP64)
+    CK(blas_axpby<QXD_F64, P>(F64v(psi), 1.0, SpinorArg{delta, g.V, 0}, sn, 0, g.V, partial, nullptr, st));
+    CK(launch_dirac(QXD_F64, DK_FULL, g, of64, F64v(psi), F64v(psi), F64v(tmp), -0.5, st));
+    CK(blas_axpby<QXD_F64, QXD_F64>(F64v(r), 0.0, F64v(eta), 1.0, 0, g.V, partial, nullptr, st));
+    CK(blas_axpby<QXD_F64, QXD_F64>(F64v(r), 1.0, F64v(tmp), -1.0, 0, g.V, partial, misc, st));
+    CS(fetch(&r2, misc, 1, st));
+    outer++;
+    if (!isfinite(r2)) {
+      set_error("defect-correction residual is NaN/Inf");
+      return QXD_EFLOAT;
+    }
+    if ((s.maxiter > 0 && inner >= s.maxiter)) break;
+  }
+  double true_res = sqrt(r2) / eta_n;
+  if (info) {
+    info->outer_iters = outer;
+    info->inner_iters = inner;
+    info->true_resid = true_res;
+  }
+  return true_res <= s.tol ? QXD_OK : QXD_ENOCONV;
+}
+
+}  // namespace
+
+qxd_status check_sap_blocks(const Field *f) {
+  const Geom &g = f->g;
+  for (int m = 0; m < 4; m++)
+    if (g.nb[m] < 2 || g.nb[m] % 2) {
+      set_error("SAP needs an even number (>= 2) of blocks in every direction (direction %d has %d)", m, g.nb[m]);
+      return QXD_EINVAL;
+    }
+  if (g.shift_mask && (g.L1b % 2)) {
+    set_error("with shifted C* boundaries SAP needs L1 / b1 even for a two-colour block decomposition");
+    return QXD_EINVAL;
+  }
+  return QXD_OK;
+}
+
+qxd_status sap_apply(Field *f, const Operator &op, int prec, int ncy, int nmr, void *rho, void *psi,
+                     hipStream_t st) {
+  switch (prec) {
+    case QXD_F64: return sap_apply_t<QXD_F64>(f, op, ncy, nmr, rho, psi, st);
+    case QXD_F32: return sap_apply_t<QXD_F32>(f, op, ncy, nmr, rho, psi, st);
+    case QXD_F16S: return sap_apply_t<QXD_F16S>(f, op, ncy, nmr, rho, psi, st);
+    case QXD_BF16: return sap_apply_t<QXD_BF16>(f, op, ncy, nmr, rho, psi, st);
+  }
+  set_error("invalid precision");
+  return QXD_EINVAL;
+}
+
+qxd_status solve(Field *f, const qxd_quark *quarks, int nquark, const qxd_solver &s, const double *eta_dev,
+                 double *psi_dev, int nrhs, int use_guess, qxd_solve_info *info, hipStream_t st) {
+  if (!(s.tol > 0.0) || s.tol >= 1.0 || (s.kind != QXD_SOLVER_EO_GCR && s.kind != QXD_SOLVER_SAP_GCR) ||
+      s.inner_prec < QXD_F64 || s.inner_prec > QXD_BF16 || s.nkv < 0 || s.nkv > MAXV || s.ncy < 0 ||
+      s.nmr < 0 || s.maxiter < 0 || s.max_outer < 0 || !(s.inner_tol >= 0.0 && s.inner_tol < 1.0)) {
+    set_error("invalid solver parameters");
+    return QXD_EINVAL;
+  }
+  if (s.kind == QXD_SOLVER_SAP_GCR) CS(check_sap_blocks(f));
+  const Geom &g = f->g;
+  Ws w{f, st};
+  size_t fb = spinor_bytes(QXD_F64, g.V);
+  void *eta = w.get("solve_eta", fb), *psi = w.get("solve_psi", fb);
+  if (w.err) return w.err;
+  qxd_status worst = QXD_OK;
+  int per = nrhs / nquark;
+  for (int r = 0; r < nrhs; r++) {
+    double t0 = now_s();
+    const qxd_quark &q = quarks[r / per];
+    Operator *op;
+    CS(f->get_op(q, QXD_F64, &op, st));
+    const double *src = eta_dev + (int64_t)r * 24 * g.V;
+    double *dst = psi_dev + (int64_t)r * 24 * g.V;
+    CK(launch_pack(QXD_F64, g, src, eta, 1, st));
+    if (use_guess) CK(launch_pack(QXD_F64, g, dst, psi, 1, st));
+    qxd_solve_info inf{};
+    qxd_status rs;
+    if (s.kind == QXD_SOLVER_EO_GCR) {
+      rs = eo_gcr(f, *op, s, eta, psi, use_guess, &inf, st);
+    } else {
+      switch (s.inner_prec) {
+        case QXD_F64: rs = sap_gcr<QXD_F64>(f, *op, q, s, eta, psi, use_guess, &inf, st); break;
+        case QXD_F32: rs = sap_gcr<QXD_F32>(f, *op, q, s, eta, psi, use_guess, &inf, st); break;
+        case QXD_F16S: rs = sap_gcr<QXD_F16S>(f, *op, q, s, eta, psi, use_guess, &inf, st); break;
+        default: rs = sap_gcr<QXD_BF16>(f, *op, q, s, eta, psi, use_guess, &inf, st); break;
+      }
+    }
+    if (rs != QXD_OK && rs != QXD_ENOCONV) return rs;
+    CK(launch_unpack(QXD_F64, g, psi, dst, 1, st));
+    CK(hipStreamSynchronize(st));
+    inf.status = rs;
+    inf.seconds = now_s() - t0;
+    if (info) info[r] = inf;
+    if (rs != QXD_OK) worst = rs;
+  }
+  return worst;
+}
+
+}  // namespace qxd

@@ -1,0 +1,212 @@
+"""Python binding of libqxd (ctypes).  Argument marshalling only: every step
+of the computation runs in the HIP library.  Device buffers are torch tensors
+on the GPU (PyTorch is used for device memory and streams); host inputs are
+numpy arrays.  Raises QxdError with the library's message on failure; raises
+ImportError if the library has not been built.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libqxd.so")
+
+F64, F32, F16S, BF16 = 0, 1, 2, 3
+PREC = {"f64": F64, "f32": F32, "f16": F16S, "f16s": F16S, "bf16": BF16}
+OP_D, OP_DHAT, OP_HOP, OP_PAULI, OP_OOINV = 0, 1, 2, 3, 4
+NATIVE = 1
+EO_GCR, SAP_GCR = 0, 1
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ENOCONV", -4: "EFLOAT", -5: "EDEVICE",
+          -6: "EBUSY", -7: "ENOTFOUND"}
+
+
+class QxdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Lattice(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int * 4), ("time_bc", ctypes.c_int), ("cstar", ctypes.c_int),
+                ("q_el", ctypes.c_double), ("block", ctypes.c_int * 4)]
+
+
+class Quark(ctypes.Structure):
+    _fields_ = [("kappa", ctypes.c_double), ("q", ctypes.c_double), ("csw", ctypes.c_double),
+                ("csw_u1", ctypes.c_double)]
+
+
+class Solver(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("tol", ctypes.c_double), ("maxiter", ctypes.c_int),
+                ("nkv", ctypes.c_int), ("ncy", ctypes.c_int), ("nmr", ctypes.c_int),
+                ("inner_prec", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                ("max_outer", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("outer_iters", ctypes.c_int), ("inner_iters", ctypes.c_int),
+                ("true_resid", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("field", ctypes.c_void_p), ("quark", Quark), ("solver", Solver),
+                ("eta_dev", ctypes.c_void_p), ("psi_dev", ctypes.c_void_p), ("nrhs", ctypes.c_int)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("nrhs", ctypes.c_int), ("latency_s", ctypes.c_double),
+                ("queue_s", ctypes.c_double), ("inner_iters", ctypes.c_int),
+                ("true_resid", ctypes.c_double)]
+
+
+# exported symbols and their signatures (also checked by the CPU test-suite)
+_VP, _I, _D, _SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+SIGNATURES = {
+    "qxd_abi_version": ([], _I),
+    "qxd_last_error": ([], ctypes.c_char_p),
+    "qxd_init": ([_I, ctypes.POINTER(_VP)], _I),
+    "qxd_finalize": ([_VP], _I),
+    "qxd_field_upload": ([_VP, ctypes.POINTER(Lattice), _VP, _VP, ctypes.POINTER(_VP)], _I),
+    "qxd_field_release": ([_VP], _I),
+    "qxd_field_volume": ([_VP, ctypes.POINTER(ctypes.c_int64)], _I),
+    "qxd_spinor_bytes": ([_VP, _I, ctypes.POINTER(_SZ)], _I),
+    "qxd_spinor_pack": ([_VP, _I, _VP, _VP, _I, _VP], _I),
+    "qxd_spinor_unpack": ([_VP, _I, _VP, _VP, _I, _VP], _I),
+    "qxd_dirac_apply": ([_VP, ctypes.POINTER(Quark), _I, _I, _I, _VP, _VP, _I, ctypes.c_uint, _VP], _I),
+    "qxd_solve": ([_VP, ctypes.POINTER(Quark), _I, ctypes.POINTER(Solver), _VP, _VP, _I, _I,
+                   ctypes.POINTER(SolveInfo), _VP], _I),
+    "qxd_sap_apply": ([_VP, ctypes.POINTER(Quark), _I, _I, _I, _VP, _VP, _I, _VP], _I),
+    "qxd_serve_start": ([_VP, _SZ, _I], _I),
+    "qxd_serve_submit": ([_VP, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], _I),
+    "qxd_serve_poll": ([_VP, ctypes.c_uint64, ctypes.POINTER(Result)], _I),
+    "qxd_serve_stop": ([_VP], _I),
+}
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"libqxd.so not built ({_LIB_PATH}); run python -m paper_1710_08839_amd.build")
+        _lib = ctypes.CDLL(_LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(_lib, name)
+            fn.argtypes = args
+            fn.restype = res
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise QxdError(status, lib().qxd_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def _ptr(t):
+    return t.data_ptr() if hasattr(t, "data_ptr") else int(t)
+
+
+def quark(kappa, q=0.0, csw=0.0, csw_u1=1.0):
+    return Quark(kappa, q, csw, csw_u1)
+
+
+def solver(kind=SAP_GCR, tol=1e-10, maxiter=0, nkv=16, ncy=5, nmr=4, inner_prec=F32, inner_tol=0.0,
+           max_outer=0):
+    return Solver(kind, tol, maxiter, nkv, ncy, nmr, inner_prec, inner_tol, max_outer)
+
+
+class Context:
+    def __init__(self, device=0):
+        self.h = ctypes.c_void_p()
+        _check(lib().qxd_init(device, ctypes.byref(self.h)))
+
+    def close(self):
+        if self.h:
+            _check(lib().qxd_finalize(self.h))
+            self.h = ctypes.c_void_p()
+
+    # serving
+    def serve_start(self, budget_bytes=0, max_active=0):
+        _check(lib().qxd_serve_start(self.h, budget_bytes, max_active))
+
+    def serve_submit(self, field, q, s, eta, psi, nrhs):
+        req = Request(field.h, q, s, _ptr(eta), _ptr(psi), nrhs)
+        t = ctypes.c_uint64()
+        _check(lib().qxd_serve_submit(self.h, ctypes.byref(req), ctypes.byref(t)))
+        return t.value
+
+    def serve_poll(self, ticket):
+        """None while pending, else the Result."""
+        r = Result()
+        st = lib().qxd_serve_poll(self.h, ticket, ctypes.byref(r))
+        if st == -6:
+            return None
+        _check(st)
+        return r
+
+    def serve_stop(self):
+        _check(lib().qxd_serve_stop(self.h))
+
+
+class Field:
+    """A resident gauge field (physical-lattice U and optional A, host numpy)."""
+
+    def __init__(self, ctx, dims, u, a=None, cstar=0, time_bc=0, q_el=1.0 / 6.0, block=(4, 4, 4, 4)):
+        self.ctx = ctx
+        self.lat = Lattice((ctypes.c_int * 4)(*dims), time_bc, cstar, q_el, (ctypes.c_int * 4)(*block))
+        u = np.ascontiguousarray(u, dtype=np.complex128)
+        self._u = u
+        a_ptr = None
+        if a is not None:
+            a = np.ascontiguousarray(a, dtype=np.float64)
+            a_ptr = a.ctypes.data
+        self.h = ctypes.c_void_p()
+        _check(lib().qxd_field_upload(ctx.h, ctypes.byref(self.lat), u.ctypes.data, a_ptr, ctypes.byref(self.h)))
+        v = ctypes.c_int64()
+        _check(lib().qxd_field_volume(self.h, ctypes.byref(v)))
+        self.volume = v.value
+
+    def release(self):
+        if self.h:
+            _check(lib().qxd_field_release(self.h))
+            self.h = ctypes.c_void_p()
+
+    def spinor_bytes(self, prec):
+        n = ctypes.c_size_t()
+        _check(lib().qxd_spinor_bytes(self.h, prec, ctypes.byref(n)))
+        return n.value
+
+    def pack(self, prec, api, native, nrhs=1, stream=None):
+        _check(lib().qxd_spinor_pack(self.h, prec, _ptr(api), _ptr(native), nrhs, _stream(stream)))
+
+    def unpack(self, prec, native, api, nrhs=1, stream=None):
+        _check(lib().qxd_spinor_unpack(self.h, prec, _ptr(native), _ptr(api), nrhs, _stream(stream)))
+
+    def apply(self, quarks, op, prec, x, y, nrhs=1, native=False, stream=None):
+        qs = quarks if isinstance(quarks, (list, tuple)) else [quarks]
+        arr = (Quark * len(qs))(*qs)
+        _check(lib().qxd_dirac_apply(self.h, arr, len(qs), op, prec, _ptr(x), _ptr(y), nrhs,
+                                     NATIVE if native else 0, _stream(stream)))
+
+    def solve(self, quarks, s, eta, psi, nrhs=1, use_guess=False, stream=None, check=True):
+        qs = quarks if isinstance(quarks, (list, tuple)) else [quarks]
+        arr = (Quark * len(qs))(*qs)
+        info = (SolveInfo * nrhs)()
+        st = lib().qxd_solve(self.h, arr, len(qs), ctypes.byref(s), _ptr(eta), _ptr(psi), nrhs,
+                             int(use_guess), info, _stream(stream))
+        if check and st not in (0,):
+            _check(st)
+        return st, list(info)
+
+    def sap_apply(self, q, prec, ncy, nmr, x, y, nrhs=1, stream=None):
+        _check(lib().qxd_sap_apply(self.h, ctypes.byref(q), prec, ncy, nmr, _ptr(x), _ptr(y), nrhs,
+                                   _stream(stream)))

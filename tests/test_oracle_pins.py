@@ -501,3 +501,14 @@ def test_defect_correction_reaches_tolerance():
     x, outer = osv.defect_correction(op.apply, inner, eta, 1e-10)
     assert od.norm(eta - op.apply(x)) <= 1e-10 * od.norm(eta)
     assert outer >= 2
+
+
+def test_apply_at_sites_matches_full_operator():
+    """The per-site evaluation used for huge lattices equals the full D."""
+    lat = Lattice((4, 4, 4, 4), cstar=3, time_bc=0)
+    ue, ae = random_field(lat, 91)
+    op = od.build_operator(lat, ue, ae, 0.13, q=-1 / 3, csw=1.9, csw_u1=1.2)
+    psi = rand_spinor(lat, 4)
+    sites = np.array([0, 5, 77, 300, lat.V - 1])
+    got = od.apply_at_sites(lat, ue, ae, psi, sites, 0.13, q=-1 / 3, csw=1.9, csw_u1=1.2)
+    assert rel(got, op.apply(psi)[sites]) < 1e-14
