@@ -91,6 +91,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             raise ImportError(f"libqxd.so not built ({_LIB_PATH}); run python -m paper_1710_08839_amd.build")
+        # PyTorch carries its own HIP runtime (same soname as the system one).
+        # Load it first so that libqxd binds to the same runtime instance and
+        # both share one device context, allocator view and stream namespace.
+        import torch  # noqa: F401
         _lib = ctypes.CDLL(_LIB_PATH)
         for name, (args, res) in SIGNATURES.items():
             fn = getattr(_lib, name)
@@ -164,7 +168,6 @@ class Field:
         self.ctx = ctx
         self.lat = Lattice((ctypes.c_int * 4)(*dims), time_bc, cstar, q_el, (ctypes.c_int * 4)(*block))
         u = np.ascontiguousarray(u, dtype=np.complex128)
-        self._u = u
         a_ptr = None
         if a is not None:
             a = np.ascontiguousarray(a, dtype=np.float64)
