@@ -1,0 +1,228 @@
+"""Benchmark of the Wilson-clover / C* / SAP-GCR hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solve] [--no-cpu]
+
+Prints one JSON line.  `value` is the achieved bandwidth of the Dirac
+operator D = hop + Pauli in FP64 on the 64 x 32^3 lattice with C* boundaries
+in x, y, z (4,194,304 extended sites): algorithmic bytes of one application
+(each field read once: in and out spinors, the hopping links W = U z^qhat and
+the Pauli term) divided by the average time of one application, measured with
+HIP events over K back-to-back applications on the launch stream.  A "step"
+is one such application; inputs are resident in HBM.  The other precisions,
+the mixed-precision versus FP64 solve rates and the oracle timed on the host
+cores are reported alongside.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Dw GB/s (% HBM peak); mixed-prec batched solves/sec & p99 vs FP64 @1e-10"
+HBM_PEAK_GBS = 8000.0
+
+# algorithmic bytes per extended site of one D application with the phase
+# folded into the links: spinor in + out (24 reals each), W links (4 x 18
+# reals), Pauli term (2 x 36 reals); FP16S adds one fp32 scale per spinor site.
+BYTES_PER_SITE = {0: 48 * 8 + 72 * 8 + 72 * 8, 1: 48 * 4 + 72 * 4 + 72 * 4,
+                  2: 48 * 2 + 8 + 72 * 2 + 72 * 2, 3: 48 * 2 + 72 * 2 + 72 * 2}
+FLOPS_PER_SITE = 1320 + 552 + 48   # hops + two 6x6 Hermitian blocks + combine
+PREC_NAME = {0: "f64", 1: "f32", 2: "f16s", 3: "bf16"}
+_T0 = time.perf_counter()
+
+
+def log(msg):
+    print(f"[bench {time.perf_counter() - _T0:7.1f}s] {msg}", file=sys.stderr, flush=True)
+
+
+def time_applies(field, q, prec, nrhs_bufs, steps, warmup):
+    import torch
+    from paper_1710_08839_amd import qxd
+    nb = field.spinor_bytes(prec)
+    bufs = [torch.empty(nb // 4, dtype=torch.float32, device="cuda") for _ in range(2 * nrhs_bufs)]
+    src = torch.empty(field.volume * 24, dtype=torch.float64, device="cuda").normal_()
+    for k in range(nrhs_bufs):
+        field.pack(prec, src, bufs[2 * k])
+    stream = torch.cuda.current_stream()
+    for i in range(warmup):
+        k = i % nrhs_bufs
+        field.apply(q, qxd.OP_D, prec, bufs[2 * k], bufs[2 * k + 1], native=True, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(steps):
+        k = i % nrhs_bufs
+        field.apply(q, qxd.OP_D, prec, bufs[2 * k], bufs[2 * k + 1], native=True, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    return ms
+
+
+def cpu_baseline(budget_s=15.0):
+    """The FP64 oracle's D on a bounded sample: 16 x 8^3 with C* (16,384
+    extended sites), repeated for about budget_s seconds."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import Lattice
+    from oracle import dirac as od
+    from oracle import fields as of
+    from paper_1710_08839_amd import synth
+    dims = (16, 8, 8, 8)
+    lat = Lattice(dims, cstar=3)
+    u, a = synth.gauge_field(dims, 20171002, 0.25, 0.15)
+    ue, ae = of.extend_gauge(lat, u, a)
+    op = od.build_operator(lat, ue, ae, 0.1365, q=-1 / 3, csw=1.9)
+    x = synth.source(dims, 3, 1003)
+    with threadpool_limits(limits=1):
+        op.apply(x)
+        n = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s:
+            op.apply(x)
+            n += 1
+        dt = time.perf_counter() - t0
+    gbs = BYTES_PER_SITE[0] * lat.V * n / dt / 1e9
+    return {"value": round(gbs, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 oracle D on 16x8^3 C* (16384 extended sites), {n} applications in "
+                      f"{dt:.1f} s ({dt / n * 1e3:.1f} ms each, {lat.V * n / dt / 1e6:.3f} Msite/s)"}
+
+
+def solve_rates(ctx, nsrc, dims=(48, 24, 24, 24)):
+    """cfg-3 lattice: point sources x 2 charges x 2 kappas, solved to 1e-10 by
+    the plain FP64 even-odd GCR and by the mixed-precision SAP-GCR."""
+    import torch
+    from paper_1710_08839_amd import qxd, synth
+    u, a = synth.gauge_field(dims, 20171003, 0.25, 0.15)
+    f = qxd.Field(ctx, dims, u, a, cstar=3)
+    del u, a
+    ops = [qxd.quark(k, q, 1.9, 1.0) for q in (2 / 3, -1 / 3) for k in (0.1360, 0.1365)]
+    V = f.volume
+    srcs = []
+    for s in range(nsrc):
+        srcs.append(synth.point_source(V, 0, s // 3 % 4, s % 3))
+    eta = torch.from_numpy(np.stack(srcs * len(ops))).cuda()
+    nrhs = eta.shape[0]
+    psi = torch.empty_like(eta)
+    out = {}
+    for name, s in [("fp64_eo_gcr", qxd.solver(kind=qxd.EO_GCR, tol=1e-10, nkv=16)),
+                    ("mixed_sap_gcr_f32", qxd.solver(kind=qxd.SAP_GCR, tol=1e-10, nkv=12, ncy=4, nmr=4,
+                                                     inner_prec=qxd.F32)),
+                    ("mixed_sap_gcr_f16s", qxd.solver(kind=qxd.SAP_GCR, tol=1e-10, nkv=12, ncy=4, nmr=4,
+                                                      inner_prec=qxd.F16S))]:
+        # warm-up: builds operators and workspaces
+        f.solve(ops[0], s, eta[:1], psi[:1])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, info = f.solve(ops, s, eta, psi, nrhs=nrhs, check=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        log(f"solve {name}: {nrhs} rhs in {dt:.2f} s, status {st}")
+        out[name] = {"solves_per_s": round(nrhs / dt, 3), "seconds": round(dt, 3), "nrhs": nrhs,
+                     "status": st, "max_true_resid": max(i.true_resid for i in info),
+                     "iters": [i.inner_iters for i in info][:len(ops) * nsrc:nsrc],
+                     "outer": [i.outer_iters for i in info][:len(ops) * nsrc:nsrc]}
+    f.release()
+    base = out["fp64_eo_gcr"]["solves_per_s"]
+    for k in out:
+        out[k]["speedup_vs_fp64"] = round(out[k]["solves_per_s"] / base, 3)
+    out["workload"] = f"{dims[0]}x{dims[1]}^3 C*, {nsrc} point sources x 4 operators (q, kappa)"
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--nsrc", type=int, default=3, help="point sources per operator in the solve leg")
+    ap.add_argument("--precs", default="0,1,2,3")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not part "
+              f"of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1710_08839_amd import qxd, synth
+
+    dims = (64, 32, 32, 32)
+    ctx = qxd.Context(0)
+    t0 = time.perf_counter()
+    log("generating the 64x32^3 gauge field")
+    u, a = synth.gauge_field(dims, 20171002, 0.25, 0.15)
+    field = qxd.Field(ctx, dims, u, a, cstar=3)
+    log("field uploaded")
+    del u, a
+    q = qxd.quark(0.1365, -1 / 3, 1.9, 1.0)
+    V = field.volume
+    setup_s = time.perf_counter() - t0
+
+    precs = [int(p) for p in args.precs.split(",")]
+    dw = {}
+    for p in precs:
+        # builds the operator in this precision before timing
+        ms = time_applies(field, q, p, 3, 2, 1)
+        ms = time_applies(field, q, p, 3, args.steps if p == 0 else max(10, args.steps // 2),
+                          args.warmup)
+        gbs = BYTES_PER_SITE[p] * V / (ms * 1e-3) / 1e9
+        log(f"D {PREC_NAME[p]}: {ms:.4f} ms per application")
+        dw[PREC_NAME[p]] = {"ms": round(ms, 4), "GB/s": round(gbs, 1),
+                            "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                            "GFLOP/s": round(FLOPS_PER_SITE * V / (ms * 1e-3) / 1e9, 1),
+                            "bytes_per_site": BYTES_PER_SITE[p]}
+
+    # the timed leg of the contract: K FP64 applications between barriers
+    torch.cuda.synchronize()
+    ms = time_applies(field, q, 0, 3, args.steps, args.warmup)
+    value = BYTES_PER_SITE[0] * V / (ms * 1e-3) / 1e9
+    field.release()
+
+    solves = None
+    if not args.no_solve:
+        solves = solve_rates(ctx, args.nsrc)
+
+    log("timing the oracle on the host")
+    cpu = None if args.no_cpu else cpu_baseline()
+    ctx.close()
+
+    rec = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "Wilson-clover D (hop + Pauli), SU(3)xU(1), C* in x,y,z, "
+                               "64x32^3 physical = 64x64x32x32 extended (4194304 sites), "
+                               "q=-1/3, kappa=0.1365, csw=1.9, eps=0.25, A~N(0,0.15)",
+                   "global_batch": 1, "seq_len": V, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(value, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(value / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "dirac_kernel<F64, DK_FULL>",
+                     "bytes_per_launch": BYTES_PER_SITE[0] * V},
+        "dw": dw,
+        "solves": solves,
+        "cpu_baseline": cpu,
+        "setup_s": round(setup_s, 1),
+    }
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

@@ -78,6 +78,12 @@ static qxd_status make_geom(const qxd_lattice *lat, Geom *g) {
   g->Vbh = g->Vb / 2;
   g->hb3 = g->b[3] / 2;
   g->nblocks = g->nb[0] * g->nb[1] * g->nb[2] * g->nb[3];
+  for (int m = 0; m < 4; m++)
+    if (g->b[m] > 255 || g->nb[m] > 255) {
+      set_error("at most 255 blocks and block sites per direction");
+      return QXD_EINVAL;
+    }
+  finish_geom(*g);
   return QXD_OK;
 }
 

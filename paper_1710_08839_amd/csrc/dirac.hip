@@ -5,6 +5,10 @@
 // so that D^ psi_e = P_e psi_e + acc(t_o)/2 with t_o = -D_oo^-1 acc(psi_e)/2.
 // One thread per site; every operand is a structure-of-arrays field in native
 // order, so the 64 lanes of a wavefront read consecutive sites.
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "dirac_site.h"
 #include "launch.h"
 
@@ -12,7 +16,7 @@ namespace qxd {
 
 namespace {
 
-template <int P, int KIND>
+template <int P, int KIND, int GROUP>
 __global__ void __launch_bounds__(256) dirac_kernel(Geom g, const typename St<P>::pair_t *links,
                                                     const typename St<P>::real_t *angles, int qhat,
                                                     const typename St<P>::pair_t *pauli,
@@ -28,7 +32,7 @@ __global__ void __launch_bounds__(256) dirac_kernel(Geom g, const typename St<P>
   cx<T> res[4][3];
   if (KIND != DK_PAULI) {
     Site s = decode(g, i);
-    hop_sum<P, T>(g, links, angles, qhat, in, s, i, res);
+    hop_sum<P, T, GROUP>(g, links, angles, qhat, in, s, i, res);
 #pragma unroll
     for (int a = 0; a < 4; a++)
 #pragma unroll
@@ -66,9 +70,30 @@ __global__ void __launch_bounds__(256) dirac_kernel(Geom g, const typename St<P>
   }
 }
 
+template <int P, int KIND, int G>
+void launch_k(unsigned gr, hipStream_t st, const Geom &g, const typename St<P>::pair_t *links,
+              const typename St<P>::real_t *angles, int qhat, const typename St<P>::pair_t *pauli,
+              const typename St<P>::pair_t *pinv, Spinor<P> vin, Spinor<P> vself, Spinor<P> vout,
+              typename St<P>::comp_t c) {
+  dirac_kernel<P, KIND, G><<<gr, 256, 0, st>>>(g, links, angles, qhat, pauli, pinv, vin, vself, vout, c);
+}
+
+template <int P, int KIND>
+void launch_g(int group, unsigned gr, hipStream_t st, const Geom &g, const typename St<P>::pair_t *links,
+              const typename St<P>::real_t *angles, int qhat, const typename St<P>::pair_t *pauli,
+              const typename St<P>::pair_t *pinv, Spinor<P> vin, Spinor<P> vself, Spinor<P> vout,
+              typename St<P>::comp_t c) {
+  switch (group) {
+    case 1: launch_k<P, KIND, 1>(gr, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
+    case 4: launch_k<P, KIND, 4>(gr, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
+    case 8: launch_k<P, KIND, 8>(gr, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
+    default: launch_k<P, KIND, 2>(gr, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
+  }
+}
+
 template <int P>
-hipError_t launch_p(DiracKind kind, const Geom &g, const OpFields &f, SpinorArg in, SpinorArg self,
-                    SpinorArg out, double c, hipStream_t st) {
+hipError_t launch_p(DiracKind kind, int group, const Geom &g, const OpFields &f, SpinorArg in,
+                    SpinorArg self, SpinorArg out, double c, hipStream_t st) {
   using pt = typename St<P>::pair_t;
   using rt = typename St<P>::real_t;
   using T = typename St<P>::comp_t;
@@ -83,27 +108,90 @@ hipError_t launch_p(DiracKind kind, const Geom &g, const OpFields &f, SpinorArg 
   unsigned gr = grid_for(n, 256);
   T cc = (T)c;
   switch (kind) {
-    case DK_FULL: dirac_kernel<P, DK_FULL><<<gr, 256, 0, st>>>(g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
-    case DK_HOP: dirac_kernel<P, DK_HOP><<<gr, 256, 0, st>>>(g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
-    case DK_PAULI: dirac_kernel<P, DK_PAULI><<<gr, 256, 0, st>>>(g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
-    case DK_ODD: dirac_kernel<P, DK_ODD><<<gr, 256, 0, st>>>(g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
-    case DK_EVEN: dirac_kernel<P, DK_EVEN><<<gr, 256, 0, st>>>(g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
-    case DK_EVEN_ID: dirac_kernel<P, DK_EVEN_ID><<<gr, 256, 0, st>>>(g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
+    case DK_FULL: launch_g<P, DK_FULL>(group, gr, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
+    case DK_HOP: launch_g<P, DK_HOP>(group, gr, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
+    case DK_PAULI: launch_g<P, DK_PAULI>(1, gr, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
+    case DK_ODD: launch_g<P, DK_ODD>(group, gr, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
+    case DK_EVEN: launch_g<P, DK_EVEN>(group, gr, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
+    case DK_EVEN_ID: launch_g<P, DK_EVEN_ID>(group, gr, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_any(int prec, DiracKind kind, int group, const Geom &g, const OpFields &f, SpinorArg in,
+                      SpinorArg self, SpinorArg out, double c, hipStream_t st) {
+  switch (prec) {
+    case QXD_F64: return launch_p<QXD_F64>(kind, group, g, f, in, self, out, c, st);
+    case QXD_F32: return launch_p<QXD_F32>(kind, group, g, f, in, self, out, c, st);
+    case QXD_F16S: return launch_p<QXD_F16S>(kind, group, g, f, in, self, out, c, st);
+    case QXD_BF16: return launch_p<QXD_BF16>(kind, group, g, f, in, self, out, c, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Autotuned choice of the hop group size, per (precision, kernel kind,
+// volume, U(1) phase on the fly): the first call times every candidate on the
+// caller's own operands (all candidates compute the same result) and keeps
+// the fastest.
+struct TuneKey {
+  int prec, kind, V, phase;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(prec, kind, V, phase) < std::tie(o.prec, o.kind, o.V, o.phase);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tuned;
+
+int tune_group(int prec, DiracKind kind, const Geom &g, const OpFields &f, SpinorArg in, SpinorArg self,
+               SpinorArg out, double c, hipStream_t st) {
+  TuneKey key{prec, (int)kind, g.V, f.qhat != 0};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) return it->second;
+  }
+  static const int cand[] = {1, 2, 4, 8};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return 2;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return 2;
+  }
+  int best = 2;
+  float best_ms = 1e30f;
+  for (int gsz : cand) {
+    (void)launch_any(prec, kind, gsz, g, f, in, self, out, c, st);  // warm-up
+    (void)hipEventRecord(e0, st);
+    for (int r = 0; r < 3; r++) (void)launch_any(prec, kind, gsz, g, f, in, self, out, c, st);
+    (void)hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) break;
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = gsz;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[key] = best;
+  return best;
 }
 
 }  // namespace
 
 hipError_t launch_dirac(int prec, DiracKind kind, const Geom &g, const OpFields &f, SpinorArg in,
                         SpinorArg self, SpinorArg out, double c, hipStream_t st) {
-  switch (prec) {
-    case QXD_F64: return launch_p<QXD_F64>(kind, g, f, in, self, out, c, st);
-    case QXD_F32: return launch_p<QXD_F32>(kind, g, f, in, self, out, c, st);
-    case QXD_F16S: return launch_p<QXD_F16S>(kind, g, f, in, self, out, c, st);
-    case QXD_BF16: return launch_p<QXD_BF16>(kind, g, f, in, self, out, c, st);
-  }
-  return hipErrorInvalidValue;
+  if (prec < QXD_F64 || prec > QXD_BF16) return hipErrorInvalidValue;
+  int group = kind == DK_PAULI ? 1 : tune_group(prec, kind, g, f, in, self, out, c, st);
+  return launch_any(prec, kind, group, g, f, in, self, out, c, st);
+}
+
+int tuned_group(int prec, int kind, int V, int phase) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(TuneKey{prec, kind, V, phase});
+  return it == g_tuned.end() ? 0 : it->second;
 }
 
 }  // namespace qxd

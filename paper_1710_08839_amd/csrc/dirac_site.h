@@ -24,7 +24,7 @@ QXD_HD void load_link(const typename St<P>::pair_t *links, int64_t V, int mu, in
   for (int r = 0; r < 3; r++)
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-      auto z = St<P>::ld(links, (int64_t)(mu * 9 + r * 3 + c) * V + i);
+      auto z = St<P>::ld(links + (int64_t)(mu * 9 + r * 3 + c) * V, (uint32_t)i);
       u[r][c] = {(T)z.re, (T)z.im};
     }
 }
@@ -39,7 +39,7 @@ QXD_HD void load_w(const typename St<P>::pair_t *links, const typename St<P>::re
                    int qhat, int64_t V, int mu, int64_t i, cx<T> w[3][3]) {
   load_link<P, T>(links, V, mu, i, w);
   if (qhat != 0) {
-    T a = (T)St<P>::ldr(angles, (int64_t)mu * V + i);
+    T a = (T)St<P>::ldr(angles + (int64_t)mu * V, (uint32_t)i);
     T sn, cs;
     sincos_t<T>((T)qhat * a, &sn, &cs);
     cx<T> z{cs, sn};
@@ -139,7 +139,7 @@ QXD_HD void herm6_mul(const typename St<P>::pair_t *pa, int64_t stride, int64_t 
   T d[6];
 #pragma unroll
   for (int k = 0; k < 3; k++) {
-    auto z = St<P>::ld(pa, (int64_t)(base + k) * stride + j);
+    auto z = St<P>::ld(pa + (int64_t)(base + k) * stride, (uint32_t)j);
     d[2 * k] = (T)z.re;
     d[2 * k + 1] = (T)z.im;
   }
@@ -149,7 +149,7 @@ QXD_HD void herm6_mul(const typename St<P>::pair_t *pa, int64_t stride, int64_t 
   for (int i = 0; i < 6; i++)
 #pragma unroll
     for (int k = i + 1; k < 6; k++) {
-      auto z = St<P>::ld(pa, (int64_t)(base + 3 + tri_index(i, k)) * stride + j);
+      auto z = St<P>::ld(pa + (int64_t)(base + 3 + tri_index(i, k)) * stride, (uint32_t)j);
       cx<T> a{(T)z.re, (T)z.im};
       out[i] = fma_acc(out[i], a, v[k]);
       out[k] = out[k] + cmulc(a, v[i]);
@@ -177,8 +177,29 @@ QXD_HD void pauli_mul(const typename St<P>::pair_t *pa, int64_t stride, int64_t 
   }
 }
 
-// Hop sum acc(x) over the eight neighbours of site s (native index i).
+// One hop of site s (native index i): dir = +1 adds (1 - g_mu) W(x,mu)
+// psi(x+mu), dir = -1 adds (1 + g_mu) W(x-mu,mu)^dag psi(x-mu).
 template <int P, class T>
+QXD_HD void hop_one(const Geom &g, const typename St<P>::pair_t *links,
+                    const typename St<P>::real_t *angles, int qhat, const Spinor<P> &in,
+                    const Site &s, int64_t i, int mu, int dir, cx<T> acc[4][3]) {
+  int sg;
+  Site t = neighbour(g, s, mu, dir, sg);
+  int64_t j = encode(g, t);
+  cx<T> psi[4][3], w[3][3];
+  load_spinor<P, T>(in, j, psi);
+  load_w<P, T>(links, angles, qhat, g.V, mu, dir > 0 ? i : j, w);
+  if (dir > 0)
+    hop_fwd<T>(mu, w, psi, (T)sg, acc);
+  else
+    hop_bwd<T>(mu, w, psi, (T)sg, acc);
+}
+
+// Hop sum acc(x) over the eight neighbours of site s (native index i).  The
+// hops are issued GROUP at a time (GROUP = 1, 2, 4 or 8): larger groups keep
+// more loads in flight per wavefront, smaller ones use fewer registers and
+// allow more wavefronts per SIMD.
+template <int P, class T, int GROUP = 2>
 QXD_HD void hop_sum(const Geom &g, const typename St<P>::pair_t *links,
                     const typename St<P>::real_t *angles, int qhat, const Spinor<P> &in,
                     const Site &s, int64_t i, cx<T> acc[4][3]) {
@@ -186,25 +207,11 @@ QXD_HD void hop_sum(const Geom &g, const typename St<P>::pair_t *links,
   for (int a = 0; a < 4; a++)
 #pragma unroll
     for (int c = 0; c < 3; c++) acc[a][c] = {0, 0};
+#pragma unroll 1
+  for (int k0 = 0; k0 < 8; k0 += GROUP) {
 #pragma unroll
-  for (int mu = 0; mu < 4; mu++) {
-    int sg;
-    {
-      Site t = neighbour(g, s, mu, +1, sg);
-      int64_t j = encode(g, t);
-      cx<T> psi[4][3], w[3][3];
-      load_spinor<P, T>(in, j, psi);
-      load_w<P, T>(links, angles, qhat, g.V, mu, i, w);
-      hop_fwd<T>(mu, w, psi, (T)sg, acc);
-    }
-    {
-      Site t = neighbour(g, s, mu, -1, sg);
-      int64_t j = encode(g, t);
-      cx<T> psi[4][3], w[3][3];
-      load_spinor<P, T>(in, j, psi);
-      load_w<P, T>(links, angles, qhat, g.V, mu, j, w);
-      hop_bwd<T>(mu, w, psi, (T)sg, acc);
-    }
+    for (int k = k0; k < k0 + GROUP; k++)
+      hop_one<P, T>(g, links, angles, qhat, in, s, i, k >> 1, (k & 1) ? -1 : 1, acc);
   }
 }
 

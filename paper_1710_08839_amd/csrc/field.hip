@@ -60,7 +60,7 @@ __global__ void orbifold_kernel(Geom g, const double *u_phs, const double *a_phs
 // ---- clover and Pauli term (Sec. 2.3) ---------------------------------------
 __device__ __forceinline__ cx<double> zlink(const Geom &g, const double *angles, int mu,
                                             int64_t i, const Site &s) {
-  int x0 = s.B[0] * g.b[0] + s.y[0];
+  int x0 = s.B(0) * g.b[0] + s.y(0);
   if (g.time_bc == 1 && mu == 0 && x0 == g.N[0] - 1) return {0.0, 0.0};
   double sn, cs;
   sincos(angles[(int64_t)mu * g.V + i], &sn, &cs);

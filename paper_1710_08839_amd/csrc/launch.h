@@ -68,7 +68,12 @@ struct SpinorArg {
   int64_t off;
 };
 
+// Autotuned on first use per (prec, kind, volume, phase-on-the-fly): the
+// first call times the hop-group variants on its own operands.
 hipError_t launch_dirac(int prec, DiracKind kind, const Geom &g, const OpFields &f,
                         SpinorArg in, SpinorArg self, SpinorArg out, double c, hipStream_t st);
+
+// Hop group chosen by the autotuner for a key (0 if not tuned yet).
+int tuned_group(int prec, int kind, int V, int phase);
 
 }  // namespace qxd

@@ -167,14 +167,17 @@ QXD_HD Spinor<P> spinor_view(void *base, int64_t sites, int64_t off) {
   return s;
 }
 
+// Component planes are addressed as (uniform base of the plane) + (32-bit
+// site offset), so that the 12 loads of a spinor share one address register.
 template <int P, class T>
 QXD_HD void load_spinor(const Spinor<P> &s, int64_t i, cx<T> psi[4][3]) {
-  int64_t j = i - s.off;
+  uint32_t j = (uint32_t)(i - s.off);
 #pragma unroll
   for (int a = 0; a < 4; a++)
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-      cx<typename St<P>::comp_t> z = St<P>::ld(s.data, (a * 3 + c) * s.stride + j);
+      const typename St<P>::pair_t *plane = s.data + (a * 3 + c) * s.stride;
+      cx<typename St<P>::comp_t> z = St<P>::ld(plane, j);
       psi[a][c] = {(T)z.re, (T)z.im};
     }
   if constexpr (St<P>::scaled) {
@@ -208,8 +211,10 @@ QXD_HD void store_spinor(const Spinor<P> &s, int64_t i, const cx<T> psi[4][3]) {
 #pragma unroll
   for (int a = 0; a < 4; a++)
 #pragma unroll
-    for (int c = 0; c < 3; c++)
-      St<P>::st(s.data, (a * 3 + c) * s.stride + j, cx<C>{(C)(f * (C)psi[a][c].re), (C)(f * (C)psi[a][c].im)});
+    for (int c = 0; c < 3; c++) {
+      typename St<P>::pair_t *plane = s.data + (a * 3 + c) * s.stride;
+      St<P>::st(plane, (uint32_t)j, cx<C>{(C)(f * (C)psi[a][c].re), (C)(f * (C)psi[a][c].im)});
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -227,14 +232,31 @@ struct Geom {
   int Vb, Vbh;     // sites per block, half of them
   int hb3;         // b3 / 2
   int nblocks;
+  uint32_t bpk;    // b[0..3] packed 8 bits each (indexed at run time)
+  uint32_t nbpk;   // nb[0..3] packed 8 bits each
 };
 
-// Decoded site: block coordinates B, local coordinates y, parity p.
+// Decoded site: block coordinates B, local coordinates y (8 bits each, packed
+// into one word so that a direction chosen at run time needs no array
+// indexing), parity p.
 struct Site {
-  int B[4];
-  int y[4];
+  uint32_t Bp;
+  uint32_t yp;
   int p;
+  QXD_HD int B(int m) const { return (Bp >> (8 * m)) & 0xff; }
+  QXD_HD int y(int m) const { return (yp >> (8 * m)) & 0xff; }
+  QXD_HD void setB(int m, int v) { Bp = (Bp & ~(0xffu << (8 * m))) | ((uint32_t)v << (8 * m)); }
+  QXD_HD void sety(int m, int v) { yp = (yp & ~(0xffu << (8 * m))) | ((uint32_t)v << (8 * m)); }
 };
+
+QXD_HD uint32_t pack4(int a0, int a1, int a2, int a3) {
+  return (uint32_t)a0 | ((uint32_t)a1 << 8) | ((uint32_t)a2 << 16) | ((uint32_t)a3 << 24);
+}
+
+inline void finish_geom(Geom &g) {
+  g.bpk = pack4(g.b[0], g.b[1], g.b[2], g.b[3]);
+  g.nbpk = pack4(g.nb[0], g.nb[1], g.nb[2], g.nb[3]);
+}
 
 QXD_HD Site decode(const Geom &g, int i) {
   Site s;
@@ -242,35 +264,36 @@ QXD_HD Site decode(const Geom &g, int i) {
   int r = i - s.p * g.Vh;
   int blk = r / g.Vbh;
   int h = r - blk * g.Vbh;
-  s.B[3] = blk % g.nb[3];
+  int B3 = blk % g.nb[3];
   blk /= g.nb[3];
-  s.B[2] = blk % g.nb[2];
+  int B2 = blk % g.nb[2];
   blk /= g.nb[2];
-  s.B[1] = blk % g.nb[1];
-  s.B[0] = blk / g.nb[1];
+  int B1 = blk % g.nb[1];
+  int B0 = blk / g.nb[1];
   int q = h / g.hb3;
   int y3h = h - q * g.hb3;
-  s.y[2] = q % g.b[2];
+  int y2 = q % g.b[2];
   q /= g.b[2];
-  s.y[1] = q % g.b[1];
-  s.y[0] = q / g.b[1];
-  int e = (s.p + s.y[0] + s.y[1] + s.y[2]) & 1;
-  s.y[3] = 2 * y3h + e;
+  int y1 = q % g.b[1];
+  int y0 = q / g.b[1];
+  int e = (s.p + y0 + y1 + y2) & 1;
+  s.Bp = pack4(B0, B1, B2, B3);
+  s.yp = pack4(y0, y1, y2, 2 * y3h + e);
   return s;
 }
 
-QXD_HD int block_index(const Geom &g, const int B[4]) {
-  return ((B[0] * g.nb[1] + B[1]) * g.nb[2] + B[2]) * g.nb[3] + B[3];
+QXD_HD int block_index(const Geom &g, const Site &s) {
+  return ((s.B(0) * g.nb[1] + s.B(1)) * g.nb[2] + s.B(2)) * g.nb[3] + s.B(3);
 }
 
 QXD_HD int encode(const Geom &g, const Site &s) {
-  int l = ((s.y[0] * g.b[1] + s.y[1]) * g.b[2] + s.y[2]) * g.b[3] + s.y[3];
-  return s.p * g.Vh + block_index(g, s.B) * g.Vbh + (l >> 1);
+  int l = ((s.y(0) * g.b[1] + s.y(1)) * g.b[2] + s.y(2)) * g.b[3] + s.y(3);
+  return s.p * g.Vh + block_index(g, s) * g.Vbh + (l >> 1);
 }
 
 QXD_HD void global_coords(const Geom &g, const Site &s, int x[4]) {
 #pragma unroll
-  for (int m = 0; m < 4; m++) x[m] = s.B[m] * g.b[m] + s.y[m];
+  for (int m = 0; m < 4; m++) x[m] = s.B(m) * g.b[m] + s.y(m);
 }
 
 // Neighbour x + mu (dir = +1) or x - mu (dir = -1).  `sign` receives the
@@ -280,29 +303,31 @@ QXD_HD Site neighbour(const Geom &g, const Site &s, int mu, int dir, int &sign) 
   Site t = s;
   t.p = s.p ^ 1;
   sign = 1;
-  int y = s.y[mu] + dir;
-  if (y >= 0 && y < g.b[mu]) {
-    t.y[mu] = y;
+  int y = s.y(mu) + dir;
+  int bmu = (g.bpk >> (8 * mu)) & 0xff;
+  if (y >= 0 && y < bmu) {
+    t.sety(mu, y);
     return t;
   }
-  t.y[mu] = dir > 0 ? 0 : g.b[mu] - 1;
-  int B = s.B[mu] + dir;
+  t.sety(mu, dir > 0 ? 0 : bmu - 1);
+  int nbm = (g.nbpk >> (8 * mu)) & 0xff;
+  int B = s.B(mu) + dir;
   bool wrap = false;
-  if (B == g.nb[mu]) {
+  if (B == nbm) {
     B = 0;
     wrap = true;
   } else if (B < 0) {
-    B = g.nb[mu] - 1;
+    B = nbm - 1;
     wrap = true;
   }
-  t.B[mu] = B;
+  t.setB(mu, B);
   if (wrap) {
     if (mu == 0) {
       sign = g.time_bc == 0 ? -1 : 0;
     } else if ((g.shift_mask >> mu) & 1) {
-      int b1 = t.B[1] + g.L1b;
+      int b1 = t.B(1) + g.L1b;
       if (b1 >= g.nb[1]) b1 -= g.nb[1];
-      t.B[1] = b1;
+      t.setB(1, b1);
     }
   }
   return t;

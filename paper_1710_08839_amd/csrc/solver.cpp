@@ -454,6 +454,10 @@ qxd_status check_sap_blocks(const Field *f) {
       set_error("SAP needs an even number (>= 2) of blocks in every direction (direction %d has %d)", m, g.nb[m]);
       return QXD_EINVAL;
     }
+  if (g.Vbh > 256) {
+    set_error("SAP blocks may hold at most 512 sites");
+    return QXD_EINVAL;
+  }
   if (g.shift_mask && (g.L1b % 2)) {
     set_error("with shifted C* boundaries SAP needs L1 / b1 even for a two-colour block decomposition");
     return QXD_EINVAL;

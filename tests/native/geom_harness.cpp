@@ -35,6 +35,7 @@ int main(int argc, char **argv) {
   g.Vbh = g.Vb / 2;
   g.hb3 = b[3] / 2;
   g.nblocks = g.nb[0] * g.nb[1] * g.nb[2] * g.nb[3];
+  finish_geom(g);
   std::vector<int> seen(V, 0);
   std::vector<int64_t> lex_of_native(V);
   for (int i = 0; i < g.V; i++) {
