@@ -146,6 +146,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--nsrc", type=int, default=3, help="point sources per operator in the solve leg")
     ap.add_argument("--precs", default="0,1,2,3")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 1 GiB device copy (profiler counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not part "
@@ -166,6 +168,15 @@ def main():
     q = qxd.quark(0.1365, -1 / 3, 1.9, 1.0)
     V = field.volume
     setup_s = time.perf_counter() - t0
+
+    if args.copy_probe:
+        # a plain device copy of known size (1 GiB read + 1 GiB written), for
+        # calibrating the HBM byte counters of the profiler against the kernels
+        a0 = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        b0 = torch.empty_like(a0)
+        b0.copy_(a0)
+        torch.cuda.synchronize()
+        del a0, b0
 
     precs = [int(p) for p in args.precs.split(",")]
     dw = {}

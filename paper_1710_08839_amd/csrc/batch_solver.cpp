@@ -1,0 +1,456 @@
+// Batched SAP-GCR (see batch_solver.h).  Per right-hand side the iteration is
+// the flexible GCR of the defect-correction inner solve:
+//   phi_k = M_SAP rho_k,  chi_k = D phi_k,
+//   chi_k -= sum_l a_lk chi_l  with a_lk = (chi_l, chi_k) / |chi_l|^2,
+//   c_k = (chi_k, rho_k) / |chi_k|^2,  rho_{k+1} = rho_k - c_k chi_k,
+// and at the end of a cycle the triangular system R beta = c (R_lk = a_lk,
+// R_kk = 1) gives delta += sum beta_k phi_k.  The outer loop is
+// x += |r| delta, r = eta - D x in FP64 until |r| <= tol |eta|.
+#include "batch_solver.h"
+
+#include <math.h>
+
+#include <chrono>
+#include <cstring>
+
+#include "batch.h"
+#include "blas.h"
+#include "sap.h"
+#include "solver.h"
+
+namespace qxd {
+
+namespace {
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+}  // namespace
+
+#define BCK(...)                                                                       \
+  do {                                                                                 \
+    hipError_t _e = (__VA_ARGS__);                                                     \
+    if (_e != hipSuccess) {                                                            \
+      set_error("HIP error %s at %s:%d", hipGetErrorString(_e), __FILE__, __LINE__);  \
+      return _e == hipErrorOutOfMemory ? QXD_ENOMEM : QXD_EDEVICE;                     \
+    }                                                                                  \
+  } while (0)
+#define BCS(...)                         \
+  do {                                   \
+    qxd_status _s = (__VA_ARGS__);       \
+    if (_s != QXD_OK) return _s;         \
+  } while (0)
+
+struct BatchSolver::Slot {
+  bool active = false;
+  void *tag = nullptr;
+  const double *eta_api = nullptr;
+  double *psi_api = nullptr;
+  qxd_quark q{};
+  Operator *op64 = nullptr, *opP = nullptr;
+  DevBuf f64, inner, scal;
+  size_t fb64 = 0, fbP = 0;
+  int k = 0, inner_it = 0, total_it = 0, outer = 0;
+  double eta_n = 0, s_norm = 0, bn = 0, r2 = 0;
+  double t0 = 0;
+  // FP64 vectors
+  void *eta() { return f64.p; }
+  void *x() { return (char *)f64.p + fb64; }
+  void *r() { return (char *)f64.p + 2 * fb64; }
+  void *tmp() { return (char *)f64.p + 3 * fb64; }
+  // inner-precision vectors
+  void *b() { return inner.p; }
+  void *rho() { return (char *)inner.p + fbP; }
+  void *delta() { return (char *)inner.p + 2 * fbP; }
+  void *sap_r() { return (char *)inner.p + 3 * fbP; }
+  void *sap_v() { return (char *)inner.p + 4 * fbP; }
+  void *phi(int k) { return (char *)inner.p + (5 + k) * fbP; }
+  void *chi(int nkv, int k) { return (char *)inner.p + (5 + nkv + k) * fbP; }
+  // scalars: amat[2*nkv*nkv], rec[3*nkv], coef[2*nkv], misc[8]
+  double *amat() { return (double *)scal.p; }
+  double *rec(int nkv) { return amat() + 2 * nkv * nkv; }
+  double *coef(int nkv) { return rec(nkv) + 3 * nkv; }
+  double *misc(int nkv) { return coef(nkv) + 2 * nkv; }
+};
+
+static size_t scal_doubles(int nkv) { return (size_t)2 * nkv * nkv + 3 * nkv + 2 * nkv + 8; }
+
+BatchSolver::BatchSolver(Field *f, int prec, const qxd_solver &s, hipStream_t st)
+    : f_(f), prec_(prec), s_(s), st_(st) {
+  nkv_ = s.nkv > 0 ? s.nkv : 8;
+  if (nkv_ > MAXV) nkv_ = MAXV;
+  ncy_ = s.ncy > 0 ? s.ncy : 5;
+  nmr_ = s.nmr > 0 ? s.nmr : 4;
+  inner_tol_ = s.inner_tol > 0 ? s.inner_tol : (prec == QXD_F64 ? 1e-6 : (prec == QXD_F32 ? 1e-5 : 1e-2));
+}
+
+BatchSolver::~BatchSolver() {
+  (void)hipStreamSynchronize(st_);
+  if (h_stage_) (void)hipHostFree(h_stage_);
+  if (h_norms_) (void)hipHostFree(h_norms_);
+}
+
+size_t BatchSolver::slot_bytes(const Field *f, int prec, const qxd_solver &s) {
+  int nkv = s.nkv > 0 ? s.nkv : 8;
+  return 4 * spinor_bytes(QXD_F64, f->g.V) + (size_t)(5 + 2 * nkv) * spinor_bytes(prec, f->g.V) +
+         scal_doubles(nkv) * 8;
+}
+
+int BatchSolver::active() const {
+  int n = 0;
+  for (auto &s : slots_) n += s->active;
+  return n;
+}
+
+qxd_status BatchSolver::reserve(int n) {
+  const Geom &g = f_->g;
+  while ((int)slots_.size() < n) {
+    std::unique_ptr<Slot> sl(new Slot());
+    sl->fb64 = spinor_bytes(QXD_F64, g.V);
+    sl->fbP = spinor_bytes(prec_, g.V);
+    BCK(sl->f64.ensure(4 * sl->fb64));
+    BCK(sl->inner.ensure((5 + 2 * nkv_) * sl->fbP));
+    BCK(sl->scal.ensure(scal_doubles(nkv_) * 8));
+    slots_.push_back(std::move(sl));
+  }
+  size_t nslot = slots_.size();
+  size_t stage = nslot * (sizeof(SapSlot<QXD_F64>) + sizeof(DSlot<QXD_F64>) + sizeof(int)) + 256;
+  if (stage > h_stage_bytes_) {
+    BCK(hipStreamSynchronize(st_));
+    if (h_stage_) (void)hipHostFree(h_stage_);
+    h_stage_ = nullptr;
+    BCK(hipHostMalloc(&h_stage_, stage, hipHostMallocDefault));
+    h_stage_bytes_ = stage;
+    if (h_norms_) (void)hipHostFree(h_norms_);
+    h_norms_ = nullptr;
+    BCK(hipHostMalloc((void **)&h_norms_, nslot * sizeof(double) + 64, hipHostMallocDefault));
+  }
+  BCK(dslots_.ensure(nslot * sizeof(DSlot<QXD_F64>)));
+  BCK(sslots_.ensure(nslot * sizeof(SapSlot<QXD_F64>)));
+  BCK(act_.ensure(nslot * sizeof(int)));
+  BCK(d_norms_.ensure(nslot * sizeof(double)));
+  BCK(partial_.ensure(blas_partial_doubles() * 8));
+  return QXD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// per-precision pieces
+// ---------------------------------------------------------------------------
+template <int P>
+struct BImpl {
+  static SpinorArg F(const Geom &g, void *p) { return SpinorArg{p, g.V, 0}; }
+
+  // b = r / |r| (inner precision), rho = b, delta = 0
+  static qxd_status new_inner(BatchSolver::Slot &sl, const Geom &g, double *partial, int nkv,
+                              hipStream_t st) {
+    sl.s_norm = sqrt(sl.r2);
+    BCK(blas_axpby<P, QXD_F64>(F(g, sl.b()), 0.0, F(g, sl.r()), 1.0 / sl.s_norm, 0, g.V, partial,
+                               sl.misc(nkv) + 1, st));
+    BCK(blas_axpby<P, P>(F(g, sl.rho()), 0.0, F(g, sl.b()), 1.0, 0, g.V, partial, nullptr, st));
+    BCK(hipMemsetAsync(sl.delta(), 0, sl.fbP, st));
+    double b2 = 0;
+    BCK(hipMemcpyAsync(&b2, sl.misc(nkv) + 1, 8, hipMemcpyDeviceToHost, st));
+    BCK(hipStreamSynchronize(st));
+    sl.bn = sqrt(b2);
+    sl.r2 = b2;
+    sl.k = 0;
+    sl.inner_it = 0;
+    return QXD_OK;
+  }
+
+  // Gram-Schmidt of chi_k and the residual update, for one slot
+  static qxd_status gs(BatchSolver::Slot &sl, const Geom &g, double *partial, int nkv, hipStream_t st,
+                       double *norm_out) {
+    int k = sl.k;
+    std::vector<SpinorArg> chi(k + 1);
+    for (int l = 0; l <= k; l++) chi[l] = F(g, sl.chi(nkv, l));
+    double *ak = sl.amat() + 2 * k * nkv;
+    double *rec = sl.rec(nkv);
+    if (k > 0) BCK(blas_mdot<P>(chi.data(), k, chi[k], 0, g.V, partial, ak, rec, 3, st));
+    MaxpyHost m;
+    m.n = k;
+    m.src[0] = chi[k];
+    m.dst[0] = chi[k];
+    m.ys[0] = chi.data();
+    m.coef = ak;
+    m.w = F(g, sl.rho());
+    BCK(blas_maxpy<P>(m, 0, g.V, partial, rec + 3 * k, st));
+    BCK(blas_update<P>(F(g, sl.rho()), chi[k], rec + 3 * k + 1, rec + 3 * k, 0, 0, g.V, partial, norm_out, st));
+    return QXD_OK;
+  }
+
+  // end of a cycle: delta += sum beta_k phi_k (kused = sl.k vectors)
+  static qxd_status cycle_end(BatchSolver::Slot &sl, const Geom &g, double *partial, int nkv,
+                              hipStream_t st) {
+    int kused = sl.k;
+    if (kused == 0) return QXD_OK;
+    std::vector<double> hv(2 * nkv * nkv + 3 * nkv);
+    BCK(hipMemcpyAsync(hv.data(), sl.amat(), hv.size() * 8, hipMemcpyDeviceToHost, st));
+    BCK(hipStreamSynchronize(st));
+    const double *rec = hv.data() + 2 * nkv * nkv;
+    std::vector<double> br(kused), bi(kused), hc(2 * kused);
+    for (int k = kused - 1; k >= 0; k--) {
+      double n = rec[3 * k];
+      double cr = rec[3 * k + 1] / n, ci = rec[3 * k + 2] / n;
+      for (int j = k + 1; j < kused; j++) {
+        double ar = hv[2 * (j * nkv + k)], ai = hv[2 * (j * nkv + k) + 1];
+        cr -= ar * br[j] - ai * bi[j];
+        ci -= ar * bi[j] + ai * br[j];
+      }
+      br[k] = cr;
+      bi[k] = ci;
+    }
+    for (int k = 0; k < kused; k++) {
+      hc[2 * k] = -br[k];
+      hc[2 * k + 1] = -bi[k];
+    }
+    BCK(hipMemcpyAsync(sl.coef(nkv), hc.data(), hc.size() * 8, hipMemcpyHostToDevice, st));
+    std::vector<SpinorArg> phi(kused);
+    for (int l = 0; l < kused; l++) phi[l] = F(g, sl.phi(l));
+    MaxpyHost m;
+    m.n = kused;
+    m.src[0] = F(g, sl.delta());
+    m.dst[0] = F(g, sl.delta());
+    m.ys[0] = phi.data();
+    m.coef = sl.coef(nkv);
+    BCK(blas_maxpy<P>(m, 0, g.V, partial, nullptr, st));
+    BCK(hipStreamSynchronize(st));  // hc lives on this stack frame
+    return QXD_OK;
+  }
+
+  // rho = b - D delta (restart inside the inner solve)
+  static qxd_status restart(BatchSolver::Slot &sl, Field *f, double *partial, int nkv, hipStream_t st) {
+    const Geom &g = f->g;
+    OpFields of = f->op_fields(*sl.opP, P);
+    BCK(launch_dirac(P, DK_FULL, g, of, F(g, sl.delta()), F(g, sl.delta()), F(g, sl.chi(nkv, 0)), -0.5, st));
+    BCK(blas_axpby<P, P>(F(g, sl.rho()), 0.0, F(g, sl.b()), 1.0, 0, g.V, partial, nullptr, st));
+    BCK(blas_axpby<P, P>(F(g, sl.rho()), 1.0, F(g, sl.chi(nkv, 0)), -1.0, 0, g.V, partial, sl.misc(nkv), st));
+    BCK(hipMemcpyAsync(&sl.r2, sl.misc(nkv), 8, hipMemcpyDeviceToHost, st));
+    BCK(hipStreamSynchronize(st));
+    sl.k = 0;
+    return QXD_OK;
+  }
+
+  // x += |r| delta; r = eta - D x (FP64); r2 = |r|^2
+  static qxd_status outer_update(BatchSolver::Slot &sl, Field *f, double *partial, int nkv, hipStream_t st) {
+    const Geom &g = f->g;
+    auto F64 = [&](void *p) { return SpinorArg{p, g.V, 0}; };
+    BCK(blas_axpby<QXD_F64, P>(F64(sl.x()), 1.0, F(g, sl.delta()), sl.s_norm, 0, g.V, partial, nullptr, st));
+    OpFields of = f->op_fields(*sl.op64, QXD_F64);
+    BCK(launch_dirac(QXD_F64, DK_FULL, g, of, F64(sl.x()), F64(sl.x()), F64(sl.tmp()), -0.5, st));
+    BCK(blas_axpby<QXD_F64, QXD_F64>(F64(sl.r()), 0.0, F64(sl.eta()), 1.0, 0, g.V, partial, nullptr, st));
+    BCK(blas_axpby<QXD_F64, QXD_F64>(F64(sl.r()), 1.0, F64(sl.tmp()), -1.0, 0, g.V, partial, sl.misc(nkv), st));
+    BCK(hipMemcpyAsync(&sl.r2, sl.misc(nkv), 8, hipMemcpyDeviceToHost, st));
+    BCK(hipStreamSynchronize(st));
+    return QXD_OK;
+  }
+
+  // the batched part of a step: phi_k = M_SAP rho, chi_k = D phi_k
+  static qxd_status batched(BatchSolver &bs, std::vector<BatchSolver::Slot *> &act, hipStream_t st,
+                            DevBuf &sslots, DevBuf &dslots, DevBuf &actbuf, void *stage, int ncy, int nmr,
+                            int nkv) {
+    Field *f = bs.field();
+    const Geom &g = f->g;
+    int n = (int)act.size();
+    SapSlot<P> *hs = (SapSlot<P> *)stage;
+    DSlot<P> *hd = (DSlot<P> *)(hs + n);
+    int *ha = (int *)(hd + n);
+    for (int j = 0; j < n; j++) {
+      BatchSolver::Slot &sl = *act[j];
+      OpFields of = f->op_fields(*sl.opP, P);
+      hs[j].op = SapOp<P>{(const typename St<P>::pair_t *)of.links, nullptr, 0,
+                          (const typename St<P>::pair_t *)of.pauli, (const typename St<P>::pair_t *)of.pinv};
+      hs[j].vec = SapVecs<P>{spinor_view<P>(sl.rho(), g.V, 0), spinor_view<P>(sl.sap_r(), g.V, 0),
+                             spinor_view<P>(sl.phi(sl.k), g.V, 0), spinor_view<P>(sl.sap_v(), g.V, 0)};
+      hd[j].links = hs[j].op.links;
+      hd[j].pauli = hs[j].op.pauli;
+      hd[j].in = spinor_view<P>(sl.phi(sl.k), g.V, 0);
+      hd[j].out = spinor_view<P>(sl.chi(nkv, sl.k), g.V, 0);
+      ha[j] = j;
+    }
+    BCK(hipMemcpyAsync(sslots.p, hs, n * sizeof(SapSlot<P>), hipMemcpyHostToDevice, st));
+    BCK(hipMemcpyAsync(dslots.p, hd, n * sizeof(DSlot<P>), hipMemcpyHostToDevice, st));
+    BCK(hipMemcpyAsync(actbuf.p, ha, n * sizeof(int), hipMemcpyHostToDevice, st));
+    const int *lists[2];
+    int nper;
+    BCS(sap_block_lists(f, lists, &nper));
+    for (int cy = 0; cy < ncy; cy++)
+      for (int c = 0; c < 2; c++)
+        BCK(launch_sap_batch<P>(g, lists[c], nper, sslots.as<SapSlot<P>>(), actbuf.as<int>(), n, cy == 0,
+                                cy == 0 && c == 0, nmr, st));
+    BCK(launch_dirac_batch<P>(g, dslots.as<DSlot<P>>(), actbuf.as<int>(), n, 2, st));
+    return QXD_OK;
+  }
+};
+
+#define DISPATCH(call)                                          \
+  switch (prec_) {                                              \
+    case QXD_F64: return BImpl<QXD_F64>::call;                  \
+    case QXD_F32: return BImpl<QXD_F32>::call;                  \
+    case QXD_F16S: return BImpl<QXD_F16S>::call;                \
+    default: return BImpl<QXD_BF16>::call;                      \
+  }
+
+qxd_status BatchSolver::new_inner(Slot &sl) {
+  DISPATCH(new_inner(sl, f_->g, partial_.as<double>(), nkv_, st_));
+}
+qxd_status BatchSolver::cycle_end(Slot &sl) {
+  DISPATCH(cycle_end(sl, f_->g, partial_.as<double>(), nkv_, st_));
+}
+qxd_status BatchSolver::outer_update(Slot &sl) {
+  DISPATCH(outer_update(sl, f_, partial_.as<double>(), nkv_, st_));
+}
+
+qxd_status BatchSolver::finish(Slot &sl, int status) {
+  const Geom &g = f_->g;
+  BCK(launch_unpack(QXD_F64, g, sl.x(), sl.psi_api, 1, st_));
+  BCK(hipStreamSynchronize(st_));
+  Finished fin;
+  fin.slot = -1;
+  fin.tag = sl.tag;
+  fin.info.status = status;
+  fin.info.outer_iters = sl.outer;
+  fin.info.inner_iters = sl.total_it;
+  fin.info.true_resid = sl.eta_n > 0 ? sqrt(sl.r2) / sl.eta_n : 0.0;
+  fin.info.seconds = now_s() - sl.t0;
+  for (size_t j = 0; j < slots_.size(); j++)
+    if (slots_[j].get() == &sl) fin.slot = (int)j;
+  done_.push_back(fin);
+  sl.active = false;
+  return QXD_OK;
+}
+
+qxd_status BatchSolver::add(const qxd_quark &q, const double *eta_api, double *psi_api, bool use_guess,
+                            void *tag) {
+  Slot *sl = nullptr;
+  for (auto &s : slots_)
+    if (!s->active) {
+      sl = s.get();
+      break;
+    }
+  if (!sl) {
+    set_error("no free slot in the batch");
+    return QXD_EBUSY;
+  }
+  const Geom &g = f_->g;
+  BCS(f_->get_op(q, QXD_F64, &sl->op64, st_));
+  BCS(f_->get_op(q, prec_, &sl->opP, st_));
+  sl->q = q;
+  sl->tag = tag;
+  sl->eta_api = eta_api;
+  sl->psi_api = psi_api;
+  sl->k = sl->inner_it = sl->total_it = sl->outer = 0;
+  sl->t0 = now_s();
+  sl->active = true;
+  double *partial = partial_.as<double>();
+  auto F64 = [&](void *p) { return SpinorArg{p, g.V, 0}; };
+  BCK(launch_pack(QXD_F64, g, eta_api, sl->eta(), 1, st_));
+  BCK(blas_norm2<QXD_F64>(F64(sl->eta()), 0, g.V, partial, sl->misc(nkv_), st_));
+  double e2 = 0;
+  BCK(hipMemcpyAsync(&e2, sl->misc(nkv_), 8, hipMemcpyDeviceToHost, st_));
+  BCK(hipStreamSynchronize(st_));
+  if (!isfinite(e2)) {
+    sl->eta_n = 0;
+    sl->r2 = 0;
+    BCK(hipMemsetAsync(sl->x(), 0, sl->fb64, st_));
+    return finish(*sl, QXD_EFLOAT);
+  }
+  sl->eta_n = sqrt(e2);
+  if (e2 == 0.0) {
+    sl->r2 = 0;
+    BCK(hipMemsetAsync(sl->x(), 0, sl->fb64, st_));
+    return finish(*sl, QXD_OK);
+  }
+  if (use_guess) {
+    BCK(launch_pack(QXD_F64, g, psi_api, sl->x(), 1, st_));
+    OpFields of = f_->op_fields(*sl->op64, QXD_F64);
+    BCK(launch_dirac(QXD_F64, DK_FULL, g, of, F64(sl->x()), F64(sl->x()), F64(sl->tmp()), -0.5, st_));
+    BCK(blas_axpby<QXD_F64, QXD_F64>(F64(sl->r()), 0.0, F64(sl->eta()), 1.0, 0, g.V, partial, nullptr, st_));
+    BCK(blas_axpby<QXD_F64, QXD_F64>(F64(sl->r()), 1.0, F64(sl->tmp()), -1.0, 0, g.V, partial, sl->misc(nkv_), st_));
+    BCK(hipMemcpyAsync(&sl->r2, sl->misc(nkv_), 8, hipMemcpyDeviceToHost, st_));
+    BCK(hipStreamSynchronize(st_));
+    if (!isfinite(sl->r2)) return finish(*sl, QXD_EFLOAT);
+  } else {
+    BCK(hipMemsetAsync(sl->x(), 0, sl->fb64, st_));
+    BCK(blas_axpby<QXD_F64, QXD_F64>(F64(sl->r()), 0.0, F64(sl->eta()), 1.0, 0, g.V, partial, nullptr, st_));
+    sl->r2 = e2;
+  }
+  if (sqrt(sl->r2) <= s_.tol * sl->eta_n) return finish(*sl, QXD_OK);
+  return new_inner(*sl);
+}
+
+qxd_status BatchSolver::step() {
+  std::vector<Slot *> act;
+  for (auto &s : slots_)
+    if (s->active) act.push_back(s.get());
+  if (act.empty()) return QXD_OK;
+  const Geom &g = f_->g;
+  int n = (int)act.size();
+  // batched: phi_k = M_SAP rho, chi_k = D phi_k
+  switch (prec_) {
+    case QXD_F64: BCS(BImpl<QXD_F64>::batched(*this, act, st_, sslots_, dslots_, act_, h_stage_, ncy_, nmr_, nkv_)); break;
+    case QXD_F32: BCS(BImpl<QXD_F32>::batched(*this, act, st_, sslots_, dslots_, act_, h_stage_, ncy_, nmr_, nkv_)); break;
+    case QXD_F16S: BCS(BImpl<QXD_F16S>::batched(*this, act, st_, sslots_, dslots_, act_, h_stage_, ncy_, nmr_, nkv_)); break;
+    default: BCS(BImpl<QXD_BF16>::batched(*this, act, st_, sslots_, dslots_, act_, h_stage_, ncy_, nmr_, nkv_)); break;
+  }
+  // per right-hand side: Gram-Schmidt and residual update
+  double *dn = d_norms_.as<double>();
+  for (int j = 0; j < n; j++) {
+    switch (prec_) {
+      case QXD_F64: BCS(BImpl<QXD_F64>::gs(*act[j], g, partial_.as<double>(), nkv_, st_, dn + j)); break;
+      case QXD_F32: BCS(BImpl<QXD_F32>::gs(*act[j], g, partial_.as<double>(), nkv_, st_, dn + j)); break;
+      case QXD_F16S: BCS(BImpl<QXD_F16S>::gs(*act[j], g, partial_.as<double>(), nkv_, st_, dn + j)); break;
+      default: BCS(BImpl<QXD_BF16>::gs(*act[j], g, partial_.as<double>(), nkv_, st_, dn + j)); break;
+    }
+  }
+  BCK(hipMemcpyAsync(h_norms_, dn, n * sizeof(double), hipMemcpyDeviceToHost, st_));
+  BCK(hipStreamSynchronize(st_));
+  const int maxiter = s_.maxiter > 0 ? s_.maxiter : 100000;
+  const int max_outer = s_.max_outer > 0 ? s_.max_outer : 50;
+  for (int j = 0; j < n; j++) {
+    Slot &sl = *act[j];
+    sl.r2 = h_norms_[j];
+    sl.k++;
+    sl.inner_it++;
+    sl.total_it++;
+    if (!isfinite(sl.r2)) {
+      BCS(finish(sl, QXD_EFLOAT));
+      continue;
+    }
+    bool inner_done = sqrt(sl.r2) <= inner_tol_ * sl.bn;
+    bool budget = sl.total_it >= maxiter;
+    if (!(inner_done || budget || sl.k == nkv_)) continue;
+    BCS(cycle_end(sl));
+    // an inner solve that has not converged after kMaxInnerCycles cycles is
+    // cut short: the FP64 correction restarts it from the true residual
+    constexpr int kMaxInnerCycles = 16;
+    if (inner_done || budget || sl.inner_it >= kMaxInnerCycles * nkv_) {
+      BCS(outer_update(sl));
+      sl.outer++;
+      if (!isfinite(sl.r2)) {
+        BCS(finish(sl, QXD_EFLOAT));
+      } else if (sqrt(sl.r2) <= s_.tol * sl.eta_n) {
+        BCS(finish(sl, QXD_OK));
+      } else if (budget || sl.outer >= max_outer) {
+        BCS(finish(sl, QXD_ENOCONV));
+      } else {
+        BCS(new_inner(sl));
+      }
+    } else {
+      switch (prec_) {
+        case QXD_F64: BCS(BImpl<QXD_F64>::restart(sl, f_, partial_.as<double>(), nkv_, st_)); break;
+        case QXD_F32: BCS(BImpl<QXD_F32>::restart(sl, f_, partial_.as<double>(), nkv_, st_)); break;
+        case QXD_F16S: BCS(BImpl<QXD_F16S>::restart(sl, f_, partial_.as<double>(), nkv_, st_)); break;
+        default: BCS(BImpl<QXD_BF16>::restart(sl, f_, partial_.as<double>(), nkv_, st_)); break;
+      }
+    }
+  }
+  return QXD_OK;
+}
+
+std::vector<Finished> BatchSolver::take_finished() {
+  std::vector<Finished> out;
+  out.swap(done_);
+  return out;
+}
+
+}  // namespace qxd

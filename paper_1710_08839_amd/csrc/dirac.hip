@@ -24,11 +24,26 @@ __global__ void __launch_bounds__(256) dirac_kernel(Geom g, const typename St<P>
                                                     Spinor<P> in, Spinor<P> self, Spinor<P> out,
                                                     typename St<P>::comp_t c) {
   using T = typename St<P>::comp_t;
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int i0 = (KIND == DK_ODD) ? g.Vh : 0;
-  int n = (KIND == DK_ODD || KIND == DK_EVEN || KIND == DK_EVEN_ID) ? g.Vh : g.V;
-  if (t >= n) return;
-  int i = i0 + t;
+  // A work-group owns whole lattice blocks (both parities for the full-lattice
+  // kinds, one parity for the half-lattice passes), in XCD-aware order, so
+  // that the even/odd neighbours of a site and the blocks next to it are read
+  // through the same L2.
+  constexpr bool half = KIND == DK_ODD || KIND == DK_EVEN || KIND == DK_EVEN_ID;
+  const int per_block = half ? g.Vbh : 2 * g.Vbh;
+  const int wg = xcd_order(blockIdx.x, gridDim.x);
+  int blk, r;
+  if (per_block <= (int)blockDim.x) {  // whole blocks per work-group
+    const int bpw = blockDim.x / per_block;
+    blk = wg * bpw + threadIdx.x / per_block;
+    r = threadIdx.x % per_block;
+  } else {                             // a block spread over several work-groups
+    const int wpb = per_block / blockDim.x;
+    blk = wg / wpb;
+    r = (wg % wpb) * blockDim.x + threadIdx.x;
+  }
+  if (blk >= g.nblocks) return;
+  int par = half ? (KIND == DK_ODD ? 1 : 0) : (r >= g.Vbh);
+  int i = par * g.Vh + blk * g.Vbh + (r >= g.Vbh ? r - g.Vbh : r);
   cx<T> res[4][3];
   if (KIND != DK_PAULI) {
     Site s = decode(g, i);
@@ -71,23 +86,23 @@ __global__ void __launch_bounds__(256) dirac_kernel(Geom g, const typename St<P>
 }
 
 template <int P, int KIND, int G>
-void launch_k(unsigned gr, hipStream_t st, const Geom &g, const typename St<P>::pair_t *links,
+void launch_k(unsigned gr, int threads, hipStream_t st, const Geom &g, const typename St<P>::pair_t *links,
               const typename St<P>::real_t *angles, int qhat, const typename St<P>::pair_t *pauli,
               const typename St<P>::pair_t *pinv, Spinor<P> vin, Spinor<P> vself, Spinor<P> vout,
               typename St<P>::comp_t c) {
-  dirac_kernel<P, KIND, G><<<gr, 256, 0, st>>>(g, links, angles, qhat, pauli, pinv, vin, vself, vout, c);
+  dirac_kernel<P, KIND, G><<<gr, threads, 0, st>>>(g, links, angles, qhat, pauli, pinv, vin, vself, vout, c);
 }
 
 template <int P, int KIND>
-void launch_g(int group, unsigned gr, hipStream_t st, const Geom &g, const typename St<P>::pair_t *links,
+void launch_g(int group, unsigned gr, int threads, hipStream_t st, const Geom &g, const typename St<P>::pair_t *links,
               const typename St<P>::real_t *angles, int qhat, const typename St<P>::pair_t *pauli,
               const typename St<P>::pair_t *pinv, Spinor<P> vin, Spinor<P> vself, Spinor<P> vout,
               typename St<P>::comp_t c) {
   switch (group) {
-    case 1: launch_k<P, KIND, 1>(gr, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
-    case 4: launch_k<P, KIND, 4>(gr, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
-    case 8: launch_k<P, KIND, 8>(gr, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
-    default: launch_k<P, KIND, 2>(gr, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
+    case 1: launch_k<P, KIND, 1>(gr, threads, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
+    case 4: launch_k<P, KIND, 4>(gr, threads, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
+    case 8: launch_k<P, KIND, 8>(gr, threads, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
+    default: launch_k<P, KIND, 2>(gr, threads, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
   }
 }
 
@@ -104,16 +119,30 @@ hipError_t launch_p(DiracKind kind, int group, const Geom &g, const OpFields &f,
   Spinor<P> vin = spinor_view<P>(in.ptr, in.sites, in.off);
   Spinor<P> vself = self.ptr ? spinor_view<P>(self.ptr, self.sites, self.off) : Spinor<P>{nullptr, nullptr, 0, 0};
   Spinor<P> vout = spinor_view<P>(out.ptr, out.sites, out.off);
-  int n = (kind == DK_ODD || kind == DK_EVEN || kind == DK_EVEN_ID) ? g.Vh : g.V;
-  unsigned gr = grid_for(n, 256);
+  // work-group size: whole blocks, about 256 threads
+  bool half = kind == DK_ODD || kind == DK_EVEN || kind == DK_EVEN_ID;
+  int per_block = half ? g.Vbh : 2 * g.Vbh;
+  int threads;
+  unsigned gr;
+  if (per_block <= 256) {
+    int bpw = 256 / per_block;
+    threads = bpw * per_block;
+    gr = grid_for(g.nblocks, bpw);
+  } else {
+    // block sites are a multiple of 16, so per_block is a multiple of 8: use
+    // the largest power-of-two divisor of per_block up to 256 threads
+    threads = 256;
+    while (per_block % threads) threads >>= 1;
+    gr = (unsigned)g.nblocks * (per_block / threads);
+  }
   T cc = (T)c;
   switch (kind) {
-    case DK_FULL: launch_g<P, DK_FULL>(group, gr, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
-    case DK_HOP: launch_g<P, DK_HOP>(group, gr, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
-    case DK_PAULI: launch_g<P, DK_PAULI>(1, gr, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
-    case DK_ODD: launch_g<P, DK_ODD>(group, gr, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
-    case DK_EVEN: launch_g<P, DK_EVEN>(group, gr, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
-    case DK_EVEN_ID: launch_g<P, DK_EVEN_ID>(group, gr, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
+    case DK_FULL: launch_g<P, DK_FULL>(group, gr, threads, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
+    case DK_HOP: launch_g<P, DK_HOP>(group, gr, threads, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
+    case DK_PAULI: launch_g<P, DK_PAULI>(1, gr, threads, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
+    case DK_ODD: launch_g<P, DK_ODD>(group, gr, threads, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
+    case DK_EVEN: launch_g<P, DK_EVEN>(group, gr, threads, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
+    case DK_EVEN_ID: launch_g<P, DK_EVEN_ID>(group, gr, threads, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
   }
   return hipGetLastError();
 }

@@ -351,4 +351,15 @@ QXD_HD int64_t ext_lex(const Geom &g, const int x[4]) {
 // ---------------------------------------------------------------------------
 inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
+// The GPU hands work-group w to XCD (w mod 8); each XCD has its own L2.  Map
+// work-groups to a logical order in which XCD x owns one contiguous range of
+// the logical index space, so that neighbouring lattice blocks are processed
+// by the same XCD at about the same time.  A bijection on [0, n).
+constexpr int N_XCD = 8;
+QXD_HD int xcd_order(int w, int n) {
+  int x = w % N_XCD, k = w / N_XCD;
+  int q = n / N_XCD, r = n % N_XCD;
+  return x * q + (x < r ? x : r) + k;
+}
+
 }  // namespace qxd

@@ -23,7 +23,33 @@ struct SapArgs {
   int nmr;
 };
 
+template <int P>
+struct SapOp {
+  const typename St<P>::pair_t *links;
+  const typename St<P>::real_t *angles;
+  int qhat;
+  const typename St<P>::pair_t *pauli;
+  const typename St<P>::pair_t *pinv;
+};
+
+template <int P>
+struct SapVecs {
+  Spinor<P> rho, r, psi, v;
+};
+
+// one right-hand side of a batched SAP pass (kept in device memory)
+template <int P>
+struct SapSlot {
+  SapOp<P> op;
+  SapVecs<P> vec;
+};
+
 size_t sap_lds_bytes(int prec, const Geom &g);
+
+// One colour pass of SAP for the active slots act[0..nact) of a batch.
+template <int P>
+hipError_t launch_sap_batch(const Geom &g, const int *blocks, int nblocks_colour, const SapSlot<P> *slots,
+                            const int *act, int nact, int first, int skip_face, int nmr, hipStream_t st);
 
 template <int P>
 hipError_t launch_sap_colour(const SapArgs<P> &a, int nblocks_colour, hipStream_t st);

@@ -106,11 +106,10 @@ __device__ __forceinline__ T wave_sum(T v) {
 // t (nh = sites of one parity per block, a multiple of 64 for the usual 4^4
 // blocks so that no wavefront mixes parities).
 template <int P>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
-sap_block_kernel(SapArgs<P> a) {
+__device__ __forceinline__ void sap_block_body(const Geom &g, const SapOp<P> &a, const SapVecs<P> &vv,
+                                               int blk, int first, int skip_face, int nmr,
+                                               unsigned char *smem) {
   using T = typename St<P>::comp_t;
-  extern __shared__ __align__(16) unsigned char smem[];
-  const Geom &g = a.g;
   const int nh = g.Vbh;
   cx<T> *buf0 = (cx<T> *)smem;        // even-site vector s
   cx<T> *buf1 = buf0 + 12 * nh;       // odd-site vector
@@ -122,7 +121,6 @@ sap_block_kernel(SapArgs<P> a) {
   const bool act = h < nh && tid < 2 * nh;
   const int even_waves = (nh + 63) >> 6;
 
-  const int blk = a.blocks[blockIdx.x];
   Site st;
   {
     int B = blk;
@@ -148,9 +146,9 @@ sap_block_kernel(SapArgs<P> a) {
 
   cx<T> r[4][3], s[4][3], tmp[4][3], acc[4][3];
   if (act) {
-    load_spinor<P, T>(a.first ? a.rho : a.r, i, r);
-    if (!a.skip_face) {
-      acc_outside<P, T>(g, a.links, a.angles, a.qhat, st, i, a.v, acc);
+    load_spinor<P, T>(first ? vv.rho : vv.r, i, r);
+    if (!skip_face) {
+      acc_outside<P, T>(g, a.links, a.angles, a.qhat, st, i, vv.v, acc);
 #pragma unroll
       for (int x = 0; x < 4; x++)
 #pragma unroll
@@ -158,7 +156,7 @@ sap_block_kernel(SapArgs<P> a) {
     }
     if (odd) {
       // u_o = D_oo^-1 r_o; r_o is parked in the residual field until the end
-      store_spinor<P, T>(a.r, i, r);
+      store_spinor<P, T>(vv.r, i, r);
       pauli_mul<P, T>(a.pinv, g.Vh, ie, r, tmp);
       lds_store<T>(buf1, nh, h, tmp);
     }
@@ -178,7 +176,7 @@ sap_block_kernel(SapArgs<P> a) {
     lds_store<T>(bufv, nh, h, tmp);
   }
   __syncthreads();
-  for (int k = 0; k < a.nmr; k++) {
+  for (int k = 0; k < nmr; k++) {
     if (act && odd) {
       // w_o = D_oo^-1 D_oe^L s = -D_oo^-1 acc_in(s)/2
       acc_inside<P, T>(g, a.links, a.angles, a.qhat, st, i, buf0, nh, acc);
@@ -190,8 +188,10 @@ sap_block_kernel(SapArgs<P> a) {
       lds_store<T>(buf1, nh, h, tmp);
     }
     __syncthreads();
+    // (t, s) and (t, t) over the even sites; every lane takes part in the
+    // wavefront reductions (odd and idle lanes add zero)
+    T ts_re = 0, ts_im = 0, tt = 0;
     if (!odd) {
-      T ts_re = 0, ts_im = 0, tt = 0;
       if (act) {
         // t = P s - D_eo^L w_o = P s + acc_in(w)/2
         acc_inside<P, T>(g, a.links, a.angles, a.qhat, st, i, buf1, nh, acc);
@@ -207,14 +207,14 @@ sap_block_kernel(SapArgs<P> a) {
             tt += norm2(tmp[x][c]);
           }
       }
-      ts_re = wave_sum(ts_re);
-      ts_im = wave_sum(ts_im);
-      tt = wave_sum(tt);
-      if ((tid & 63) == 0) {
-        red[3 * (tid >> 6)] = ts_re;
-        red[3 * (tid >> 6) + 1] = ts_im;
-        red[3 * (tid >> 6) + 2] = tt;
-      }
+    }
+    ts_re = wave_sum(ts_re);
+    ts_im = wave_sum(ts_im);
+    tt = wave_sum(tt);
+    if ((tid & 63) == 0) {
+      red[3 * (tid >> 6)] = ts_re;
+      red[3 * (tid >> 6) + 1] = ts_im;
+      red[3 * (tid >> 6) + 2] = tt;
     }
     __syncthreads();
     if (!odd) {
@@ -244,7 +244,7 @@ sap_block_kernel(SapArgs<P> a) {
   cx<T> v[4][3];
   if (odd) {
     // v_o = D_oo^-1 (r_o - D_oe^L v_e) = D_oo^-1 (r_o + acc_in(v_e)/2)
-    load_spinor<P, T>(a.r, i, r);
+    load_spinor<P, T>(vv.r, i, r);
     acc_inside<P, T>(g, a.links, a.angles, a.qhat, st, i, bufv, nh, acc);
 #pragma unroll
     for (int x = 0; x < 4; x++)
@@ -255,15 +255,15 @@ sap_block_kernel(SapArgs<P> a) {
     lds_load<T>(bufv, nh, h, v);
   }
   // psi += v; residual on the block: r_e = s, r_o = 0; keep v for the faces
-  if (a.first) {
-    store_spinor<P, T>(a.psi, i, v);
+  if (first) {
+    store_spinor<P, T>(vv.psi, i, v);
   } else {
-    load_spinor<P, T>(a.psi, i, tmp);
+    load_spinor<P, T>(vv.psi, i, tmp);
 #pragma unroll
     for (int x = 0; x < 4; x++)
 #pragma unroll
       for (int c = 0; c < 3; c++) tmp[x][c] = tmp[x][c] + v[x][c];
-    store_spinor<P, T>(a.psi, i, tmp);
+    store_spinor<P, T>(vv.psi, i, tmp);
   }
   if (odd) {
 #pragma unroll
@@ -271,8 +271,33 @@ sap_block_kernel(SapArgs<P> a) {
 #pragma unroll
       for (int c = 0; c < 3; c++) s[x][c] = {0, 0};
   }
-  store_spinor<P, T>(a.r, i, s);
-  store_spinor<P, T>(a.v, i, v);
+  store_spinor<P, T>(vv.r, i, s);
+  store_spinor<P, T>(vv.v, i, v);
+}
+
+template <int P>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
+sap_block_kernel(SapArgs<P> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  SapOp<P> op{a.links, a.angles, a.qhat, a.pauli, a.pinv};
+  SapVecs<P> vv{a.rho, a.r, a.psi, a.v};
+  sap_block_body<P>(a.g, op, vv, a.blocks[xcd_order(blockIdx.x, gridDim.x)], a.first, a.skip_face,
+                    a.nmr, smem);
+}
+
+// Batched: work-group L (in XCD-aware order) solves block L / nact of the
+// colour for right-hand side slot act[L % nact]; the blocks of the batch that
+// share a lattice block run next to each other, so their links and Pauli
+// terms are read through the same L2.
+template <int P>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
+sap_batch_kernel(Geom g, const int *blocks, const SapSlot<P> *slots, const int *act, int nact,
+                 int first, int skip_face, int nmr) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int L = xcd_order(blockIdx.x, gridDim.x);
+  int bi = L / nact;
+  const SapSlot<P> &sl = slots[act[L - bi * nact]];
+  sap_block_body<P>(g, sl.op, sl.vec, blocks[bi], first, skip_face, nmr, smem);
 }
 
 }  // namespace
@@ -295,6 +320,26 @@ hipError_t launch_sap_colour(const SapArgs<P> &a, int nblocks_colour, hipStream_
   sap_block_kernel<P><<<nblocks_colour, nthreads, lds, st>>>(a);
   return hipGetLastError();
 }
+
+template <int P>
+hipError_t launch_sap_batch(const Geom &g, const int *blocks, int nblocks_colour, const SapSlot<P> *slots,
+                            const int *act, int nact, int first, int skip_face, int nmr, hipStream_t st) {
+  if (nact < 1) return hipSuccess;
+  int nthreads = sap_threads(g);
+  size_t lds = sap_lds_bytes(P, g);
+  sap_batch_kernel<P><<<(unsigned)nblocks_colour * nact, nthreads, lds, st>>>(g, blocks, slots, act, nact,
+                                                                            first, skip_face, nmr);
+  return hipGetLastError();
+}
+
+#define QXD_INST(P)                                                                                  \
+  template hipError_t launch_sap_batch<P>(const Geom &, const int *, int, const SapSlot<P> *, const int *, \
+                                          int, int, int, int, hipStream_t);
+QXD_INST(QXD_F64)
+QXD_INST(QXD_F32)
+QXD_INST(QXD_F16S)
+QXD_INST(QXD_BF16)
+#undef QXD_INST
 
 template hipError_t launch_sap_colour<QXD_F64>(const SapArgs<QXD_F64> &, int, hipStream_t);
 template hipError_t launch_sap_colour<QXD_F32>(const SapArgs<QXD_F32> &, int, hipStream_t);

@@ -1,8 +1,328 @@
-// placeholder, replaced by the serving scheduler
+// Serving: continuous batching of solve requests (qxd_serve_*).
+//
+// A scheduler thread admits queued requests in arrival order when the device
+// memory their right-hand sides need fits the budget; admitted right-hand
+// sides join the batch of their group -- same gauge field, inner precision and
+// solver parameters -- at the next step boundary.  Each group has a worker
+// thread with its own HIP stream, so groups (for example lattices of
+// different sizes) overlap on the device.  A worker repeatedly advances all
+// its right-hand sides by one inner iteration (BatchSolver::step) and hands
+// finished ones back; a finished right-hand side frees its slot at once.
+// Gauge fields stay resident: requests refer to fields uploaded beforehand.
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <tuple>
+#include <vector>
+
+#include "batch_solver.h"
 #include "host.h"
-extern "C" {
-qxd_status qxd_serve_start(qxd_ctx *, size_t, int) { qxd::set_error("serving not built"); return QXD_EINVAL; }
-qxd_status qxd_serve_submit(qxd_ctx *, const qxd_request *, uint64_t *) { qxd::set_error("serving not built"); return QXD_EINVAL; }
-qxd_status qxd_serve_poll(qxd_ctx *, uint64_t, qxd_result *) { qxd::set_error("serving not built"); return QXD_EINVAL; }
-qxd_status qxd_serve_stop(qxd_ctx *) { return QXD_OK; }
+#include "solver.h"
+
+using namespace qxd;
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
+
+struct Req {
+  uint64_t ticket;
+  qxd_request r;
+  double t_submit = 0, t_admit = 0;
+  int remaining = 0;
+  int status = QXD_OK;
+  int max_iters = 0;
+  double max_res = 0;
+  size_t bytes = 0;
+};
+
+struct Rhs {  // one right-hand side handed to a worker
+  Req *req;
+  int idx;
+};
+
+using GroupKey = std::tuple<qxd_field *, int, int, int, int, double, double, int, int>;
+
+GroupKey key_of(const qxd_request &r) {
+  const qxd_solver &s = r.solver;
+  return GroupKey(r.field, s.inner_prec, s.nkv, s.ncy, s.nmr, s.tol, s.inner_tol, s.maxiter, s.max_outer);
+}
+
+}  // namespace
+
+struct Worker;
+
+struct qxd_serve {
+  qxd_ctx *ctx = nullptr;
+  size_t budget = 0;
+  int max_active = 0;
+  std::mutex mu;
+  std::condition_variable cv;
+  bool stopping = false;
+  uint64_t next_ticket = 1;
+  std::deque<Req *> queue;
+  std::map<uint64_t, std::unique_ptr<Req>> reqs;
+  std::map<uint64_t, qxd_result> results;
+  std::map<GroupKey, std::unique_ptr<Worker>> workers;
+  size_t used = 0;
+  int active_rhs = 0;
+  std::thread sched;
+  std::string error;
+};
+
+struct Worker {
+  qxd_serve *sv;
+  qxd_request proto;
+  hipStream_t st = nullptr;
+  std::unique_ptr<BatchSolver> bs;
+  std::deque<Rhs> inbox;  // guarded by sv->mu
+  std::thread th;
+  bool quit = false;      // guarded by sv->mu
+
+  void run() {
+    (void)hipSetDevice(sv->ctx->device);
+    for (;;) {
+      std::vector<Rhs> take;
+      {
+        std::unique_lock<std::mutex> lk(sv->mu);
+        sv->cv.wait_for(lk, std::chrono::milliseconds(20),
+                        [&] { return quit || !inbox.empty() || (bs && bs->active() > 0); });
+        if (quit && inbox.empty() && (!bs || bs->active() == 0)) return;
+        while (!inbox.empty()) {
+          take.push_back(inbox.front());
+          inbox.pop_front();
+        }
+      }
+      if (!bs) continue;
+      std::vector<Finished> fin;
+      {
+        qxd_field *f = proto.field;
+        std::lock_guard<std::recursive_mutex> flk(f->mu);
+        // every admitted right-hand side gets a slot (the scheduler has
+        // already charged its memory to the budget)
+        if (!take.empty() && bs->free_slots() < (int)take.size()) {
+          qxd_status s = bs->reserve(bs->active() + (int)take.size());
+          if (s != QXD_OK) {
+            for (auto &x : take) {
+              Finished e;
+              e.slot = -1;
+              e.tag = x.req;
+              e.info = qxd_solve_info{s, 0, 0, 0.0, 0.0};
+              fin.push_back(e);
+            }
+            take.clear();
+          }
+        }
+        for (auto &x : take) {
+          qxd_status s = bs->add(x.req->r.quark, x.req->r.eta_dev + (int64_t)x.idx * 24 * f->g.V,
+                                 x.req->r.psi_dev + (int64_t)x.idx * 24 * f->g.V, false, x.req);
+          if (s != QXD_OK) {
+            Finished e;
+            e.slot = -1;
+            e.tag = x.req;
+            e.info = qxd_solve_info{s, 0, 0, 0.0, 0.0};
+            fin.push_back(e);
+          }
+        }
+        if (bs->active() > 0) {
+          qxd_status s = bs->step();
+          if (s != QXD_OK) {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            sv->error = qxd_last_error();
+          }
+        }
+        for (auto &x : bs->take_finished()) fin.push_back(x);
+      }
+      if (!fin.empty()) {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        for (auto &x : fin) {
+          Req *q = (Req *)x.tag;
+          if (x.info.status != QXD_OK && q->status == QXD_OK) q->status = x.info.status;
+          if (x.info.inner_iters > q->max_iters) q->max_iters = x.info.inner_iters;
+          if (x.info.true_resid > q->max_res) q->max_res = x.info.true_resid;
+          sv->active_rhs--;
+          if (--q->remaining == 0) {
+            qxd_result res;
+            res.status = q->status;
+            res.nrhs = q->r.nrhs;
+            res.latency_s = now_s() - q->t_submit;
+            res.queue_s = q->t_admit - q->t_submit;
+            res.inner_iters = q->max_iters;
+            res.true_resid = q->max_res;
+            sv->results[q->ticket] = res;
+            sv->used -= q->bytes;
+          }
+        }
+        sv->cv.notify_all();
+      }
+    }
+  }
+};
+
+static void scheduler(qxd_serve *sv) {
+  (void)hipSetDevice(sv->ctx->device);
+  std::unique_lock<std::mutex> lk(sv->mu);
+  for (;;) {
+    // admit in arrival order while the footprint fits
+    while (!sv->queue.empty()) {
+      Req *q = sv->queue.front();
+      qxd_field *f = q->r.field;
+      size_t need = (size_t)q->r.nrhs * BatchSolver::slot_bytes(f, q->r.solver.inner_prec, q->r.solver);
+      bool fits = sv->used + need <= sv->budget || sv->used == 0;
+      bool room = sv->max_active <= 0 || sv->active_rhs + q->r.nrhs <= sv->max_active || sv->active_rhs == 0;
+      if (!fits || !room) break;
+      sv->queue.pop_front();
+      GroupKey key = key_of(q->r);
+      auto &w = sv->workers[key];
+      if (!w) {
+        w.reset(new Worker());
+        w->sv = sv;
+        w->proto = q->r;
+        lk.unlock();
+        hipStream_t st = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        std::unique_ptr<BatchSolver> bs(new BatchSolver(f, q->r.solver.inner_prec, q->r.solver, st));
+        lk.lock();
+        if (e != hipSuccess) {
+          sv->error = "hipStreamCreate failed";
+        }
+        w->st = st;
+        w->bs = std::move(bs);
+        w->th = std::thread([wp = w.get()] { wp->run(); });
+      }
+      q->t_admit = now_s();
+      q->remaining = q->r.nrhs;
+      q->bytes = need;
+      sv->used += need;
+      sv->active_rhs += q->r.nrhs;
+      for (int i = 0; i < q->r.nrhs; i++) w->inbox.push_back(Rhs{q, i});
+      sv->cv.notify_all();
+    }
+    if (sv->stopping && sv->queue.empty()) break;
+    sv->cv.wait_for(lk, std::chrono::milliseconds(20));
+  }
+  for (auto &kv : sv->workers) kv.second->quit = true;
+  sv->cv.notify_all();
+  std::vector<Worker *> ws;
+  for (auto &kv : sv->workers) ws.push_back(kv.second.get());
+  lk.unlock();
+  for (auto *w : ws)
+    if (w->th.joinable()) w->th.join();
+  for (auto *w : ws) {
+    w->bs.reset();
+    if (w->st) (void)hipStreamDestroy(w->st);
+  }
+}
+
+static bool valid_request(const qxd_request *r) {
+  if (!r || !r->field || !r->eta_dev || !r->psi_dev || r->nrhs < 1) return false;
+  const qxd_solver &s = r->solver;
+  return s.kind == QXD_SOLVER_SAP_GCR && s.tol > 0 && s.tol < 1 && s.inner_prec >= QXD_F64 &&
+         s.inner_prec <= QXD_BF16 && s.nkv >= 0 && s.nkv <= 64 && s.ncy >= 0 && s.nmr >= 0 &&
+         s.inner_tol >= 0 && s.inner_tol < 1;
+}
+
+extern "C" {
+
+qxd_status qxd_serve_start(qxd_ctx *ctx, size_t budget_bytes, int max_active) {
+  if (!ctx) {
+    set_error("ctx is NULL");
+    return QXD_EINVAL;
+  }
+  if (ctx->serve) {
+    set_error("serving already started on this context");
+    return QXD_EINVAL;
+  }
+  QXD_HIP_CHECK(hipSetDevice(ctx->device));
+  if (budget_bytes == 0) {
+    size_t fr = 0, tot = 0;
+    QXD_HIP_CHECK(hipMemGetInfo(&fr, &tot));
+    budget_bytes = (size_t)(0.8 * fr);
+  }
+  qxd_serve *sv = new qxd_serve();
+  sv->ctx = ctx;
+  sv->budget = budget_bytes;
+  sv->max_active = max_active;
+  ctx->serve = sv;
+  sv->sched = std::thread(scheduler, sv);
+  return QXD_OK;
+}
+
+qxd_status qxd_serve_submit(qxd_ctx *ctx, const qxd_request *req, uint64_t *ticket) {
+  if (!ctx || !ctx->serve || !ticket) {
+    set_error("serving not started or ticket is NULL");
+    return QXD_EINVAL;
+  }
+  if (!valid_request(req)) {
+    set_error("invalid request (SAP_GCR solver, nrhs >= 1, device buffers and a field are required)");
+    return QXD_EINVAL;
+  }
+  if (req->field->ctx != ctx) {
+    set_error("the request's field belongs to another context");
+    return QXD_EINVAL;
+  }
+  {
+    qxd_status s = check_sap_blocks(req->field);
+    if (s != QXD_OK) return s;
+  }
+  qxd_serve *sv = ctx->serve;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (sv->stopping) {
+    set_error("serving is stopping");
+    return QXD_EINVAL;
+  }
+  std::unique_ptr<Req> q(new Req());
+  q->ticket = sv->next_ticket++;
+  q->r = *req;
+  q->t_submit = now_s();
+  *ticket = q->ticket;
+  sv->queue.push_back(q.get());
+  sv->reqs[q->ticket] = std::move(q);
+  sv->cv.notify_all();
+  return QXD_OK;
+}
+
+qxd_status qxd_serve_poll(qxd_ctx *ctx, uint64_t ticket, qxd_result *out) {
+  if (!ctx || !ctx->serve || !out) {
+    set_error("serving not started or out is NULL");
+    return QXD_EINVAL;
+  }
+  qxd_serve *sv = ctx->serve;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  auto it = sv->results.find(ticket);
+  if (it == sv->results.end()) {
+    if (sv->reqs.count(ticket)) return QXD_EBUSY;
+    set_error("unknown ticket %llu", (unsigned long long)ticket);
+    return QXD_ENOTFOUND;
+  }
+  *out = it->second;
+  sv->results.erase(it);
+  sv->reqs.erase(ticket);
+  return QXD_OK;
+}
+
+qxd_status qxd_serve_stop(qxd_ctx *ctx) {
+  if (!ctx) {
+    set_error("ctx is NULL");
+    return QXD_EINVAL;
+  }
+  qxd_serve *sv = ctx->serve;
+  if (!sv) return QXD_OK;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stopping = true;
+    sv->cv.notify_all();
+  }
+  if (sv->sched.joinable()) sv->sched.join();
+  ctx->serve = nullptr;
+  delete sv;
+  return QXD_OK;
+}
+
+}  // extern "C"

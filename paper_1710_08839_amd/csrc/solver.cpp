@@ -17,6 +17,9 @@
 #include <chrono>
 #include <vector>
 
+#include <algorithm>
+
+#include "batch_solver.h"
 #include "blas.h"
 #include "sap.h"
 #include "solver.h"
@@ -205,7 +208,9 @@ qxd_status eo_gcr(Field *f, const Operator &op, const qxd_solver &s, void *eta, 
 // ---------------------------------------------------------------------------
 // SAP preconditioner
 // ---------------------------------------------------------------------------
-qxd_status colour_lists(Field *f, const int **lists, int *per_colour) {
+}  // namespace
+
+qxd_status sap_block_lists(Field *f, const int **lists, int *per_colour) {
   const Geom &g = f->g;
   hipError_t e;
   int *d = (int *)f->workspace("sap_blocks", sizeof(int) * g.nblocks, &e);
@@ -231,13 +236,15 @@ qxd_status colour_lists(Field *f, const int **lists, int *per_colour) {
   return QXD_OK;
 }
 
+namespace {
+
 template <int P>
 qxd_status sap_apply_t(Field *f, const Operator &op, int ncy, int nmr, void *rho, void *psi, hipStream_t st) {
   const Geom &g = f->g;
   CS(check_sap_blocks(f));
   const int *lists[2];
   int nper;
-  CS(colour_lists(f, lists, &nper));
+  CS(sap_block_lists(f, lists, &nper));
   Ws w{f, st};
   size_t fb = spinor_bytes(P, g.V);
   void *r = w.get("sap_r", fb), *v = w.get("sap_v", fb);
@@ -263,186 +270,6 @@ qxd_status sap_apply_t(Field *f, const Operator &op, int ncy, int nmr, void *rho
       CK(launch_sap_colour<P>(a, nper, st));
     }
   return QXD_OK;
-}
-
-// ---------------------------------------------------------------------------
-// flexible GCR (inner solver, precision P) with SAP; solves D delta = b
-// approximately to |b - D delta| <= tol |b|.
-// ---------------------------------------------------------------------------
-template <int P>
-qxd_status fgcr(Field *f, const Operator &op, const qxd_solver &s, void *b, void *delta, double tol,
-                int *iters_out, double *res_out, hipStream_t st) {
-  const Geom &g = f->g;
-  const int nkv = s.nkv > 0 ? s.nkv : 16;
-  if (nkv > MAXV) {
-    set_error("nkv must be <= %d", MAXV);
-    return QXD_EINVAL;
-  }
-  Ws w{f, st};
-  size_t fb = spinor_bytes(P, g.V);
-  char *phv = (char *)w.get("fgcr_phi", fb * nkv);
-  char *chv = (char *)w.get("fgcr_chi", fb * nkv);
-  void *rho = w.get("fgcr_rho", fb);
-  double *partial = (double *)w.get("partial", blas_partial_doubles() * 8);
-  double *scal = (double *)w.get("fgcr_scal", (size_t)(2 * MAXV * MAXV + 3 * MAXV + 2 * MAXV + 16) * 8);
-  if (w.err) return w.err;
-  double *amat = scal;                    // a_lk at amat[2*(k*MAXV + l)]
-  double *rec = amat + 2 * MAXV * MAXV;   // per k: |chi_k|^2, (chi_k, rho)
-  double *coef = rec + 3 * MAXV;          // back-substitution coefficients
-  double *rn2 = coef + 2 * MAXV;
-  auto F = [&](void *p) { return SpinorArg{p, g.V, 0}; };
-  std::vector<SpinorArg> phi(nkv), chi(nkv);
-  for (int k = 0; k < nkv; k++) {
-    phi[k] = F(phv + k * fb);
-    chi[k] = F(chv + k * fb);
-  }
-  CK(blas_axpby<P, P>(F(rho), 0.0, F(b), 1.0, 0, g.V, partial, rn2, st));
-  double b2;
-  CS(fetch(&b2, rn2, 1, st));
-  const double bn = sqrt(b2);
-  CK(hipMemsetAsync(delta, 0, fb, st));
-  double r2 = b2;
-  int it = 0;
-  const int maxiter = s.maxiter > 0 ? s.maxiter : 1000;
-  const int ncy = s.ncy > 0 ? s.ncy : 5, nmr = s.nmr > 0 ? s.nmr : 4;
-  OpFields of = f->op_fields(op, P);
-  while (sqrt(r2) > tol * bn && it < maxiter) {
-    int kused = 0;
-    for (int k = 0; k < nkv && it < maxiter; k++) {
-      CS(sap_apply_t<P>(f, op, ncy, nmr, rho, phi[k].ptr, st));
-      CK(launch_dirac(P, DK_FULL, g, of, phi[k], phi[k], chi[k], -0.5, st));
-      double *ak = amat + 2 * k * MAXV;
-      if (k > 0) CK(blas_mdot<P>(chi.data(), k, chi[k], 0, g.V, partial, ak, rec, 3, st));
-      MaxpyHost m;
-      m.n = k;
-      m.src[0] = chi[k];
-      m.dst[0] = chi[k];
-      m.ys[0] = chi.data();
-      m.coef = ak;
-      m.w = F(rho);
-      CK(blas_maxpy<P>(m, 0, g.V, partial, rec + 3 * k, st));
-      CK(blas_update<P>(F(rho), chi[k], rec + 3 * k + 1, rec + 3 * k, 0, 0, g.V, partial, rn2, st));
-      CS(fetch(&r2, rn2, 1, st));
-      it++;
-      kused = k + 1;
-      if (!isfinite(r2)) {
-        set_error("FGCR residual is NaN/Inf");
-        return QXD_EFLOAT;
-      }
-      if (sqrt(r2) <= tol * bn) break;
-    }
-    // back-substitution: R beta = c with R_lk = a_lk (l < k), R_kk = 1,
-    // c_k = (chi_k, rho_k) / |chi_k|^2; then delta += sum beta_k phi_k
-    std::vector<double> hv(2 * MAXV * MAXV + 3 * MAXV);
-    CS(fetch(hv.data(), amat, (int)hv.size(), st));
-    std::vector<double> br(kused), bi(kused);
-    for (int k = kused - 1; k >= 0; k--) {
-      double n = hv[2 * MAXV * MAXV + 3 * k];
-      double cr = hv[2 * MAXV * MAXV + 3 * k + 1] / n, ci = hv[2 * MAXV * MAXV + 3 * k + 2] / n;
-      for (int j = k + 1; j < kused; j++) {
-        double ar = hv[2 * (j * MAXV + k)], ai = hv[2 * (j * MAXV + k) + 1];
-        cr -= ar * br[j] - ai * bi[j];
-        ci -= ar * bi[j] + ai * br[j];
-      }
-      br[k] = cr;
-      bi[k] = ci;
-    }
-    std::vector<double> hc(2 * kused);
-    for (int k = 0; k < kused; k++) {
-      hc[2 * k] = -br[k];
-      hc[2 * k + 1] = -bi[k];
-    }
-    CK(hipMemcpyAsync(coef, hc.data(), hc.size() * 8, hipMemcpyHostToDevice, st));
-    MaxpyHost m;
-    m.n = kused;
-    m.src[0] = F(delta);
-    m.dst[0] = F(delta);
-    m.ys[0] = phi.data();
-    m.coef = coef;
-    CK(blas_maxpy<P>(m, 0, g.V, partial, nullptr, st));
-    CK(hipStreamSynchronize(st));  // hc must stay alive until the copy is done
-    if (sqrt(r2) > tol * bn && it < maxiter) {
-      // restart from the true residual rho = b - D delta
-      CK(launch_dirac(P, DK_FULL, g, of, F(delta), F(delta), chi[0], -0.5, st));
-      CK(blas_axpby<P, P>(F(rho), 0.0, F(b), 1.0, 0, g.V, partial, nullptr, st));
-      CK(blas_axpby<P, P>(F(rho), 1.0, chi[0], -1.0, 0, g.V, partial, rn2, st));
-      CS(fetch(&r2, rn2, 1, st));
-    }
-  }
-  *iters_out = it;
-  *res_out = sqrt(r2) / bn;
-  return QXD_OK;
-}
-
-template <int P>
-qxd_status sap_gcr(Field *f, const Operator &op64, const qxd_quark &q, const qxd_solver &s, void *eta,
-                   void *psi, bool guess, qxd_solve_info *info, hipStream_t st) {
-  const Geom &g = f->g;
-  Operator *op;
-  CS(f->get_op(q, P, &op, st));
-  Ws w{f, st};
-  size_t fb64 = spinor_bytes(QXD_F64, g.V), fb = spinor_bytes(P, g.V);
-  void *r = w.get("dc_r", fb64), *tmp = w.get("dc_tmp", fb64);
-  void *bin = w.get("dc_b", fb), *delta = w.get("dc_delta", fb);
-  double *partial = (double *)w.get("partial", blas_partial_doubles() * 8);
-  double *misc = (double *)w.get("dc_misc", 64);
-  if (w.err) return w.err;
-  auto F64v = [&](void *p) { return SpinorArg{p, g.V, 0}; };
-  OpFields of64 = f->op_fields(op64, QXD_F64);
-  CK(blas_norm2<QXD_F64>(F64v(eta), 0, g.V, partial, misc, st));
-  double eta2;
-  CS(fetch(&eta2, misc, 1, st));
-  if (!isfinite(eta2)) {
-    set_error("source contains NaN/Inf");
-    return QXD_EFLOAT;
-  }
-  if (eta2 == 0.0) {
-    CK(hipMemsetAsync(psi, 0, fb64, st));
-    if (info) info->true_resid = 0.0;
-    return QXD_OK;
-  }
-  const double eta_n = sqrt(eta2);
-  double r2;
-  if (guess) {
-    CK(launch_dirac(QXD_F64, DK_FULL, g, of64, F64v(psi), F64v(psi), F64v(tmp), -0.5, st));
-    CK(blas_axpby<QXD_F64, QXD_F64>(F64v(r), 0.0, F64v(eta), 1.0, 0, g.V, partial, nullptr, st));
-    CK(blas_axpby<QXD_F64, QXD_F64>(F64v(r), 1.0, F64v(tmp), -1.0, 0, g.V, partial, misc, st));
-  } else {
-    CK(hipMemsetAsync(psi, 0, fb64, st));
-    CK(blas_axpby<QXD_F64, QXD_F64>(F64v(r), 0.0, F64v(eta), 1.0, 0, g.V, partial, misc, st));
-  }
-  CS(fetch(&r2, misc, 1, st));
-  int outer = 0, inner = 0;
-  const int max_outer = s.max_outer > 0 ? s.max_outer : 50;
-  double inner_tol = s.inner_tol > 0 ? s.inner_tol : (P == QXD_F64 ? 1e-6 : (P == QXD_F32 ? 1e-5 : 1e-2));
-  while (sqrt(r2) > s.tol * eta_n && outer < max_outer) {
-    double sn = sqrt(r2);
-    // b = r / |r| in the inner precision
-    CK(blas_axpby<P, QXD_F64>(SpinorArg{bin, g.V, 0}, 0.0, F64v(r), 1.0 / sn, 0, g.V, partial, nullptr, st));
-    int it;
-    double res;
-    CS(fgcr<P>(f, *op, s, bin, delta, inner_tol, &it, &res, st));
-    inner += it;
-    // x += |r| delta; r = eta - D x (FP64)
-    CK(blas_axpby<QXD_F64, P>(F64v(psi), 1.0, SpinorArg{delta, g.V, 0}, sn, 0, g.V, partial, nullptr, st));
-    CK(launch_dirac(QXD_F64, DK_FULL, g, of64, F64v(psi), F64v(psi), F64v(tmp), -0.5, st));
-    CK(blas_axpby<QXD_F64, QXD_F64>(F64v(r), 0.0, F64v(eta), 1.0, 0, g.V, partial, nullptr, st));
-    CK(blas_axpby<QXD_F64, QXD_F64>(F64v(r), 1.0, F64v(tmp), -1.0, 0, g.V, partial, misc, st));
-    CS(fetch(&r2, misc, 1, st));
-    outer++;
-    if (!isfinite(r2)) {
-      set_error("defect-correction residual is NaN/Inf");
-      return QXD_EFLOAT;
-    }
-    if ((s.maxiter > 0 && inner >= s.maxiter)) break;
-  }
-  double true_res = sqrt(r2) / eta_n;
-  if (info) {
-    info->outer_iters = outer;
-    info->inner_iters = inner;
-    info->true_resid = true_res;
-  }
-  return true_res <= s.tol ? QXD_OK : QXD_ENOCONV;
 }
 
 }  // namespace
@@ -485,14 +312,47 @@ qxd_status solve(Field *f, const qxd_quark *quarks, int nquark, const qxd_solver
     set_error("invalid solver parameters");
     return QXD_EINVAL;
   }
-  if (s.kind == QXD_SOLVER_SAP_GCR) CS(check_sap_blocks(f));
   const Geom &g = f->g;
+  int per = nrhs / nquark;
+  qxd_status worst = QXD_OK;
+  if (s.kind == QXD_SOLVER_SAP_GCR) {
+    CS(check_sap_blocks(f));
+    if (2 * g.Vbh > 256) {
+      set_error("the batched SAP-GCR needs blocks of at most 128 sites");
+      return QXD_EINVAL;
+    }
+    // every right-hand side gets a slot of the batch while device memory
+    // allows; the others join as slots free up (continuous batching)
+    size_t freeb = 0, totalb = 0;
+    CK(hipMemGetInfo(&freeb, &totalb));
+    size_t per_slot = BatchSolver::slot_bytes(f, s.inner_prec, s);
+    int cap = (int)std::min<size_t>((size_t)nrhs, std::max<size_t>(1, (size_t)(0.8 * freeb) / per_slot));
+    BatchSolver bs(f, s.inner_prec, s, st);
+    CS(bs.reserve(cap));
+    int next = 0, finished = 0;
+    while (finished < nrhs) {
+      while (next < nrhs && bs.free_slots() > 0) {
+        const qxd_quark &q = quarks[next / per];
+        CS(bs.add(q, eta_dev + (int64_t)next * 24 * g.V, psi_dev + (int64_t)next * 24 * g.V, use_guess,
+                  (void *)(intptr_t)next));
+        next++;
+      }
+      CS(bs.step());
+      for (auto &fin : bs.take_finished()) {
+        int r = (int)(intptr_t)fin.tag;
+        if (info) info[r] = fin.info;
+        if (fin.info.status != QXD_OK) {
+          if (fin.info.status == QXD_EFLOAT || worst == QXD_OK) worst = (qxd_status)fin.info.status;
+        }
+        finished++;
+      }
+    }
+    return worst;
+  }
   Ws w{f, st};
   size_t fb = spinor_bytes(QXD_F64, g.V);
   void *eta = w.get("solve_eta", fb), *psi = w.get("solve_psi", fb);
   if (w.err) return w.err;
-  qxd_status worst = QXD_OK;
-  int per = nrhs / nquark;
   for (int r = 0; r < nrhs; r++) {
     double t0 = now_s();
     const qxd_quark &q = quarks[r / per];
@@ -503,24 +363,14 @@ qxd_status solve(Field *f, const qxd_quark *quarks, int nquark, const qxd_solver
     CK(launch_pack(QXD_F64, g, src, eta, 1, st));
     if (use_guess) CK(launch_pack(QXD_F64, g, dst, psi, 1, st));
     qxd_solve_info inf{};
-    qxd_status rs;
-    if (s.kind == QXD_SOLVER_EO_GCR) {
-      rs = eo_gcr(f, *op, s, eta, psi, use_guess, &inf, st);
-    } else {
-      switch (s.inner_prec) {
-        case QXD_F64: rs = sap_gcr<QXD_F64>(f, *op, q, s, eta, psi, use_guess, &inf, st); break;
-        case QXD_F32: rs = sap_gcr<QXD_F32>(f, *op, q, s, eta, psi, use_guess, &inf, st); break;
-        case QXD_F16S: rs = sap_gcr<QXD_F16S>(f, *op, q, s, eta, psi, use_guess, &inf, st); break;
-        default: rs = sap_gcr<QXD_BF16>(f, *op, q, s, eta, psi, use_guess, &inf, st); break;
-      }
-    }
-    if (rs != QXD_OK && rs != QXD_ENOCONV) return rs;
+    qxd_status rs = eo_gcr(f, *op, s, eta, psi, use_guess, &inf, st);
+    if (rs != QXD_OK && rs != QXD_ENOCONV && rs != QXD_EFLOAT) return rs;
     CK(launch_unpack(QXD_F64, g, psi, dst, 1, st));
     CK(hipStreamSynchronize(st));
     inf.status = rs;
     inf.seconds = now_s() - t0;
     if (info) info[r] = inf;
-    if (rs != QXD_OK) worst = rs;
+    if (rs != QXD_OK && (rs == QXD_EFLOAT || worst == QXD_OK)) worst = rs;
   }
   return worst;
 }

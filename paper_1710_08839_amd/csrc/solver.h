@@ -18,6 +18,9 @@ qxd_status apply_native(Field *fd, const Operator &op, qxd_op which, int prec, v
 qxd_status sap_apply(Field *f, const Operator &op, int prec, int ncy, int nmr, void *rho, void *psi,
                      hipStream_t st);
 
+// Device lists of the block indices of each SAP colour (built on first use).
+qxd_status sap_block_lists(Field *f, const int **lists, int *per_colour);
+
 // Check that the layout blocks admit the two-colour SAP decomposition.
 qxd_status check_sap_blocks(const Field *f);
 
