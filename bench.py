@@ -95,9 +95,12 @@ def cpu_baseline(budget_s=15.0):
                       f"{dt:.1f} s ({dt / n * 1e3:.1f} ms each, {lat.V * n / dt / 1e6:.3f} Msite/s)"}
 
 
-def solve_rates(ctx, nsrc, dims=(48, 24, 24, 24)):
-    """cfg-3 lattice: point sources x 2 charges x 2 kappas, solved to 1e-10 by
-    the plain FP64 even-odd GCR and by the mixed-precision SAP-GCR."""
+def solve_rates(ctx, nsrc, nsrc_fp64, dims=(48, 24, 24, 24)):
+    """48 x 24^3 with C*: nsrc spin-colour point sources at the origin x 2
+    charges x 2 kappas, solved to a true FP64 residual of 1e-10 by the batched
+    mixed-precision SAP-GCR (all right-hand sides in one call) and, one after
+    another, by the plain FP64 even-odd GCR (a sample of nsrc_fp64 sources per
+    operator: its rate is per right-hand side)."""
     import torch
     from paper_1710_08839_amd import qxd, synth
     u, a = synth.gauge_field(dims, 20171003, 0.25, 0.15)
@@ -105,36 +108,129 @@ def solve_rates(ctx, nsrc, dims=(48, 24, 24, 24)):
     del u, a
     ops = [qxd.quark(k, q, 1.9, 1.0) for q in (2 / 3, -1 / 3) for k in (0.1360, 0.1365)]
     V = f.volume
-    srcs = []
-    for s in range(nsrc):
-        srcs.append(synth.point_source(V, 0, s // 3 % 4, s % 3))
-    eta = torch.from_numpy(np.stack(srcs * len(ops))).cuda()
-    nrhs = eta.shape[0]
-    psi = torch.empty_like(eta)
+
+    def sources(n):
+        return [synth.point_source(V, 0, s // 3 % 4, s % 3) for s in range(n)]
+
     out = {}
-    for name, s in [("fp64_eo_gcr", qxd.solver(kind=qxd.EO_GCR, tol=1e-10, nkv=16)),
-                    ("mixed_sap_gcr_f32", qxd.solver(kind=qxd.SAP_GCR, tol=1e-10, nkv=12, ncy=4, nmr=4,
-                                                     inner_prec=qxd.F32)),
-                    ("mixed_sap_gcr_f16s", qxd.solver(kind=qxd.SAP_GCR, tol=1e-10, nkv=12, ncy=4, nmr=4,
-                                                      inner_prec=qxd.F16S))]:
-        # warm-up: builds operators and workspaces
-        f.solve(ops[0], s, eta[:1], psi[:1])
+    legs = [("mixed_sap_gcr_f32", qxd.solver(kind=qxd.SAP_GCR, tol=1e-10, nkv=24, ncy=4, nmr=4,
+                                              inner_prec=qxd.F32), nsrc),
+            ("mixed_sap_gcr_f16s", qxd.solver(kind=qxd.SAP_GCR, tol=1e-10, nkv=24, ncy=4, nmr=4,
+                                               inner_prec=qxd.F16S), nsrc),
+            ("fp64_eo_gcr", qxd.solver(kind=qxd.EO_GCR, tol=1e-10, nkv=64, maxiter=20000), nsrc_fp64)]
+    for name, s, ns in legs:
+        if ns <= 0:
+            continue
+        eta = torch.from_numpy(np.stack(sources(ns) * len(ops))).cuda()
+        nrhs = eta.shape[0]
+        psi = torch.empty_like(eta)
+        # warm-up on a small right-hand side set: builds operators and tunes kernels
+        f.solve(ops[0], qxd.solver(kind=s.kind, tol=1e-4, nkv=s.nkv, ncy=s.ncy, nmr=s.nmr,
+                                   inner_prec=s.inner_prec), eta[:1], psi[:1], check=False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st, info = f.solve(ops, s, eta, psi, nrhs=nrhs, check=False)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         log(f"solve {name}: {nrhs} rhs in {dt:.2f} s, status {st}")
-        out[name] = {"solves_per_s": round(nrhs / dt, 3), "seconds": round(dt, 3), "nrhs": nrhs,
+        out[name] = {"solves_per_s": round(nrhs / dt, 4), "seconds": round(dt, 3), "nrhs": nrhs,
                      "status": st, "max_true_resid": max(i.true_resid for i in info),
-                     "iters": [i.inner_iters for i in info][:len(ops) * nsrc:nsrc],
-                     "outer": [i.outer_iters for i in info][:len(ops) * nsrc:nsrc]}
+                     "inner_iters_per_operator": [i.inner_iters for i in info][::ns],
+                     "outer_iters_per_operator": [i.outer_iters for i in info][::ns]}
+        del eta, psi
     f.release()
-    base = out["fp64_eo_gcr"]["solves_per_s"]
+    base = out.get("fp64_eo_gcr", {}).get("solves_per_s")
     for k in out:
-        out[k]["speedup_vs_fp64"] = round(out[k]["solves_per_s"] / base, 3)
-    out["workload"] = f"{dims[0]}x{dims[1]}^3 C*, {nsrc} point sources x 4 operators (q, kappa)"
+        if base:
+            out[k]["speedup_vs_fp64_eo_gcr"] = round(out[k]["solves_per_s"] / base, 2)
+    out["workload"] = (f"{dims[0]}x{dims[1]}^3 C* (1327104 extended sites), point sources x (q, kappa) in "
+                       f"{{2/3,-1/3}} x {{0.1360,0.1365}}, csw=1.9; batched SAP-GCR: {nsrc} sources x 4 "
+                       f"operators in one call; FP64 even-odd GCR(64): {nsrc_fp64} source(s) x 4 "
+                       f"operators one after another")
     return out
+
+
+SERVE_SIZES = [(8, 8, 8, 8), (32, 16, 16, 16), (48, 24, 24, 24), (64, 32, 32, 32)]
+
+
+def serve_stream(ctx, nreq, max_rhs, rate, inner_prec, seed=4242):
+    """Poisson arrivals of solve requests on resident fields of the four
+    lattice sizes (C*), random charge, kappa ~ U[0.130, 0.1365], Gaussian or
+    point sources, 1..max_rhs right-hand sides; returns latency statistics."""
+    import torch
+    from paper_1710_08839_amd import qxd, synth
+    rng = np.random.default_rng(seed)
+    fields = []
+    for i, d in enumerate(SERVE_SIZES):
+        u, a = synth.gauge_field(d, 20171010 + i, 0.25, 0.15)
+        fields.append(qxd.Field(ctx, d, u, a, cstar=3))
+        del u, a
+    s = qxd.solver(kind=qxd.SAP_GCR, tol=1e-10, nkv=16, ncy=4, nmr=4, inner_prec=inner_prec)
+    reqs = []
+    t = 0.0
+    for j in range(nreq):
+        t += rng.exponential(1.0 / rate)
+        fi = int(rng.integers(len(SERVE_SIZES)))
+        q = float(rng.choice([2 / 3, -1 / 3]))
+        k = float(rng.uniform(0.130, 0.1365))
+        nrhs = int(rng.integers(1, max_rhs + 1))
+        point = bool(rng.integers(2))
+        reqs.append((t, fi, q, k, nrhs, point, 5000 + j))
+    # buffers (sources generated up front, outside the timed stream)
+    bufs = []
+    for (_, fi, q, k, nrhs, point, sd) in reqs:
+        V = fields[fi].volume
+        r = synth.rng_from_seed(sd)
+        if point:
+            eta = np.stack([synth.point_source(V, int(r.integers(V)), int(r.integers(4)), int(r.integers(3)))
+                            for _ in range(nrhs)])
+        else:
+            eta = np.stack([synth.gaussian_source(r, V) for _ in range(nrhs)])
+        e = torch.from_numpy(eta).cuda()
+        bufs.append((e, torch.empty_like(e)))
+    torch.cuda.synchronize()
+    # warm the operators of every request (Pauli terms are built per quark)
+    for (_, fi, q, k, nrhs, point, sd), (e, p) in zip(reqs, bufs):
+        fields[fi].apply(qxd.quark(k, q, 1.9, 1.0), qxd.OP_D, inner_prec, e[:1], p[:1])
+        fields[fi].apply(qxd.quark(k, q, 1.9, 1.0), qxd.OP_D, qxd.F64, e[:1], p[:1])
+    torch.cuda.synchronize()
+    ctx.serve_start()
+    tickets = {}
+    results = {}
+    t0 = time.perf_counter()
+    j = 0
+    try:
+        while len(results) < len(reqs):
+            now = time.perf_counter() - t0
+            while j < len(reqs) and reqs[j][0] <= now:
+                (_, fi, q, k, nrhs, point, sd) = reqs[j]
+                e, p = bufs[j]
+                tickets[ctx.serve_submit(fields[fi], qxd.quark(k, q, 1.9, 1.0), s, e, p, nrhs)] = j
+                j += 1
+            for tk in list(tickets):
+                if tickets[tk] not in results:
+                    r = ctx.serve_poll(tk)
+                    if r is not None:
+                        results[tickets[tk]] = (r, time.perf_counter() - t0)
+            if time.perf_counter() - t0 > 600:
+                break
+            time.sleep(0.002)
+    finally:
+        ctx.serve_stop()
+    wall = time.perf_counter() - t0
+    for f in fields:
+        f.release()
+    lat = np.array([results[i][0].latency_s for i in sorted(results)])
+    status = [results[i][0].status for i in sorted(results)]
+    nrhs_done = sum(reqs[i][4] for i in results)
+    return {"requests": len(reqs), "completed": len(results), "all_ok": all(x == 0 for x in status),
+            "p50_s": round(float(np.percentile(lat, 50)), 3), "p99_s": round(float(np.percentile(lat, 99)), 3),
+            "mean_s": round(float(lat.mean()), 3), "wall_s": round(wall, 2),
+            "requests_per_s": round(len(results) / wall, 3), "rhs_per_s": round(nrhs_done / wall, 3),
+            "max_true_resid": max(results[i][0].true_resid for i in results),
+            "stream": f"{nreq} Poisson requests at {rate}/s over lattices "
+                      f"{[f'{d[0]}x{d[1]}^3' for d in SERVE_SIZES]} (C*), 1-{max_rhs} RHS each, "
+                      f"q in {{2/3,-1/3}}, kappa~U[0.130,0.1365], csw=1.9, Gaussian or point sources"}
 
 
 def main():
@@ -144,7 +240,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--nsrc", type=int, default=3, help="point sources per operator in the solve leg")
+    ap.add_argument("--nsrc", type=int, default=12, help="point sources per operator, batched solve leg")
+    ap.add_argument("--nsrc-fp64", type=int, default=1, help="point sources per operator, FP64 baseline")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=12)
+    ap.add_argument("--serve-max-rhs", type=int, default=3)
+    ap.add_argument("--serve-rate", type=float, default=2.0, help="request arrivals per second")
     ap.add_argument("--precs", default="0,1,2,3")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (profiler counter calibration)")
@@ -200,7 +301,15 @@ def main():
 
     solves = None
     if not args.no_solve:
-        solves = solve_rates(ctx, args.nsrc)
+        solves = solve_rates(ctx, args.nsrc, args.nsrc_fp64)
+
+    serve = None
+    if not args.no_serve:
+        serve = {}
+        for name, prec in (("mixed_f32_inner", qxd.F32), ("fp64_inner", qxd.F64)):
+            log(f"serving stream, {name}")
+            serve[name] = serve_stream(ctx, args.serve_requests, args.serve_max_rhs, args.serve_rate, prec)
+            log(f"serving {name}: p50 {serve[name]['p50_s']} s, p99 {serve[name]['p99_s']} s")
 
     log("timing the oracle on the host")
     cpu = None if args.no_cpu else cpu_baseline()
@@ -229,6 +338,7 @@ def main():
                      "bytes_per_launch": BYTES_PER_SITE[0] * V},
         "dw": dw,
         "solves": solves,
+        "serve": serve,
         "cpu_baseline": cpu,
         "setup_s": round(setup_s, 1),
     }
