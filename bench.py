@@ -33,6 +33,21 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_SITE = {0: 48 * 8 + 72 * 8 + 72 * 8, 1: 48 * 4 + 72 * 4 + 72 * 4,
                   2: 48 * 2 + 8 + 72 * 2 + 72 * 2, 3: 48 * 2 + 72 * 2 + 72 * 2}
 FLOPS_PER_SITE = 1320 + 552 + 48   # hops + two 6x6 Hermitian blocks + combine
+
+# HBM bytes per FP64 launch from the calibrated FETCH_SIZE + WRITE_SIZE
+# counters (profiles/dirac_64x32c_hbm_counters.md), valid only for the kernel
+# sources they were taken on (hash of the files below).
+KERNEL_FILES = ["dirac.hip", "dirac_site.h", "qxd_impl.h"]
+TRAFFIC = {"50eb4c9d256d9280": 9.801e9}
+
+
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_FILES:
+        with open(os.path.join(ROOT, "paper_1710_08839_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 PREC_NAME = {0: "f64", 1: "f32", 2: "f16s", 3: "bf16"}
 _T0 = time.perf_counter()
 
@@ -333,7 +348,7 @@ def main():
                                "q=-1/3, kappa=0.1365, csw=1.9, eps=0.25, A~N(0,0.15)",
                    "global_batch": 1, "seq_len": V, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(value, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(value / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(value / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get(kernel_hash()),
                      "kernel": "dirac_kernel<F64, DK_FULL>",
                      "bytes_per_launch": BYTES_PER_SITE[0] * V},
         "dw": dw,
