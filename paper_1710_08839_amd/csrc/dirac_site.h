@@ -108,8 +108,8 @@ QXD_HD void hop_bwd(int mu, const cx<T> w[3][3], const cx<T> psi[4][3], T sign, 
 #pragma unroll
     for (int c = 0; c < 3; c++) {
       // (W^dag)_{rc} = conj(W_{cr})
-      a = a + cmulc(w[c][r], h0[c]);
-      b = b + cmulc(w[c][r], h1[c]);
+      a = fma_accc(a, w[c][r], h0[c]);
+      b = fma_accc(b, w[c][r], h1[c]);
     }
     g0[r] = sign * a;
     g1[r] = sign * b;
@@ -152,7 +152,7 @@ QXD_HD void herm6_mul(const typename St<P>::pair_t *pa, int64_t stride, int64_t 
       auto z = St<P>::ld(pa + (int64_t)(base + 3 + tri_index(i, k)) * stride, (uint32_t)j);
       cx<T> a{(T)z.re, (T)z.im};
       out[i] = fma_acc(out[i], a, v[k]);
-      out[k] = out[k] + cmulc(a, v[i]);
+      out[k] = fma_accc(out[k], a, v[i]);
     }
 }
 

@@ -54,9 +54,23 @@ template <class T> QXD_HD cx<T> cmulc(cx<T> a, cx<T> b) {
 template <class T> QXD_HD cx<T> times_i(cx<T> a) { return {-a.im, a.re}; }
 template <class T> QXD_HD cx<T> times_mi(cx<T> a) { return {a.im, -a.re}; }
 template <class T> QXD_HD T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+template <class T> QXD_HD T fmat(T a, T b, T c);
+template <> QXD_HD float fmat<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <> QXD_HD double fmat<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// acc + a b, as four fused multiply-adds
 template <class T> QXD_HD cx<T> fma_acc(cx<T> acc, cx<T> a, cx<T> b) {
-  acc.re += a.re * b.re - a.im * b.im;
-  acc.im += a.re * b.im + a.im * b.re;
+  acc.re = fmat(a.re, b.re, acc.re);
+  acc.re = fmat(-a.im, b.im, acc.re);
+  acc.im = fmat(a.re, b.im, acc.im);
+  acc.im = fmat(a.im, b.re, acc.im);
+  return acc;
+}
+// acc + conj(a) b, as four fused multiply-adds
+template <class T> QXD_HD cx<T> fma_accc(cx<T> acc, cx<T> a, cx<T> b) {
+  acc.re = fmat(a.re, b.re, acc.re);
+  acc.re = fmat(a.im, b.im, acc.re);
+  acc.im = fmat(a.re, b.im, acc.im);
+  acc.im = fmat(-a.im, b.re, acc.im);
   return acc;
 }
 
@@ -131,6 +145,40 @@ template <> struct St<QXD_BF16> {
   QXD_HD static float ldr(const real_t *p, int64_t i) { return p[i]; }
   QXD_HD static void str(real_t *p, int64_t i, float v) { p[i] = v; }
 };
+
+// Loads and stores through the global address space.  Pointers that a kernel
+// reads from memory (the per-slot tables of the batched kernels) are generic
+// to the compiler, which then emits flat instructions (they also count against
+// the LDS wait counter); these casts give global ones.  Only for pointers into
+// device memory.
+template <int N> struct RawOf;
+template <> struct RawOf<4> { using type = uint32_t; };
+template <> struct RawOf<8> { using type = uint64_t; };
+template <> struct RawOf<16> { typedef uint32_t type __attribute__((ext_vector_type(4))); };
+
+template <class T>
+__device__ __forceinline__ T gld(const T *p, int64_t i) {
+  using R = typename RawOf<sizeof(T)>::type;
+  R r = ((const __attribute__((address_space(1))) R *)p)[i];
+  return __builtin_bit_cast(T, r);
+}
+template <class T>
+__device__ __forceinline__ void gst(T *p, int64_t i, T v) {
+  using R = typename RawOf<sizeof(T)>::type;
+  ((__attribute__((address_space(1))) R *)p)[i] = __builtin_bit_cast(R, v);
+}
+// pair i of a device array in storage format, as complex
+template <int P>
+__device__ __forceinline__ cx<typename St<P>::comp_t> gld_pair(const typename St<P>::pair_t *p, int64_t i) {
+  typename St<P>::pair_t v = gld(p, i);
+  return St<P>::ld(&v, 0);
+}
+template <int P>
+__device__ __forceinline__ void gst_pair(typename St<P>::pair_t *p, int64_t i, cx<typename St<P>::comp_t> z) {
+  typename St<P>::pair_t v;
+  St<P>::st(&v, 0, z);
+  gst(p, i, v);
+}
 
 inline size_t pair_bytes(int prec) {
   switch (prec) {

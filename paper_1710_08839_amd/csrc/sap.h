@@ -54,4 +54,13 @@ hipError_t launch_sap_batch(const Geom &g, const int *blocks, int nblocks_colour
 template <int P>
 hipError_t launch_sap_colour(const SapArgs<P> &a, int nblocks_colour, hipStream_t st);
 
+// Four-lanes-per-site block solver (sap_quad.hip): reduced precisions, links
+// with the phase folded in, at most 128 sites of each parity per block.
+bool sap_quad_ok(int prec, const Geom &g, int qhat);
+template <int P>
+hipError_t launch_sapq_colour(const SapArgs<P> &a, int nblocks_colour, hipStream_t st);
+template <int P>
+hipError_t launch_sapq_batch(const Geom &g, const int *blocks, int nblocks_colour, const SapSlot<P> *slots,
+                             const int *act, int nact, int first, int skip_face, int nmr, hipStream_t st);
+
 }  // namespace qxd

@@ -1,9 +1,10 @@
 // Schwarz alternating procedure: block solves of one colour (SAP preconditioner
 // of the GCR solver named in the openQ*D paper's abstract and Sec. 2).
 //
-// One work-group per block Lambda of the colour, one thread per (even site,
-// odd site) pair of the block.  On entry the thread pair first applies the
-// face update left over from the other colour's last pass,
+// This file: one work-group per block Lambda of the colour, one thread per
+// site (FP64, and blocks of more than 256 sites); the reduced precisions use
+// the four-lanes-per-site variant in sap_quad.hip.  On entry each site first
+// applies the face update left over from the other colour's last pass,
 //     r(x) -= (D v')(x) = +acc_out(v')(x)/2,
 // where acc_out sums the hops from sites outside Lambda and v' holds the other
 // colour's latest block corrections.  Then the even-odd block problem is
@@ -315,6 +316,9 @@ size_t sap_lds_bytes(int prec, const Geom &g) {
 
 template <int P>
 hipError_t launch_sap_colour(const SapArgs<P> &a, int nblocks_colour, hipStream_t st) {
+  if constexpr (P != QXD_F64) {
+    if (sap_quad_ok(P, a.g, a.qhat)) return launch_sapq_colour<P>(a, nblocks_colour, st);
+  }
   int nthreads = sap_threads(a.g);
   size_t lds = sap_lds_bytes(P, a.g);
   sap_block_kernel<P><<<nblocks_colour, nthreads, lds, st>>>(a);
@@ -325,6 +329,10 @@ template <int P>
 hipError_t launch_sap_batch(const Geom &g, const int *blocks, int nblocks_colour, const SapSlot<P> *slots,
                             const int *act, int nact, int first, int skip_face, int nmr, hipStream_t st) {
   if (nact < 1) return hipSuccess;
+  if constexpr (P != QXD_F64) {
+    if (sap_quad_ok(P, g, 0))
+      return launch_sapq_batch<P>(g, blocks, nblocks_colour, slots, act, nact, first, skip_face, nmr, st);
+  }
   int nthreads = sap_threads(g);
   size_t lds = sap_lds_bytes(P, g);
   sap_batch_kernel<P><<<(unsigned)nblocks_colour * nact, nthreads, lds, st>>>(g, blocks, slots, act, nact,

@@ -54,3 +54,18 @@ def test_native_geometry(harness, dims, cstar, tbc, block):
         assert np.array_equal(bw, lat.bwd[mu])
         assert np.array_equal(fs, lat.sign[mu].astype(int))
         assert np.array_equal(bs, lat.bsign[mu].astype(int))
+
+
+def test_generic_hop_matches_projections(tmp_path):
+    """The direction-generic hop used where lanes of one wavefront hop in
+    different directions equals the per-direction projections (1 -+ g_mu)."""
+    exe = str(tmp_path / "hop_harness")
+    cmd = ["/opt/rocm/bin/hipcc", "-x", "hip", "--offload-host-only", "-O1", "-std=c++17",
+           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROOT, "paper_1710_08839_amd", "csrc"),
+           os.path.join(HERE, "native", "hop_harness.cpp"), "-o", exe]
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    assert p.returncode == 0, p.stderr[-2000:]
+    out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
+    worst, scale = float(out[0]), float(out[1])
+    assert scale > 1.0
+    assert worst < 1e-12 * scale
