@@ -7,7 +7,9 @@
 
 #include <cstring>
 
+#include "../../include/qxd_debug.h"
 #include "host.h"
+#include "launch.h"
 #include "solver.h"
 
 namespace qxd {
@@ -233,6 +235,14 @@ static bool valid_prec(int p) { return p >= QXD_F64 && p <= QXD_BF16; }
 extern "C" {
 
 int qxd_abi_version(void) { return QXD_ABI_VERSION; }
+
+qxd_status qxd_debug_set_dirac_variant(int choice) {
+  if (!force_dirac_variant(choice)) {
+    set_error("invalid Dirac kernel variant %d", choice);
+    return QXD_EINVAL;
+  }
+  return QXD_OK;
+}
 
 const char *qxd_last_error(void) { return g_err; }
 

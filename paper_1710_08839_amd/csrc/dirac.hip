@@ -5,6 +5,7 @@
 // so that D^ psi_e = P_e psi_e + acc(t_o)/2 with t_o = -D_oo^-1 acc(psi_e)/2.
 // One thread per site; every operand is a structure-of-arrays field in native
 // order, so the 64 lanes of a wavefront read consecutive sites.
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -15,6 +16,8 @@
 namespace qxd {
 
 namespace {
+
+constexpr int LDS_VARIANT = 16;
 
 template <int P, int KIND, int GROUP>
 __global__ void __launch_bounds__(256) dirac_kernel(Geom g, const typename St<P>::pair_t *links,
@@ -85,29 +88,151 @@ __global__ void __launch_bounds__(256) dirac_kernel(Geom g, const typename St<P>
   }
 }
 
+// Variant with the hop neighbours' input spinors staged in LDS.  Each thread
+// first copies one site of its block(s) into LDS -- its own site for the
+// full-lattice kinds, the site of the other parity with the same half index
+// for the half-lattice passes -- so that every input spinor of the block is
+// read from memory once; the hops then take in-block neighbours from LDS and
+// only the neighbours across the block faces from memory.  The links and the
+// Pauli term are read as in dirac_kernel.  Requires whole blocks per
+// work-group; LDS: 12 complex per staged site.
+template <int P, int KIND, int GROUP>
+__global__ void __launch_bounds__(256) dirac_lds_kernel(Geom g, const typename St<P>::pair_t *links,
+                                                        const typename St<P>::real_t *angles, int qhat,
+                                                        const typename St<P>::pair_t *pauli,
+                                                        const typename St<P>::pair_t *pinv,
+                                                        Spinor<P> in, Spinor<P> self, Spinor<P> out,
+                                                        typename St<P>::comp_t c) {
+  using T = typename St<P>::comp_t;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T> *lds = (cx<T> *)smem_raw;
+  constexpr bool half = KIND == DK_ODD || KIND == DK_EVEN || KIND == DK_EVEN_ID;
+  const int per_block = half ? g.Vbh : 2 * g.Vbh;  // threads (and staged sites) per block
+  const int bpw = blockDim.x / per_block;
+  const int ns = bpw * per_block;                   // LDS plane length
+  const int wg = xcd_order(blockIdx.x, gridDim.x);
+  const int lb = threadIdx.x / per_block;
+  const int r = threadIdx.x - lb * per_block;
+  const int blk = wg * bpw + lb;
+  const bool valid = blk < g.nblocks;
+  const int par = half ? (KIND == DK_ODD ? 1 : 0) : (r >= g.Vbh);
+  const int h = r >= g.Vbh ? r - g.Vbh : r;
+  const int i = par * g.Vh + blk * g.Vbh + h;
+  // stage one input site: own site (full kinds) or the other parity's site
+  if (valid) {
+    const int spar = half ? 1 - par : par;
+    cx<T> v[4][3];
+    load_spinor<P, T>(in, (int64_t)spar * g.Vh + (int64_t)blk * g.Vbh + h, v);
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int b = 0; b < 3; b++) lds[(a * 3 + b) * ns + threadIdx.x] = v[a][b];
+  }
+  __syncthreads();
+  if (!valid) return;
+  const int base = lb * per_block;  // LDS slot of the block's first staged site
+  cx<T> res[4][3];
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 3; b++) res[a][b] = {0, 0};
+  if (KIND != DK_PAULI) {
+    const Site s = decode(g, i);
+#pragma unroll 1
+    for (int k0 = 0; k0 < 8; k0 += GROUP) {
+#pragma unroll
+      for (int k = k0; k < k0 + GROUP; k++) {
+        const int mu = k >> 1, dir = (k & 1) ? -1 : 1;
+        int sg;
+        const Site t = neighbour(g, s, mu, dir, sg);
+        const int y = s.y(mu) + dir;
+        const bool inside = y >= 0 && y < (int)((g.bpk >> (8 * mu)) & 0xff);
+        const int j = encode(g, t);
+        cx<T> psi[4][3], w[3][3];
+        if (inside) {
+          const int l = ((t.y(0) * g.b[1] + t.y(1)) * g.b[2] + t.y(2)) * g.b[3] + t.y(3);
+          const int slot = base + (half ? 0 : t.p * g.Vbh) + (l >> 1);
+#pragma unroll
+          for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int b = 0; b < 3; b++) psi[a][b] = lds[(a * 3 + b) * ns + slot];
+        } else {
+          load_spinor<P, T>(in, j, psi);
+        }
+        load_w<P, T>(links, angles, qhat, g.V, mu, dir > 0 ? (int64_t)i : (int64_t)j, w);
+        if (dir > 0)
+          hop_fwd<T>(mu, w, psi, (T)sg, res);
+        else
+          hop_bwd<T>(mu, w, psi, (T)sg, res);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int b = 0; b < 3; b++) res[a][b] = c * res[a][b];
+  }
+  // the self term: the own site is in LDS when self is the input field
+  const bool self_in_lds = !half && self.data == in.data && self.off == in.off;
+  if (KIND == DK_FULL || KIND == DK_PAULI || KIND == DK_EVEN) {
+    cx<T> v[4][3], pv[4][3];
+    if (self_in_lds) {
+#pragma unroll
+      for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 3; b++) v[a][b] = lds[(a * 3 + b) * ns + threadIdx.x];
+    } else {
+      load_spinor<P, T>(self, i, v);
+    }
+    pauli_mul<P, T>(pauli, g.V, i, v, pv);
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int b = 0; b < 3; b++) res[a][b] = res[a][b] + pv[a][b];
+  } else if (KIND == DK_EVEN_ID || KIND == DK_ODD) {
+    if (self.data != nullptr) {
+      cx<T> v[4][3];
+      load_spinor<P, T>(self, i, v);
+#pragma unroll
+      for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 3; b++) res[a][b] = res[a][b] + v[a][b];
+    }
+  }
+  if (KIND == DK_ODD) {
+    cx<T> pv[4][3];
+    pauli_mul<P, T>(pinv, g.Vh, i - g.Vh, res, pv);
+    store_spinor<P, T>(out, i, pv);
+  } else {
+    store_spinor<P, T>(out, i, res);
+  }
+}
+
 template <int P, int KIND, int G>
-void launch_k(unsigned gr, int threads, hipStream_t st, const Geom &g, const typename St<P>::pair_t *links,
-              const typename St<P>::real_t *angles, int qhat, const typename St<P>::pair_t *pauli,
-              const typename St<P>::pair_t *pinv, Spinor<P> vin, Spinor<P> vself, Spinor<P> vout,
-              typename St<P>::comp_t c) {
-  dirac_kernel<P, KIND, G><<<gr, threads, 0, st>>>(g, links, angles, qhat, pauli, pinv, vin, vself, vout, c);
+void launch_k(unsigned gr, int threads, size_t lds, hipStream_t st, const Geom &g,
+              const typename St<P>::pair_t *links, const typename St<P>::real_t *angles, int qhat,
+              const typename St<P>::pair_t *pauli, const typename St<P>::pair_t *pinv, Spinor<P> vin,
+              Spinor<P> vself, Spinor<P> vout, typename St<P>::comp_t c) {
+  if (lds)
+    dirac_lds_kernel<P, KIND, G><<<gr, threads, lds, st>>>(g, links, angles, qhat, pauli, pinv, vin, vself, vout, c);
+  else
+    dirac_kernel<P, KIND, G><<<gr, threads, 0, st>>>(g, links, angles, qhat, pauli, pinv, vin, vself, vout, c);
 }
 
 template <int P, int KIND>
-void launch_g(int group, unsigned gr, int threads, hipStream_t st, const Geom &g, const typename St<P>::pair_t *links,
-              const typename St<P>::real_t *angles, int qhat, const typename St<P>::pair_t *pauli,
-              const typename St<P>::pair_t *pinv, Spinor<P> vin, Spinor<P> vself, Spinor<P> vout,
-              typename St<P>::comp_t c) {
+void launch_g(int group, unsigned gr, int threads, size_t lds, hipStream_t st, const Geom &g,
+              const typename St<P>::pair_t *links, const typename St<P>::real_t *angles, int qhat,
+              const typename St<P>::pair_t *pauli, const typename St<P>::pair_t *pinv, Spinor<P> vin,
+              Spinor<P> vself, Spinor<P> vout, typename St<P>::comp_t c) {
   switch (group) {
-    case 1: launch_k<P, KIND, 1>(gr, threads, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
-    case 4: launch_k<P, KIND, 4>(gr, threads, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
-    case 8: launch_k<P, KIND, 8>(gr, threads, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
-    default: launch_k<P, KIND, 2>(gr, threads, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
+    case 1: launch_k<P, KIND, 1>(gr, threads, lds, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
+    case 4: launch_k<P, KIND, 4>(gr, threads, lds, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
+    case 8: launch_k<P, KIND, 8>(gr, threads, lds, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
+    default: launch_k<P, KIND, 2>(gr, threads, lds, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
   }
 }
 
 template <int P>
-hipError_t launch_p(DiracKind kind, int group, const Geom &g, const OpFields &f, SpinorArg in,
+hipError_t launch_p(DiracKind kind, int choice, const Geom &g, const OpFields &f, SpinorArg in,
                     SpinorArg self, SpinorArg out, double c, hipStream_t st) {
   using pt = typename St<P>::pair_t;
   using rt = typename St<P>::real_t;
@@ -136,32 +261,38 @@ hipError_t launch_p(DiracKind kind, int group, const Geom &g, const OpFields &f,
     gr = (unsigned)g.nblocks * (per_block / threads);
   }
   T cc = (T)c;
+  // choice = hop group size, + LDS_VARIANT for the LDS-staged kernel (whole
+  // blocks per work-group only)
+  const bool use_lds = (choice & LDS_VARIANT) && per_block <= 256 && kind != DK_PAULI;
+  const int group = choice & (LDS_VARIANT - 1);
+  const size_t lds = use_lds ? 12 * (size_t)threads * sizeof(cx<T>) : 0;
   switch (kind) {
-    case DK_FULL: launch_g<P, DK_FULL>(group, gr, threads, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
-    case DK_HOP: launch_g<P, DK_HOP>(group, gr, threads, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
-    case DK_PAULI: launch_g<P, DK_PAULI>(1, gr, threads, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
-    case DK_ODD: launch_g<P, DK_ODD>(group, gr, threads, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
-    case DK_EVEN: launch_g<P, DK_EVEN>(group, gr, threads, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
-    case DK_EVEN_ID: launch_g<P, DK_EVEN_ID>(group, gr, threads, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
+    case DK_FULL: launch_g<P, DK_FULL>(group, gr, threads, lds, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
+    case DK_HOP: launch_g<P, DK_HOP>(group, gr, threads, lds, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
+    case DK_PAULI: launch_g<P, DK_PAULI>(1, gr, threads, 0, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
+    case DK_ODD: launch_g<P, DK_ODD>(group, gr, threads, lds, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
+    case DK_EVEN: launch_g<P, DK_EVEN>(group, gr, threads, lds, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
+    case DK_EVEN_ID: launch_g<P, DK_EVEN_ID>(group, gr, threads, lds, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_any(int prec, DiracKind kind, int group, const Geom &g, const OpFields &f, SpinorArg in,
+hipError_t launch_any(int prec, DiracKind kind, int choice, const Geom &g, const OpFields &f, SpinorArg in,
                       SpinorArg self, SpinorArg out, double c, hipStream_t st) {
   switch (prec) {
-    case QXD_F64: return launch_p<QXD_F64>(kind, group, g, f, in, self, out, c, st);
-    case QXD_F32: return launch_p<QXD_F32>(kind, group, g, f, in, self, out, c, st);
-    case QXD_F16S: return launch_p<QXD_F16S>(kind, group, g, f, in, self, out, c, st);
-    case QXD_BF16: return launch_p<QXD_BF16>(kind, group, g, f, in, self, out, c, st);
+    case QXD_F64: return launch_p<QXD_F64>(kind, choice, g, f, in, self, out, c, st);
+    case QXD_F32: return launch_p<QXD_F32>(kind, choice, g, f, in, self, out, c, st);
+    case QXD_F16S: return launch_p<QXD_F16S>(kind, choice, g, f, in, self, out, c, st);
+    case QXD_BF16: return launch_p<QXD_BF16>(kind, choice, g, f, in, self, out, c, st);
   }
   return hipErrorInvalidValue;
 }
 
-// Autotuned choice of the hop group size, per (precision, kernel kind,
-// volume, U(1) phase on the fly): the first call times every candidate on the
-// caller's own operands (all candidates compute the same result) and keeps
-// the fastest.
+// Autotuned choice of the kernel variant (hop group size, LDS staging of the
+// input spinor), per (precision, kernel kind, volume, U(1) phase on the
+// fly): the first call times every candidate on the caller's own operands
+// (all candidates compute the same result up to rounding) and keeps the
+// fastest.
 struct TuneKey {
   int prec, kind, V, phase;
   bool operator<(const TuneKey &o) const {
@@ -179,7 +310,9 @@ int tune_group(int prec, DiracKind kind, const Geom &g, const OpFields &f, Spino
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) return it->second;
   }
-  static const int cand[] = {1, 2, 4, 8};
+  static const int cand[] = {1, 2, 4, 8, LDS_VARIANT | 1, LDS_VARIANT | 2, LDS_VARIANT | 4, LDS_VARIANT | 8};
+  const bool half = kind == DK_ODD || kind == DK_EVEN || kind == DK_EVEN_ID;
+  const int ncand = (half ? g.Vbh : 2 * g.Vbh) <= 256 ? 8 : 4;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return 2;
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -188,7 +321,8 @@ int tune_group(int prec, DiracKind kind, const Geom &g, const OpFields &f, Spino
   }
   int best = 2;
   float best_ms = 1e30f;
-  for (int gsz : cand) {
+  for (int ci = 0; ci < ncand; ci++) {
+    const int gsz = cand[ci];
     (void)launch_any(prec, kind, gsz, g, f, in, self, out, c, st);  // warm-up
     (void)hipEventRecord(e0, st);
     for (int r = 0; r < 3; r++) (void)launch_any(prec, kind, gsz, g, f, in, self, out, c, st);
@@ -210,11 +344,22 @@ int tune_group(int prec, DiracKind kind, const Geom &g, const OpFields &f, Spino
 
 }  // namespace
 
+std::atomic<int> g_forced_choice{0};
+
 hipError_t launch_dirac(int prec, DiracKind kind, const Geom &g, const OpFields &f, SpinorArg in,
                         SpinorArg self, SpinorArg out, double c, hipStream_t st) {
   if (prec < QXD_F64 || prec > QXD_BF16) return hipErrorInvalidValue;
-  int group = kind == DK_PAULI ? 1 : tune_group(prec, kind, g, f, in, self, out, c, st);
-  return launch_any(prec, kind, group, g, f, in, self, out, c, st);
+  const int forced = g_forced_choice.load(std::memory_order_relaxed);
+  int choice = kind == DK_PAULI ? 1 : forced ? forced : tune_group(prec, kind, g, f, in, self, out, c, st);
+  return launch_any(prec, kind, choice, g, f, in, self, out, c, st);
+}
+
+bool force_dirac_variant(int choice) {
+  const int group = choice & (LDS_VARIANT - 1);
+  if (choice != 0 && ((choice & ~(LDS_VARIANT | 15)) || (group != 1 && group != 2 && group != 4 && group != 8)))
+    return false;
+  g_forced_choice.store(choice);
+  return true;
 }
 
 int tuned_group(int prec, int kind, int V, int phase) {

@@ -24,7 +24,7 @@ QXD_HD void load_link(const typename St<P>::pair_t *links, int64_t V, int mu, in
   for (int r = 0; r < 3; r++)
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-      auto z = St<P>::ld(links + (int64_t)(mu * 9 + r * 3 + c) * V, (uint32_t)i);
+      auto z = St<P>::ld(at32(links + (int64_t)(mu * 9 + r * 3 + c) * V, (uint32_t)i), 0);
       u[r][c] = {(T)z.re, (T)z.im};
     }
 }
@@ -139,7 +139,7 @@ QXD_HD void herm6_mul(const typename St<P>::pair_t *pa, int64_t stride, int64_t 
   T d[6];
 #pragma unroll
   for (int k = 0; k < 3; k++) {
-    auto z = St<P>::ld(pa + (int64_t)(base + k) * stride, (uint32_t)j);
+    auto z = St<P>::ld(at32(pa + (int64_t)(base + k) * stride, (uint32_t)j), 0);
     d[2 * k] = (T)z.re;
     d[2 * k + 1] = (T)z.im;
   }
@@ -149,7 +149,7 @@ QXD_HD void herm6_mul(const typename St<P>::pair_t *pa, int64_t stride, int64_t 
   for (int i = 0; i < 6; i++)
 #pragma unroll
     for (int k = i + 1; k < 6; k++) {
-      auto z = St<P>::ld(pa + (int64_t)(base + 3 + tri_index(i, k)) * stride, (uint32_t)j);
+      auto z = St<P>::ld(at32(pa + (int64_t)(base + 3 + tri_index(i, k)) * stride, (uint32_t)j), 0);
       cx<T> a{(T)z.re, (T)z.im};
       out[i] = fma_acc(out[i], a, v[k]);
       out[k] = fma_accc(out[k], a, v[i]);

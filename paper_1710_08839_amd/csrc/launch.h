@@ -73,7 +73,12 @@ struct SpinorArg {
 hipError_t launch_dirac(int prec, DiracKind kind, const Geom &g, const OpFields &f,
                         SpinorArg in, SpinorArg self, SpinorArg out, double c, hipStream_t st);
 
-// Hop group chosen by the autotuner for a key (0 if not tuned yet).
+// Kernel variant chosen by the autotuner for a key (0 if not tuned yet):
+// hop group size, plus 16 for the LDS-staged variant.
 int tuned_group(int prec, int kind, int V, int phase);
+
+// Force a variant for every later launch (0: back to the autotuner); false
+// for an invalid choice.
+bool force_dirac_variant(int choice);
 
 }  // namespace qxd

@@ -180,6 +180,20 @@ __device__ __forceinline__ void gst_pair(typename St<P>::pair_t *p, int64_t i, c
   gst(p, i, v);
 }
 
+// Element i of a field plane addressed as (plane base) + (32-bit byte
+// offset).  With a wavefront-uniform plane base the compiler can use the
+// scalar-base + 32-bit-offset form of the global memory instructions: one
+// address register per lane instead of a 64-bit address.  Every plane is
+// smaller than 4 GiB (the lattice volume is checked when a field is created).
+template <class T>
+QXD_HD const T *at32(const T *p, uint32_t i) {
+  return (const T *)((const char *)p + i * (uint32_t)sizeof(T));
+}
+template <class T>
+QXD_HD T *at32(T *p, uint32_t i) {
+  return (T *)((char *)p + i * (uint32_t)sizeof(T));
+}
+
 inline size_t pair_bytes(int prec) {
   switch (prec) {
     case QXD_F64: return 16;
@@ -225,11 +239,11 @@ QXD_HD void load_spinor(const Spinor<P> &s, int64_t i, cx<T> psi[4][3]) {
 #pragma unroll
     for (int c = 0; c < 3; c++) {
       const typename St<P>::pair_t *plane = s.data + (a * 3 + c) * s.stride;
-      cx<typename St<P>::comp_t> z = St<P>::ld(plane, j);
+      cx<typename St<P>::comp_t> z = St<P>::ld(at32(plane, j), 0);
       psi[a][c] = {(T)z.re, (T)z.im};
     }
   if constexpr (St<P>::scaled) {
-    T f = (T)s.scale[j];
+    T f = (T)*at32(s.scale, j);
 #pragma unroll
     for (int a = 0; a < 4; a++)
 #pragma unroll
@@ -253,7 +267,7 @@ QXD_HD void store_spinor(const Spinor<P> &s, int64_t i, const cx<T> psi[4][3]) {
         m = r > m ? r : m;
         m = q > m ? q : m;
       }
-    s.scale[j] = (float)m;
+    *at32(s.scale, (uint32_t)j) = (float)m;
     f = m > 0 ? (C)(1.0f / (float)m) : (C)0;
   }
 #pragma unroll
@@ -261,7 +275,7 @@ QXD_HD void store_spinor(const Spinor<P> &s, int64_t i, const cx<T> psi[4][3]) {
 #pragma unroll
     for (int c = 0; c < 3; c++) {
       typename St<P>::pair_t *plane = s.data + (a * 3 + c) * s.stride;
-      St<P>::st(plane, (uint32_t)j, cx<C>{(C)(f * (C)psi[a][c].re), (C)(f * (C)psi[a][c].im)});
+      St<P>::st(at32(plane, (uint32_t)j), 0, cx<C>{(C)(f * (C)psi[a][c].re), (C)(f * (C)psi[a][c].im)});
     }
 }
 

@@ -81,6 +81,8 @@ SIGNATURES = {
     "qxd_serve_submit": ([_VP, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], _I),
     "qxd_serve_poll": ([_VP, ctypes.c_uint64, ctypes.POINTER(Result)], _I),
     "qxd_serve_stop": ([_VP], _I),
+    # testing hooks (include/qxd_debug.h)
+    "qxd_debug_set_dirac_variant": ([_I], _I),
 }
 
 _lib = None
@@ -117,6 +119,12 @@ def _stream(stream):
 
 def _ptr(t):
     return t.data_ptr() if hasattr(t, "data_ptr") else int(t)
+
+
+def set_dirac_variant(choice=0):
+    """Force a Dirac kernel variant (hop group 1/2/4/8, +16 for LDS staging);
+    0 returns to the autotuner.  A testing hook."""
+    _check(lib().qxd_debug_set_dirac_variant(int(choice)))
 
 
 def quark(kappa, q=0.0, csw=0.0, csw_u1=1.0):

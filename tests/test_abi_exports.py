@@ -11,12 +11,12 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "qxd.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("qxd.h", "qxd_debug.h")]
 
 
 def header_functions():
-    """name -> number of parameters of every function declared in qxd.h."""
-    text = open(HEADER).read()
+    """name -> number of parameters of every function declared in include/."""
+    text = "\n".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     text = re.sub(r"//[^\n]*", "", text)
     out = {}
@@ -38,7 +38,8 @@ def libpath():
 
 def test_header_parses():
     fns = header_functions()
-    assert len(fns) >= 17
+    assert len(fns) >= 18
+    assert fns["qxd_debug_set_dirac_variant"] == 1
     assert fns["qxd_abi_version"] == 0
     assert fns["qxd_dirac_apply"] == 10
     assert fns["qxd_solve"] == 10
@@ -75,3 +76,6 @@ def test_library_loads_and_reports(libpath):
     # argument checks happen before any device work
     assert lib.qxd_finalize(None) != 0
     assert lib.qxd_field_release(None) != 0
+    assert lib.qxd_debug_set_dirac_variant(3) != 0
+    assert lib.qxd_debug_set_dirac_variant(16 | 4) == 0
+    assert lib.qxd_debug_set_dirac_variant(0) == 0

@@ -77,6 +77,30 @@ def test_operator_low_precision(case, prec):
         assert rel(to_host(y), oracle_op(case, which, x)) < TOL[prec]
 
 
+VARIANTS = [1, 2, 4, 8, 16 | 1, 16 | 2, 16 | 4, 16 | 8]
+
+
+@pytest.mark.parametrize("choice", VARIANTS, ids=[f"g{v & 15}{'-lds' if v & 16 else ''}" for v in VARIANTS])
+def test_every_kernel_variant(case, choice):
+    """Each hop-group size and the LDS-staged input, forced in turn (the
+    autotuner would otherwise pick one), for D, D^ and the hopping term in
+    FP64 and FP32."""
+    import torch
+    from paper_1710_08839_amd import qxd
+    x = case.source(9)
+    refs = {w: oracle_op(case, w, x) for w in (0, 1, 2)}
+    qxd.set_dirac_variant(choice)
+    try:
+        for prec in (0, 1):
+            for which in (0, 1, 2):
+                y = torch.empty_like(to_dev(x))
+                case.field.apply(case.quark, which, prec, to_dev(x), y)
+                torch.cuda.synchronize()
+                assert rel(to_host(y), refs[which]) < TOL[prec], (prec, which)
+    finally:
+        qxd.set_dirac_variant(0)
+
+
 def test_pack_roundtrip_and_native(case):
     """API -> native -> API is exact in FP64; the native-layout apply equals
     the API-layout apply bit for bit."""
