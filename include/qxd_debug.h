@@ -3,8 +3,9 @@
  * The Dirac kernels come in several variants that compute the same operator
  * (Sec. 2.3 of the openQ*D paper) up to the order of floating-point
  * additions: the number of hops whose loads are issued together (1, 2, 4 or
- * 8) and whether the input spinors of a lattice block are first staged in
- * LDS.  An autotuner picks the fastest variant per (precision, kernel,
+ * 8), whether the input spinors of a lattice block are first staged in
+ * LDS, and whether the Pauli term and the output are streamed with
+ * non-temporal loads and stores.  An autotuner picks the fastest variant per (precision, kernel,
  * lattice volume) on first use.  Tests force each variant in turn to check
  * all of them against the reference.
  */
@@ -19,7 +20,9 @@ extern "C" {
 
 /* Force the Dirac kernel variant of every later application in this process:
  * choice = group (1, 2, 4 or 8), plus 16 for the LDS-staged variant (ignored
- * where a block does not fit one work-group); 0 returns to the autotuner.
+ * where a block does not fit one work-group), plus 32 for non-temporal Pauli
+ * and output streams (with the LDS-staged variant only); 0 returns to the
+ * autotuner.
  * Process-wide; not synchronised with applications in flight on other
  * threads.  QXD_EINVAL for any other value. */
 qxd_status qxd_debug_set_dirac_variant(int choice);

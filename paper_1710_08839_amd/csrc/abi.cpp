@@ -61,8 +61,11 @@ static qxd_status make_geom(const qxd_lattice *lat, Geom *g) {
     g->nb[m] = N[m] / b;
     V *= N[m];
   }
-  if (V > (int64_t)1 << 30) {
-    set_error("extended volume %lld exceeds 2^30 sites", (long long)V);
+  // fields are addressed with 32-bit byte offsets: the largest array (36
+  // FP64 pairs per site) must stay below 4 GiB
+  if (V * 36 * 16 >= ((int64_t)1 << 32)) {
+    set_error("extended volume %lld exceeds the %lld sites addressable with 32-bit offsets", (long long)V,
+              (long long)((((int64_t)1 << 32) - 1) / (36 * 16)));
     return QXD_EINVAL;
   }
   g->L1 = lat->dims[1];
@@ -194,7 +197,7 @@ qxd_status apply_native(Field *fd, const Operator &op, qxd_op which, int prec, v
                         hipStream_t st) {
   const Geom &g = fd->g;
   OpFields f = fd->op_fields(op, prec);
-  SpinorArg full_in{in, g.V, 0}, full_out{out, g.V, 0}, none{nullptr, 0, 0};
+  SpinorArg full_in{in, g.V, 0, g.rd}, full_out{out, g.V, 0, g.rd}, none{nullptr, 0, 0, g.rd};
   switch (which) {
     case QXD_OP_D:
       QXD_HIP_CHECK(launch_dirac(prec, DK_FULL, g, f, full_in, full_in, full_out, -0.5, st));
@@ -209,7 +212,7 @@ qxd_status apply_native(Field *fd, const Operator &op, qxd_op which, int prec, v
       hipError_t e;
       void *tmp = fd->workspace("dhat_tmp", spinor_bytes(prec, g.Vh), &e);
       QXD_HIP_CHECK(e);
-      SpinorArg t_o{tmp, g.Vh, g.Vh};
+      SpinorArg t_o{tmp, g.Vh, g.Vh, g.rd};
       QXD_HIP_CHECK(launch_dirac(prec, DK_ODD, g, f, full_in, none, t_o, -0.5, st));
       QXD_HIP_CHECK(launch_dirac(prec, DK_EVEN, g, f, t_o, full_in, full_out, 0.5, st));
       QXD_HIP_CHECK(launch_zero_sites(prec, full_out, g.Vh, g.Vh, st));

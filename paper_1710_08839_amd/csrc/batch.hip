@@ -28,7 +28,7 @@ __global__ void __launch_bounds__(256) dirac_batch_kernel(Geom g, const DSlot<P>
   cx<T> res[4][3], v[4][3], pv[4][3];
   hop_sum<P, T, G>(g, sl.links, nullptr, 0, sl.in, s, i, res);
   load_spinor<P, T>(sl.in, i, v);
-  pauli_mul<P, T>(sl.pauli, g.V, i, v, pv);
+  pauli_mul<P, T>(sl.pauli, g, i, v, pv);
 #pragma unroll
   for (int a = 0; a < 4; a++)
 #pragma unroll

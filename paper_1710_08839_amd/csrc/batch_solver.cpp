@@ -137,7 +137,7 @@ qxd_status BatchSolver::reserve(int n) {
 // ---------------------------------------------------------------------------
 template <int P>
 struct BImpl {
-  static SpinorArg F(const Geom &g, void *p) { return SpinorArg{p, g.V, 0}; }
+  static SpinorArg F(const Geom &g, void *p) { return SpinorArg{p, g.V, 0, g.rd}; }
 
   // b = r / |r| (inner precision), rho = b, delta = 0
   static qxd_status new_inner(BatchSolver::Slot &sl, const Geom &g, double *partial, int nkv,
@@ -233,7 +233,7 @@ struct BImpl {
   // x += |r| delta; r = eta - D x (FP64); r2 = |r|^2
   static qxd_status outer_update(BatchSolver::Slot &sl, Field *f, double *partial, int nkv, hipStream_t st) {
     const Geom &g = f->g;
-    auto F64 = [&](void *p) { return SpinorArg{p, g.V, 0}; };
+    auto F64 = [&](void *p) { return SpinorArg{p, g.V, 0, g.rd}; };
     BCK(blas_axpby<QXD_F64, P>(F64(sl.x()), 1.0, F(g, sl.delta()), sl.s_norm, 0, g.V, partial, nullptr, st));
     OpFields of = f->op_fields(*sl.op64, QXD_F64);
     BCK(launch_dirac(QXD_F64, DK_FULL, g, of, F64(sl.x()), F64(sl.x()), F64(sl.tmp()), -0.5, st));
@@ -259,12 +259,12 @@ struct BImpl {
       OpFields of = f->op_fields(*sl.opP, P);
       hs[j].op = SapOp<P>{(const typename St<P>::pair_t *)of.links, nullptr, 0,
                           (const typename St<P>::pair_t *)of.pauli, (const typename St<P>::pair_t *)of.pinv};
-      hs[j].vec = SapVecs<P>{spinor_view<P>(sl.rho(), g.V, 0), spinor_view<P>(sl.sap_r(), g.V, 0),
-                             spinor_view<P>(sl.phi(sl.k), g.V, 0), spinor_view<P>(sl.sap_v(), g.V, 0)};
+      hs[j].vec = SapVecs<P>{spinor_view<P>(sl.rho(), g.V, 0, g), spinor_view<P>(sl.sap_r(), g.V, 0, g),
+                             spinor_view<P>(sl.phi(sl.k), g.V, 0, g), spinor_view<P>(sl.sap_v(), g.V, 0, g)};
       hd[j].links = hs[j].op.links;
       hd[j].pauli = hs[j].op.pauli;
-      hd[j].in = spinor_view<P>(sl.phi(sl.k), g.V, 0);
-      hd[j].out = spinor_view<P>(sl.chi(nkv, sl.k), g.V, 0);
+      hd[j].in = spinor_view<P>(sl.phi(sl.k), g.V, 0, g);
+      hd[j].out = spinor_view<P>(sl.chi(nkv, sl.k), g.V, 0, g);
       ha[j] = j;
     }
     BCK(hipMemcpyAsync(sslots.p, hs, n * sizeof(SapSlot<P>), hipMemcpyHostToDevice, st));
@@ -342,7 +342,7 @@ qxd_status BatchSolver::add(const qxd_quark &q, const double *eta_api, double *p
   sl->t0 = now_s();
   sl->active = true;
   double *partial = partial_.as<double>();
-  auto F64 = [&](void *p) { return SpinorArg{p, g.V, 0}; };
+  auto F64 = [&](void *p) { return SpinorArg{p, g.V, 0, g.rd}; };
   BCK(launch_pack(QXD_F64, g, eta_api, sl->eta(), 1, st_));
   BCK(blas_norm2<QXD_F64>(F64(sl->eta()), 0, g.V, partial, sl->misc(nkv_), st_));
   double e2 = 0;

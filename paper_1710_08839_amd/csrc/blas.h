@@ -26,7 +26,7 @@ struct MaxpyHost {
   const double *coef = nullptr;   // device, complex [n]
   const double *div = nullptr;    // device, real, element l at div[l * div_stride]
   int div_stride = 1;
-  SpinorArg w{nullptr, 0, 0};     // optional: also (z_0, w)
+  SpinorArg w{nullptr, 0, 0, RunDiv{}};     // optional: also (z_0, w)
 };
 
 // Partial-sum scratch needed by any call: 3 * 2 * MAXV * RED_BLOCKS doubles

@@ -248,7 +248,7 @@ __global__ void norm_kernel(Spinor<P> x, int64_t first, int64_t count, double *p
 
 template <int P>
 Spinor<P> view(const SpinorArg &a) {
-  return spinor_view<P>(a.ptr, a.sites, a.off);
+  return spinor_view<P>(a.ptr, a.sites, a.off, a.rd);
 }
 
 }  // namespace
@@ -301,7 +301,7 @@ hipError_t blas_maxpy(const MaxpyHost &h, int64_t first, int64_t count, double *
     a.coef_base = c0;
     a.want_norms = last && out != nullptr;
     a.has_w = h.w.ptr != nullptr;
-    a.w = a.has_w ? view<P>(h.w) : Spinor<P>{nullptr, nullptr, 0, 0};
+    a.w = a.has_w ? view<P>(h.w) : Spinor<P>{nullptr, nullptr, 0, RunDiv{}};
     switch (m) {
 #define QXD_CASE(N) case N: maxpy_kernel<P, N><<<g, BT, 0, st>>>(a, first, count, partial); break;
       QXD_CASE(0) QXD_CASE(1) QXD_CASE(2) QXD_CASE(3) QXD_CASE(4) QXD_CASE(5) QXD_CASE(6) QXD_CASE(7) QXD_CASE(8)

@@ -18,6 +18,7 @@ namespace qxd {
 namespace {
 
 constexpr int LDS_VARIANT = 16;
+constexpr int NT_VARIANT = 32;
 
 template <int P, int KIND, int GROUP>
 __global__ void __launch_bounds__(256) dirac_kernel(Geom g, const typename St<P>::pair_t *links,
@@ -64,7 +65,7 @@ __global__ void __launch_bounds__(256) dirac_kernel(Geom g, const typename St<P>
   if (KIND == DK_FULL || KIND == DK_PAULI || KIND == DK_EVEN) {
     cx<T> v[4][3], pv[4][3];
     load_spinor<P, T>(self, i, v);
-    pauli_mul<P, T>(pauli, g.V, i, v, pv);
+    pauli_mul<P, T>(pauli, g, i, v, pv);
 #pragma unroll
     for (int a = 0; a < 4; a++)
 #pragma unroll
@@ -81,7 +82,7 @@ __global__ void __launch_bounds__(256) dirac_kernel(Geom g, const typename St<P>
   }
   if (KIND == DK_ODD) {
     cx<T> pv[4][3];
-    pauli_mul<P, T>(pinv, g.Vh, i - g.Vh, res, pv);
+    pauli_mul<P, T>(pinv, g, i - g.Vh, res, pv);
     store_spinor<P, T>(out, i, pv);
   } else {
     store_spinor<P, T>(out, i, res);
@@ -96,7 +97,7 @@ __global__ void __launch_bounds__(256) dirac_kernel(Geom g, const typename St<P>
 // only the neighbours across the block faces from memory.  The links and the
 // Pauli term are read as in dirac_kernel.  Requires whole blocks per
 // work-group; LDS: 12 complex per staged site.
-template <int P, int KIND, int GROUP>
+template <int P, int KIND, int GROUP, bool NT>
 __global__ void __launch_bounds__(256) dirac_lds_kernel(Geom g, const typename St<P>::pair_t *links,
                                                         const typename St<P>::real_t *angles, int qhat,
                                                         const typename St<P>::pair_t *pauli,
@@ -159,7 +160,7 @@ __global__ void __launch_bounds__(256) dirac_lds_kernel(Geom g, const typename S
         } else {
           load_spinor<P, T>(in, j, psi);
         }
-        load_w<P, T>(links, angles, qhat, g.V, mu, dir > 0 ? (int64_t)i : (int64_t)j, w);
+        load_w<P, T>(links, angles, qhat, g, mu, dir > 0 ? (int64_t)i : (int64_t)j, w);
         if (dir > 0)
           hop_fwd<T>(mu, w, psi, (T)sg, res);
         else
@@ -183,7 +184,7 @@ __global__ void __launch_bounds__(256) dirac_lds_kernel(Geom g, const typename S
     } else {
       load_spinor<P, T>(self, i, v);
     }
-    pauli_mul<P, T>(pauli, g.V, i, v, pv);
+    pauli_mul<P, T, NT>(pauli, g, i, v, pv);
 #pragma unroll
     for (int a = 0; a < 4; a++)
 #pragma unroll
@@ -200,34 +201,36 @@ __global__ void __launch_bounds__(256) dirac_lds_kernel(Geom g, const typename S
   }
   if (KIND == DK_ODD) {
     cx<T> pv[4][3];
-    pauli_mul<P, T>(pinv, g.Vh, i - g.Vh, res, pv);
-    store_spinor<P, T>(out, i, pv);
+    pauli_mul<P, T, NT>(pinv, g, i - g.Vh, res, pv);
+    store_spinor<P, T, NT>(out, i, pv);
   } else {
-    store_spinor<P, T>(out, i, res);
+    store_spinor<P, T, NT>(out, i, res);
   }
 }
 
 template <int P, int KIND, int G>
-void launch_k(unsigned gr, int threads, size_t lds, hipStream_t st, const Geom &g,
+void launch_k(unsigned gr, int threads, size_t lds, bool nt, hipStream_t st, const Geom &g,
               const typename St<P>::pair_t *links, const typename St<P>::real_t *angles, int qhat,
               const typename St<P>::pair_t *pauli, const typename St<P>::pair_t *pinv, Spinor<P> vin,
               Spinor<P> vself, Spinor<P> vout, typename St<P>::comp_t c) {
-  if (lds)
-    dirac_lds_kernel<P, KIND, G><<<gr, threads, lds, st>>>(g, links, angles, qhat, pauli, pinv, vin, vself, vout, c);
+  if (lds && nt)
+    dirac_lds_kernel<P, KIND, G, true><<<gr, threads, lds, st>>>(g, links, angles, qhat, pauli, pinv, vin, vself, vout, c);
+  else if (lds)
+    dirac_lds_kernel<P, KIND, G, false><<<gr, threads, lds, st>>>(g, links, angles, qhat, pauli, pinv, vin, vself, vout, c);
   else
     dirac_kernel<P, KIND, G><<<gr, threads, 0, st>>>(g, links, angles, qhat, pauli, pinv, vin, vself, vout, c);
 }
 
 template <int P, int KIND>
-void launch_g(int group, unsigned gr, int threads, size_t lds, hipStream_t st, const Geom &g,
+void launch_g(int group, unsigned gr, int threads, size_t lds, bool nt, hipStream_t st, const Geom &g,
               const typename St<P>::pair_t *links, const typename St<P>::real_t *angles, int qhat,
               const typename St<P>::pair_t *pauli, const typename St<P>::pair_t *pinv, Spinor<P> vin,
               Spinor<P> vself, Spinor<P> vout, typename St<P>::comp_t c) {
   switch (group) {
-    case 1: launch_k<P, KIND, 1>(gr, threads, lds, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
-    case 4: launch_k<P, KIND, 4>(gr, threads, lds, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
-    case 8: launch_k<P, KIND, 8>(gr, threads, lds, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
-    default: launch_k<P, KIND, 2>(gr, threads, lds, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
+    case 1: launch_k<P, KIND, 1>(gr, threads, lds, nt, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
+    case 4: launch_k<P, KIND, 4>(gr, threads, lds, nt, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
+    case 8: launch_k<P, KIND, 8>(gr, threads, lds, nt, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
+    default: launch_k<P, KIND, 2>(gr, threads, lds, nt, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
   }
 }
 
@@ -241,9 +244,9 @@ hipError_t launch_p(DiracKind kind, int choice, const Geom &g, const OpFields &f
   auto angles = (const rt *)f.angles;
   auto pauli = (const pt *)f.pauli;
   auto pinv = (const pt *)f.pinv;
-  Spinor<P> vin = spinor_view<P>(in.ptr, in.sites, in.off);
-  Spinor<P> vself = self.ptr ? spinor_view<P>(self.ptr, self.sites, self.off) : Spinor<P>{nullptr, nullptr, 0, 0};
-  Spinor<P> vout = spinor_view<P>(out.ptr, out.sites, out.off);
+  Spinor<P> vin = spinor_view<P>(in.ptr, in.sites, in.off, g);
+  Spinor<P> vself = self.ptr ? spinor_view<P>(self.ptr, self.sites, self.off, g) : Spinor<P>{nullptr, nullptr, 0, g.rd};
+  Spinor<P> vout = spinor_view<P>(out.ptr, out.sites, out.off, g);
   // work-group size: whole blocks, about 256 threads
   bool half = kind == DK_ODD || kind == DK_EVEN || kind == DK_EVEN_ID;
   int per_block = half ? g.Vbh : 2 * g.Vbh;
@@ -264,15 +267,16 @@ hipError_t launch_p(DiracKind kind, int choice, const Geom &g, const OpFields &f
   // choice = hop group size, + LDS_VARIANT for the LDS-staged kernel (whole
   // blocks per work-group only)
   const bool use_lds = (choice & LDS_VARIANT) && per_block <= 256 && kind != DK_PAULI;
+  const bool nt = use_lds && (choice & NT_VARIANT);
   const int group = choice & (LDS_VARIANT - 1);
   const size_t lds = use_lds ? 12 * (size_t)threads * sizeof(cx<T>) : 0;
   switch (kind) {
-    case DK_FULL: launch_g<P, DK_FULL>(group, gr, threads, lds, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
-    case DK_HOP: launch_g<P, DK_HOP>(group, gr, threads, lds, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
-    case DK_PAULI: launch_g<P, DK_PAULI>(1, gr, threads, 0, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
-    case DK_ODD: launch_g<P, DK_ODD>(group, gr, threads, lds, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
-    case DK_EVEN: launch_g<P, DK_EVEN>(group, gr, threads, lds, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
-    case DK_EVEN_ID: launch_g<P, DK_EVEN_ID>(group, gr, threads, lds, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
+    case DK_FULL: launch_g<P, DK_FULL>(group, gr, threads, lds, nt, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
+    case DK_HOP: launch_g<P, DK_HOP>(group, gr, threads, lds, nt, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
+    case DK_PAULI: launch_g<P, DK_PAULI>(1, gr, threads, 0, false, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
+    case DK_ODD: launch_g<P, DK_ODD>(group, gr, threads, lds, nt, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
+    case DK_EVEN: launch_g<P, DK_EVEN>(group, gr, threads, lds, nt, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
+    case DK_EVEN_ID: launch_g<P, DK_EVEN_ID>(group, gr, threads, lds, nt, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
   }
   return hipGetLastError();
 }
@@ -310,9 +314,10 @@ int tune_group(int prec, DiracKind kind, const Geom &g, const OpFields &f, Spino
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) return it->second;
   }
-  static const int cand[] = {1, 2, 4, 8, LDS_VARIANT | 1, LDS_VARIANT | 2, LDS_VARIANT | 4, LDS_VARIANT | 8};
+  constexpr int L = LDS_VARIANT, N = NT_VARIANT;
+  static const int cand[] = {1, 2, 4, 8, L | 1, L | 2, L | 4, L | N | 1, L | N | 2, L | N | 4};
   const bool half = kind == DK_ODD || kind == DK_EVEN || kind == DK_EVEN_ID;
-  const int ncand = (half ? g.Vbh : 2 * g.Vbh) <= 256 ? 8 : 4;
+  const int ncand = (half ? g.Vbh : 2 * g.Vbh) <= 256 ? 10 : 4;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return 2;
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -356,7 +361,7 @@ hipError_t launch_dirac(int prec, DiracKind kind, const Geom &g, const OpFields 
 
 bool force_dirac_variant(int choice) {
   const int group = choice & (LDS_VARIANT - 1);
-  if (choice != 0 && ((choice & ~(LDS_VARIANT | 15)) || (group != 1 && group != 2 && group != 4 && group != 8)))
+  if (choice != 0 && ((choice & ~(NT_VARIANT | LDS_VARIANT | 15)) || (group != 1 && group != 2 && group != 4 && group != 8)))
     return false;
   g_forced_choice.store(choice);
   return true;

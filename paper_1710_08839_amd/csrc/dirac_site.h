@@ -17,16 +17,23 @@
 
 namespace qxd {
 
+// Link of direction mu of the site whose block-major element base (K = 36)
+// is e.
 template <int P, class T>
-QXD_HD void load_link(const typename St<P>::pair_t *links, int64_t V, int mu, int64_t i,
-                      cx<T> u[3][3]) {
+QXD_HD void load_link_at(const typename St<P>::pair_t *links, const Geom &g, int mu, uint32_t e,
+                         cx<T> u[3][3]) {
 #pragma unroll
   for (int r = 0; r < 3; r++)
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-      auto z = St<P>::ld(at32(links + (int64_t)(mu * 9 + r * 3 + c) * V, (uint32_t)i), 0);
+      auto z = St<P>::ld(at32(links + (mu * 9 + r * 3 + c) * g.Vbh, e), 0);
       u[r][c] = {(T)z.re, (T)z.im};
     }
+}
+
+template <int P, class T>
+QXD_HD void load_link(const typename St<P>::pair_t *links, const Geom &g, int mu, int64_t i, cx<T> u[3][3]) {
+  load_link_at<P, T>(links, g, mu, g.rd.base((uint32_t)i, 36), u);
 }
 
 template <class T> QXD_HD void sincos_t(T x, T *s, T *c);
@@ -36,10 +43,10 @@ template <> QXD_HD void sincos_t<float>(float x, float *s, float *c) { sincosf(x
 // W = U * exp(i qhat A)
 template <int P, class T>
 QXD_HD void load_w(const typename St<P>::pair_t *links, const typename St<P>::real_t *angles,
-                   int qhat, int64_t V, int mu, int64_t i, cx<T> w[3][3]) {
-  load_link<P, T>(links, V, mu, i, w);
+                   int qhat, const Geom &g, int mu, int64_t i, cx<T> w[3][3]) {
+  load_link<P, T>(links, g, mu, i, w);
   if (qhat != 0) {
-    T a = (T)St<P>::ldr(angles + (int64_t)mu * V, (uint32_t)i);
+    T a = (T)*at32(angles + mu * g.Vbh, g.rd.base((uint32_t)i, 4));
     T sn, cs;
     sincos_t<T>((T)qhat * a, &sn, &cs);
     cx<T> z{cs, sn};
@@ -132,14 +139,21 @@ QXD_HD void hop_bwd(int mu, const cx<T> w[3][3], const cx<T> psi[4][3], T sign, 
 QXD_HD constexpr int tri_index(int i, int j) { return i * 6 - i * (i + 1) / 2 + (j - i - 1); }
 
 // out = A v for one packed Hermitian block whose 18 pairs start at pair
-// `base` (pair k of site j is at pa[(base + k) * stride + j]).
-template <int P, class T>
-QXD_HD void herm6_mul(const typename St<P>::pair_t *pa, int64_t stride, int64_t j, int base,
+// `base` of site j (block-major, K = 36 pairs per site).
+template <int P, class T, bool NT = false>
+QXD_HD void herm6_mul(const typename St<P>::pair_t *pa, const Geom &g, int64_t j, int base,
                       const cx<T> v[6], cx<T> out[6]) {
+  const uint32_t e = g.rd.base((uint32_t)j, 36);
+  auto ldp = [&](int pair) {
+    if constexpr (NT)
+      return ld_nt<P>(at32(pa + pair * g.Vbh, e));
+    else
+      return St<P>::ld(at32(pa + pair * g.Vbh, e), 0);
+  };
   T d[6];
 #pragma unroll
   for (int k = 0; k < 3; k++) {
-    auto z = St<P>::ld(at32(pa + (int64_t)(base + k) * stride, (uint32_t)j), 0);
+    auto z = ldp(base + k);
     d[2 * k] = (T)z.re;
     d[2 * k + 1] = (T)z.im;
   }
@@ -149,16 +163,17 @@ QXD_HD void herm6_mul(const typename St<P>::pair_t *pa, int64_t stride, int64_t 
   for (int i = 0; i < 6; i++)
 #pragma unroll
     for (int k = i + 1; k < 6; k++) {
-      auto z = St<P>::ld(at32(pa + (int64_t)(base + 3 + tri_index(i, k)) * stride, (uint32_t)j), 0);
+      auto z = ldp(base + 3 + tri_index(i, k));
       cx<T> a{(T)z.re, (T)z.im};
       out[i] = fma_acc(out[i], a, v[k]);
       out[k] = fma_accc(out[k], a, v[i]);
     }
 }
 
-// out = P psi with both chiral blocks.
-template <int P, class T>
-QXD_HD void pauli_mul(const typename St<P>::pair_t *pa, int64_t stride, int64_t j,
+// out = P psi with both chiral blocks; j indexes the sites the array covers
+// (all sites for P, the odd sites j = i - V/2 for D_oo^-1).
+template <int P, class T, bool NT = false>
+QXD_HD void pauli_mul(const typename St<P>::pair_t *pa, const Geom &g, int64_t j,
                       const cx<T> psi[4][3], cx<T> out[4][3]) {
 #pragma unroll
   for (int blk = 0; blk < 2; blk++) {
@@ -168,7 +183,7 @@ QXD_HD void pauli_mul(const typename St<P>::pair_t *pa, int64_t stride, int64_t 
       v[c] = psi[2 * blk][c];
       v[3 + c] = psi[2 * blk + 1][c];
     }
-    herm6_mul<P, T>(pa, stride, j, 18 * blk, v, o);
+    herm6_mul<P, T, NT>(pa, g, j, 18 * blk, v, o);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
       out[2 * blk][c] = o[c];
@@ -188,7 +203,7 @@ QXD_HD void hop_one(const Geom &g, const typename St<P>::pair_t *links,
   int64_t j = encode(g, t);
   cx<T> psi[4][3], w[3][3];
   load_spinor<P, T>(in, j, psi);
-  load_w<P, T>(links, angles, qhat, g.V, mu, dir > 0 ? i : j, w);
+  load_w<P, T>(links, angles, qhat, g, mu, dir > 0 ? i : j, w);
   if (dir > 0)
     hop_fwd<T>(mu, w, psi, (T)sg, acc);
   else

@@ -11,9 +11,9 @@ struct M3 {
   cx<double> m[3][3];
 };
 
-__device__ __forceinline__ M3 ld_u(const double2 *links, int64_t V, int mu, int64_t i) {
+__device__ __forceinline__ M3 ld_u(const double2 *links, const Geom &g, int mu, int64_t i) {
   M3 r;
-  load_link<QXD_F64, double>(links, V, mu, i, r.m);
+  load_link<QXD_F64, double>(links, g, mu, i, r.m);
   return r;
 }
 __device__ __forceinline__ M3 mul(const M3 &a, const M3 &b) {
@@ -43,6 +43,7 @@ __global__ void orbifold_kernel(Geom g, const double *u_phs, const double *a_phs
   global_coords(g, s, x);
   bool mirror;
   int64_t j = phys_lex(g, x, mirror);
+  const uint32_t el = g.rd.base((uint32_t)i, 36), ea = g.rd.base((uint32_t)i, 4);
   for (int mu = 0; mu < 4; mu++) {
     bool cut = g.time_bc == 1 && mu == 0 && x[0] == g.N[0] - 1;
     const double *u = u_phs + (j * 4 + mu) * 18;
@@ -50,10 +51,10 @@ __global__ void orbifold_kernel(Geom g, const double *u_phs, const double *a_phs
       double re = u[2 * k], im = u[2 * k + 1];
       if (mirror) im = -im;
       if (cut) re = im = 0.0;
-      links[(int64_t)(mu * 9 + k) * g.V + i] = make_double2(re, im);
+      links[el + (mu * 9 + k) * g.Vbh] = make_double2(re, im);
     }
     double a = a_phs ? a_phs[j * 4 + mu] : 0.0;
-    angles[(int64_t)mu * g.V + i] = mirror ? -a : a;
+    angles[ea + mu * g.Vbh] = mirror ? -a : a;
   }
 }
 
@@ -63,7 +64,7 @@ __device__ __forceinline__ cx<double> zlink(const Geom &g, const double *angles,
   int x0 = s.B(0) * g.b[0] + s.y(0);
   if (g.time_bc == 1 && mu == 0 && x0 == g.N[0] - 1) return {0.0, 0.0};
   double sn, cs;
-  sincos(angles[(int64_t)mu * g.V + i], &sn, &cs);
+  sincos(angles[g.rd.base((uint32_t)i, 4) + mu * g.Vbh], &sn, &cs);
   return {cs, sn};
 }
 
@@ -85,14 +86,14 @@ __global__ void pauli_build_kernel(Geom g, const double2 *links, const double *a
       int64_t ixpm = encode(g, xpm), ixpn = encode(g, xpn), ixmm = encode(g, xmm),
               ixmn = encode(g, xmn), ixmm_pn = encode(g, xmm_pn), ixmm_mn = encode(g, xmm_mn),
               ixpm_mn = encode(g, xpm_mn);
-      M3 q1 = mul(mul(ld_u(links, g.V, mu, i), ld_u(links, g.V, nu, ixpm)),
-                  mul(dag(ld_u(links, g.V, mu, ixpn)), dag(ld_u(links, g.V, nu, i))));
-      M3 q2 = mul(mul(ld_u(links, g.V, nu, i), dag(ld_u(links, g.V, mu, ixmm_pn))),
-                  mul(dag(ld_u(links, g.V, nu, ixmm)), ld_u(links, g.V, mu, ixmm)));
-      M3 q3 = mul(mul(dag(ld_u(links, g.V, mu, ixmm)), dag(ld_u(links, g.V, nu, ixmm_mn))),
-                  mul(ld_u(links, g.V, mu, ixmm_mn), ld_u(links, g.V, nu, ixmn)));
-      M3 q4 = mul(mul(dag(ld_u(links, g.V, nu, ixmn)), ld_u(links, g.V, mu, ixmn)),
-                  mul(ld_u(links, g.V, nu, ixpm_mn), dag(ld_u(links, g.V, mu, i))));
+      M3 q1 = mul(mul(ld_u(links, g, mu, i), ld_u(links, g, nu, ixpm)),
+                  mul(dag(ld_u(links, g, mu, ixpn)), dag(ld_u(links, g, nu, i))));
+      M3 q2 = mul(mul(ld_u(links, g, nu, i), dag(ld_u(links, g, mu, ixmm_pn))),
+                  mul(dag(ld_u(links, g, nu, ixmm)), ld_u(links, g, mu, ixmm)));
+      M3 q3 = mul(mul(dag(ld_u(links, g, mu, ixmm)), dag(ld_u(links, g, nu, ixmm_mn))),
+                  mul(ld_u(links, g, mu, ixmm_mn), ld_u(links, g, nu, ixmn)));
+      M3 q4 = mul(mul(dag(ld_u(links, g, nu, ixmn)), ld_u(links, g, mu, ixmn)),
+                  mul(ld_u(links, g, nu, ixpm_mn), dag(ld_u(links, g, mu, i))));
       double ah = 0.0;  // Ahat' = i * ah
       if (has_u1) {
         auto zp = [&](int64_t y, const Site &sy, int64_t ypm, const Site &sypm, int64_t ypn,
@@ -138,11 +139,12 @@ __global__ void pauli_build_kernel(Geom g, const double2 *links, const double *a
         A[3 + a][3 + b] = dd - h[2].m[a][b];
       }
     int base = 18 * blk;
+    const uint32_t e = g.rd.base((uint32_t)i, 36);
     for (int k = 0; k < 3; k++)
-      pauli[(int64_t)(base + k) * g.V + i] = make_double2(A[2 * k][2 * k].re, A[2 * k + 1][2 * k + 1].re);
+      pauli[e + (base + k) * g.Vbh] = make_double2(A[2 * k][2 * k].re, A[2 * k + 1][2 * k + 1].re);
     for (int r = 0; r < 6; r++)
       for (int c = r + 1; c < 6; c++)
-        pauli[(int64_t)(base + 3 + tri_index(r, c)) * g.V + i] = make_double2(A[r][c].re, A[r][c].im);
+        pauli[e + (base + 3 + tri_index(r, c)) * g.Vbh] = make_double2(A[r][c].re, A[r][c].im);
   }
 }
 
@@ -156,15 +158,16 @@ __global__ void pauli_invert_kernel(Geom g, const double2 *pauli, double2 *pinv,
   int j = t - blk * g.Vh;      // odd-site half index
   int64_t i = (int64_t)g.Vh + j;
   int base = 18 * blk;
+  const uint32_t ep = g.rd.base((uint32_t)i, 36), eq = g.rd.base((uint32_t)j, 36);
   cx<double> a[6][6];
   for (int k = 0; k < 3; k++) {
-    double2 v = pauli[(int64_t)(base + k) * g.V + i];
+    double2 v = pauli[ep + (base + k) * g.Vbh];
     a[2 * k][2 * k] = {v.x, 0.0};
     a[2 * k + 1][2 * k + 1] = {v.y, 0.0};
   }
   for (int r = 0; r < 6; r++)
     for (int c = r + 1; c < 6; c++) {
-      double2 v = pauli[(int64_t)(base + 3 + tri_index(r, c)) * g.V + i];
+      double2 v = pauli[ep + (base + 3 + tri_index(r, c)) * g.Vbh];
       a[r][c] = {v.x, v.y};
       a[c][r] = {v.x, -v.y};
     }
@@ -187,12 +190,12 @@ __global__ void pauli_invert_kernel(Geom g, const double2 *pauli, double2 *pinv,
   }
   if (!ok) atomicAdd(bad, 1);
   for (int k = 0; k < 3; k++)
-    pinv[(int64_t)(base + k) * g.Vh + j] = make_double2(a[2 * k][2 * k].re, a[2 * k + 1][2 * k + 1].re);
+    pinv[eq + (base + k) * g.Vbh] = make_double2(a[2 * k][2 * k].re, a[2 * k + 1][2 * k + 1].re);
   for (int r = 0; r < 6; r++)
     for (int c = r + 1; c < 6; c++) {
       // symmetrise the rounding of the two triangles
       cx<double> v = 0.5 * (a[r][c] + conj(a[c][r]));
-      pinv[(int64_t)(base + 3 + tri_index(r, c)) * g.Vh + j] = make_double2(v.re, v.im);
+      pinv[eq + (base + 3 + tri_index(r, c)) * g.Vbh] = make_double2(v.re, v.im);
     }
 }
 
@@ -224,7 +227,7 @@ __global__ void pack_kernel(Geom g, const double *api, void *native, size_t byte
   cx<double> psi[4][3];
   for (int a = 0; a < 4; a++)
     for (int c = 0; c < 3; c++) psi[a][c] = {src[(a * 3 + c) * 2], src[(a * 3 + c) * 2 + 1]};
-  Spinor<P> out = spinor_view<P>((char *)native + r * bytes, g.V, 0);
+  Spinor<P> out = spinor_view<P>((char *)native + r * bytes, g.V, 0, g);
   store_spinor<P, double>(out, i, psi);
 }
 
@@ -237,7 +240,7 @@ __global__ void unpack_kernel(Geom g, const void *native, double *api, size_t by
   int x[4];
   global_coords(g, s, x);
   int64_t l = ext_lex(g, x);
-  Spinor<P> in = spinor_view<P>((char *)const_cast<void *>(native) + r * bytes, g.V, 0);
+  Spinor<P> in = spinor_view<P>((char *)const_cast<void *>(native) + r * bytes, g.V, 0, g);
   cx<double> psi[4][3];
   load_spinor<P, double>(in, i, psi);
   double *dst = api + ((int64_t)r * g.V + l) * 24;
@@ -248,20 +251,21 @@ __global__ void unpack_kernel(Geom g, const void *native, double *api, size_t by
     }
 }
 
-// W(x,mu) = U(x,mu) exp(i qhat A(x,mu)) in FP64
-__global__ void fold_phase_kernel(int64_t V, const double2 *links, const double *angles, int qhat,
+// W(x,mu) = U(x,mu) exp(i qhat A(x,mu)) in FP64; one thread per (site, mu)
+__global__ void fold_phase_kernel(Geom g, const double2 *links, const double *angles, int qhat,
                                   double2 *w) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 4 * V) return;
-  int mu = (int)(t / V);
-  int64_t i = t - mu * V;
+  if (t >= 4 * (int64_t)g.V) return;
+  int mu = (int)(t / g.V);
+  uint32_t i = (uint32_t)(t - (int64_t)mu * g.V);
+  const uint32_t el = g.rd.base(i, 36);
   double sn, cs;
-  sincos(qhat * angles[t], &sn, &cs);
+  sincos(qhat * angles[g.rd.base(i, 4) + mu * g.Vbh], &sn, &cs);
   cx<double> z{cs, sn};
   for (int k = 0; k < 9; k++) {
-    double2 u = links[(int64_t)(mu * 9 + k) * V + i];
+    double2 u = links[el + (mu * 9 + k) * g.Vbh];
     cx<double> r = cx<double>{u.x, u.y} * z;
-    w[(int64_t)(mu * 9 + k) * V + i] = make_double2(r.re, r.im);
+    w[el + (mu * 9 + k) * g.Vbh] = make_double2(r.re, r.im);
   }
 }
 
@@ -281,10 +285,10 @@ __global__ void zero_sites_kernel(Spinor<P> v, int64_t first, int64_t count) {
 hipError_t launch_zero_sites(int prec, SpinorArg v, int64_t first, int64_t count, hipStream_t st) {
   unsigned gr = grid_for(count, 256);
   switch (prec) {
-    case QXD_F64: zero_sites_kernel<QXD_F64><<<gr, 256, 0, st>>>(spinor_view<QXD_F64>(v.ptr, v.sites, v.off), first, count); break;
-    case QXD_F32: zero_sites_kernel<QXD_F32><<<gr, 256, 0, st>>>(spinor_view<QXD_F32>(v.ptr, v.sites, v.off), first, count); break;
-    case QXD_F16S: zero_sites_kernel<QXD_F16S><<<gr, 256, 0, st>>>(spinor_view<QXD_F16S>(v.ptr, v.sites, v.off), first, count); break;
-    case QXD_BF16: zero_sites_kernel<QXD_BF16><<<gr, 256, 0, st>>>(spinor_view<QXD_BF16>(v.ptr, v.sites, v.off), first, count); break;
+    case QXD_F64: zero_sites_kernel<QXD_F64><<<gr, 256, 0, st>>>(spinor_view<QXD_F64>(v.ptr, v.sites, v.off, v.rd), first, count); break;
+    case QXD_F32: zero_sites_kernel<QXD_F32><<<gr, 256, 0, st>>>(spinor_view<QXD_F32>(v.ptr, v.sites, v.off, v.rd), first, count); break;
+    case QXD_F16S: zero_sites_kernel<QXD_F16S><<<gr, 256, 0, st>>>(spinor_view<QXD_F16S>(v.ptr, v.sites, v.off, v.rd), first, count); break;
+    case QXD_BF16: zero_sites_kernel<QXD_BF16><<<gr, 256, 0, st>>>(spinor_view<QXD_BF16>(v.ptr, v.sites, v.off, v.rd), first, count); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -292,7 +296,7 @@ hipError_t launch_zero_sites(int prec, SpinorArg v, int64_t first, int64_t count
 
 hipError_t launch_fold_phase(const Geom &g, const double2 *links, const double *angles, int qhat,
                              double2 *w, hipStream_t st) {
-  fold_phase_kernel<<<grid_for(4 * (int64_t)g.V, 256), 256, 0, st>>>(g.V, links, angles, qhat, w);
+  fold_phase_kernel<<<grid_for(4 * (int64_t)g.V, 256), 256, 0, st>>>(g, links, angles, qhat, w);
   return hipGetLastError();
 }
 

@@ -62,10 +62,12 @@ enum DiracKind {
 // Spinor operands: pointer to a native spinor with `sites` sites whose first
 // site has native index `off` (full field: sites = V, off = 0; even half:
 // sites = V/2, off = 0; odd half: sites = V/2, off = V/2).
+// A native spinor over the sites [off, off + sites) (block-major runs rd).
 struct SpinorArg {
   void *ptr;
   int64_t sites;
   int64_t off;
+  RunDiv rd;
 };
 
 // Autotuned on first use per (prec, kind, volume, phase-on-the-fly): the

@@ -10,14 +10,21 @@
 // so even sites come first, and inside one parity every block is contiguous
 // (the SAP block solver reads its block as one contiguous range).
 //
-// Fields are structure-of-arrays over native sites:
-//   spinor   [12 complex (spin*3 + colour)][sites]        (+ [sites] fp32 scale for F16S)
-//   links    [4 mu][9 complex (row*3 + col)][V]           forward links U(x,mu)
-//   angles   [4 mu][V]                                     U(1) potential A(x,mu)
-//   pauli    [36 pairs][V]  two 6x6 Hermitian blocks, 18 pairs each:
-//            pairs 0-2 hold the 6 real diagonal entries, pairs 3-17 the upper
-//            triangle (0,1),(0,2)...(0,5),(1,2)...(4,5) as (re, im).
-//   pauli_inv [36 pairs][V/2]  inverse blocks on odd sites (D_oo^-1)
+// Fields are stored block-major: the sites of one parity of one block form a
+// run of R = Vb/2 consecutive native indices, and an array with K components
+// per site keeps each component of a run contiguous,
+//   element (site j, component k) at  ((j / R) * K + k) * R + j % R,
+// where j is the site's index in the range of sites the array covers (the
+// whole lattice, or one parity half).  A work-group that processes a block
+// therefore reads a few contiguous stretches of memory per field instead of
+// one short piece of each of many lattice-sized planes.
+//   spinor    K = 12 (spin*3 + colour)    (+ [sites] fp32 scale for F16S)
+//   links     K = 36 (mu*9 + row*3 + col) forward links U(x,mu), all sites
+//   angles    K = 4  (mu)                 U(1) potential A(x,mu), all sites
+//   pauli     K = 36 pairs, all sites: two 6x6 Hermitian blocks, 18 pairs
+//             each: pairs 0-2 hold the 6 real diagonal entries, pairs 3-17
+//             the upper triangle (0,1),(0,2)...(0,5),(1,2)...(4,5) as (re, im)
+//   pauli_inv K = 36 pairs over the odd sites (j = i - V/2): D_oo^-1
 // Block 0 acts on spins 0,1 (gamma5 = +1), block 1 on spins 2,3; inside a
 // block the index is s*3 + colour.
 #pragma once
@@ -167,6 +174,24 @@ __device__ __forceinline__ void gst(T *p, int64_t i, T v) {
   using R = typename RawOf<sizeof(T)>::type;
   ((__attribute__((address_space(1))) R *)p)[i] = __builtin_bit_cast(R, v);
 }
+// Non-temporal (streaming) load and store of one stored pair, for data that
+// a kernel touches exactly once: they keep such data from displacing lines
+// that are read again (neighbour spinors, links) in the caches.
+template <int P>
+QXD_HD cx<typename St<P>::comp_t> ld_nt(const typename St<P>::pair_t *p) {
+  using R = typename RawOf<sizeof(typename St<P>::pair_t)>::type;
+  R r = __builtin_nontemporal_load((const R *)p);
+  typename St<P>::pair_t v = __builtin_bit_cast(typename St<P>::pair_t, r);
+  return St<P>::ld(&v, 0);
+}
+template <int P>
+QXD_HD void st_nt(typename St<P>::pair_t *p, cx<typename St<P>::comp_t> z) {
+  using R = typename RawOf<sizeof(typename St<P>::pair_t)>::type;
+  typename St<P>::pair_t v;
+  St<P>::st(&v, 0, z);
+  __builtin_nontemporal_store(__builtin_bit_cast(R, v), (R *)p);
+}
+
 // pair i of a device array in storage format, as complex
 template <int P>
 __device__ __forceinline__ cx<typename St<P>::comp_t> gld_pair(const typename St<P>::pair_t *p, int64_t i) {
@@ -210,78 +235,36 @@ inline size_t spinor_bytes(int prec, int64_t sites) {
   return b;
 }
 
-// A spinor view: component c of native site i lives at data[c*stride + i - off].
-template <int P>
-struct Spinor {
-  typename St<P>::pair_t *data;
-  float *scale;   // F16S only: one fp32 scale per site (same indexing)
-  int64_t stride;
-  int64_t off;
-};
-
-template <int P>
-QXD_HD Spinor<P> spinor_view(void *base, int64_t sites, int64_t off) {
-  Spinor<P> s;
-  s.data = (typename St<P>::pair_t *)base;
-  s.scale = St<P>::scaled ? (float *)((char *)base + 12 * sizeof(typename St<P>::pair_t) * sites) : nullptr;
-  s.stride = sites;
-  s.off = off;
-  return s;
-}
-
-// Component planes are addressed as (uniform base of the plane) + (32-bit
-// site offset), so that the 12 loads of a spinor share one address register.
-template <int P, class T>
-QXD_HD void load_spinor(const Spinor<P> &s, int64_t i, cx<T> psi[4][3]) {
-  uint32_t j = (uint32_t)(i - s.off);
-#pragma unroll
-  for (int a = 0; a < 4; a++)
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-      const typename St<P>::pair_t *plane = s.data + (a * 3 + c) * s.stride;
-      cx<typename St<P>::comp_t> z = St<P>::ld(at32(plane, j), 0);
-      psi[a][c] = {(T)z.re, (T)z.im};
-    }
-  if constexpr (St<P>::scaled) {
-    T f = (T)*at32(s.scale, j);
-#pragma unroll
-    for (int a = 0; a < 4; a++)
-#pragma unroll
-      for (int c = 0; c < 3; c++) psi[a][c] = f * psi[a][c];
-  }
-}
-
-template <int P, class T>
-QXD_HD void store_spinor(const Spinor<P> &s, int64_t i, const cx<T> psi[4][3]) {
-  int64_t j = i - s.off;
-  using C = typename St<P>::comp_t;
-  C f = (C)1;
-  if constexpr (St<P>::scaled) {
-    T m = 0;
-#pragma unroll
-    for (int a = 0; a < 4; a++)
-#pragma unroll
-      for (int c = 0; c < 3; c++) {
-        T r = psi[a][c].re < 0 ? -psi[a][c].re : psi[a][c].re;
-        T q = psi[a][c].im < 0 ? -psi[a][c].im : psi[a][c].im;
-        m = r > m ? r : m;
-        m = q > m ? q : m;
-      }
-    *at32(s.scale, (uint32_t)j) = (float)m;
-    f = m > 0 ? (C)(1.0f / (float)m) : (C)0;
-  }
-#pragma unroll
-  for (int a = 0; a < 4; a++)
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-      typename St<P>::pair_t *plane = s.data + (a * 3 + c) * s.stride;
-      St<P>::st(at32(plane, (uint32_t)j), 0, cx<C>{(C)(f * (C)psi[a][c].re), (C)(f * (C)psi[a][c].im)});
-    }
-}
-
 // ---------------------------------------------------------------------------
 // geometry of the extended lattice (Sec. 2.1)
 // ---------------------------------------------------------------------------
+// Division by the run length R of the block-major layout by multiplication:
+// with l = ceil(log2 R) and m = ceil(2^(32+l) / R), floor(j m / 2^(32+l)) =
+// floor(j / R) for every 0 <= j < 2^31 (the error term j (m R - 2^(32+l)) /
+// (R 2^(32+l)) is below 2^-(l+1) <= 1/(2R)).
+struct RunDiv {
+  uint64_t m;
+  uint32_t shift;
+  uint32_t R;
+  QXD_HD uint32_t div(uint32_t j) const { return (uint32_t)(((uint64_t)j * m) >> shift); }
+  // element index of component 0 of site j in an array with K components
+  // per site; component k is at + k * R
+  QXD_HD uint32_t base(uint32_t j, int K) const {
+    uint32_t q = div(j);
+    return q * (uint32_t)K * R + (j - q * R);
+  }
+};
+
+inline RunDiv make_rundiv(uint32_t R) {
+  uint32_t l = 0;
+  while (((uint64_t)1 << l) < R) l++;
+  RunDiv d;
+  d.R = R;
+  d.shift = 32 + l;
+  d.m = (uint64_t)((((unsigned __int128)1 << d.shift) + R - 1) / R);
+  return d;
+}
+
 struct Geom {
   int N[4];        // extended extents T, N1, L2, L3
   int b[4];        // block extents
@@ -296,6 +279,7 @@ struct Geom {
   int nblocks;
   uint32_t bpk;    // b[0..3] packed 8 bits each (indexed at run time)
   uint32_t nbpk;   // nb[0..3] packed 8 bits each
+  RunDiv rd;       // runs of Vbh sites (block-major field layout)
 };
 
 // Decoded site: block coordinates B, local coordinates y (8 bits each, packed
@@ -318,6 +302,7 @@ QXD_HD uint32_t pack4(int a0, int a1, int a2, int a3) {
 inline void finish_geom(Geom &g) {
   g.bpk = pack4(g.b[0], g.b[1], g.b[2], g.b[3]);
   g.nbpk = pack4(g.nb[0], g.nb[1], g.nb[2], g.nb[3]);
+  g.rd = make_rundiv((uint32_t)g.Vbh);
 }
 
 QXD_HD Site decode(const Geom &g, int i) {
@@ -351,6 +336,14 @@ QXD_HD int block_index(const Geom &g, const Site &s) {
 QXD_HD int encode(const Geom &g, const Site &s) {
   int l = ((s.y(0) * g.b[1] + s.y(1)) * g.b[2] + s.y(2)) * g.b[3] + s.y(3);
   return s.p * g.Vh + block_index(g, s) * g.Vbh + (l >> 1);
+}
+
+// Element index of component 0 of site s in a block-major array with K
+// components over all sites (runs: even blocks, then odd blocks).
+QXD_HD uint32_t site_base(const Geom &g, const Site &s, int K) {
+  int l = ((s.y(0) * g.b[1] + s.y(1)) * g.b[2] + s.y(2)) * g.b[3] + s.y(3);
+  uint32_t run = (uint32_t)(s.p * g.nblocks + block_index(g, s));
+  return run * (uint32_t)K * (uint32_t)g.Vbh + (uint32_t)(l >> 1);
 }
 
 QXD_HD void global_coords(const Geom &g, const Site &s, int x[4]) {
@@ -406,6 +399,92 @@ QXD_HD int64_t phys_lex(const Geom &g, const int x[4], bool &mirror) {
 
 QXD_HD int64_t ext_lex(const Geom &g, const int x[4]) {
   return (((int64_t)x[0] * g.N[1] + x[1]) * g.N[2] + x[2]) * g.N[3] + x[3];
+}
+
+// ---------------------------------------------------------------------------
+// spinor views
+// ---------------------------------------------------------------------------
+// A spinor view over the sites [off, off + sites) of the native order:
+// component c of native site i is element (j / R * 12 + c) * R + j % R with
+// j = i - off (block-major layout); F16S keeps one fp32 scale per site after
+// the 12 * sites pairs.
+template <int P>
+struct Spinor {
+  typename St<P>::pair_t *data;
+  float *scale;   // F16S only: one fp32 scale per site, index j
+  int64_t off;
+  RunDiv rd;
+};
+
+template <int P>
+QXD_HD Spinor<P> spinor_view(void *base, int64_t sites, int64_t off, const RunDiv &rd) {
+  Spinor<P> s;
+  s.data = (typename St<P>::pair_t *)base;
+  s.scale = St<P>::scaled ? (float *)((char *)base + 12 * sizeof(typename St<P>::pair_t) * sites) : nullptr;
+  s.off = off;
+  s.rd = rd;
+  return s;
+}
+template <int P>
+QXD_HD Spinor<P> spinor_view(void *base, int64_t sites, int64_t off, const Geom &g) {
+  return spinor_view<P>(base, sites, off, g.rd);
+}
+
+// Components are addressed as (wavefront-uniform base of the component) +
+// (32-bit element offset of the site), so that the 12 loads of a spinor share
+// one address register.
+template <int P, class T>
+QXD_HD void load_spinor(const Spinor<P> &s, int64_t i, cx<T> psi[4][3]) {
+  uint32_t j = (uint32_t)(i - s.off);
+  uint32_t e = s.rd.base(j, 12);
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      const typename St<P>::pair_t *plane = s.data + (a * 3 + c) * s.rd.R;
+      cx<typename St<P>::comp_t> z = St<P>::ld(at32(plane, e), 0);
+      psi[a][c] = {(T)z.re, (T)z.im};
+    }
+  if constexpr (St<P>::scaled) {
+    T f = (T)*at32(s.scale, j);
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int c = 0; c < 3; c++) psi[a][c] = f * psi[a][c];
+  }
+}
+
+template <int P, class T, bool NT = false>
+QXD_HD void store_spinor(const Spinor<P> &s, int64_t i, const cx<T> psi[4][3]) {
+  int64_t j = i - s.off;
+  uint32_t e = s.rd.base((uint32_t)j, 12);
+  using C = typename St<P>::comp_t;
+  C f = (C)1;
+  if constexpr (St<P>::scaled) {
+    T m = 0;
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        T r = psi[a][c].re < 0 ? -psi[a][c].re : psi[a][c].re;
+        T q = psi[a][c].im < 0 ? -psi[a][c].im : psi[a][c].im;
+        m = r > m ? r : m;
+        m = q > m ? q : m;
+      }
+    *at32(s.scale, (uint32_t)j) = (float)m;
+    f = m > 0 ? (C)(1.0f / (float)m) : (C)0;
+  }
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      typename St<P>::pair_t *plane = s.data + (a * 3 + c) * s.rd.R;
+      const cx<C> z{(C)(f * (C)psi[a][c].re), (C)(f * (C)psi[a][c].im)};
+      if constexpr (NT)
+        st_nt<P>(at32(plane, e), z);
+      else
+        St<P>::st(at32(plane, e), 0, z);
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -61,7 +61,7 @@ __device__ void acc_inside(const Geom &g, const typename St<P>::pair_t *links,
     Site t = neighbour(g, s, mu, dir, sg);
     cx<T> psi[4][3], w[3][3];
     lds_load<T>(buf, nh, local_half(g, t), psi);
-    load_w<P, T>(links, angles, qhat, g.V, mu, dir > 0 ? i : (int64_t)encode(g, t), w);
+    load_w<P, T>(links, angles, qhat, g, mu, dir > 0 ? i : (int64_t)encode(g, t), w);
     if (dir > 0)
       hop_fwd<T>(mu, w, psi, (T)1, acc);
     else
@@ -88,7 +88,7 @@ __device__ void acc_outside(const Geom &g, const typename St<P>::pair_t *links,
     int64_t j = encode(g, t);
     cx<T> psi[4][3], w[3][3];
     load_spinor<P, T>(v, j, psi);
-    load_w<P, T>(links, angles, qhat, g.V, mu, dir > 0 ? i : j, w);
+    load_w<P, T>(links, angles, qhat, g, mu, dir > 0 ? i : j, w);
     if (dir > 0)
       hop_fwd<T>(mu, w, psi, (T)sg, acc);
     else
@@ -158,7 +158,7 @@ __device__ __forceinline__ void sap_block_body(const Geom &g, const SapOp<P> &a,
     if (odd) {
       // u_o = D_oo^-1 r_o; r_o is parked in the residual field until the end
       store_spinor<P, T>(vv.r, i, r);
-      pauli_mul<P, T>(a.pinv, g.Vh, ie, r, tmp);
+      pauli_mul<P, T>(a.pinv, g, ie, r, tmp);
       lds_store<T>(buf1, nh, h, tmp);
     }
   }
@@ -185,7 +185,7 @@ __device__ __forceinline__ void sap_block_body(const Geom &g, const SapOp<P> &a,
       for (int x = 0; x < 4; x++)
 #pragma unroll
         for (int c = 0; c < 3; c++) acc[x][c] = (T)(-0.5) * acc[x][c];
-      pauli_mul<P, T>(a.pinv, g.Vh, ie, acc, tmp);
+      pauli_mul<P, T>(a.pinv, g, ie, acc, tmp);
       lds_store<T>(buf1, nh, h, tmp);
     }
     __syncthreads();
@@ -196,7 +196,7 @@ __device__ __forceinline__ void sap_block_body(const Geom &g, const SapOp<P> &a,
       if (act) {
         // t = P s - D_eo^L w_o = P s + acc_in(w)/2
         acc_inside<P, T>(g, a.links, a.angles, a.qhat, st, i, buf1, nh, acc);
-        pauli_mul<P, T>(a.pauli, g.V, i, s, tmp);
+        pauli_mul<P, T>(a.pauli, g, i, s, tmp);
 #pragma unroll
         for (int x = 0; x < 4; x++)
 #pragma unroll
@@ -251,7 +251,7 @@ __device__ __forceinline__ void sap_block_body(const Geom &g, const SapOp<P> &a,
     for (int x = 0; x < 4; x++)
 #pragma unroll
       for (int c = 0; c < 3; c++) acc[x][c] = r[x][c] + (T)0.5 * acc[x][c];
-    pauli_mul<P, T>(a.pinv, g.Vh, ie, acc, v);
+    pauli_mul<P, T>(a.pinv, g, ie, acc, v);
   } else {
     lds_load<T>(bufv, nh, h, v);
   }

@@ -100,8 +100,9 @@ __device__ __forceinline__ void rows_mul(typename St<P>::pair_t m[3][6], const c
 // triangle), kept in storage precision: the diagonal entry (d, 0) and the
 // conjugates below the diagonal are exact in every storage format.
 template <int P>
-__device__ __forceinline__ void load_rows(const typename St<P>::pair_t *pa, int64_t stride, uint32_t j, int b,
+__device__ __forceinline__ void load_rows(const typename St<P>::pair_t *pa, const Geom &g, uint32_t j, int b,
                                           int rh, typename St<P>::pair_t m[3][6]) {
+  const uint32_t e = g.rd.base(j, 36);
 #pragma unroll
   for (int r = 0; r < 3; r++) {
     const int i = 3 * rh + r;
@@ -109,7 +110,7 @@ __device__ __forceinline__ void load_rows(const typename St<P>::pair_t *pa, int6
     for (int k = 0; k < 6; k++) {
       const int lo = i < k ? i : k, hi = i < k ? k : i;
       const int pair = 18 * b + (i == k ? (i >> 1) : 3 + tri_index(lo, hi));
-      cx<float> z = gld_pair<P>(pa + (int64_t)pair * stride, j);
+      cx<float> z = gld_pair<P>(pa + pair * g.Vbh, e);
       cx<float> e;
       if (i == k)
         e = {(i & 1) ? z.im : z.re, 0.f};
@@ -124,8 +125,9 @@ __device__ __forceinline__ void load_rows(const typename St<P>::pair_t *pa, int6
 template <int P>
 __device__ __forceinline__ void load_spin(const Spinor<P> &s, int64_t i, int a, cx<float> out[3]) {
   const uint32_t j = (uint32_t)(i - s.off);
+  const uint32_t e = s.rd.base(j, 12);
 #pragma unroll
-  for (int c = 0; c < 3; c++) out[c] = gld_pair<P>(s.data + (a * 3 + c) * s.stride, j);
+  for (int c = 0; c < 3; c++) out[c] = gld_pair<P>(s.data + (a * 3 + c) * s.rd.R, e);
   if constexpr (St<P>::scaled) {
     float f = gld(s.scale, j);
 #pragma unroll
@@ -140,6 +142,7 @@ __device__ __forceinline__ void load_spin(const Spinor<P> &s, int64_t i, int a, 
 template <int P>
 __device__ __forceinline__ void store_spin(const Spinor<P> &s, int64_t i, int a, const cx<float> v[3], bool act) {
   const uint32_t j = (uint32_t)(i - s.off);
+  const uint32_t e = s.rd.base(j, 12);
   float f = 1.f;
   if constexpr (St<P>::scaled) {
     float m = 0.f;
@@ -155,7 +158,7 @@ __device__ __forceinline__ void store_spin(const Spinor<P> &s, int64_t i, int a,
   }
   if (act) {
 #pragma unroll
-    for (int c = 0; c < 3; c++) gst_pair<P>(s.data + (a * 3 + c) * s.stride, j, cx<float>{f * v[c].re, f * v[c].im});
+    for (int c = 0; c < 3; c++) gst_pair<P>(s.data + (a * 3 + c) * s.rd.R, e, cx<float>{f * v[c].re, f * v[c].im});
   }
 }
 
@@ -251,9 +254,10 @@ __device__ __forceinline__ void sapq_body(const Geom &g, const SapOp<P> &a, cons
     lf[x] = fin ? lx : vb;
     lb[x] = bin ? local_lex(g, tb) : vb;
     if (act) {
+      const uint32_t el = g.rd.base((uint32_t)isite[x], 36);
 #pragma unroll
       for (int k = 0; k < 9; k++) {
-        pt z = gld(a.links, (int64_t)(mu * 9 + k) * g.V + isite[x]);
+        pt z = gld(a.links, el + (mu * 9 + k) * g.Vbh);
         lw[(mu * 9 + k) * vbp + lx] = fin ? z : zero_pair<P>();
       }
     }
@@ -261,8 +265,8 @@ __device__ __forceinline__ void sapq_body(const Geom &g, const SapOp<P> &a, cons
   if (tid < 36) lw[tid * vbp + vb] = zero_pair<P>();
   // Pauli rows: P on the even site, D_oo^-1 on the odd site
   pt m[2][3][6];
-  load_rows<P>(a.pauli, g.V, (uint32_t)(act ? isite[0] : 0), bb, rh, m[0]);
-  load_rows<P>(a.pinv, g.Vh, (uint32_t)(act ? ie : 0), bb, rh, m[1]);
+  load_rows<P>(a.pauli, g, (uint32_t)(act ? isite[0] : 0), bb, rh, m[0]);
+  load_rows<P>(a.pinv, g, (uint32_t)(act ? ie : 0), bb, rh, m[1]);
 
   // in-block hops of direction mu of the lane's site of parity x, from the
   // other parity's vector in LDS; partial sums over the quad
@@ -325,12 +329,13 @@ __device__ __forceinline__ void sapq_body(const Geom &g, const SapOp<P> &a, cons
           Site t = neighbour(g, st[x], mu, dir, sg);
           int64_t j = encode(g, t);
           cx<T> psi[4][3], w[3][3];
-          const int64_t il = dir > 0 ? isite[x] : j;
-          const T f = St<P>::scaled ? gld(vv.v.scale, j - vv.v.off) : (T)1;
+          const uint32_t el = g.rd.base((uint32_t)(dir > 0 ? isite[x] : j), 36);
+          const uint32_t jv = (uint32_t)(j - vv.v.off), ev = vv.v.rd.base(jv, 12);
+          const T f = St<P>::scaled ? gld(vv.v.scale, jv) : (T)1;
 #pragma unroll
-          for (int q = 0; q < 12; q++) psi[q / 3][q % 3] = f * gld_pair<P>(vv.v.data + q * vv.v.stride, j - vv.v.off);
+          for (int q = 0; q < 12; q++) psi[q / 3][q % 3] = f * gld_pair<P>(vv.v.data + q * vv.v.rd.R, ev);
 #pragma unroll
-          for (int q = 0; q < 9; q++) w[q / 3][q % 3] = gld_pair<P>(a.links + (int64_t)(mu * 9 + q) * g.V, il);
+          for (int q = 0; q < 9; q++) w[q / 3][q % 3] = gld_pair<P>(a.links + (mu * 9 + q) * g.Vbh, el);
           if (dir > 0)
             hop_fwd<T>(mu, w, psi, (T)sg, acc);
           else

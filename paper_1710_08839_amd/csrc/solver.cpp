@@ -78,7 +78,7 @@ struct Schur {
   void *tmp;  // odd-half temporary
   qxd_status apply(void *in_e, void *out_e, hipStream_t st) {
     const Geom &g = f->g;
-    SpinorArg in{in_e, g.Vh, 0}, out{out_e, g.Vh, 0}, t{tmp, g.Vh, g.Vh}, none{nullptr, 0, 0};
+    SpinorArg in{in_e, g.Vh, 0, g.rd}, out{out_e, g.Vh, 0, g.rd}, t{tmp, g.Vh, g.Vh, g.rd}, none{nullptr, 0, 0, g.rd};
     CK(launch_dirac(prec, DK_ODD, g, of, in, none, t, -0.5, st));
     CK(launch_dirac(prec, DK_EVEN, g, of, t, in, out, 0.5, st));
     return QXD_OK;
@@ -108,7 +108,7 @@ qxd_status eo_gcr(Field *f, const Operator &op, const qxd_solver &s, void *eta, 
   if (w.err) return w.err;
   double *beta = scal, *rec = scal + 2 * MAXV, *rn2 = rec + 3 * MAXV, *misc = rn2 + 4;
   Schur A{f, f->op_fields(op, P), P, tmp};
-  auto H = [&](void *p) { return SpinorArg{p, g.Vh, 0}; };
+  auto H = [&](void *p) { return SpinorArg{p, g.Vh, 0, g.rd}; };
   SpinorArg FULL_eta{eta, g.V, 0}, FULL_psi{psi, g.V, 0}, FULL{full, g.V, 0}, none{nullptr, 0, 0};
   OpFields of = f->op_fields(op, P);
 
@@ -127,7 +127,7 @@ qxd_status eo_gcr(Field *f, const Operator &op, const qxd_solver &s, void *eta, 
   }
   const double eta_n = sqrt(eta2);
   // b = eta^_e = eta_e + acc(D_oo^-1 eta_o)/2
-  SpinorArg t_o{tmp, g.Vh, g.Vh};
+  SpinorArg t_o{tmp, g.Vh, g.Vh, g.rd};
   CK(launch_dirac(P, DK_ODD, g, of, FULL_eta, FULL_eta, t_o, 0.0, st));
   CK(launch_dirac(P, DK_EVEN_ID, g, of, t_o, FULL_eta, H(b), 0.5, st));
   // x = guess_e or 0; r = b - D^ x
@@ -187,7 +187,7 @@ qxd_status eo_gcr(Field *f, const Operator &op, const qxd_solver &s, void *eta, 
       CS(fetch(&r2, rn2, 1, st));
     }
     // psi_e = x, psi_o = D_oo^-1 (eta_o + acc(x)/2); true residual in FP64
-    CK(blas_axpby<P, P>(SpinorArg{psi, g.V, 0}, 0.0, H(x), 1.0, 0, g.Vh, partial, nullptr, st));
+    CK(blas_axpby<P, P>(SpinorArg{psi, g.V, 0, g.rd}, 0.0, H(x), 1.0, 0, g.Vh, partial, nullptr, st));
     CK(launch_dirac(P, DK_ODD, g, of, H(x), FULL_eta, FULL_psi, 0.5, st));
     CK(launch_dirac(P, DK_FULL, g, of, FULL_psi, FULL_psi, FULL, -0.5, st));
     CK(blas_axpby<P, P>(FULL, -1.0, FULL_eta, 1.0, 0, g.V, partial, misc, st));
@@ -257,10 +257,10 @@ qxd_status sap_apply_t(Field *f, const Operator &op, int ncy, int nmr, void *rho
   a.qhat = of.qhat;
   a.pauli = (const typename St<P>::pair_t *)of.pauli;
   a.pinv = (const typename St<P>::pair_t *)of.pinv;
-  a.rho = spinor_view<P>(rho, g.V, 0);
-  a.r = spinor_view<P>(r, g.V, 0);
-  a.psi = spinor_view<P>(psi, g.V, 0);
-  a.v = spinor_view<P>(v, g.V, 0);
+  a.rho = spinor_view<P>(rho, g.V, 0, g);
+  a.r = spinor_view<P>(r, g.V, 0, g);
+  a.psi = spinor_view<P>(psi, g.V, 0, g);
+  a.v = spinor_view<P>(v, g.V, 0, g);
   a.nmr = nmr;
   for (int cy = 0; cy < ncy; cy++)
     for (int c = 0; c < 2; c++) {

@@ -122,8 +122,9 @@ def _ptr(t):
 
 
 def set_dirac_variant(choice=0):
-    """Force a Dirac kernel variant (hop group 1/2/4/8, +16 for LDS staging);
-    0 returns to the autotuner.  A testing hook."""
+    """Force a Dirac kernel variant (hop group 1/2/4/8, +16 for LDS staging,
+    +32 for non-temporal Pauli/output streams with LDS staging); 0 returns to
+    the autotuner.  A testing hook."""
     _check(lib().qxd_debug_set_dirac_variant(int(choice)))
 
 

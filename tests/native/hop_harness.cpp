@@ -51,6 +51,23 @@ int main() {
             scale = std::fmax(scale, std::fabs(a[s][c].re));
           }
       }
-  printf("%.3e %.3e\n", worst, scale);
+  // division by the run length of the block-major layout
+  long bad = 0;
+  for (uint32_t R = 1; R <= 2048; R++) {
+    RunDiv d = make_rundiv(R);
+    const uint32_t probes[] = {0u, 1u, R - 1, R, R + 1, 2 * R - 1, 12345677u, (1u << 31) - 1, (1u << 31) - R};
+    for (uint32_t j : probes)
+      if (j < (1u << 31) && d.div(j) != j / R) bad++;
+    for (uint32_t j = 0; j < 3 * R + 7; j++)
+      if (d.div(j) != j / R) bad++;
+    std::mt19937 r32(R);
+    for (int t = 0; t < 200; t++) {
+      uint32_t j = r32() & 0x7fffffffu;
+      if (d.div(j) != j / R) bad++;
+      uint32_t e = d.base(j, 12);
+      if (e != (j / R) * 12 * R + j % R) bad++;
+    }
+  }
+  printf("%.3e %.3e %ld\n", worst, scale, bad);
   return 0;
 }

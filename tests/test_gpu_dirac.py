@@ -77,14 +77,15 @@ def test_operator_low_precision(case, prec):
         assert rel(to_host(y), oracle_op(case, which, x)) < TOL[prec]
 
 
-VARIANTS = [1, 2, 4, 8, 16 | 1, 16 | 2, 16 | 4, 16 | 8]
+VARIANTS = [1, 2, 4, 8, 16 | 1, 16 | 2, 16 | 4, 16 | 8, 48 | 1, 48 | 2, 48 | 4, 48 | 8]
 
 
-@pytest.mark.parametrize("choice", VARIANTS, ids=[f"g{v & 15}{'-lds' if v & 16 else ''}" for v in VARIANTS])
+@pytest.mark.parametrize("choice", VARIANTS,
+                         ids=[f"g{v & 15}{'-lds' if v & 16 else ''}{'-nt' if v & 32 else ''}" for v in VARIANTS])
 def test_every_kernel_variant(case, choice):
-    """Each hop-group size and the LDS-staged input, forced in turn (the
-    autotuner would otherwise pick one), for D, D^ and the hopping term in
-    FP64 and FP32."""
+    """Each hop-group size, the LDS-staged input and the non-temporal Pauli
+    and output streams, forced in turn (the autotuner would otherwise pick
+    one), for D, D^ and the hopping term in FP64 and FP32."""
     import torch
     from paper_1710_08839_amd import qxd
     x = case.source(9)

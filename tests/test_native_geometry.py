@@ -58,7 +58,9 @@ def test_native_geometry(harness, dims, cstar, tbc, block):
 
 def test_generic_hop_matches_projections(tmp_path):
     """The direction-generic hop used where lanes of one wavefront hop in
-    different directions equals the per-direction projections (1 -+ g_mu)."""
+    different directions equals the per-direction projections (1 -+ g_mu);
+    and the multiply-shift division by the run length of the block-major
+    field layout equals integer division."""
     exe = str(tmp_path / "hop_harness")
     cmd = ["/opt/rocm/bin/hipcc", "-x", "hip", "--offload-host-only", "-O1", "-std=c++17",
            "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROOT, "paper_1710_08839_amd", "csrc"),
@@ -66,6 +68,8 @@ def test_generic_hop_matches_projections(tmp_path):
     p = subprocess.run(cmd, capture_output=True, text=True)
     assert p.returncode == 0, p.stderr[-2000:]
     out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
-    worst, scale = float(out[0]), float(out[1])
+    worst, scale, bad = float(out[0]), float(out[1]), int(out[2])
     assert scale > 1.0
     assert worst < 1e-12 * scale
+    # the multiply-shift division of the block-major field layout is exact
+    assert bad == 0
