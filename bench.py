@@ -49,6 +49,17 @@ def kernel_hash():
             h.update(fh.read())
     return h.hexdigest()[:16]
 PREC_NAME = {0: "f64", 1: "f32", 2: "f16s", 3: "bf16"}
+
+
+def kernel_name(choice, prec):
+    """The Dirac kernel the autotuner picked (hop group, LDS staging,
+    non-temporal streams), as its template appears in profiler traces."""
+    if choice == 0:
+        return "dirac_kernel (not tuned)"
+    g, lds, nt = choice & 15, bool(choice & 16), bool(choice & 32)
+    if lds:
+        return f"dirac_lds_kernel<{prec}, 0, {g}, {'true' if nt else 'false'}>"
+    return f"dirac_kernel<{prec}, 0, {g}>"
 _T0 = time.perf_counter()
 
 
@@ -262,6 +273,8 @@ def main():
     ap.add_argument("--serve-max-rhs", type=int, default=3)
     ap.add_argument("--serve-rate", type=float, default=2.0, help="request arrivals per second")
     ap.add_argument("--precs", default="0,1,2,3")
+    ap.add_argument("--dirac-variant", type=int, default=0,
+                    help="force a Dirac kernel variant (0: autotune), e.g. to profile the tuned one")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (profiler counter calibration)")
     args = ap.parse_args()
@@ -275,6 +288,8 @@ def main():
 
     dims = (64, 32, 32, 32)
     ctx = qxd.Context(0)
+    if args.dirac_variant:
+        qxd.set_dirac_variant(args.dirac_variant)
     t0 = time.perf_counter()
     log("generating the 64x32^3 gauge field")
     u, a = synth.gauge_field(dims, 20171002, 0.25, 0.15)
@@ -304,6 +319,7 @@ def main():
         gbs = BYTES_PER_SITE[p] * V / (ms * 1e-3) / 1e9
         log(f"D {PREC_NAME[p]}: {ms:.4f} ms per application")
         dw[PREC_NAME[p]] = {"ms": round(ms, 4), "GB/s": round(gbs, 1),
+                            "kernel": kernel_name(args.dirac_variant or field.dirac_variant(p), p),
                             "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
                             "GFLOP/s": round(FLOPS_PER_SITE * V / (ms * 1e-3) / 1e9, 1),
                             "bytes_per_site": BYTES_PER_SITE[p]}
@@ -312,6 +328,7 @@ def main():
     torch.cuda.synchronize()
     ms = time_applies(field, q, 0, 3, args.steps, args.warmup)
     value = BYTES_PER_SITE[0] * V / (ms * 1e-3) / 1e9
+    kernel = kernel_name(args.dirac_variant or field.dirac_variant(0), 0)
     field.release()
 
     solves = None
@@ -349,7 +366,7 @@ def main():
                    "global_batch": 1, "seq_len": V, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(value, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(value / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get(kernel_hash()),
-                     "kernel": "dirac_kernel<F64, DK_FULL>",
+                     "kernel": kernel,
                      "bytes_per_launch": BYTES_PER_SITE[0] * V},
         "dw": dw,
         "solves": solves,

@@ -37,7 +37,10 @@
  *
  * Native layout: for speed, spinors can be kept in the library's private
  * device layout and precision (qxd_spinor_bytes / qxd_spinor_pack /
- * qxd_spinor_unpack); pass QXD_NATIVE to qxd_dirac_apply to use it.
+ * qxd_spinor_unpack); pass QXD_NATIVE to qxd_dirac_apply to use it.  Native
+ * buffers must be 16-byte aligned (QXD_EINVAL otherwise); their content is
+ * opaque (lattice blocks stored one after another, components grouped per
+ * 16 bytes) and may change between library versions.
  */
 #ifndef QXD_H
 #define QXD_H

@@ -27,6 +27,11 @@ extern "C" {
  * threads.  QXD_EINVAL for any other value. */
 qxd_status qxd_debug_set_dirac_variant(int choice);
 
+/* The variant the autotuner chose for the full operator D (phase folded into
+ * the links) on this field's lattice in precision prec, in the encoding of
+ * qxd_debug_set_dirac_variant; 0 if D has not been applied yet. */
+qxd_status qxd_debug_get_dirac_variant(const qxd_field *field, qxd_prec prec, int *choice);
+
 #ifdef __cplusplus
 }
 #endif

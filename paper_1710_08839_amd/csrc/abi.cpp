@@ -103,7 +103,7 @@ qxd_status Field::ensure_links(int prec, hipStream_t st) {
   if (links_ready[prec]) return QXD_OK;
   int64_t n_pairs = (int64_t)36 * g.V;
   QXD_HIP_CHECK(links[prec].ensure(n_pairs * pair_bytes(prec)));
-  QXD_HIP_CHECK(launch_convert_pairs(prec, links[QXD_F64].as<double2>(), links[prec].p, n_pairs, st));
+  QXD_HIP_CHECK(launch_convert_field(prec, g, 36, g.V, links[QXD_F64].as<double2>(), links[prec].p, st));
   QXD_HIP_CHECK(angles[prec].ensure((size_t)4 * g.V * sizeof(float)));
   QXD_HIP_CHECK(launch_convert_reals(angles[QXD_F64].as<double>(), angles[prec].as<float>(), (int64_t)4 * g.V, st));
   links_ready[prec] = true;
@@ -160,10 +160,10 @@ qxd_status Field::get_op(const qxd_quark &q, int prec, Operator **out, hipStream
   if (!op->ready[prec]) {
     QXD_HIP_CHECK(op->pauli[prec].ensure((size_t)36 * g.V * pair_bytes(prec)));
     QXD_HIP_CHECK(op->pinv[prec].ensure((size_t)36 * g.Vh * pair_bytes(prec)));
-    QXD_HIP_CHECK(launch_convert_pairs(prec, op->pauli[QXD_F64].as<double2>(), op->pauli[prec].p, (int64_t)36 * g.V, st));
-    QXD_HIP_CHECK(launch_convert_pairs(prec, op->pinv[QXD_F64].as<double2>(), op->pinv[prec].p, (int64_t)36 * g.Vh, st));
+    QXD_HIP_CHECK(launch_convert_field(prec, g, 36, g.V, op->pauli[QXD_F64].as<double2>(), op->pauli[prec].p, st));
+    QXD_HIP_CHECK(launch_convert_field(prec, g, 36, g.Vh, op->pinv[QXD_F64].as<double2>(), op->pinv[prec].p, st));
     QXD_HIP_CHECK(op->wl[prec].ensure((size_t)36 * g.V * pair_bytes(prec)));
-    QXD_HIP_CHECK(launch_convert_pairs(prec, op->wl[QXD_F64].as<double2>(), op->wl[prec].p, (int64_t)36 * g.V, st));
+    QXD_HIP_CHECK(launch_convert_field(prec, g, 36, g.V, op->wl[QXD_F64].as<double2>(), op->wl[prec].p, st));
     op->ready[prec] = true;
   }
   qxd_status s = ensure_links(prec, st);
@@ -238,6 +238,15 @@ static bool valid_prec(int p) { return p >= QXD_F64 && p <= QXD_BF16; }
 extern "C" {
 
 int qxd_abi_version(void) { return QXD_ABI_VERSION; }
+
+qxd_status qxd_debug_get_dirac_variant(const qxd_field *field, qxd_prec prec, int *choice) {
+  if (!field || !choice || prec < QXD_F64 || prec > QXD_BF16) {
+    set_error("field and choice must be non-NULL and prec valid");
+    return QXD_EINVAL;
+  }
+  *choice = tuned_group((int)prec, (int)DK_FULL, field->g.V, 0);
+  return QXD_OK;
+}
 
 qxd_status qxd_debug_set_dirac_variant(int choice) {
   if (!force_dirac_variant(choice)) {
@@ -356,10 +365,16 @@ qxd_status qxd_spinor_bytes(const qxd_field *field, qxd_prec prec, size_t *bytes
   return QXD_OK;
 }
 
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
 qxd_status qxd_spinor_pack(qxd_field *field, qxd_prec prec, const double *in_dev, void *out_dev,
                            int nrhs, void *stream) {
   if (!field || !in_dev || !out_dev || nrhs < 1 || !valid_prec(prec)) {
     set_error("invalid arguments to qxd_spinor_pack");
+    return QXD_EINVAL;
+  }
+  if (!aligned16(out_dev)) {
+    set_error("native spinors must be 16-byte aligned");
     return QXD_EINVAL;
   }
   QXD_HIP_CHECK(hipSetDevice(field->ctx->device));
@@ -371,6 +386,10 @@ qxd_status qxd_spinor_unpack(qxd_field *field, qxd_prec prec, const void *in_dev
                              int nrhs, void *stream) {
   if (!field || !in_dev || !out_dev || nrhs < 1 || !valid_prec(prec)) {
     set_error("invalid arguments to qxd_spinor_unpack");
+    return QXD_EINVAL;
+  }
+  if (!aligned16(in_dev)) {
+    set_error("native spinors must be 16-byte aligned");
     return QXD_EINVAL;
   }
   QXD_HIP_CHECK(hipSetDevice(field->ctx->device));
@@ -388,6 +407,10 @@ qxd_status qxd_dirac_apply(qxd_field *field, const qxd_quark *quarks, int nquark
   }
   if (in_dev == out_dev) {
     set_error("in and out must not overlap");
+    return QXD_EINVAL;
+  }
+  if ((flags & QXD_NATIVE) && (!aligned16(in_dev) || !aligned16(out_dev))) {
+    set_error("native spinors must be 16-byte aligned");
     return QXD_EINVAL;
   }
   std::lock_guard<std::recursive_mutex> lk(field->mu);

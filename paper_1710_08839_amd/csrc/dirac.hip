@@ -361,7 +361,8 @@ hipError_t launch_dirac(int prec, DiracKind kind, const Geom &g, const OpFields 
 
 bool force_dirac_variant(int choice) {
   const int group = choice & (LDS_VARIANT - 1);
-  if (choice != 0 && ((choice & ~(NT_VARIANT | LDS_VARIANT | 15)) || (group != 1 && group != 2 && group != 4 && group != 8)))
+  if (choice != 0 && ((choice & ~(NT_VARIANT | LDS_VARIANT | 15)) ||
+                      (group != 1 && group != 2 && group != 4 && group != 8)))
     return false;
   g_forced_choice.store(choice);
   return true;

@@ -17,23 +17,34 @@
 
 namespace qxd {
 
-// Link of direction mu of the site whose block-major element base (K = 36)
-// is e.
+// Link of direction MU (components 9 MU .. 9 MU + 8 of K = 36) of the site
+// whose block-major element base is e: the 16-byte groups that cover them.
+template <int P, class T, int MU>
+QXD_HD void load_link_mu(const typename St<P>::pair_t *links, uint32_t R, uint32_t e, cx<T> u[3][3]) {
+  constexpr int W = VW<P>, k0 = 9 * MU, g0 = k0 / W, ng = (k0 + 8) / W - g0 + 1;
+  cx<typename St<P>::comp_t> buf[ng * W];
+#pragma unroll
+  for (int gk = 0; gk < ng; gk++) ld_group<P>(at32(links + (g0 + gk) * W * R, e), buf + gk * W);
+#pragma unroll
+  for (int rc = 0; rc < 9; rc++) u[rc / 3][rc % 3] = {(T)buf[k0 - g0 * W + rc].re, (T)buf[k0 - g0 * W + rc].im};
+}
+
+// Link of direction mu (wavefront-uniform) of the site with element base e.
 template <int P, class T>
 QXD_HD void load_link_at(const typename St<P>::pair_t *links, const Geom &g, int mu, uint32_t e,
                          cx<T> u[3][3]) {
-#pragma unroll
-  for (int r = 0; r < 3; r++)
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-      auto z = St<P>::ld(at32(links + (mu * 9 + r * 3 + c) * g.Vbh, e), 0);
-      u[r][c] = {(T)z.re, (T)z.im};
-    }
+  const uint32_t R = (uint32_t)g.Vbh;
+  switch (mu) {
+    case 0: load_link_mu<P, T, 0>(links, R, e, u); break;
+    case 1: load_link_mu<P, T, 1>(links, R, e, u); break;
+    case 2: load_link_mu<P, T, 2>(links, R, e, u); break;
+    default: load_link_mu<P, T, 3>(links, R, e, u); break;
+  }
 }
 
 template <int P, class T>
 QXD_HD void load_link(const typename St<P>::pair_t *links, const Geom &g, int mu, int64_t i, cx<T> u[3][3]) {
-  load_link_at<P, T>(links, g, mu, g.rd.base((uint32_t)i, 36), u);
+  load_link_at<P, T>(links, g, mu, g.rd.base((uint32_t)i, 36, VW<P>), u);
 }
 
 template <class T> QXD_HD void sincos_t(T x, T *s, T *c);
@@ -138,22 +149,21 @@ QXD_HD void hop_bwd(int mu, const cx<T> w[3][3], const cx<T> psi[4][3], T sign, 
 // 3-17 upper triangle row by row.
 QXD_HD constexpr int tri_index(int i, int j) { return i * 6 - i * (i + 1) / 2 + (j - i - 1); }
 
-// out = A v for one packed Hermitian block whose 18 pairs start at pair
-// `base` of site j (block-major, K = 36 pairs per site).
-template <int P, class T, bool NT = false>
-QXD_HD void herm6_mul(const typename St<P>::pair_t *pa, const Geom &g, int64_t j, int base,
-                      const cx<T> v[6], cx<T> out[6]) {
-  const uint32_t e = g.rd.base((uint32_t)j, 36);
-  auto ldp = [&](int pair) {
-    if constexpr (NT)
-      return ld_nt<P>(at32(pa + pair * g.Vbh, e));
-    else
-      return St<P>::ld(at32(pa + pair * g.Vbh, e), 0);
-  };
+// out = A v for the packed Hermitian block BLK (pairs 18 BLK .. 18 BLK + 17
+// of K = 36) of site j, read as the 16-byte groups that cover them.
+template <int P, class T, bool NT, int BLK>
+QXD_HD void herm6_mul(const typename St<P>::pair_t *pa, const Geom &g, int64_t j, const cx<T> v[6],
+                      cx<T> out[6]) {
+  constexpr int W = VW<P>, k0 = 18 * BLK, g0 = k0 / W, ng = (k0 + 17) / W - g0 + 1;
+  const uint32_t e = g.rd.base((uint32_t)j, 36, W), R = (uint32_t)g.Vbh;
+  cx<typename St<P>::comp_t> buf[ng * W];
+#pragma unroll
+  for (int gk = 0; gk < ng; gk++) ld_group<P, NT>(at32(pa + (g0 + gk) * W * R, e), buf + gk * W);
+  auto ldp = [&](int pair) { return buf[k0 - g0 * W + pair]; };
   T d[6];
 #pragma unroll
   for (int k = 0; k < 3; k++) {
-    auto z = ldp(base + k);
+    auto z = ldp(k);
     d[2 * k] = (T)z.re;
     d[2 * k + 1] = (T)z.im;
   }
@@ -163,7 +173,7 @@ QXD_HD void herm6_mul(const typename St<P>::pair_t *pa, const Geom &g, int64_t j
   for (int i = 0; i < 6; i++)
 #pragma unroll
     for (int k = i + 1; k < 6; k++) {
-      auto z = ldp(base + 3 + tri_index(i, k));
+      auto z = ldp(3 + tri_index(i, k));
       cx<T> a{(T)z.re, (T)z.im};
       out[i] = fma_acc(out[i], a, v[k]);
       out[k] = fma_accc(out[k], a, v[i]);
@@ -183,7 +193,10 @@ QXD_HD void pauli_mul(const typename St<P>::pair_t *pa, const Geom &g, int64_t j
       v[c] = psi[2 * blk][c];
       v[3 + c] = psi[2 * blk + 1][c];
     }
-    herm6_mul<P, T, NT>(pa, g, j, 18 * blk, v, o);
+    if (blk == 0)
+      herm6_mul<P, T, NT, 0>(pa, g, j, v, o);
+    else
+      herm6_mul<P, T, NT, 1>(pa, g, j, v, o);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
       out[2 * blk][c] = o[c];

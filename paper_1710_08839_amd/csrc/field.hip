@@ -199,13 +199,26 @@ __global__ void pauli_invert_kernel(Geom g, const double2 *pauli, double2 *pinv,
     }
 }
 
+// FP64 block-major field (K pairs per site, packing 1) -> storage precision P
+// (packing VW<P>); one thread per (site, 16-byte group).
 template <int P>
-__global__ void convert_pairs_kernel(const double2 *src, typename St<P>::pair_t *dst, int64_t n) {
-  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  double2 v = src[k];
+__global__ void convert_field_kernel(RunDiv rd, int K, int64_t sites, const double2 *src,
+                                     typename St<P>::pair_t *dst) {
+  constexpr int W = VW<P>;
+  const int ng = K / W;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= sites * ng) return;
+  const uint32_t j = (uint32_t)(t / ng);
+  const int gk = (int)(t - (int64_t)j * ng);
+  const uint32_t e1 = rd.base(j, K, 1), ew = rd.base(j, K, W);
   using C = typename St<P>::comp_t;
-  St<P>::st(dst, k, cx<C>{(C)v.x, (C)v.y});
+  cx<C> z[W];
+#pragma unroll
+  for (int w = 0; w < W; w++) {
+    double2 v = src[e1 + rd.comp_off(gk * W + w, 1)];
+    z[w] = {(C)v.x, (C)v.y};
+  }
+  st_group<P>(dst + ew + (uint32_t)gk * W * rd.R, z);
 }
 
 __global__ void convert_reals_kernel(const double *src, float *dst, int64_t n) {
@@ -320,13 +333,20 @@ hipError_t launch_pauli_invert(const Geom &g, const double2 *pauli, double2 *pin
   return hipGetLastError();
 }
 
-hipError_t launch_convert_pairs(int prec, const double2 *src, void *dst, int64_t n, hipStream_t st) {
-  unsigned gr = grid_for(n, 256);
+hipError_t launch_convert_field(int prec, const Geom &g, int K, int64_t sites, const double2 *src, void *dst,
+                                hipStream_t st) {
+  const RunDiv rd = g.rd;
   switch (prec) {
-    case QXD_F64: return hipMemcpyAsync(dst, src, n * 16, hipMemcpyDeviceToDevice, st);
-    case QXD_F32: convert_pairs_kernel<QXD_F32><<<gr, 256, 0, st>>>(src, (float2 *)dst, n); break;
-    case QXD_F16S: convert_pairs_kernel<QXD_F16S><<<gr, 256, 0, st>>>(src, (h2_t *)dst, n); break;
-    case QXD_BF16: convert_pairs_kernel<QXD_BF16><<<gr, 256, 0, st>>>(src, (uint32_t *)dst, n); break;
+    case QXD_F64: return hipMemcpyAsync(dst, src, (size_t)K * sites * 16, hipMemcpyDeviceToDevice, st);
+    case QXD_F32:
+      convert_field_kernel<QXD_F32><<<grid_for(sites * K / 2, 256), 256, 0, st>>>(rd, K, sites, src, (float2 *)dst);
+      break;
+    case QXD_F16S:
+      convert_field_kernel<QXD_F16S><<<grid_for(sites * K / 4, 256), 256, 0, st>>>(rd, K, sites, src, (h2_t *)dst);
+      break;
+    case QXD_BF16:
+      convert_field_kernel<QXD_BF16><<<grid_for(sites * K / 4, 256), 256, 0, st>>>(rd, K, sites, src, (uint32_t *)dst);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -28,7 +28,10 @@ hipError_t launch_fold_phase(const Geom &g, const double2 *links, const double *
                              double2 *w, hipStream_t st);
 
 // FP64 pairs -> storage precision `prec` (n pairs).
-hipError_t launch_convert_pairs(int prec, const double2 *src, void *dst, int64_t n, hipStream_t st);
+// FP64 block-major field with K pairs per site over `sites` sites -> the
+// storage precision and component packing of prec.
+hipError_t launch_convert_field(int prec, const Geom &g, int K, int64_t sites, const double2 *src, void *dst,
+                                hipStream_t st);
 hipError_t launch_convert_reals(const double *src, float *dst, int64_t n, hipStream_t st);
 
 // API-layout FP64 spinors <-> native spinors of precision prec (nrhs each).

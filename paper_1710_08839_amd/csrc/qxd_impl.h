@@ -12,12 +12,16 @@
 //
 // Fields are stored block-major: the sites of one parity of one block form a
 // run of R = Vb/2 consecutive native indices, and an array with K components
-// per site keeps each component of a run contiguous,
-//   element (site j, component k) at  ((j / R) * K + k) * R + j % R,
+// per site keeps the components of a run together, W at a time: W = 16 bytes
+// / (bytes of one stored complex) consecutive components of a site form one
+// 16-byte group (W = 1 in FP64, 2 in FP32, 4 with 16-bit storage), and each
+// group index of a run is contiguous over the run's sites,
+//   element (site j, component k) at
+//       (j / R) K R + (k / W) W R + (j % R) W + k % W,
 // where j is the site's index in the range of sites the array covers (the
 // whole lattice, or one parity half).  A work-group that processes a block
-// therefore reads a few contiguous stretches of memory per field instead of
-// one short piece of each of many lattice-sized planes.
+// therefore reads a few contiguous stretches of memory per field, and a lane
+// fetches W components with one 16-byte load.
 //   spinor    K = 12 (spin*3 + colour)    (+ [sites] fp32 scale for F16S)
 //   links     K = 36 (mu*9 + row*3 + col) forward links U(x,mu), all sites
 //   angles    K = 4  (mu)                 U(1) potential A(x,mu), all sites
@@ -192,6 +196,38 @@ QXD_HD void st_nt(typename St<P>::pair_t *p, cx<typename St<P>::comp_t> z) {
   __builtin_nontemporal_store(__builtin_bit_cast(R, v), (R *)p);
 }
 
+// Components per 16-byte group of the block-major layout.
+template <int P>
+constexpr int VW = 16 / (int)sizeof(typename St<P>::pair_t);
+
+// One 16-byte group (VW<P> stored complex numbers) at p, 16-byte aligned.
+template <int P, bool NT = false>
+QXD_HD void ld_group(const typename St<P>::pair_t *p, cx<typename St<P>::comp_t> out[VW<P>]) {
+  using R = typename RawOf<16>::type;
+  R r;
+  if constexpr (NT)
+    r = __builtin_nontemporal_load((const R *)p);
+  else
+    r = *(const R *)p;
+  typename St<P>::pair_t v[VW<P>];
+  __builtin_memcpy(v, &r, 16);
+#pragma unroll
+  for (int w = 0; w < VW<P>; w++) out[w] = St<P>::ld(v, w);
+}
+template <int P, bool NT = false>
+QXD_HD void st_group(typename St<P>::pair_t *p, const cx<typename St<P>::comp_t> in[VW<P>]) {
+  using R = typename RawOf<16>::type;
+  typename St<P>::pair_t v[VW<P>];
+#pragma unroll
+  for (int w = 0; w < VW<P>; w++) St<P>::st(v, w, in[w]);
+  R r;
+  __builtin_memcpy(&r, v, 16);
+  if constexpr (NT)
+    __builtin_nontemporal_store(r, (R *)p);
+  else
+    *(R *)p = r;
+}
+
 // pair i of a device array in storage format, as complex
 template <int P>
 __device__ __forceinline__ cx<typename St<P>::comp_t> gld_pair(const typename St<P>::pair_t *p, int64_t i) {
@@ -248,11 +284,12 @@ struct RunDiv {
   uint32_t R;
   QXD_HD uint32_t div(uint32_t j) const { return (uint32_t)(((uint64_t)j * m) >> shift); }
   // element index of component 0 of site j in an array with K components
-  // per site; component k is at + k * R
-  QXD_HD uint32_t base(uint32_t j, int K) const {
+  // per site packed W at a time; component k is at + comp_off(k, W)
+  QXD_HD uint32_t base(uint32_t j, int K, int W = 1) const {
     uint32_t q = div(j);
-    return q * (uint32_t)K * R + (j - q * R);
+    return q * (uint32_t)K * R + (j - q * R) * (uint32_t)W;
   }
+  QXD_HD uint32_t comp_off(int k, int W) const { return (uint32_t)(k / W) * (uint32_t)W * R + (uint32_t)(k % W); }
 };
 
 inline RunDiv make_rundiv(uint32_t R) {
@@ -405,9 +442,9 @@ QXD_HD int64_t ext_lex(const Geom &g, const int x[4]) {
 // spinor views
 // ---------------------------------------------------------------------------
 // A spinor view over the sites [off, off + sites) of the native order:
-// component c of native site i is element (j / R * 12 + c) * R + j % R with
-// j = i - off (block-major layout); F16S keeps one fp32 scale per site after
-// the 12 * sites pairs.
+// component c (= spin * 3 + colour) of native site i is the block-major
+// element of (j = i - off, c) with K = 12; F16S keeps one fp32 scale per site
+// after the 12 * sites pairs.
 template <int P>
 struct Spinor {
   typename St<P>::pair_t *data;
@@ -435,16 +472,16 @@ QXD_HD Spinor<P> spinor_view(void *base, int64_t sites, int64_t off, const Geom 
 // one address register.
 template <int P, class T>
 QXD_HD void load_spinor(const Spinor<P> &s, int64_t i, cx<T> psi[4][3]) {
+  constexpr int W = VW<P>;
   uint32_t j = (uint32_t)(i - s.off);
-  uint32_t e = s.rd.base(j, 12);
+  uint32_t e = s.rd.base(j, 12, W);
 #pragma unroll
-  for (int a = 0; a < 4; a++)
+  for (int gk = 0; gk < 12 / W; gk++) {
+    cx<typename St<P>::comp_t> z[W];
+    ld_group<P>(at32(s.data + gk * W * s.rd.R, e), z);
 #pragma unroll
-    for (int c = 0; c < 3; c++) {
-      const typename St<P>::pair_t *plane = s.data + (a * 3 + c) * s.rd.R;
-      cx<typename St<P>::comp_t> z = St<P>::ld(at32(plane, e), 0);
-      psi[a][c] = {(T)z.re, (T)z.im};
-    }
+    for (int w = 0; w < W; w++) psi[(gk * W + w) / 3][(gk * W + w) % 3] = {(T)z[w].re, (T)z[w].im};
+  }
   if constexpr (St<P>::scaled) {
     T f = (T)*at32(s.scale, j);
 #pragma unroll
@@ -456,8 +493,9 @@ QXD_HD void load_spinor(const Spinor<P> &s, int64_t i, cx<T> psi[4][3]) {
 
 template <int P, class T, bool NT = false>
 QXD_HD void store_spinor(const Spinor<P> &s, int64_t i, const cx<T> psi[4][3]) {
+  constexpr int W = VW<P>;
   int64_t j = i - s.off;
-  uint32_t e = s.rd.base((uint32_t)j, 12);
+  uint32_t e = s.rd.base((uint32_t)j, 12, W);
   using C = typename St<P>::comp_t;
   C f = (C)1;
   if constexpr (St<P>::scaled) {
@@ -475,16 +513,15 @@ QXD_HD void store_spinor(const Spinor<P> &s, int64_t i, const cx<T> psi[4][3]) {
     f = m > 0 ? (C)(1.0f / (float)m) : (C)0;
   }
 #pragma unroll
-  for (int a = 0; a < 4; a++)
+  for (int gk = 0; gk < 12 / W; gk++) {
+    cx<C> z[W];
 #pragma unroll
-    for (int c = 0; c < 3; c++) {
-      typename St<P>::pair_t *plane = s.data + (a * 3 + c) * s.rd.R;
-      const cx<C> z{(C)(f * (C)psi[a][c].re), (C)(f * (C)psi[a][c].im)};
-      if constexpr (NT)
-        st_nt<P>(at32(plane, e), z);
-      else
-        St<P>::st(at32(plane, e), 0, z);
+    for (int w = 0; w < W; w++) {
+      const cx<T> &x = psi[(gk * W + w) / 3][(gk * W + w) % 3];
+      z[w] = {(C)(f * (C)x.re), (C)(f * (C)x.im)};
     }
+    st_group<P, NT>(at32(s.data + gk * W * s.rd.R, e), z);
+  }
 }
 
 // ---------------------------------------------------------------------------

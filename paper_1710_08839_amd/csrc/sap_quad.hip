@@ -102,7 +102,8 @@ __device__ __forceinline__ void rows_mul(typename St<P>::pair_t m[3][6], const c
 template <int P>
 __device__ __forceinline__ void load_rows(const typename St<P>::pair_t *pa, const Geom &g, uint32_t j, int b,
                                           int rh, typename St<P>::pair_t m[3][6]) {
-  const uint32_t e = g.rd.base(j, 36);
+  constexpr int W = VW<P>;
+  const uint32_t e = g.rd.base(j, 36, W);
 #pragma unroll
   for (int r = 0; r < 3; r++) {
     const int i = 3 * rh + r;
@@ -110,7 +111,7 @@ __device__ __forceinline__ void load_rows(const typename St<P>::pair_t *pa, cons
     for (int k = 0; k < 6; k++) {
       const int lo = i < k ? i : k, hi = i < k ? k : i;
       const int pair = 18 * b + (i == k ? (i >> 1) : 3 + tri_index(lo, hi));
-      cx<float> z = gld_pair<P>(pa + pair * g.Vbh, e);
+      cx<float> z = gld_pair<P>(pa + g.rd.comp_off(pair, W), e);
       cx<float> e;
       if (i == k)
         e = {(i & 1) ? z.im : z.re, 0.f};
@@ -125,9 +126,10 @@ __device__ __forceinline__ void load_rows(const typename St<P>::pair_t *pa, cons
 template <int P>
 __device__ __forceinline__ void load_spin(const Spinor<P> &s, int64_t i, int a, cx<float> out[3]) {
   const uint32_t j = (uint32_t)(i - s.off);
-  const uint32_t e = s.rd.base(j, 12);
+  constexpr int W = VW<P>;
+  const uint32_t e = s.rd.base(j, 12, W);
 #pragma unroll
-  for (int c = 0; c < 3; c++) out[c] = gld_pair<P>(s.data + (a * 3 + c) * s.rd.R, e);
+  for (int c = 0; c < 3; c++) out[c] = gld_pair<P>(s.data + s.rd.comp_off(a * 3 + c, W), e);
   if constexpr (St<P>::scaled) {
     float f = gld(s.scale, j);
 #pragma unroll
@@ -142,7 +144,8 @@ __device__ __forceinline__ void load_spin(const Spinor<P> &s, int64_t i, int a, 
 template <int P>
 __device__ __forceinline__ void store_spin(const Spinor<P> &s, int64_t i, int a, const cx<float> v[3], bool act) {
   const uint32_t j = (uint32_t)(i - s.off);
-  const uint32_t e = s.rd.base(j, 12);
+  constexpr int W = VW<P>;
+  const uint32_t e = s.rd.base(j, 12, W);
   float f = 1.f;
   if constexpr (St<P>::scaled) {
     float m = 0.f;
@@ -158,7 +161,8 @@ __device__ __forceinline__ void store_spin(const Spinor<P> &s, int64_t i, int a,
   }
   if (act) {
 #pragma unroll
-    for (int c = 0; c < 3; c++) gst_pair<P>(s.data + (a * 3 + c) * s.rd.R, e, cx<float>{f * v[c].re, f * v[c].im});
+    for (int c = 0; c < 3; c++)
+      gst_pair<P>(s.data + s.rd.comp_off(a * 3 + c, W), e, cx<float>{f * v[c].re, f * v[c].im});
   }
 }
 
@@ -254,10 +258,10 @@ __device__ __forceinline__ void sapq_body(const Geom &g, const SapOp<P> &a, cons
     lf[x] = fin ? lx : vb;
     lb[x] = bin ? local_lex(g, tb) : vb;
     if (act) {
-      const uint32_t el = g.rd.base((uint32_t)isite[x], 36);
+      const uint32_t el = g.rd.base((uint32_t)isite[x], 36, VW<P>);
 #pragma unroll
       for (int k = 0; k < 9; k++) {
-        pt z = gld(a.links, el + (mu * 9 + k) * g.Vbh);
+        pt z = gld(a.links, el + g.rd.comp_off(mu * 9 + k, VW<P>));
         lw[(mu * 9 + k) * vbp + lx] = fin ? z : zero_pair<P>();
       }
     }
@@ -329,13 +333,13 @@ __device__ __forceinline__ void sapq_body(const Geom &g, const SapOp<P> &a, cons
           Site t = neighbour(g, st[x], mu, dir, sg);
           int64_t j = encode(g, t);
           cx<T> psi[4][3], w[3][3];
-          const uint32_t el = g.rd.base((uint32_t)(dir > 0 ? isite[x] : j), 36);
-          const uint32_t jv = (uint32_t)(j - vv.v.off), ev = vv.v.rd.base(jv, 12);
+          const uint32_t el = g.rd.base((uint32_t)(dir > 0 ? isite[x] : j), 36, VW<P>);
+          const uint32_t jv = (uint32_t)(j - vv.v.off), ev = vv.v.rd.base(jv, 12, VW<P>);
           const T f = St<P>::scaled ? gld(vv.v.scale, jv) : (T)1;
 #pragma unroll
-          for (int q = 0; q < 12; q++) psi[q / 3][q % 3] = f * gld_pair<P>(vv.v.data + q * vv.v.rd.R, ev);
+          for (int q = 0; q < 12; q++) psi[q / 3][q % 3] = f * gld_pair<P>(vv.v.data + vv.v.rd.comp_off(q, VW<P>), ev);
 #pragma unroll
-          for (int q = 0; q < 9; q++) w[q / 3][q % 3] = gld_pair<P>(a.links + (mu * 9 + q) * g.Vbh, el);
+          for (int q = 0; q < 9; q++) w[q / 3][q % 3] = gld_pair<P>(a.links + g.rd.comp_off(mu * 9 + q, VW<P>), el);
           if (dir > 0)
             hop_fwd<T>(mu, w, psi, (T)sg, acc);
           else

@@ -83,6 +83,7 @@ SIGNATURES = {
     "qxd_serve_stop": ([_VP], _I),
     # testing hooks (include/qxd_debug.h)
     "qxd_debug_set_dirac_variant": ([_I], _I),
+    "qxd_debug_get_dirac_variant": ([_VP, _I, ctypes.POINTER(_I)], _I),
 }
 
 _lib = None
@@ -202,6 +203,14 @@ class Field:
 
     def unpack(self, prec, native, api, nrhs=1, stream=None):
         _check(lib().qxd_spinor_unpack(self.h, prec, _ptr(native), _ptr(api), nrhs, _stream(stream)))
+
+    def dirac_variant(self, prec):
+        """Kernel variant the autotuner chose for D in precision prec (0 if
+        D has not been applied yet): hop group + 16 (LDS staging) + 32
+        (non-temporal streams)."""
+        c = ctypes.c_int(0)
+        _check(lib().qxd_debug_get_dirac_variant(self.h, int(prec), ctypes.byref(c)))
+        return c.value
 
     def apply(self, quarks, op, prec, x, y, nrhs=1, native=False, stream=None):
         qs = quarks if isinstance(quarks, (list, tuple)) else [quarks]

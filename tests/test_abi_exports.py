@@ -40,6 +40,7 @@ def test_header_parses():
     fns = header_functions()
     assert len(fns) >= 18
     assert fns["qxd_debug_set_dirac_variant"] == 1
+    assert fns["qxd_debug_get_dirac_variant"] == 3
     assert fns["qxd_abi_version"] == 0
     assert fns["qxd_dirac_apply"] == 10
     assert fns["qxd_solve"] == 10
