@@ -36,9 +36,10 @@ FLOPS_PER_SITE = 1320 + 552 + 48   # hops + two 6x6 Hermitian blocks + combine
 
 # HBM bytes per FP64 launch from the calibrated FETCH_SIZE + WRITE_SIZE
 # counters (profiles/dirac_64x32c_hbm_counters.md), valid only for the kernel
-# sources they were taken on (hash of the files below).
+# sources they were taken on (hash of the files below) and for the variant
+# the autotuner picked there.
 KERNEL_FILES = ["dirac.hip", "dirac_site.h", "qxd_impl.h"]
-TRAFFIC = {"50eb4c9d256d9280": 9.801e9}
+TRAFFIC = {("4a6bc5197fbb23f6", "dirac_lds_kernel<0, 0, 1, true>"): 1.0861e10}
 
 
 def kernel_hash():
@@ -365,7 +366,7 @@ def main():
                                "q=-1/3, kappa=0.1365, csw=1.9, eps=0.25, A~N(0,0.15)",
                    "global_batch": 1, "seq_len": V, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(value, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(value / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get(kernel_hash()),
+                     "frac": round(value / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get((kernel_hash(), kernel)),
                      "kernel": kernel,
                      "bytes_per_launch": BYTES_PER_SITE[0] * V},
         "dw": dw,
