@@ -101,6 +101,34 @@ QXD_HD void hop_generic(const SpinProj &sp, const cx<T> w[3][3], const cx<T> u0[
   }
 }
 
+// A hop whose direction is chosen at run time: w is W (forward, sg = +1) or
+// W^dag (backward, sg = -1), and the projector is (1 - sg g_mu).  Writes
+// (au, al) as hop_generic<SIGN, true> does.
+template <class T>
+QXD_HD void hop_generic_dir(const SpinProj &sp, T sg, const cx<T> w[3][3], const cx<T> u0[3], const cx<T> u1[3],
+                            const cx<T> q0[3], const cx<T> q1[3], cx<T> au[2][3], cx<T> al[2][3]) {
+  const T g0s = sg * (T)sp.s0, g1s = sg * (T)sp.s1;
+  cx<T> h0[3], h1[3];
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    h0[c] = add_unit(u0[c], sp.imag, g0s, q0[c]);
+    h1[c] = add_unit(u1[c], sp.imag, g1s, q1[c]);
+  }
+#pragma unroll
+  for (int r = 0; r < 3; r++) {
+    cx<T> a = w[r][0] * h0[0], b = w[r][0] * h1[0];
+#pragma unroll
+    for (int c = 1; c < 3; c++) {
+      a = fma_acc(a, w[r][c], h0[c]);
+      b = fma_acc(b, w[r][c], h1[c]);
+    }
+    au[0][r] = a;
+    au[1][r] = b;
+    al[0][r] = mul_unit_conj(sp.imag, g0s, a);
+    al[1][r] = mul_unit_conj(sp.imag, g1s, b);
+  }
+}
+
 // (au, al) of hop_generic -> acc[4][3] in spin order
 template <class T>
 QXD_HD void lower_to_spins(const SpinProj &sp, const cx<T> au[2][3], const cx<T> al[2][3], cx<T> acc[4][3]) {

@@ -318,34 +318,38 @@ __device__ __forceinline__ void sapq_body(const Geom &g, const SapOp<P> &a, cons
   if (!skip_face) {
 #pragma unroll
     for (int x = 0; x < 2; x++) {
-      cx<T> acc[4][3];
-#pragma unroll
-      for (int s = 0; s < 4; s++)
-#pragma unroll
-        for (int c = 0; c < 3; c++) acc[s][c] = {0.f, 0.f};
+      // at most one hop of direction mu leaves the block (b_mu >= 2); every
+      // lane runs the same instructions, lanes without a face hop read their
+      // own site and discard it (select, not a product with zero: the other
+      // colour's corrections may not be written yet where no face hop reads)
       const int y = st[x].y(mu);
-      if (act && (y == 0 || y == bmu - 1)) {
-#pragma unroll 1
-        for (int d = 0; d < 2; d++) {
-          const int dir = d ? -1 : 1;
-          if ((dir > 0 && y != bmu - 1) || (dir < 0 && y != 0)) continue;
-          int sg;
-          Site t = neighbour(g, st[x], mu, dir, sg);
-          int64_t j = encode(g, t);
-          cx<T> psi[4][3], w[3][3];
-          const uint32_t el = g.rd.base((uint32_t)(dir > 0 ? isite[x] : j), 36, VW<P>);
-          const uint32_t jv = (uint32_t)(j - vv.v.off), ev = vv.v.rd.base(jv, 12, VW<P>);
-          const T f = St<P>::scaled ? gld(vv.v.scale, jv) : (T)1;
+      const int dir = y == bmu - 1 ? 1 : (y == 0 ? -1 : 0);
+      const bool face = act && dir != 0;
+      int sg = 0;
+      const Site t = neighbour(g, st[x], mu, dir < 0 ? -1 : 1, sg);
+      const int64_t j = face ? (int64_t)encode(g, t) : isite[x];
+      const uint32_t el = g.rd.base((uint32_t)(dir < 0 && face ? j : isite[x]), 36, VW<P>);
+      const uint32_t jv = (uint32_t)(j - vv.v.off), ev = vv.v.rd.base(jv, 12, VW<P>);
+      const T f = (T)sg * (St<P>::scaled ? gld(vv.v.scale, jv) : (T)1);
+      const cx<T> z0{0.f, 0.f};
+      cx<T> u0[3], u1[3], q0[3], q1[3], w[3][3], au[2][3], al[2][3], acc[4][3];
 #pragma unroll
-          for (int q = 0; q < 12; q++) psi[q / 3][q % 3] = f * gld_pair<P>(vv.v.data + vv.v.rd.comp_off(q, VW<P>), ev);
-#pragma unroll
-          for (int q = 0; q < 9; q++) w[q / 3][q % 3] = gld_pair<P>(a.links + g.rd.comp_off(mu * 9 + q, VW<P>), el);
-          if (dir > 0)
-            hop_fwd<T>(mu, w, psi, (T)sg, acc);
-          else
-            hop_bwd<T>(mu, w, psi, (T)sg, acc);
-        }
+      for (int c = 0; c < 3; c++) {
+        u0[c] = csel(face, f * gld_pair<P>(vv.v.data + vv.v.rd.comp_off(c, VW<P>), ev), z0);
+        u1[c] = csel(face, f * gld_pair<P>(vv.v.data + vv.v.rd.comp_off(3 + c, VW<P>), ev), z0);
+        q0[c] = csel(face, f * gld_pair<P>(vv.v.data + vv.v.rd.comp_off(sp.p0 * 3 + c, VW<P>), ev), z0);
+        q1[c] = csel(face, f * gld_pair<P>(vv.v.data + vv.v.rd.comp_off(p1 * 3 + c, VW<P>), ev), z0);
       }
+      cx<T> wl[3][3];
+#pragma unroll
+      for (int q = 0; q < 9; q++) wl[q / 3][q % 3] = gld_pair<P>(a.links + g.rd.comp_off(mu * 9 + q, VW<P>), el);
+      // backward hop: W(x - mu, mu)^dag
+#pragma unroll
+      for (int rr = 0; rr < 3; rr++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) w[rr][c] = dir < 0 ? conj(wl[c][rr]) : wl[rr][c];
+      hop_generic_dir<T>(sp, dir < 0 ? (T)-1 : (T)1, w, u0, u1, q0, q1, au, al);
+      lower_to_spins(sp, au, al, acc);
       cx<T> blkv[2][3];
       quad_sum_block(acc, bb, blkv);
 #pragma unroll

@@ -33,14 +33,24 @@ int main() {
         if (dir == 0) {
           hop_fwd<double>(mu, w, psi, 1.0, a);
           hop_fwd<double>(mu, w, psi, 1.0, a);
+          hop_fwd<double>(mu, w, psi, 1.0, a);
           hop_generic<1, true, double>(sp, w, psi[0], psi[1], psi[sp.p0], psi[p1], au, al);
           hop_generic<1, false, double>(sp, w, psi[0], psi[1], psi[sp.p0], psi[p1], au, al);
         } else {
           hop_bwd<double>(mu, w, psi, 1.0, a);
           hop_bwd<double>(mu, w, psi, 1.0, a);
+          hop_bwd<double>(mu, w, psi, 1.0, a);
           hop_generic<-1, true, double>(sp, w, psi[0], psi[1], psi[sp.p0], psi[p1], au, al);
           hop_generic<-1, false, double>(sp, w, psi[0], psi[1], psi[sp.p0], psi[p1], au, al);
         }
+        lower_to_spins(sp, au, al, g);
+        for (int s = 0; s < 4; s++)
+          for (int c = 0; c < 3; c++) b[s][c] = b[s][c] + g[s][c];
+        // the run-time direction form, with W^dag materialised for backward
+        cx<double> wd[3][3];
+        for (int r = 0; r < 3; r++)
+          for (int c = 0; c < 3; c++) wd[r][c] = dir == 0 ? w[r][c] : conj(w[c][r]);
+        hop_generic_dir<double>(sp, dir == 0 ? 1.0 : -1.0, wd, psi[0], psi[1], psi[sp.p0], psi[p1], au, al);
         lower_to_spins(sp, au, al, g);
         for (int s = 0; s < 4; s++)
           for (int c = 0; c < 3; c++) b[s][c] = b[s][c] + g[s][c];
