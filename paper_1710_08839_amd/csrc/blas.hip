@@ -251,6 +251,133 @@ Spinor<P> view(const SpinorArg &a) {
   return spinor_view<P>(a.ptr, a.sites, a.off, a.rd);
 }
 
+// ---- flat forms --------------------------------------------------------------
+// For whole runs of sites (first and count multiples of the run length) the
+// elements of a site range are one contiguous stretch in the block-major
+// layout, and every vector of a call shares the layout, so dot products and
+// axpys can run over 16-byte groups of components in storage order: one
+// 16-byte load per vector and group, few registers, fully contiguous
+// streams.  Not for FP16S (per-site scales).
+
+template <int P>
+__device__ __forceinline__ void ldg_group(const typename St<P>::pair_t *base, int64_t gi,
+                                          cx<double> out[VW<P>]) {
+  cx<typename St<P>::comp_t> z[VW<P>];
+  ld_group<P>(base + gi * VW<P>, z);
+#pragma unroll
+  for (int w = 0; w < VW<P>; w++) out[w] = {(double)z[w].re, (double)z[w].im};
+}
+
+// partial[(base + 2l (+1)) * grid + blk] = block sums of (y_l, x) over groups [g0, g0 + ng)
+template <int P, int N>
+__global__ void mdot_flat_kernel(VecList<P> ys, Spinor<P> x, int64_t g0, int64_t ng, double *partial,
+                                 int base) {
+  constexpr int W = VW<P>;
+  __shared__ double sh[4];
+  double acc[2 * N];
+#pragma unroll
+  for (int k = 0; k < 2 * N; k++) acc[k] = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * BT + threadIdx.x; t < ng; t += (int64_t)gridDim.x * BT) {
+    cx<double> xv[W];
+    ldg_group<P>(x.data, g0 + t, xv);
+#pragma unroll
+    for (int l = 0; l < N; l++) {
+      cx<double> yv[W];
+      ldg_group<P>(ys.v[l].data, g0 + t, yv);
+#pragma unroll
+      for (int w = 0; w < W; w++) {
+        acc[2 * l] = fmat(yv[w].re, xv[w].re, acc[2 * l]);
+        acc[2 * l] = fmat(yv[w].im, xv[w].im, acc[2 * l]);
+        acc[2 * l + 1] = fmat(yv[w].re, xv[w].im, acc[2 * l + 1]);
+        acc[2 * l + 1] = fmat(-yv[w].im, xv[w].re, acc[2 * l + 1]);
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 2 * N; k++) {
+    double s = block_sum(acc[k], sh);
+    if (threadIdx.x == 0) partial[(int64_t)(base + k) * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// z_t = src_t - sum_l cf_l ys_t[l] over groups; norms of the stored z_0 (the
+// value rounded to the storage precision, as a later read would see it)
+template <int P, int N>
+__global__ void maxpy_flat_kernel(MaxpyArgs<P> a, int64_t g0, int64_t ng, double *partial) {
+  constexpr int W = VW<P>;
+  using C = typename St<P>::comp_t;
+  __shared__ double sh[4];
+  cx<double> cf[N > 0 ? N : 1];
+#pragma unroll
+  for (int l = 0; l < N; l++) {
+    int L = a.coef_base + l;
+    double d = a.div ? a.div[L * a.div_stride] : 1.0;
+    cf[l] = {a.coef[2 * L] / d, a.coef[2 * L + 1] / d};
+  }
+  double nn = 0.0, wr = 0.0, wi = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * BT + threadIdx.x; t < ng; t += (int64_t)gridDim.x * BT) {
+    const int64_t gi = g0 + t;
+    for (int tr = 0; tr < a.ntriples; tr++) {
+      cx<double> z[W];
+      ldg_group<P>(a.src[tr].data, gi, z);
+#pragma unroll
+      for (int l = 0; l < N; l++) {
+        cx<double> y[W];
+        ldg_group<P>(a.ys[tr].v[l].data, gi, y);
+#pragma unroll
+        for (int w = 0; w < W; w++) z[w] = z[w] - cf[l] * y[w];
+      }
+      cx<C> zs[W];
+#pragma unroll
+      for (int w = 0; w < W; w++) {
+        typename St<P>::pair_t v;
+        St<P>::st(&v, 0, cx<C>{(C)z[w].re, (C)z[w].im});
+        zs[w] = St<P>::ld(&v, 0);
+      }
+      st_group<P>(a.dst[tr].data + gi * W, zs);
+      if (tr == 0 && a.want_norms) {
+        cx<double> wv[W];
+        if (a.has_w) ldg_group<P>(a.w.data, gi, wv);
+#pragma unroll
+        for (int w = 0; w < W; w++) {
+          cx<double> q{(double)zs[w].re, (double)zs[w].im};
+          nn += norm2(q);
+          if (a.has_w) {
+            cx<double> c = cmulc(q, wv[w]);
+            wr += c.re;
+            wi += c.im;
+          }
+        }
+      }
+    }
+  }
+  if (a.want_norms) {
+    double s0 = block_sum(nn, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s0;
+    double s1 = block_sum(wr, sh);
+    if (threadIdx.x == 0) partial[gridDim.x + blockIdx.x] = s1;
+    double s2 = block_sum(wi, sh);
+    if (threadIdx.x == 0) partial[2 * gridDim.x + blockIdx.x] = s2;
+  }
+}
+
+// the site range [first, first + count) of views starting at site `off` is
+// whole runs: the flat forms apply (group range returned)
+template <int P>
+bool flat_range(const SpinorArg &x, int64_t first, int64_t count, int64_t *g0, int64_t *ng) {
+  if (St<P>::scaled) return false;
+  const int64_t R = x.rd.R;
+  const int64_t j0 = first - x.off;
+  if (R < 1 || j0 < 0 || j0 % R || count % R) return false;
+  *g0 = j0 * 12 / VW<P>;
+  *ng = count * 12 / VW<P>;
+  return true;
+}
+template <int P>
+bool same_offset(const SpinorArg &a, const SpinorArg &x) {
+  return a.off == x.off && a.rd.R == x.rd.R;
+}
+
 }  // namespace
 
 hipError_t finish(const double *partial, int nblk, int nred, double *out, const double *div,
@@ -265,11 +392,22 @@ hipError_t blas_mdot(const SpinorArg *ys, int n, SpinorArg x, int64_t first, int
   if (n < 1 || n > MAXV) return hipErrorInvalidValue;
   unsigned g = red_grid(count);
   Spinor<P> xv = view<P>(x);
+  int64_t g0 = 0, ng = 0;
+  bool flat = flat_range<P>(x, first, count, &g0, &ng);
+  for (int k = 0; k < n && flat; k++) flat = same_offset<P>(ys[k], x);
   for (int c0 = 0; c0 < n; c0 += CHUNK) {
     int m = n - c0 < CHUNK ? n - c0 : CHUNK;
     VecList<P> l;
     for (int k = 0; k < m; k++) l.v[k] = view<P>(ys[c0 + k]);
     int base = 2 * c0;
+    if (flat) {
+      switch (m) {
+#define QXD_CASE(N) case N: mdot_flat_kernel<P, N><<<g, BT, 0, st>>>(l, xv, g0, ng, partial, base); break;
+        QXD_CASE(1) QXD_CASE(2) QXD_CASE(3) QXD_CASE(4) QXD_CASE(5) QXD_CASE(6) QXD_CASE(7) QXD_CASE(8)
+#undef QXD_CASE
+      }
+      continue;
+    }
     switch (m) {
 #define QXD_CASE(N) case N: mdot_kernel<P, N><<<g, BT, 0, st>>>(l, xv, first, count, partial, base); break;
       QXD_CASE(1) QXD_CASE(2) QXD_CASE(3) QXD_CASE(4) QXD_CASE(5) QXD_CASE(6) QXD_CASE(7) QXD_CASE(8)
@@ -284,6 +422,13 @@ hipError_t blas_maxpy(const MaxpyHost &h, int64_t first, int64_t count, double *
                       hipStream_t st) {
   if (h.n < 0 || h.n > MAXV || h.ntriples < 1 || h.ntriples > 2) return hipErrorInvalidValue;
   unsigned g = red_grid(count);
+  int64_t g0 = 0, ng = 0;
+  bool flat = flat_range<P>(h.dst[0], first, count, &g0, &ng);
+  for (int tr = 0; tr < h.ntriples && flat; tr++) {
+    flat = same_offset<P>(h.src[tr], h.dst[0]) && same_offset<P>(h.dst[tr], h.dst[0]);
+    for (int k = 0; k < h.n && flat; k++) flat = same_offset<P>(h.ys[tr][k], h.dst[0]);
+  }
+  if (flat && h.w.ptr) flat = same_offset<P>(h.w, h.dst[0]);
   int c0 = 0;
   do {
     int m = h.n - c0 < CHUNK ? h.n - c0 : CHUNK;
@@ -302,6 +447,15 @@ hipError_t blas_maxpy(const MaxpyHost &h, int64_t first, int64_t count, double *
     a.want_norms = last && out != nullptr;
     a.has_w = h.w.ptr != nullptr;
     a.w = a.has_w ? view<P>(h.w) : Spinor<P>{nullptr, nullptr, 0, RunDiv{}};
+    if (flat) {
+      switch (m) {
+#define QXD_CASE(N) case N: maxpy_flat_kernel<P, N><<<g, BT, 0, st>>>(a, g0, ng, partial); break;
+        QXD_CASE(0) QXD_CASE(1) QXD_CASE(2) QXD_CASE(3) QXD_CASE(4) QXD_CASE(5) QXD_CASE(6) QXD_CASE(7) QXD_CASE(8)
+#undef QXD_CASE
+      }
+      c0 += m;
+      continue;
+    }
     switch (m) {
 #define QXD_CASE(N) case N: maxpy_kernel<P, N><<<g, BT, 0, st>>>(a, first, count, partial); break;
       QXD_CASE(0) QXD_CASE(1) QXD_CASE(2) QXD_CASE(3) QXD_CASE(4) QXD_CASE(5) QXD_CASE(6) QXD_CASE(7) QXD_CASE(8)
