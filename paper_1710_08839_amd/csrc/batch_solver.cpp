@@ -10,8 +10,11 @@
 
 #include <math.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <tuple>
+#include <vector>
 
 #include "batch.h"
 #include "blas.h"
@@ -113,7 +116,7 @@ qxd_status BatchSolver::reserve(int n) {
     slots_.push_back(std::move(sl));
   }
   size_t nslot = slots_.size();
-  size_t stage = nslot * (sizeof(SapSlot<QXD_F64>) + sizeof(DSlot<QXD_F64>) + sizeof(int)) + 256;
+  size_t stage = nslot * (sizeof(SapSlot<QXD_F64>) + sizeof(DSlot<QXD_F64>) + 2 * sizeof(int)) + 256;
   if (stage > h_stage_bytes_) {
     BCK(hipStreamSynchronize(st_));
     if (h_stage_) (void)hipHostFree(h_stage_);
@@ -126,7 +129,7 @@ qxd_status BatchSolver::reserve(int n) {
   }
   BCK(dslots_.ensure(nslot * sizeof(DSlot<QXD_F64>)));
   BCK(sslots_.ensure(nslot * sizeof(SapSlot<QXD_F64>)));
-  BCK(act_.ensure(nslot * sizeof(int)));
+  BCK(act_.ensure(2 * nslot * sizeof(int)));
   BCK(d_norms_.ensure(nslot * sizeof(double)));
   BCK(partial_.ensure(blas_partial_doubles() * 8));
   return QXD_OK;
@@ -267,16 +270,49 @@ struct BImpl {
       hd[j].out = spinor_view<P>(sl.chi(nkv, sl.k), g.V, 0, g);
       ha[j] = j;
     }
+    // pair up right-hand sides with the same operator (two per work-group in
+    // the block solver); the rest go one per work-group.  ha: [0, n) for the
+    // Dirac launch, then the single slots, then the pairs.
+    int *hsingle = ha + n, nsingle = 0, npair = 0;
+    std::vector<int> order(n);
+    for (int j = 0; j < n; j++) order[j] = j;
+    const bool pairs_ok = P != QXD_F64 && sap_quad_pairs_ok(P, g);
+    if (pairs_ok)
+      std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return std::make_tuple(hs[x].op.links, hs[x].op.pauli) < std::make_tuple(hs[y].op.links, hs[y].op.pauli);
+      });
+    std::vector<int> pairs;
+    for (int k = 0; k < n;) {
+      if (pairs_ok && k + 1 < n && hs[order[k]].op.links == hs[order[k + 1]].op.links &&
+          hs[order[k]].op.pauli == hs[order[k + 1]].op.pauli && hs[order[k]].op.pinv == hs[order[k + 1]].op.pinv) {
+        pairs.push_back(order[k]);
+        pairs.push_back(order[k + 1]);
+        k += 2;
+      } else {
+        hsingle[nsingle++] = order[k++];
+      }
+    }
+    npair = (int)pairs.size() / 2;
+    int *hpair = hsingle + nsingle;
+    for (size_t k = 0; k < pairs.size(); k++) hpair[k] = pairs[k];
     BCK(hipMemcpyAsync(sslots.p, hs, n * sizeof(SapSlot<P>), hipMemcpyHostToDevice, st));
     BCK(hipMemcpyAsync(dslots.p, hd, n * sizeof(DSlot<P>), hipMemcpyHostToDevice, st));
-    BCK(hipMemcpyAsync(actbuf.p, ha, n * sizeof(int), hipMemcpyHostToDevice, st));
+    BCK(hipMemcpyAsync(actbuf.p, ha, 2 * n * sizeof(int), hipMemcpyHostToDevice, st));
+    const int *dsingle = actbuf.as<int>() + n, *dpair = dsingle + nsingle;
     const int *lists[2];
     int nper;
     BCS(sap_block_lists(f, lists, &nper));
     for (int cy = 0; cy < ncy; cy++)
-      for (int c = 0; c < 2; c++)
-        BCK(launch_sap_batch<P>(g, lists[c], nper, sslots.as<SapSlot<P>>(), actbuf.as<int>(), n, cy == 0,
-                                cy == 0 && c == 0, nmr, st));
+      for (int c = 0; c < 2; c++) {
+        if constexpr (P != QXD_F64) {
+          if (npair > 0)
+            BCK(launch_sapq_pairs<P>(g, lists[c], nper, sslots.as<SapSlot<P>>(), dpair, npair, cy == 0,
+                                     cy == 0 && c == 0, nmr, st));
+        }
+        if (nsingle > 0)
+          BCK(launch_sap_batch<P>(g, lists[c], nper, sslots.as<SapSlot<P>>(), dsingle, nsingle, cy == 0,
+                                  cy == 0 && c == 0, nmr, st));
+      }
     BCK(launch_dirac_batch<P>(g, dslots.as<DSlot<P>>(), actbuf.as<int>(), n, 2, st));
     return QXD_OK;
   }

@@ -63,4 +63,11 @@ template <int P>
 hipError_t launch_sapq_batch(const Geom &g, const int *blocks, int nblocks_colour, const SapSlot<P> *slots,
                              const int *act, int nact, int first, int skip_face, int nmr, hipStream_t st);
 
+// Pairs of slots that share the operator, two right-hand sides per
+// work-group (links and Pauli rows staged once): pairs[2 p], pairs[2 p + 1].
+bool sap_quad_pairs_ok(int prec, const Geom &g);
+template <int P>
+hipError_t launch_sapq_pairs(const Geom &g, const int *blocks, int nblocks_colour, const SapSlot<P> *slots,
+                             const int *pairs, int npair, int first, int skip_face, int nmr, hipStream_t st);
+
 }  // namespace qxd

@@ -182,25 +182,38 @@ constexpr int QNHP = QNH_MAX + 8;
 constexpr int QVBP = 2 * QNH_MAX + 4;
 constexpr int QZERO = 2 * QNH_MAX;  // zero-link slot
 
-// LDS: two spinor buffers, the reduction scratch (one triple per wavefront,
-// at most 8), then the links
-constexpr size_t QLINKS_OFFSET = 2 * 12 * (size_t)QNHP * sizeof(cx<float>) + 3 * 8 * sizeof(float);
+// LDS: per right-hand side two spinor buffers and the reduction scratch (one
+// triple per wavefront, at most 8), then the links (shared)
+__host__ __device__ constexpr size_t qspin_bytes() { return 2 * 12 * (size_t)QNHP * sizeof(cx<float>); }
+__host__ __device__ constexpr size_t qlinks_offset(int nr) {
+  return (size_t)nr * (qspin_bytes() + 3 * 8 * sizeof(float));
+}
 
 __device__ __forceinline__ int local_lex(const Geom &g, const Site &t) {
   return ((t.y(0) * g.b[1] + t.y(1)) * g.b[2] + t.y(2)) * g.b[3] + t.y(3);
 }
 
-template <int P>
-__device__ __forceinline__ void sapq_body(const Geom &g, const SapOp<P> &a, const SapVecs<P> &vv, int blk,
+// NR right-hand sides (1 or 2) that share the operator are solved on the
+// same block by one work-group: the links and Pauli rows are staged once, the
+// barriers are shared, and the two solves give independent work between
+// barriers.  Each right-hand side's arithmetic is the same as when it is
+// solved alone.
+template <int P, int NR>
+__device__ __forceinline__ void sapq_body(const Geom &g, const SapOp<P> &a, const SapVecs<P> *vvs, int blk,
                                           int first, int skip_face, int nmr, unsigned char *smem) {
   using T = float;
   const int nh = g.Vbh;
   constexpr int nhp = QNHP;
-  cx<T> *bufe = (cx<T> *)smem;   // even-site vector [12][nhp]
-  cx<T> *bufo = bufe + 12 * nhp; // odd-site vector
-  T *red = (T *)(bufo + 12 * nhp);
+  cx<T> *bufe[NR], *bufo[NR];  // per right-hand side: even- and odd-site vector [12][nhp]
+  T *red[NR];
+#pragma unroll
+  for (int q = 0; q < NR; q++) {
+    bufe[q] = (cx<T> *)(smem + q * qspin_bytes());
+    bufo[q] = bufe[q] + 12 * nhp;
+    red[q] = (T *)(smem + NR * qspin_bytes()) + q * 24;
+  }
   using pt = typename St<P>::pair_t;
-  pt *lw = (pt *)(smem + QLINKS_OFFSET);
+  pt *lw = (pt *)(smem + qlinks_offset(NR));
   const int tid = threadIdx.x;
   const int h = tid >> 2, rho = tid & 3, mu = rho;
   const bool bb = rho >> 1, rh = rho & 1;
@@ -306,15 +319,17 @@ __device__ __forceinline__ void sapq_body(const Geom &g, const SapOp<P> &a, cons
   };
 
   // residual with the face update r -= D v' over the hops that leave the block
-  cx<T> r[2][3];
+  cx<T> r[NR][2][3];
 #pragma unroll
-  for (int x = 0; x < 2; x++) {
-    if (act)
-      load_spin<P>(first ? vv.rho : vv.r, isite[x], rho, r[x]);
-    else
+  for (int q = 0; q < NR; q++)
 #pragma unroll
-      for (int c = 0; c < 3; c++) r[x][c] = {0.f, 0.f};
-  }
+    for (int x = 0; x < 2; x++) {
+      if (act)
+        load_spin<P>(first ? vvs[q].rho : vvs[q].r, isite[x], rho, r[q][x]);
+      else
+#pragma unroll
+        for (int c = 0; c < 3; c++) r[q][x][c] = {0.f, 0.f};
+    }
   if (!skip_face) {
 #pragma unroll
     for (int x = 0; x < 2; x++) {
@@ -329,154 +344,170 @@ __device__ __forceinline__ void sapq_body(const Geom &g, const SapOp<P> &a, cons
       const Site t = neighbour(g, st[x], mu, dir < 0 ? -1 : 1, sg);
       const int64_t j = face ? (int64_t)encode(g, t) : isite[x];
       const uint32_t el = g.rd.base((uint32_t)(dir < 0 && face ? j : isite[x]), 36, VW<P>);
-      const uint32_t jv = (uint32_t)(j - vv.v.off), ev = vv.v.rd.base(jv, 12, VW<P>);
-      const T f = (T)sg * (St<P>::scaled ? gld(vv.v.scale, jv) : (T)1);
-      const cx<T> z0{0.f, 0.f};
-      cx<T> u0[3], u1[3], q0[3], q1[3], w[3][3], au[2][3], al[2][3], acc[4][3];
+      cx<T> wl[3][3], w[3][3];
 #pragma unroll
-      for (int c = 0; c < 3; c++) {
-        u0[c] = csel(face, f * gld_pair<P>(vv.v.data + vv.v.rd.comp_off(c, VW<P>), ev), z0);
-        u1[c] = csel(face, f * gld_pair<P>(vv.v.data + vv.v.rd.comp_off(3 + c, VW<P>), ev), z0);
-        q0[c] = csel(face, f * gld_pair<P>(vv.v.data + vv.v.rd.comp_off(sp.p0 * 3 + c, VW<P>), ev), z0);
-        q1[c] = csel(face, f * gld_pair<P>(vv.v.data + vv.v.rd.comp_off(p1 * 3 + c, VW<P>), ev), z0);
-      }
-      cx<T> wl[3][3];
-#pragma unroll
-      for (int q = 0; q < 9; q++) wl[q / 3][q % 3] = gld_pair<P>(a.links + g.rd.comp_off(mu * 9 + q, VW<P>), el);
+      for (int k = 0; k < 9; k++) wl[k / 3][k % 3] = gld_pair<P>(a.links + g.rd.comp_off(mu * 9 + k, VW<P>), el);
       // backward hop: W(x - mu, mu)^dag
 #pragma unroll
       for (int rr = 0; rr < 3; rr++)
 #pragma unroll
         for (int c = 0; c < 3; c++) w[rr][c] = dir < 0 ? conj(wl[c][rr]) : wl[rr][c];
-      hop_generic_dir<T>(sp, dir < 0 ? (T)-1 : (T)1, w, u0, u1, q0, q1, au, al);
-      lower_to_spins(sp, au, al, acc);
-      cx<T> blkv[2][3];
-      quad_sum_block(acc, bb, blkv);
 #pragma unroll
-      for (int c = 0; c < 3; c++) r[x][c] = r[x][c] + (T)0.5 * csel(rh, blkv[1][c], blkv[0][c]);
+      for (int q = 0; q < NR; q++) {
+        const Spinor<P> &vq = vvs[q].v;
+        const uint32_t jv = (uint32_t)(j - vq.off), ev = vq.rd.base(jv, 12, VW<P>);
+        const T f = (T)sg * (St<P>::scaled ? gld(vq.scale, jv) : (T)1);
+        const cx<T> z0{0.f, 0.f};
+        cx<T> u0[3], u1[3], q0[3], q1[3], au[2][3], al[2][3], acc[4][3];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+          u0[c] = csel(face, f * gld_pair<P>(vq.data + vq.rd.comp_off(c, VW<P>), ev), z0);
+          u1[c] = csel(face, f * gld_pair<P>(vq.data + vq.rd.comp_off(3 + c, VW<P>), ev), z0);
+          q0[c] = csel(face, f * gld_pair<P>(vq.data + vq.rd.comp_off(sp.p0 * 3 + c, VW<P>), ev), z0);
+          q1[c] = csel(face, f * gld_pair<P>(vq.data + vq.rd.comp_off(p1 * 3 + c, VW<P>), ev), z0);
+        }
+        hop_generic_dir<T>(sp, dir < 0 ? (T)-1 : (T)1, w, u0, u1, q0, q1, au, al);
+        lower_to_spins(sp, au, al, acc);
+        cx<T> blkv[2][3];
+        quad_sum_block(acc, bb, blkv);
+#pragma unroll
+        for (int c = 0; c < 3; c++) r[q][x][c] = r[q][x][c] + (T)0.5 * csel(rh, blkv[1][c], blkv[0][c]);
+      }
     }
   }
   // u_o = D_oo^-1 r_o
-  {
+#pragma unroll
+  for (int q = 0; q < NR; q++) {
     cx<T> xb[2][3], u[3];
-    quad_block_of(r[1], rh, xb);
+    quad_block_of(r[q][1], rh, xb);
     rows_mul<P>(m[1], xb, u);
-    lds_put(bufo, u);
+    lds_put(bufo[q], u);
   }
   __syncthreads();
   // s = rho_e = r_e - D_eo^L u_o = r_e + acc_in(u)/2; v_e = 0
-  cx<T> s[3], v[3];
-  {
+  cx<T> s[NR][3], v[NR][3];
+#pragma unroll
+  for (int q = 0; q < NR; q++) {
     cx<T> acc[4][3], blkv[2][3];
-    hops(bufo, 0, acc);
+    hops(bufo[q], 0, acc);
     quad_sum_block(acc, bb, blkv);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-      s[c] = r[0][c] + (T)0.5 * csel(rh, blkv[1][c], blkv[0][c]);
-      v[c] = {0.f, 0.f};
+      s[q][c] = r[q][0][c] + (T)0.5 * csel(rh, blkv[1][c], blkv[0][c]);
+      v[q][c] = {0.f, 0.f};
     }
-    lds_put(bufe, s);
+    lds_put(bufe[q], s[q]);
   }
   __syncthreads();
 #pragma unroll 1
   for (int k = 0; k < nmr; k++) {
     // w_o = D_oo^-1 D_oe^L s = -D_oo^-1 acc_in(s)/2
-    {
+#pragma unroll
+    for (int q = 0; q < NR; q++) {
       cx<T> acc[4][3], blkv[2][3], w[3];
-      hops(bufe, 1, acc);
+      hops(bufe[q], 1, acc);
       quad_sum_block(acc, bb, blkv);
 #pragma unroll
-      for (int q = 0; q < 2; q++)
+      for (int e = 0; e < 2; e++)
 #pragma unroll
-        for (int c = 0; c < 3; c++) blkv[q][c] = (T)(-0.5) * blkv[q][c];
+        for (int c = 0; c < 3; c++) blkv[e][c] = (T)(-0.5) * blkv[e][c];
       rows_mul<P>(m[1], blkv, w);
-      lds_put(bufo, w);
+      lds_put(bufo[q], w);
     }
     __syncthreads();
     // t = P s - D_eo^L w_o = P s + acc_in(w)/2; alpha = (t,s)/(t,t)
-    cx<T> t[3];
-    {
+    cx<T> t[NR][3];
+#pragma unroll
+    for (int q = 0; q < NR; q++) {
       cx<T> acc[4][3], blkv[2][3], sb[2][3];
-      hops(bufo, 0, acc);
+      hops(bufo[q], 0, acc);
       quad_sum_block(acc, bb, blkv);
-      quad_block_of(s, rh, sb);
-      rows_mul<P>(m[0], sb, t);
+      quad_block_of(s[q], rh, sb);
+      rows_mul<P>(m[0], sb, t[q]);
 #pragma unroll
-      for (int c = 0; c < 3; c++) t[c] = t[c] + (T)0.5 * csel(rh, blkv[1][c], blkv[0][c]);
-    }
-    T ts_re = 0, ts_im = 0, tt = 0;
-    if (act) {
+      for (int c = 0; c < 3; c++) t[q][c] = t[q][c] + (T)0.5 * csel(rh, blkv[1][c], blkv[0][c]);
+      T ts_re = 0, ts_im = 0, tt = 0;
+      if (act) {
 #pragma unroll
-      for (int c = 0; c < 3; c++) {
-        cx<T> z = cmulc(t[c], s[c]);
-        ts_re += z.re;
-        ts_im += z.im;
-        tt += norm2(t[c]);
+        for (int c = 0; c < 3; c++) {
+          cx<T> z = cmulc(t[q][c], s[q][c]);
+          ts_re += z.re;
+          ts_im += z.im;
+          tt += norm2(t[q][c]);
+        }
+      }
+      ts_re = wave_sum(ts_re);
+      ts_im = wave_sum(ts_im);
+      tt = wave_sum(tt);
+      if ((tid & 63) == 0) {
+        red[q][3 * (tid >> 6)] = ts_re;
+        red[q][3 * (tid >> 6) + 1] = ts_im;
+        red[q][3 * (tid >> 6) + 2] = tt;
       }
     }
-    ts_re = wave_sum(ts_re);
-    ts_im = wave_sum(ts_im);
-    tt = wave_sum(tt);
-    if ((tid & 63) == 0) {
-      red[3 * (tid >> 6)] = ts_re;
-      red[3 * (tid >> 6) + 1] = ts_im;
-      red[3 * (tid >> 6) + 2] = tt;
-    }
     __syncthreads();
-    T sr = 0, si = 0, stt = 0;
-    for (int w = 0; w < nwaves; w++) {
-      sr += red[3 * w];
-      si += red[3 * w + 1];
-      stt += red[3 * w + 2];
-    }
-    cx<T> alpha{0.f, 0.f};
-    if (stt > (T)0) alpha = {sr / stt, si / stt};
 #pragma unroll
-    for (int c = 0; c < 3; c++) {
-      v[c] = v[c] + alpha * s[c];
-      s[c] = s[c] - alpha * t[c];
+    for (int q = 0; q < NR; q++) {
+      T sr = 0, si = 0, stt = 0;
+      for (int w = 0; w < nwaves; w++) {
+        sr += red[q][3 * w];
+        si += red[q][3 * w + 1];
+        stt += red[q][3 * w + 2];
+      }
+      cx<T> alpha{0.f, 0.f};
+      if (stt > (T)0) alpha = {sr / stt, si / stt};
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        v[q][c] = v[q][c] + alpha * s[q][c];
+        s[q][c] = s[q][c] - alpha * t[q][c];
+      }
+      lds_put(bufe[q], s[q]);
     }
-    lds_put(bufe, s);
     __syncthreads();
   }
   // v_o = D_oo^-1 (r_o - D_oe^L v_e) = D_oo^-1 (r_o + acc_in(v_e)/2)
-  lds_put(bufo, v);
+#pragma unroll
+  for (int q = 0; q < NR; q++) lds_put(bufo[q], v[q]);
   __syncthreads();
-  cx<T> vo[3];
-  {
-    cx<T> acc[4][3], blkv[2][3], rb[2][3];
-    hops(bufo, 1, acc);
-    quad_sum_block(acc, bb, blkv);
-    quad_block_of(r[1], rh, rb);
 #pragma unroll
-    for (int q = 0; q < 2; q++)
+  for (int q = 0; q < NR; q++) {
+    cx<T> vo[3];
+    {
+      cx<T> acc[4][3], blkv[2][3], rb[2][3];
+      hops(bufo[q], 1, acc);
+      quad_sum_block(acc, bb, blkv);
+      quad_block_of(r[q][1], rh, rb);
 #pragma unroll
-      for (int c = 0; c < 3; c++) rb[q][c] = rb[q][c] + (T)0.5 * blkv[q][c];
-    rows_mul<P>(m[1], rb, vo);
-  }
-  // psi += v; residual on the block: r_e = s, r_o = 0; keep v for the faces
-  const cx<T> *vx[2] = {v, vo};
+      for (int e = 0; e < 2; e++)
 #pragma unroll
-  for (int x = 0; x < 2; x++) {
-    cx<T> p[3];
-    if (first) {
-#pragma unroll
-      for (int c = 0; c < 3; c++) p[c] = vx[x][c];
-    } else {
-      if (act)
-        load_spin<P>(vv.psi, isite[x], rho, p);
-      else
-#pragma unroll
-        for (int c = 0; c < 3; c++) p[c] = {0.f, 0.f};
-#pragma unroll
-      for (int c = 0; c < 3; c++) p[c] = p[c] + vx[x][c];
+        for (int c = 0; c < 3; c++) rb[e][c] = rb[e][c] + (T)0.5 * blkv[e][c];
+      rows_mul<P>(m[1], rb, vo);
     }
-    store_spin<P>(vv.psi, isite[x], rho, p, act);
-    store_spin<P>(vv.v, isite[x], rho, vx[x], act);
+    // psi += v; residual on the block: r_e = s, r_o = 0; keep v for the faces
+    const SapVecs<P> &vv = vvs[q];
+    const cx<T> *vx[2] = {v[q], vo};
+#pragma unroll
+    for (int x = 0; x < 2; x++) {
+      cx<T> p[3];
+      if (first) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) p[c] = vx[x][c];
+      } else {
+        if (act)
+          load_spin<P>(vv.psi, isite[x], rho, p);
+        else
+#pragma unroll
+          for (int c = 0; c < 3; c++) p[c] = {0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < 3; c++) p[c] = p[c] + vx[x][c];
+      }
+      store_spin<P>(vv.psi, isite[x], rho, p, act);
+      store_spin<P>(vv.v, isite[x], rho, vx[x], act);
+    }
+    cx<T> zero[3] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
+    store_spin<P>(vv.r, isite[0], rho, s[q], act);
+    store_spin<P>(vv.r, isite[1], rho, zero, act);
   }
-  cx<T> zero[3] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
-  store_spin<P>(vv.r, isite[0], rho, s, act);
-  store_spin<P>(vv.r, isite[1], rho, zero, act);
 }
 
 template <int P>
@@ -485,7 +516,7 @@ sapq_block_kernel(SapArgs<P> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   SapOp<P> op{a.links, a.angles, a.qhat, a.pauli, a.pinv};
   SapVecs<P> vv{a.rho, a.r, a.psi, a.v};
-  sapq_body<P>(a.g, op, vv, a.blocks[xcd_order(blockIdx.x, gridDim.x)], a.first, a.skip_face, a.nmr, smem);
+  sapq_body<P, 1>(a.g, op, &vv, a.blocks[xcd_order(blockIdx.x, gridDim.x)], a.first, a.skip_face, a.nmr, smem);
 }
 
 template <int P>
@@ -496,12 +527,29 @@ sapq_batch_kernel(Geom g, const int *blocks, const SapSlot<P> *slots, const int 
   int L = xcd_order(blockIdx.x, gridDim.x);
   int bi = L / nact;
   const SapSlot<P> &sl = slots[act[L - bi * nact]];
-  sapq_body<P>(g, sl.op, sl.vec, blocks[bi], first, skip_face, nmr, smem);
+  sapq_body<P, 1>(g, sl.op, &sl.vec, blocks[bi], first, skip_face, nmr, smem);
+}
+
+// Pairs of right-hand sides with the same operator: work-group L solves block
+// L / npair for the two slots pairs[2 (L % npair)], pairs[2 (L % npair) + 1].
+template <int P>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
+sapq_pair_kernel(Geom g, const int *blocks, const SapSlot<P> *slots, const int *pairs, int npair, int first,
+                 int skip_face, int nmr) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int L = xcd_order(blockIdx.x, gridDim.x);
+  int bi = L / npair;
+  int pi = L - bi * npair;
+  const SapSlot<P> &s0 = slots[pairs[2 * pi]];
+  SapVecs<P> vv[2] = {s0.vec, slots[pairs[2 * pi + 1]].vec};
+  sapq_body<P, 2>(g, s0.op, vv, blocks[bi], first, skip_face, nmr, smem);
 }
 
 int quad_threads(const Geom &g) { return (4 * g.Vbh + 63) / 64 * 64; }
 
-size_t quad_lds(int prec, const Geom &) { return QLINKS_OFFSET + 36 * (size_t)QVBP * pair_bytes(prec); }
+size_t quad_lds(int prec, const Geom &, int nr = 1) {
+  return qlinks_offset(nr) + 36 * (size_t)QVBP * pair_bytes(prec);
+}
 
 }  // namespace
 
@@ -548,9 +596,27 @@ hipError_t launch_sapq_batch(const Geom &g, const int *blocks, int nblocks_colou
   return hipGetLastError();
 }
 
+bool sap_quad_pairs_ok(int prec, const Geom &g) {
+  return sap_quad_ok(prec, g, 0) && quad_lds(prec, g, 2) <= (size_t)lds_limit();
+}
+
+template <int P>
+hipError_t launch_sapq_pairs(const Geom &g, const int *blocks, int nblocks_colour, const SapSlot<P> *slots,
+                             const int *pairs, int npair, int first, int skip_face, int nmr, hipStream_t st) {
+  if (npair < 1) return hipSuccess;
+  size_t lds = quad_lds(P, g, 2);
+  hipError_t e = allow_lds(sapq_pair_kernel<P>, lds);
+  if (e != hipSuccess) return e;
+  sapq_pair_kernel<P><<<(unsigned)nblocks_colour * npair, quad_threads(g), lds, st>>>(
+      g, blocks, slots, pairs, npair, first, skip_face, nmr);
+  return hipGetLastError();
+}
+
 #define QXD_INST(P)                                                                                      \
   template hipError_t launch_sapq_colour<P>(const SapArgs<P> &, int, hipStream_t);                        \
   template hipError_t launch_sapq_batch<P>(const Geom &, const int *, int, const SapSlot<P> *, const int *, \
+                                           int, int, int, int, hipStream_t);                              \
+  template hipError_t launch_sapq_pairs<P>(const Geom &, const int *, int, const SapSlot<P> *, const int *, \
                                            int, int, int, int, hipStream_t);
 QXD_INST(QXD_F32)
 QXD_INST(QXD_F16S)
