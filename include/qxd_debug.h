@@ -27,6 +27,17 @@ extern "C" {
  * threads.  QXD_EINVAL for any other value. */
 qxd_status qxd_debug_set_dirac_variant(int choice);
 
+/* Batched SAP-GCR steps replay the fixed launch sequence of a step (block
+ * solves of every colour pass and the batched D) from a HIP graph captured
+ * the second time a batch configuration occurs.  enable = 0 issues every
+ * launch directly instead (the results are the same bits); process-wide. */
+qxd_status qxd_debug_set_step_graphs(int enable);
+
+/* Process-wide totals since load: step graphs captured, and step graphs
+ * launched (each capture is launched once at once, then replayed while its
+ * configuration repeats).  QXD_EINVAL if either pointer is NULL. */
+qxd_status qxd_debug_step_graph_counts(int64_t *captures, int64_t *replays);
+
 /* The variant the autotuner chose for the full operator D (phase folded into
  * the links) on this field's lattice in precision prec, in the encoding of
  * qxd_debug_set_dirac_variant; 0 if D has not been applied yet. */

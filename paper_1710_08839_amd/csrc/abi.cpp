@@ -9,6 +9,7 @@
 
 #include "../../include/qxd_debug.h"
 #include "host.h"
+#include "batch_solver.h"
 #include "launch.h"
 #include "solver.h"
 
@@ -245,6 +246,20 @@ qxd_status qxd_debug_get_dirac_variant(const qxd_field *field, qxd_prec prec, in
     return QXD_EINVAL;
   }
   *choice = tuned_group((int)prec, (int)DK_FULL, field->g.V, 0);
+  return QXD_OK;
+}
+
+qxd_status qxd_debug_set_step_graphs(int enable) {
+  set_step_graphs(enable != 0);
+  return QXD_OK;
+}
+
+qxd_status qxd_debug_step_graph_counts(int64_t *captures, int64_t *replays) {
+  if (!captures || !replays) {
+    set_error("captures and replays must be non-NULL");
+    return QXD_EINVAL;
+  }
+  step_graph_counts(captures, replays);
   return QXD_OK;
 }
 

@@ -11,6 +11,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstring>
 #include <tuple>
@@ -88,6 +89,8 @@ BatchSolver::BatchSolver(Field *f, int prec, const qxd_solver &s, hipStream_t st
 
 BatchSolver::~BatchSolver() {
   (void)hipStreamSynchronize(st_);
+  drop_graphs();
+  if (cap_st_) (void)hipStreamDestroy(cap_st_);
   if (h_stage_) (void)hipHostFree(h_stage_);
   if (h_norms_) (void)hipHostFree(h_norms_);
 }
@@ -127,9 +130,12 @@ qxd_status BatchSolver::reserve(int n) {
     h_norms_ = nullptr;
     BCK(hipHostMalloc((void **)&h_norms_, nslot * sizeof(double) + 64, hipHostMallocDefault));
   }
+  const void *old[3] = {dslots_.p, sslots_.p, act_.p};
   BCK(dslots_.ensure(nslot * sizeof(DSlot<QXD_F64>)));
   BCK(sslots_.ensure(nslot * sizeof(SapSlot<QXD_F64>)));
   BCK(act_.ensure(2 * nslot * sizeof(int)));
+  // graphs name the tables by address: none survives a reallocation
+  if (old[0] != dslots_.p || old[1] != sslots_.p || old[2] != act_.p) drop_graphs();
   BCK(d_norms_.ensure(nslot * sizeof(double)));
   BCK(partial_.ensure(blas_partial_doubles() * 8));
   return QXD_OK;
@@ -302,21 +308,32 @@ struct BImpl {
     const int *lists[2];
     int nper;
     BCS(sap_block_lists(f, lists, &nper));
-    for (int cy = 0; cy < ncy; cy++)
-      for (int c = 0; c < 2; c++) {
-        if constexpr (P != QXD_F64) {
-          if (npair > 0)
-            BCK(launch_sapq_pairs<P>(g, lists[c], nper, sslots.as<SapSlot<P>>(), dpair, npair, cy == 0,
-                                     cy == 0 && c == 0, nmr, st));
+    auto issue = [&](hipStream_t st) -> qxd_status {
+      for (int cy = 0; cy < ncy; cy++)
+        for (int c = 0; c < 2; c++) {
+          if constexpr (P != QXD_F64) {
+            if (npair > 0)
+              BCK(launch_sapq_pairs<P>(g, lists[c], nper, sslots.as<SapSlot<P>>(), dpair, npair, cy == 0,
+                                       cy == 0 && c == 0, nmr, st));
+          }
+          if (nsingle > 0)
+            BCK(launch_sap_batch<P>(g, lists[c], nper, sslots.as<SapSlot<P>>(), dsingle, nsingle, cy == 0,
+                                    cy == 0 && c == 0, nmr, st));
         }
-        if (nsingle > 0)
-          BCK(launch_sap_batch<P>(g, lists[c], nper, sslots.as<SapSlot<P>>(), dsingle, nsingle, cy == 0,
-                                  cy == 0 && c == 0, nmr, st));
-      }
-    BCK(launch_dirac_batch<P>(g, dslots.as<DSlot<P>>(), actbuf.as<int>(), n, 2, st));
+      BCK(launch_dirac_batch<P>(g, dslots.as<DSlot<P>>(), actbuf.as<int>(), n, 2, st));
+      return QXD_OK;
+    };
+    const std::array<int64_t, 8> key{P, n, npair, (int64_t)ncy * 256 + nmr, (int64_t)(intptr_t)sslots.p,
+                                     (int64_t)(intptr_t)dslots.p, (int64_t)(intptr_t)actbuf.p, nper};
+    // FP64 inner solves (not a performance path) launch directly
+    if constexpr (P == QXD_F64) return issue(st);
+    return bs.run_step_launches(key, issue);
     return QXD_OK;
   }
 };
+
+std::atomic<bool> g_step_graphs{true};
+std::atomic<int64_t> g_graph_captures{0}, g_graph_replays{0};
 
 #define DISPATCH(call)                                          \
   switch (prec_) {                                              \
@@ -325,6 +342,75 @@ struct BImpl {
     case QXD_F16S: return BImpl<QXD_F16S>::call;                \
     default: return BImpl<QXD_BF16>::call;                      \
   }
+
+void set_step_graphs(bool on) { g_step_graphs.store(on); }
+void step_graph_counts(int64_t *captures, int64_t *replays) {
+  *captures = g_graph_captures.load();
+  *replays = g_graph_replays.load();
+}
+
+void BatchSolver::drop_graphs() {
+  if (!graphs_.empty()) (void)hipStreamSynchronize(st_);
+  for (auto &ge : graphs_) (void)hipGraphExecDestroy(ge.second);
+  graphs_.clear();
+  seen_.clear();
+}
+
+qxd_status BatchSolver::run_step_launches(const StepKey &key,
+                                          const std::function<qxd_status(hipStream_t)> &issue) {
+  constexpr size_t MAX_GRAPHS = 16, MAX_SEEN = 64;
+  if (!graphs_ok_ || !g_step_graphs.load()) return issue(st_);
+  for (size_t k = 0; k < graphs_.size(); k++)
+    if (graphs_[k].first == key) {
+      std::rotate(graphs_.begin() + k, graphs_.begin() + k + 1, graphs_.end());
+      BCK(hipGraphLaunch(graphs_.back().second, st_));
+      g_graph_replays.fetch_add(1);
+      return QXD_OK;
+    }
+  if (std::find(seen_.begin(), seen_.end(), key) == seen_.end()) {
+    // first sight of this configuration: run eagerly (also sets up kernel
+    // attributes outside any capture); capture when it comes again
+    if (seen_.size() == MAX_SEEN) seen_.erase(seen_.begin());
+    seen_.push_back(key);
+    return issue(st_);
+  }
+  if (!cap_st_ && hipStreamCreateWithFlags(&cap_st_, hipStreamNonBlocking) != hipSuccess) {
+    cap_st_ = nullptr;
+    graphs_ok_ = false;
+    return issue(st_);
+  }
+  hipGraph_t graph = nullptr;
+  if (hipStreamBeginCapture(cap_st_, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    graphs_ok_ = false;
+    return issue(st_);
+  }
+  qxd_status s = issue(cap_st_);
+  hipError_t e = hipStreamEndCapture(cap_st_, &graph);
+  if (s != QXD_OK || e != hipSuccess || !graph) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    graphs_ok_ = false;
+    return issue(st_);  // nothing ran during the failed capture
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    graphs_ok_ = false;
+    return issue(st_);
+  }
+  if (graphs_.size() == MAX_GRAPHS) {
+    // the least recently used graph may still be queued on st_
+    BCK(hipStreamSynchronize(st_));
+    (void)hipGraphExecDestroy(graphs_.front().second);
+    graphs_.erase(graphs_.begin());
+  }
+  graphs_.emplace_back(key, exec);
+  g_graph_captures.fetch_add(1);
+  BCK(hipGraphLaunch(exec, st_));
+  g_graph_replays.fetch_add(1);
+  return QXD_OK;
+}
 
 qxd_status BatchSolver::new_inner(Slot &sl) {
   DISPATCH(new_inner(sl, f_->g, partial_.as<double>(), nkv_, st_));

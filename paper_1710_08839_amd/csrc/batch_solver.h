@@ -7,6 +7,8 @@
 // others share its steps, so a solve gives the same bits alone or batched.
 #pragma once
 
+#include <array>
+#include <functional>
 #include <memory>
 #include <vector>
 
@@ -48,6 +50,17 @@ class BatchSolver {
 
   struct Slot;  // one right-hand side in flight (batch_solver.cpp)
 
+  // Issue the fixed launch sequence of a step (the batched SAP passes and D)
+  // on the solver's stream: eagerly the first time a configuration `key` is
+  // seen, then captured once into a HIP graph (on a private stream: the
+  // caller's may be the legacy default stream, which cannot be captured) and
+  // replayed whenever the configuration comes again (a few graphs are kept:
+  // the number of active and paired right-hand sides changes as they pass
+  // through cycle ends).  The sequence reads its per-step data from device
+  // tables written before it.
+  qxd_status run_step_launches(const std::array<int64_t, 8> &key,
+                               const std::function<qxd_status(hipStream_t)> &issue);
+
  private:
   qxd_status finish(Slot &sl, int status);
   qxd_status new_inner(Slot &sl);
@@ -67,6 +80,19 @@ class BatchSolver {
   size_t h_stage_bytes_ = 0;
   double *h_norms_ = nullptr;
   DevBuf d_norms_;
+  // graphs of the step's launch sequence, most recently used last, and the
+  // configurations seen once
+  using StepKey = std::array<int64_t, 8>;
+  std::vector<std::pair<StepKey, hipGraphExec_t>> graphs_;
+  std::vector<StepKey> seen_;
+  hipStream_t cap_st_ = nullptr;
+  bool graphs_ok_ = true;
+  void drop_graphs();
 };
+
+// Process-wide switch for graph capture of the batched steps (testing hook).
+void set_step_graphs(bool on);
+// process-wide totals: step graphs captured, and step graphs launched
+void step_graph_counts(int64_t *captures, int64_t *replays);
 
 }  // namespace qxd

@@ -18,6 +18,8 @@
 // bit-identical sums.  All lanes work in both half steps, and the links and
 // Pauli rows of the block stay in registers for the whole block solve; LDS
 // holds only the two spinor buffers exchanged between the parities.
+#include <atomic>
+
 #include "dirac_site.h"
 #include "hop_generic.h"
 #include "sap.h"
@@ -569,16 +571,22 @@ bool sap_quad_ok(int prec, const Geom &g, int qhat) {
   return prec != QXD_F64 && qhat == 0 && g.Vbh <= QNH_MAX && quad_lds(prec, g) <= (size_t)lds_limit();
 }
 
-template <class K>
-static hipError_t allow_lds(K kernel, size_t lds) {
-  if (lds <= 65536) return hipSuccess;
-  return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+// Raise a kernel's dynamic LDS limit once (the largest size asked for so far
+// per kernel), so that launches issued under graph capture make no
+// attribute calls.
+template <auto Kernel>
+static hipError_t allow_lds(size_t lds) {
+  static std::atomic<size_t> granted{65536};
+  if (lds <= granted.load()) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute((const void *)Kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess) granted.store(lds);
+  return e;
 }
 
 template <int P>
 hipError_t launch_sapq_colour(const SapArgs<P> &a, int nblocks_colour, hipStream_t st) {
   size_t lds = quad_lds(P, a.g);
-  hipError_t e = allow_lds(sapq_block_kernel<P>, lds);
+  hipError_t e = allow_lds<sapq_block_kernel<P>>(lds);
   if (e != hipSuccess) return e;
   sapq_block_kernel<P><<<nblocks_colour, quad_threads(a.g), lds, st>>>(a);
   return hipGetLastError();
@@ -589,7 +597,7 @@ hipError_t launch_sapq_batch(const Geom &g, const int *blocks, int nblocks_colou
                              const int *act, int nact, int first, int skip_face, int nmr, hipStream_t st) {
   if (nact < 1) return hipSuccess;
   size_t lds = quad_lds(P, g);
-  hipError_t e = allow_lds(sapq_batch_kernel<P>, lds);
+  hipError_t e = allow_lds<sapq_batch_kernel<P>>(lds);
   if (e != hipSuccess) return e;
   sapq_batch_kernel<P><<<(unsigned)nblocks_colour * nact, quad_threads(g), lds, st>>>(
       g, blocks, slots, act, nact, first, skip_face, nmr);
@@ -605,7 +613,7 @@ hipError_t launch_sapq_pairs(const Geom &g, const int *blocks, int nblocks_colou
                              const int *pairs, int npair, int first, int skip_face, int nmr, hipStream_t st) {
   if (npair < 1) return hipSuccess;
   size_t lds = quad_lds(P, g, 2);
-  hipError_t e = allow_lds(sapq_pair_kernel<P>, lds);
+  hipError_t e = allow_lds<sapq_pair_kernel<P>>(lds);
   if (e != hipSuccess) return e;
   sapq_pair_kernel<P><<<(unsigned)nblocks_colour * npair, quad_threads(g), lds, st>>>(
       g, blocks, slots, pairs, npair, first, skip_face, nmr);

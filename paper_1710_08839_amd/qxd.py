@@ -83,6 +83,8 @@ SIGNATURES = {
     "qxd_serve_stop": ([_VP], _I),
     # testing hooks (include/qxd_debug.h)
     "qxd_debug_set_dirac_variant": ([_I], _I),
+    "qxd_debug_set_step_graphs": ([_I], _I),
+    "qxd_debug_step_graph_counts": ([ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], _I),
     "qxd_debug_get_dirac_variant": ([_VP, _I, ctypes.POINTER(_I)], _I),
 }
 
@@ -127,6 +129,20 @@ def set_dirac_variant(choice=0):
     +32 for non-temporal Pauli/output streams with LDS staging); 0 returns to
     the autotuner.  A testing hook."""
     _check(lib().qxd_debug_set_dirac_variant(int(choice)))
+
+
+def set_step_graphs(enable=True):
+    """Replay batched SAP-GCR steps from captured HIP graphs (default) or
+    issue every launch directly.  A testing hook."""
+    _check(lib().qxd_debug_set_step_graphs(1 if enable else 0))
+
+
+def step_graph_counts():
+    """(captures, launches) of batched-step HIP graphs so far in this
+    process.  A testing hook."""
+    c, r = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().qxd_debug_step_graph_counts(ctypes.byref(c), ctypes.byref(r)))
+    return c.value, r.value
 
 
 def quark(kappa, q=0.0, csw=0.0, csw_u1=1.0):

@@ -41,6 +41,8 @@ def test_header_parses():
     assert len(fns) >= 18
     assert fns["qxd_debug_set_dirac_variant"] == 1
     assert fns["qxd_debug_get_dirac_variant"] == 3
+    assert fns["qxd_debug_set_step_graphs"] == 1
+    assert fns["qxd_debug_step_graph_counts"] == 2
     assert fns["qxd_abi_version"] == 0
     assert fns["qxd_dirac_apply"] == 10
     assert fns["qxd_solve"] == 10

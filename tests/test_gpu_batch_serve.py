@@ -77,6 +77,38 @@ def test_batched_solve_matches_alone(big, prec):
         assert np.array_equal(to_host(one), ph[r]), r
 
 
+def test_step_graphs_match_direct_launches(big):
+    """The captured-graph replay of the batched steps gives the same bits as
+    launching every kernel directly, on repeated solves (each replays the
+    graph many times, with the solver's own host work and synchronisations
+    in between)."""
+    import torch
+    from paper_1710_08839_amd import qxd
+    c = big
+    qs = [qxd.quark(k, q, cs, 1.0) for (k, q, cs) in QUARKS]
+    etas = np.stack([c.source(800 + s) for _ in QUARKS for s in range(2)])
+    s = qxd.solver(kind=qxd.SAP_GCR, tol=1e-10, nkv=8, ncy=3, nmr=4, inner_prec=qxd.F32)
+    outs, counts = [], []
+    try:
+        for graphs in (False, True, True):
+            qxd.set_step_graphs(graphs)
+            c0 = qxd.step_graph_counts()
+            psi = torch.empty_like(to_dev(etas))
+            st, _ = c.field.solve(qs, s, to_dev(etas), psi, nrhs=len(etas))
+            assert st == 0
+            outs.append(to_host(psi))
+            c1 = qxd.step_graph_counts()
+            counts.append((c1[0] - c0[0], c1[1] - c0[1]))
+    finally:
+        qxd.set_step_graphs(True)
+    assert counts[0] == (0, 0)
+    # with graphs on, steps are launched from graphs, and some graphs again
+    for cap, launches in counts[1:]:
+        assert cap >= 1 and launches > cap, counts
+    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[2])
+
+
 def test_serve_mixed_stream(ctx, big, small):
     import torch
     from paper_1710_08839_amd import qxd, synth
