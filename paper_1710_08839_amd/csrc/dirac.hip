@@ -96,7 +96,8 @@ __global__ void __launch_bounds__(256) dirac_kernel(Geom g, const typename St<P>
 // read from memory once; the hops then take in-block neighbours from LDS and
 // only the neighbours across the block faces from memory.  The links and the
 // Pauli term are read as in dirac_kernel.  Requires whole blocks per
-// work-group; LDS: 12 complex per staged site.
+// work-group and hopping links with the U(1) phase folded in (qhat = 0);
+// LDS: 12 complex per staged site.
 template <int P, int KIND, int GROUP, bool NT>
 __global__ void __launch_bounds__(256) dirac_lds_kernel(Geom g, const typename St<P>::pair_t *links,
                                                         const typename St<P>::real_t *angles, int qhat,
@@ -119,6 +120,13 @@ __global__ void __launch_bounds__(256) dirac_lds_kernel(Geom g, const typename S
   const int par = half ? (KIND == DK_ODD ? 1 : 0) : (r >= g.Vbh);
   const int h = r >= g.Vbh ? r - g.Vbh : r;
   const int i = par * g.Vh + blk * g.Vbh + h;
+  // The Pauli self term (full D, the even pass) is computed first, straight
+  // into the result, and the hops are then added with the factor c folded
+  // into their sign: no second 12-component buffer is live at any point.
+  constexpr bool pauli_first = KIND == DK_FULL || KIND == DK_PAULI || KIND == DK_EVEN;
+  // the own site is the staged one when self is the input field
+  const bool self_in_lds = !half && self.data == in.data && self.off == in.off;
+  cx<T> res[4][3];
   // stage one input site: own site (full kinds) or the other parity's site
   if (valid) {
     const int spar = half ? 1 - par : par;
@@ -128,22 +136,31 @@ __global__ void __launch_bounds__(256) dirac_lds_kernel(Geom g, const typename S
     for (int a = 0; a < 4; a++)
 #pragma unroll
       for (int b = 0; b < 3; b++) lds[(a * 3 + b) * ns + threadIdx.x] = v[a][b];
+    if constexpr (pauli_first) {
+      if (!self_in_lds) load_spinor<P, T>(self, i, v);
+      pauli_mul<P, T, NT>(pauli, g, i, v, res);
+    }
   }
   __syncthreads();
   if (!valid) return;
   const int base = lb * per_block;  // LDS slot of the block's first staged site
-  cx<T> res[4][3];
+  if constexpr (!pauli_first) {
 #pragma unroll
-  for (int a = 0; a < 4; a++)
+    for (int a = 0; a < 4; a++)
 #pragma unroll
-    for (int b = 0; b < 3; b++) res[a][b] = {0, 0};
+      for (int b = 0; b < 3; b++) res[a][b] = {0, 0};
+  }
   if (KIND != DK_PAULI) {
     const Site s = decode(g, i);
 #pragma unroll 1
     for (int k0 = 0; k0 < 8; k0 += GROUP) {
 #pragma unroll
       for (int k = k0; k < k0 + GROUP; k++) {
-        const int mu = k >> 1, dir = (k & 1) ? -1 : 1;
+        // odd sites of a full-lattice block take the backward hop of each
+        // direction first: in every step both parities then read the same
+        // links (the forward links of one parity are the backward links of
+        // the other), so each link line is fetched once per work-group
+        const int mu = k >> 1, dir = ((k & 1) ^ (half ? 0 : par)) ? -1 : 1;
         int sg;
         const Site t = neighbour(g, s, mu, dir, sg);
         const int y = s.y(mu) + dir;
@@ -160,36 +177,15 @@ __global__ void __launch_bounds__(256) dirac_lds_kernel(Geom g, const typename S
         } else {
           load_spinor<P, T>(in, j, psi);
         }
-        load_w<P, T>(links, angles, qhat, g, mu, dir > 0 ? (int64_t)i : (int64_t)j, w);
+        load_link<P, T>(links, g, mu, dir > 0 ? (int64_t)i : (int64_t)j, w);
         if (dir > 0)
-          hop_fwd<T>(mu, w, psi, (T)sg, res);
+          hop_fwd<T>(mu, w, psi, c * (T)sg, res);
         else
-          hop_bwd<T>(mu, w, psi, (T)sg, res);
+          hop_bwd<T>(mu, w, psi, c * (T)sg, res);
       }
     }
-#pragma unroll
-    for (int a = 0; a < 4; a++)
-#pragma unroll
-      for (int b = 0; b < 3; b++) res[a][b] = c * res[a][b];
   }
-  // the self term: the own site is in LDS when self is the input field
-  const bool self_in_lds = !half && self.data == in.data && self.off == in.off;
-  if (KIND == DK_FULL || KIND == DK_PAULI || KIND == DK_EVEN) {
-    cx<T> v[4][3], pv[4][3];
-    if (self_in_lds) {
-#pragma unroll
-      for (int a = 0; a < 4; a++)
-#pragma unroll
-        for (int b = 0; b < 3; b++) v[a][b] = lds[(a * 3 + b) * ns + threadIdx.x];
-    } else {
-      load_spinor<P, T>(self, i, v);
-    }
-    pauli_mul<P, T, NT>(pauli, g, i, v, pv);
-#pragma unroll
-    for (int a = 0; a < 4; a++)
-#pragma unroll
-      for (int b = 0; b < 3; b++) res[a][b] = res[a][b] + pv[a][b];
-  } else if (KIND == DK_EVEN_ID || KIND == DK_ODD) {
+  if (KIND == DK_EVEN_ID || KIND == DK_ODD) {
     if (self.data != nullptr) {
       cx<T> v[4][3];
       load_spinor<P, T>(self, i, v);
@@ -266,7 +262,7 @@ hipError_t launch_p(DiracKind kind, int choice, const Geom &g, const OpFields &f
   T cc = (T)c;
   // choice = hop group size, + LDS_VARIANT for the LDS-staged kernel (whole
   // blocks per work-group only)
-  const bool use_lds = (choice & LDS_VARIANT) && per_block <= 256 && kind != DK_PAULI;
+  const bool use_lds = (choice & LDS_VARIANT) && per_block <= 256 && kind != DK_PAULI && f.qhat == 0;
   const bool nt = use_lds && (choice & NT_VARIANT);
   const int group = choice & (LDS_VARIANT - 1);
   const size_t lds = use_lds ? 12 * (size_t)threads * sizeof(cx<T>) : 0;
@@ -296,7 +292,7 @@ hipError_t launch_any(int prec, DiracKind kind, int choice, const Geom &g, const
 // input spinor), per (precision, kernel kind, volume, U(1) phase on the
 // fly): the first call times every candidate on the caller's own operands
 // (all candidates compute the same result up to rounding) and keeps the
-// fastest.
+// fastest, or the first in candidate order within 2% of it.
 struct TuneKey {
   int prec, kind, V, phase;
   bool operator<(const TuneKey &o) const {
@@ -324,22 +320,30 @@ int tune_group(int prec, DiracKind kind, const Geom &g, const OpFields &f, Spino
     (void)hipEventDestroy(e0);
     return 2;
   }
-  int best = 2;
-  float best_ms = 1e30f;
+  float ms_of[16];
+  for (float &m : ms_of) m = 1e30f;
   for (int ci = 0; ci < ncand; ci++) {
     const int gsz = cand[ci];
-    (void)launch_any(prec, kind, gsz, g, f, in, self, out, c, st);  // warm-up
+    // warm-up; a candidate that cannot launch here is skipped
+    if (launch_any(prec, kind, gsz, g, f, in, self, out, c, st) != hipSuccess) continue;
     (void)hipEventRecord(e0, st);
     for (int r = 0; r < 3; r++) (void)launch_any(prec, kind, gsz, g, f, in, self, out, c, st);
     (void)hipEventRecord(e1, st);
     if (hipEventSynchronize(e1) != hipSuccess) break;
     float ms = 0;
     (void)hipEventElapsedTime(&ms, e0, e1);
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = gsz;
-    }
+    ms_of[ci] = ms;
   }
+  // the first candidate within 2% of the fastest: near-ties resolve the same
+  // way in every process
+  float best_ms = 1e30f;
+  for (int ci = 0; ci < ncand; ci++) best_ms = ms_of[ci] < best_ms ? ms_of[ci] : best_ms;
+  int best = 2;
+  for (int ci = 0; ci < ncand; ci++)
+    if (ms_of[ci] <= 1.02f * best_ms) {
+      best = cand[ci];
+      break;
+    }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   std::lock_guard<std::mutex> lk(g_tune_mu);
