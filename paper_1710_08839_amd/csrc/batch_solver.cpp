@@ -101,6 +101,12 @@ size_t BatchSolver::slot_bytes(const Field *f, int prec, const qxd_solver &s) {
          scal_doubles(nkv) * 8;
 }
 
+// 16-byte groups of one inner-precision vector (flat layouts)
+int64_t BatchSolver::ngroups() const {
+  const int w = prec_ == QXD_F64 ? 1 : (prec_ == QXD_F32 ? 2 : 4);
+  return f_->g.V * 12 / w;
+}
+
 int BatchSolver::active() const {
   int n = 0;
   for (auto &s : slots_) n += s->active;
@@ -119,7 +125,8 @@ qxd_status BatchSolver::reserve(int n) {
     slots_.push_back(std::move(sl));
   }
   size_t nslot = slots_.size();
-  size_t stage = nslot * (sizeof(SapSlot<QXD_F64>) + sizeof(DSlot<QXD_F64>) + 2 * sizeof(int)) + 256;
+  size_t stage =
+      nslot * (sizeof(SapSlot<QXD_F64>) + sizeof(DSlot<QXD_F64>) + 2 * sizeof(int) + sizeof(GsSlot<QXD_F64>)) + 256;
   if (stage > h_stage_bytes_) {
     BCK(hipStreamSynchronize(st_));
     if (h_stage_) (void)hipHostFree(h_stage_);
@@ -130,12 +137,18 @@ qxd_status BatchSolver::reserve(int n) {
     h_norms_ = nullptr;
     BCK(hipHostMalloc((void **)&h_norms_, nslot * sizeof(double) + 64, hipHostMallocDefault));
   }
-  const void *old[3] = {dslots_.p, sslots_.p, act_.p};
+  const void *old[5] = {dslots_.p, sslots_.p, act_.p, gsslots_.p, gspart_.p};
   BCK(dslots_.ensure(nslot * sizeof(DSlot<QXD_F64>)));
   BCK(sslots_.ensure(nslot * sizeof(SapSlot<QXD_F64>)));
   BCK(act_.ensure(2 * nslot * sizeof(int)));
+  if (gs_batch_ok(prec_)) {
+    BCK(gsslots_.ensure(nslot * sizeof(GsSlot<QXD_F64>)));
+    BCK(gspart_.ensure(gs_batch_partial_doubles((int)nslot, ngroups()) * 8));
+  }
   // graphs name the tables by address: none survives a reallocation
-  if (old[0] != dslots_.p || old[1] != sslots_.p || old[2] != act_.p) drop_graphs();
+  if (old[0] != dslots_.p || old[1] != sslots_.p || old[2] != act_.p || old[3] != gsslots_.p ||
+      old[4] != gspart_.p)
+    drop_graphs();
   BCK(d_norms_.ensure(nslot * sizeof(double)));
   BCK(partial_.ensure(blas_partial_doubles() * 8));
   return QXD_OK;
@@ -255,8 +268,8 @@ struct BImpl {
 
   // the batched part of a step: phi_k = M_SAP rho, chi_k = D phi_k
   static qxd_status batched(BatchSolver &bs, std::vector<BatchSolver::Slot *> &act, hipStream_t st,
-                            DevBuf &sslots, DevBuf &dslots, DevBuf &actbuf, void *stage, int ncy, int nmr,
-                            int nkv) {
+                            DevBuf &sslots, DevBuf &dslots, DevBuf &actbuf, DevBuf &gsslots, DevBuf &gspart,
+                            int64_t ngroups, double *norms, void *stage, int ncy, int nmr, int nkv) {
     Field *f = bs.field();
     const Geom &g = f->g;
     int n = (int)act.size();
@@ -304,6 +317,22 @@ struct BImpl {
     BCK(hipMemcpyAsync(sslots.p, hs, n * sizeof(SapSlot<P>), hipMemcpyHostToDevice, st));
     BCK(hipMemcpyAsync(dslots.p, hd, n * sizeof(DSlot<P>), hipMemcpyHostToDevice, st));
     BCK(hipMemcpyAsync(actbuf.p, ha, 2 * n * sizeof(int), hipMemcpyHostToDevice, st));
+    // Gram-Schmidt table (chi_k = D phi_k is orthogonalised in the same step)
+    constexpr bool gs_batched = gs_batch_ok(P);
+    if constexpr (gs_batched) {
+      GsSlot<P> *hg = (GsSlot<P> *)(((uintptr_t)(ha + 2 * n) + 15) & ~(uintptr_t)15);
+      for (int j = 0; j < n; j++) {
+        BatchSolver::Slot &sl = *act[j];
+        hg[j].chi0 = (typename St<P>::pair_t *)sl.chi(nkv, 0);
+        hg[j].vstride = (int64_t)(sl.fbP / sizeof(typename St<P>::pair_t));
+        hg[j].rho = (typename St<P>::pair_t *)sl.rho();
+        hg[j].ak = sl.amat() + 2 * sl.k * nkv;
+        hg[j].rec = sl.rec(nkv);
+        hg[j].norm = norms + j;
+        hg[j].k = sl.k;
+      }
+      BCK(hipMemcpyAsync(gsslots.p, hg, n * sizeof(GsSlot<P>), hipMemcpyHostToDevice, st));
+    }
     const int *dsingle = actbuf.as<int>() + n, *dpair = dsingle + nsingle;
     const int *lists[2];
     int nper;
@@ -321,10 +350,13 @@ struct BImpl {
                                     cy == 0 && c == 0, nmr, st));
         }
       BCK(launch_dirac_batch<P>(g, dslots.as<DSlot<P>>(), actbuf.as<int>(), n, 2, st));
+      if constexpr (gs_batched)
+        BCK(blas_gs_batch<P>(gsslots.as<GsSlot<P>>(), n, ngroups, gspart.as<double>(), st));
       return QXD_OK;
     };
-    const std::array<int64_t, 8> key{P, n, npair, (int64_t)ncy * 256 + nmr, (int64_t)(intptr_t)sslots.p,
-                                     (int64_t)(intptr_t)dslots.p, (int64_t)(intptr_t)actbuf.p, nper};
+    const std::array<int64_t, 10> key{P, n, npair, (int64_t)ncy * 256 + nmr, (int64_t)(intptr_t)sslots.p,
+                                      (int64_t)(intptr_t)dslots.p, (int64_t)(intptr_t)actbuf.p, nper,
+                                      (int64_t)(intptr_t)gsslots.p, (int64_t)(intptr_t)gspart.p};
     // FP64 inner solves (not a performance path) launch directly
     if constexpr (P == QXD_F64) return issue(st);
     return bs.run_step_launches(key, issue);
@@ -509,14 +541,15 @@ qxd_status BatchSolver::step() {
   int n = (int)act.size();
   // batched: phi_k = M_SAP rho, chi_k = D phi_k
   switch (prec_) {
-    case QXD_F64: BCS(BImpl<QXD_F64>::batched(*this, act, st_, sslots_, dslots_, act_, h_stage_, ncy_, nmr_, nkv_)); break;
-    case QXD_F32: BCS(BImpl<QXD_F32>::batched(*this, act, st_, sslots_, dslots_, act_, h_stage_, ncy_, nmr_, nkv_)); break;
-    case QXD_F16S: BCS(BImpl<QXD_F16S>::batched(*this, act, st_, sslots_, dslots_, act_, h_stage_, ncy_, nmr_, nkv_)); break;
-    default: BCS(BImpl<QXD_BF16>::batched(*this, act, st_, sslots_, dslots_, act_, h_stage_, ncy_, nmr_, nkv_)); break;
+    case QXD_F64: BCS(BImpl<QXD_F64>::batched(*this, act, st_, sslots_, dslots_, act_, gsslots_, gspart_, ngroups(), d_norms_.as<double>(), h_stage_, ncy_, nmr_, nkv_)); break;
+    case QXD_F32: BCS(BImpl<QXD_F32>::batched(*this, act, st_, sslots_, dslots_, act_, gsslots_, gspart_, ngroups(), d_norms_.as<double>(), h_stage_, ncy_, nmr_, nkv_)); break;
+    case QXD_F16S: BCS(BImpl<QXD_F16S>::batched(*this, act, st_, sslots_, dslots_, act_, gsslots_, gspart_, ngroups(), d_norms_.as<double>(), h_stage_, ncy_, nmr_, nkv_)); break;
+    default: BCS(BImpl<QXD_BF16>::batched(*this, act, st_, sslots_, dslots_, act_, gsslots_, gspart_, ngroups(), d_norms_.as<double>(), h_stage_, ncy_, nmr_, nkv_)); break;
   }
-  // per right-hand side: Gram-Schmidt and residual update
+  // per right-hand side: Gram-Schmidt and residual update (done for the whole
+  // batch inside the step's launches where the layout is flat)
   double *dn = d_norms_.as<double>();
-  for (int j = 0; j < n; j++) {
+  for (int j = 0; j < n && !gs_batch_ok(prec_); j++) {
     switch (prec_) {
       case QXD_F64: BCS(BImpl<QXD_F64>::gs(*act[j], g, partial_.as<double>(), nkv_, st_, dn + j)); break;
       case QXD_F32: BCS(BImpl<QXD_F32>::gs(*act[j], g, partial_.as<double>(), nkv_, st_, dn + j)); break;

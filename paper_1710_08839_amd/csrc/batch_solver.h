@@ -50,7 +50,8 @@ class BatchSolver {
 
   struct Slot;  // one right-hand side in flight (batch_solver.cpp)
 
-  // Issue the fixed launch sequence of a step (the batched SAP passes and D)
+  // Issue the fixed launch sequence of a step (the batched SAP passes, D and
+  // the batched Gram-Schmidt)
   // on the solver's stream: eagerly the first time a configuration `key` is
   // seen, then captured once into a HIP graph (on a private stream: the
   // caller's may be the legacy default stream, which cannot be captured) and
@@ -58,7 +59,7 @@ class BatchSolver {
   // the number of active and paired right-hand sides changes as they pass
   // through cycle ends).  The sequence reads its per-step data from device
   // tables written before it.
-  qxd_status run_step_launches(const std::array<int64_t, 8> &key,
+  qxd_status run_step_launches(const std::array<int64_t, 10> &key,
                                const std::function<qxd_status(hipStream_t)> &issue);
 
  private:
@@ -76,13 +77,17 @@ class BatchSolver {
   std::vector<Finished> done_;
   // device/pinned staging of slot descriptors and the active list
   DevBuf dslots_, sslots_, act_, partial_;
+  // batched Gram-Schmidt: per-slot table and partial sums (all precisions but
+  // FP16 + scale, which orthogonalise one right-hand side at a time)
+  DevBuf gsslots_, gspart_;
+  int64_t ngroups() const;
   void *h_stage_ = nullptr;
   size_t h_stage_bytes_ = 0;
   double *h_norms_ = nullptr;
   DevBuf d_norms_;
   // graphs of the step's launch sequence, most recently used last, and the
   // configurations seen once
-  using StepKey = std::array<int64_t, 8>;
+  using StepKey = std::array<int64_t, 10>;
   std::vector<std::pair<StepKey, hipGraphExec_t>> graphs_;
   std::vector<StepKey> seen_;
   hipStream_t cap_st_ = nullptr;

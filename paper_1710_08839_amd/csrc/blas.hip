@@ -28,6 +28,26 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
   return r;
 }
 
+// K block sums at once, each in the order of block_sum (wavefront tree, then
+// the four wavefronts pairwise) but with a single barrier; partial[k * stride]
+// receives sum k (written by thread k)
+template <int K>
+__device__ __forceinline__ void block_sums(const double (&v)[K], double *sh, double *partial, int64_t stride) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    double x = v[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0) sh[4 * k + w] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    const int k = threadIdx.x;
+    partial[k * stride] = (sh[4 * k] + sh[4 * k + 1]) + (sh[4 * k + 2] + sh[4 * k + 3]);
+  }
+}
+
 inline unsigned red_grid(int64_t n) {
   int64_t g = (n + BT - 1) / BT;
   return (unsigned)(g < RED_BLOCKS ? (g < 1 ? 1 : g) : RED_BLOCKS);
@@ -273,7 +293,7 @@ template <int P, int N>
 __global__ void mdot_flat_kernel(VecList<P> ys, Spinor<P> x, int64_t g0, int64_t ng, double *partial,
                                  int base) {
   constexpr int W = VW<P>;
-  __shared__ double sh[4];
+  __shared__ double sh[4 * 2 * N];
   double acc[2 * N];
 #pragma unroll
   for (int k = 0; k < 2 * N; k++) acc[k] = 0.0;
@@ -293,11 +313,7 @@ __global__ void mdot_flat_kernel(VecList<P> ys, Spinor<P> x, int64_t g0, int64_t
       }
     }
   }
-#pragma unroll
-  for (int k = 0; k < 2 * N; k++) {
-    double s = block_sum(acc[k], sh);
-    if (threadIdx.x == 0) partial[(int64_t)(base + k) * gridDim.x + blockIdx.x] = s;
-  }
+  block_sums<2 * N>(acc, sh, partial + (int64_t)base * gridDim.x + blockIdx.x, gridDim.x);
 }
 
 // z_t = src_t - sum_l cf_l ys_t[l] over groups; norms of the stored z_0 (the
@@ -306,7 +322,7 @@ template <int P, int N>
 __global__ void maxpy_flat_kernel(MaxpyArgs<P> a, int64_t g0, int64_t ng, double *partial) {
   constexpr int W = VW<P>;
   using C = typename St<P>::comp_t;
-  __shared__ double sh[4];
+  __shared__ double sh[12];
   cx<double> cf[N > 0 ? N : 1];
 #pragma unroll
   for (int l = 0; l < N; l++) {
@@ -352,12 +368,8 @@ __global__ void maxpy_flat_kernel(MaxpyArgs<P> a, int64_t g0, int64_t ng, double
     }
   }
   if (a.want_norms) {
-    double s0 = block_sum(nn, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s0;
-    double s1 = block_sum(wr, sh);
-    if (threadIdx.x == 0) partial[gridDim.x + blockIdx.x] = s1;
-    double s2 = block_sum(wi, sh);
-    if (threadIdx.x == 0) partial[2 * gridDim.x + blockIdx.x] = s2;
+    const double v3[3] = {nn, wr, wi};
+    block_sums<3>(v3, sh, partial + blockIdx.x, gridDim.x);
   }
 }
 
@@ -378,6 +390,193 @@ bool same_offset(const SpinorArg &a, const SpinorArg &x) {
   return a.off == x.off && a.rd.R == x.rd.R;
 }
 
+// --- batched Gram-Schmidt (GsSlot) ------------------------------------------
+
+// one 16-byte group of a flat vector whose base pointer was read from a table
+template <int P>
+__device__ __forceinline__ void gld_grp(const typename St<P>::pair_t *base, int64_t gi, cx<double> out[VW<P>]) {
+  using R = typename RawOf<16>::type;
+  const R r = gld((const R *)base, gi);
+  typename St<P>::pair_t v[VW<P>];
+  __builtin_memcpy(v, &r, 16);
+#pragma unroll
+  for (int w = 0; w < VW<P>; w++) {
+    const auto z = St<P>::ld(v, w);
+    out[w] = {(double)z.re, (double)z.im};
+  }
+}
+// store a group rounded to the storage precision; `stored` = what was written
+template <int P>
+__device__ __forceinline__ void gst_grp(typename St<P>::pair_t *base, int64_t gi, const cx<double> in[VW<P>],
+                                        cx<double> stored[VW<P>]) {
+  using R = typename RawOf<16>::type;
+  using C = typename St<P>::comp_t;
+  typename St<P>::pair_t v[VW<P>];
+#pragma unroll
+  for (int w = 0; w < VW<P>; w++) {
+    St<P>::st(v, w, cx<C>{(C)in[w].re, (C)in[w].im});
+    const auto z = St<P>::ld(v, w);
+    stored[w] = {(double)z.re, (double)z.im};
+  }
+  R r;
+  __builtin_memcpy(&r, v, 16);
+  gst((R *)base, gi, r);
+}
+
+constexpr int GS_CH = 8;  // vectors per sweep of the dot kernel
+
+// partial[(y * 2 MAXV + 2l (+1)) * gx + bx] = block sums of (chi_l, chi_k)
+template <int P>
+__global__ void gs_dot_kernel(const GsSlot<P> *slots, int64_t ng, double *partial) {
+  constexpr int W = VW<P>;
+  __shared__ double sh[4 * 2 * GS_CH];
+  const GsSlot<P> s = slots[blockIdx.y];
+  const int k = s.k, gx = gridDim.x;
+  double *pp = partial + (int64_t)blockIdx.y * 2 * MAXV * gx + blockIdx.x;
+  const typename St<P>::pair_t *xk = s.chi0 + (int64_t)k * s.vstride;
+  for (int c0 = 0; c0 < k; c0 += GS_CH) {
+    const int m = k - c0 < GS_CH ? k - c0 : GS_CH;
+    double acc[2 * GS_CH];
+#pragma unroll
+    for (int j = 0; j < 2 * GS_CH; j++) acc[j] = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * BT + threadIdx.x; t < ng; t += (int64_t)gx * BT) {
+      cx<double> xv[W];
+      gld_grp<P>(xk, t, xv);
+#pragma unroll
+      for (int l = 0; l < GS_CH; l++) {
+        if (l < m) {
+          cx<double> yv[W];
+          gld_grp<P>(s.chi0 + (int64_t)(c0 + l) * s.vstride, t, yv);
+#pragma unroll
+          for (int w = 0; w < W; w++) {
+            acc[2 * l] = fmat(yv[w].re, xv[w].re, acc[2 * l]);
+            acc[2 * l] = fmat(yv[w].im, xv[w].im, acc[2 * l]);
+            acc[2 * l + 1] = fmat(yv[w].re, xv[w].im, acc[2 * l + 1]);
+            acc[2 * l + 1] = fmat(-yv[w].im, xv[w].re, acc[2 * l + 1]);
+          }
+        }
+      }
+    }
+    // block sums of the 2m values (wavefront trees, then the 4 wavefronts)
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < 2 * GS_CH; j++) {
+      double x = acc[j];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+      if (lane == 0) sh[4 * j + wv] = x;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < 2 * m) {
+      const int j = threadIdx.x;
+      pp[(int64_t)(2 * c0 + j) * gx] = (sh[4 * j] + sh[4 * j + 1]) + (sh[4 * j + 2] + sh[4 * j + 3]);
+    }
+    __syncthreads();
+  }
+}
+
+// chi_k -= sum_l ak_l chi_l; partial values 0..2 = |chi_k|^2, (chi_k, rho)
+template <int P>
+__global__ void gs_axpy_kernel(const GsSlot<P> *slots, int64_t ng, double *partial) {
+  constexpr int W = VW<P>;
+  __shared__ double sh[12];
+  const GsSlot<P> s = slots[blockIdx.y];
+  const int k = s.k, gx = gridDim.x;
+  typename St<P>::pair_t *xk = s.chi0 + (int64_t)k * s.vstride;
+  double nn = 0.0, wr = 0.0, wi = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * BT + threadIdx.x; t < ng; t += (int64_t)gx * BT) {
+    cx<double> z[W];
+    gld_grp<P>(xk, t, z);
+#pragma unroll 4
+    for (int l = 0; l < k; l++) {
+      const cx<double> cf{gld(s.ak, 2 * l), gld(s.ak, 2 * l + 1)};
+      cx<double> y[W];
+      gld_grp<P>(s.chi0 + (int64_t)l * s.vstride, t, y);
+#pragma unroll
+      for (int w = 0; w < W; w++) z[w] = z[w] - cf * y[w];
+    }
+    cx<double> zs[W], rv[W];
+    gst_grp<P>(xk, t, z, zs);
+    gld_grp<P>(s.rho, t, rv);
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+      nn += norm2(zs[w]);
+      const cx<double> c = cmulc(zs[w], rv[w]);
+      wr += c.re;
+      wi += c.im;
+    }
+  }
+  const double v3[3] = {nn, wr, wi};
+  block_sums<3>(v3, sh, partial + (int64_t)blockIdx.y * 2 * MAXV * gx + blockIdx.x, gx);
+}
+
+// rho -= (rec[3k+1..2] / rec[3k]) chi_k; partial value 0 = |rho|^2
+template <int P>
+__global__ void gs_update_kernel(const GsSlot<P> *slots, int64_t ng, double *partial) {
+  constexpr int W = VW<P>;
+  __shared__ double sh[4];
+  const GsSlot<P> s = slots[blockIdx.y];
+  const int k = s.k, gx = gridDim.x;
+  const typename St<P>::pair_t *xk = s.chi0 + (int64_t)k * s.vstride;
+  const double d = gld(s.rec, 3 * k);
+  const cx<double> c{gld(s.rec, 3 * k + 1) / d, gld(s.rec, 3 * k + 2) / d};
+  double nn = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * BT + threadIdx.x; t < ng; t += (int64_t)gx * BT) {
+    cx<double> r[W], x[W], rs[W];
+    gld_grp<P>(s.rho, t, r);
+    gld_grp<P>(xk, t, x);
+#pragma unroll
+    for (int w = 0; w < W; w++) r[w] = r[w] - c * x[w];
+    gst_grp<P>(s.rho, t, r, rs);
+#pragma unroll
+    for (int w = 0; w < W; w++) nn += norm2(rs[w]);
+  }
+  const double v1[1] = {nn};
+  block_sums<1>(v1, sh, partial + (int64_t)blockIdx.y * 2 * MAXV * gx + blockIdx.x, gx);
+}
+
+// Per slot (one work-group each): add the partial sums of a phase in a fixed
+// order and write the results.  phase 0: ak_l = dot_l / rec[3l] (l < k);
+// phase 1: rec[3k..3k+2]; phase 2: *norm.
+template <int P>
+__global__ void gs_finish_kernel(const GsSlot<P> *slots, int gx, const double *partial, int phase) {
+  constexpr int K = 16;
+  __shared__ double sh[4 * K], res[K];
+  const GsSlot<P> s = slots[blockIdx.x];
+  const int k = s.k;
+  const int nval = phase == 0 ? 2 * k : (phase == 1 ? 3 : 1);
+  const double *pp = partial + (int64_t)blockIdx.x * 2 * MAXV * gx;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int v0 = 0; v0 < nval; v0 += K) {
+    const int m = nval - v0 < K ? nval - v0 : K;
+#pragma unroll
+    for (int j = 0; j < K; j++) {
+      double x = 0.0;
+      if (j < m)
+        for (int b = threadIdx.x; b < gx; b += BT) x += pp[(int64_t)(v0 + j) * gx + b];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+      if (lane == 0) sh[4 * j + wv] = x;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < m) {
+      const int j = threadIdx.x;
+      res[j] = (sh[4 * j] + sh[4 * j + 1]) + (sh[4 * j + 2] + sh[4 * j + 3]);
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < m) {
+      const int j = threadIdx.x, v = v0 + j;
+      if (phase == 0)
+        gst(s.ak, v, res[j] / gld(s.rec, 3 * (v >> 1)));
+      else if (phase == 1)
+        gst(s.rec, 3 * k + v, res[j]);
+      else
+        gst(s.norm, 0, res[j]);
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 hipError_t finish(const double *partial, int nblk, int nred, double *out, const double *div,
@@ -395,6 +594,7 @@ hipError_t blas_mdot(const SpinorArg *ys, int n, SpinorArg x, int64_t first, int
   int64_t g0 = 0, ng = 0;
   bool flat = flat_range<P>(x, first, count, &g0, &ng);
   for (int k = 0; k < n && flat; k++) flat = same_offset<P>(ys[k], x);
+  if (flat) g = red_grid(ng);  // one thread per 16-byte group where the vector is short
   for (int c0 = 0; c0 < n; c0 += CHUNK) {
     int m = n - c0 < CHUNK ? n - c0 : CHUNK;
     VecList<P> l;
@@ -429,6 +629,7 @@ hipError_t blas_maxpy(const MaxpyHost &h, int64_t first, int64_t count, double *
     for (int k = 0; k < h.n && flat; k++) flat = same_offset<P>(h.ys[tr][k], h.dst[0]);
   }
   if (flat && h.w.ptr) flat = same_offset<P>(h.w, h.dst[0]);
+  if (flat) g = red_grid(ng);  // one thread per 16-byte group where the vector is short
   int c0 = 0;
   do {
     int m = h.n - c0 < CHUNK ? h.n - c0 : CHUNK;
@@ -520,5 +721,28 @@ QXD_INST2(QXD_F32, QXD_F32)
 QXD_INST2(QXD_F16S, QXD_F16S)
 QXD_INST2(QXD_BF16, QXD_BF16)
 #undef QXD_INST2
+
+unsigned gs_batch_grid(int64_t ngroups) { return red_grid(ngroups); }
+
+template <int P>
+hipError_t blas_gs_batch(const GsSlot<P> *slots, int n, int64_t ngroups, double *partial, hipStream_t st) {
+  if (n < 1) return hipSuccess;
+  if constexpr (St<P>::scaled) {
+    return hipErrorInvalidValue;
+  } else {
+    const unsigned gx = red_grid(ngroups);
+    const dim3 grid(gx, (unsigned)n);
+    gs_dot_kernel<P><<<grid, BT, 0, st>>>(slots, ngroups, partial);
+    gs_finish_kernel<P><<<(unsigned)n, BT, 0, st>>>(slots, (int)gx, partial, 0);
+    gs_axpy_kernel<P><<<grid, BT, 0, st>>>(slots, ngroups, partial);
+    gs_finish_kernel<P><<<(unsigned)n, BT, 0, st>>>(slots, (int)gx, partial, 1);
+    gs_update_kernel<P><<<grid, BT, 0, st>>>(slots, ngroups, partial);
+    gs_finish_kernel<P><<<(unsigned)n, BT, 0, st>>>(slots, (int)gx, partial, 2);
+    return hipGetLastError();
+  }
+}
+template hipError_t blas_gs_batch<QXD_F64>(const GsSlot<QXD_F64> *, int, int64_t, double *, hipStream_t);
+template hipError_t blas_gs_batch<QXD_F32>(const GsSlot<QXD_F32> *, int, int64_t, double *, hipStream_t);
+template hipError_t blas_gs_batch<QXD_BF16>(const GsSlot<QXD_BF16> *, int, int64_t, double *, hipStream_t);
 
 }  // namespace qxd
