@@ -177,6 +177,91 @@ def solve_rates(ctx, nsrc, nsrc_fp64, dims=(48, 24, 24, 24)):
     return out
 
 
+def single_solve(f, q, s, eta):
+    """One right-hand side to a true FP64 residual of 1e-10; the residual is
+    the library's own FP64 ||eta - D psi|| / ||eta|| (the FP64 operator is
+    tested against the oracle to 1e-12)."""
+    import torch
+    from paper_1710_08839_amd import qxd
+    psi = torch.empty_like(eta)
+    # warm-up: builds the operator in the inner precision and tunes its kernels
+    f.solve(q, qxd.solver(kind=s.kind, tol=1e-3, nkv=s.nkv, ncy=s.ncy, nmr=s.nmr, inner_prec=s.inner_prec),
+            eta, psi, check=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, info = f.solve(q, s, eta, psi, check=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    i = info[0]
+    return {"seconds": round(dt, 3), "status": st, "outer_iters": i.outer_iters, "inner_iters": i.inner_iters,
+            "true_resid": i.true_resid}
+
+
+def single_rhs_32x16(ctx):
+    """32 x 16^3 with C* in x, y, z (eps 0.3, A ~ N(0, 0.15), kappa 0.124,
+    csw 1.0), one Gaussian source per charge: SAP-GCR with 4^4 blocks and an
+    FP32 or an FP64 inner solver."""
+    import torch
+    from paper_1710_08839_amd import qxd, synth
+    dims = (32, 16, 16, 16)
+    u, a = synth.gauge_field(dims, 20171001, 0.3, 0.15)
+    f = qxd.Field(ctx, dims, u, a, cstar=3)
+    del u, a
+    out = {}
+    for q, seed in ((2 / 3, 1001), (-1 / 3, 1002)):
+        eta = torch.from_numpy(synth.source(dims, 3, seed)).cuda()
+        for name, prec in (("f32_inner", qxd.F32), ("f64_inner", qxd.F64)):
+            s = qxd.solver(kind=qxd.SAP_GCR, tol=1e-10, nkv=24, ncy=4, nmr=4, inner_prec=prec)
+            r = single_solve(f, qxd.quark(0.124, q, 1.0, 1.0), s, eta)
+            out[f"q={q:+.3f} {name}"] = r
+            log(f"32x16^3 q={q:+.3f} {name}: {r['seconds']} s, outer {r['outer_iters']}, "
+                f"inner {r['inner_iters']}, resid {r['true_resid']:.2e}")
+    f.release()
+    return out
+
+
+def single_rhs_64x32(f):
+    """The 64 x 32^3 field of the D leg (q = -1/3, kappa 0.1365, csw 1.9), one
+    Gaussian source: SAP-GCR with FP16+scale or BF16 inner storage (FP32
+    arithmetic) and FP64 outer defect correction."""
+    import torch
+    from paper_1710_08839_amd import qxd, synth
+    dims = (64, 32, 32, 32)
+    eta = torch.from_numpy(synth.source(dims, 3, 1003)).cuda()
+    q = qxd.quark(0.1365, -1 / 3, 1.9, 1.0)
+    out = {}
+    for name, prec in (("f16s_inner", qxd.F16S), ("bf16_inner", qxd.BF16)):
+        s = qxd.solver(kind=qxd.SAP_GCR, tol=1e-10, nkv=24, ncy=4, nmr=4, inner_prec=prec)
+        r = single_solve(f, q, s, eta)
+        out[name] = r
+        log(f"64x32^3 {name}: {r['seconds']} s, outer {r['outer_iters']}, inner {r['inner_iters']}, "
+            f"resid {r['true_resid']:.2e}")
+    return out
+
+
+def stream_gbs(reads_per_write, dst_bytes=49152 * 21845, reps=10):
+    """The library's streaming probe (reads_per_write bytes read per byte
+    written, each once), timed with HIP events: the practical HBM ceiling for
+    that read/write mix next to the kernels' rates."""
+    import torch
+    from paper_1710_08839_amd import qxd
+    a = torch.empty(reads_per_write * dst_bytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty(dst_bytes // 4, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    qxd.stream_probe(a, b, dst_bytes, reads_per_write, stream=stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        qxd.stream_probe(a, b, dst_bytes, reads_per_write, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return round((reads_per_write + 1) * dst_bytes / (ms * 1e-3) / 1e9, 1)
+
+
 SERVE_SIZES = [(8, 8, 8, 8), (32, 16, 16, 16), (48, 24, 24, 24), (64, 32, 32, 32)]
 
 
@@ -270,6 +355,7 @@ def main():
     ap.add_argument("--nsrc", type=int, default=12, help="point sources per operator, batched solve leg")
     ap.add_argument("--nsrc-fp64", type=int, default=1, help="point sources per operator, FP64 baseline")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-single", action="store_true", help="skip the single right-hand-side solves")
     ap.add_argument("--serve-requests", type=int, default=12)
     ap.add_argument("--serve-max-rhs", type=int, default=3)
     ap.add_argument("--serve-rate", type=float, default=2.0, help="request arrivals per second")
@@ -330,7 +416,18 @@ def main():
     ms = time_applies(field, q, 0, 3, args.steps, args.warmup)
     value = BYTES_PER_SITE[0] * V / (ms * 1e-3) / 1e9
     kernel = kernel_name(args.dirac_variant or field.dirac_variant(0), 0)
+    stream_ceiling = {"read7_write1_GB/s": stream_gbs(7), "copy_GB/s": stream_gbs(1),
+                      "what": "library streaming probe: per thread 12 r 16-byte non-temporal loads folded "
+                              "into 12 stores, 4 KB planes as in the block-major fields, 1 GiB written; "
+                              "r = 7 is the FP64 D kernel's read/write mix"}
+    log(f"streaming ceiling: {stream_ceiling}")
+
+    single = None
+    if not args.no_single:
+        single = {"64x32^3": single_rhs_64x32(field)}
     field.release()
+    if single is not None:
+        single["32x16^3"] = single_rhs_32x16(ctx)
 
     solves = None
     if not args.no_solve:
@@ -370,6 +467,8 @@ def main():
                      "kernel": kernel,
                      "bytes_per_launch": BYTES_PER_SITE[0] * V},
         "dw": dw,
+        "stream_ceiling": stream_ceiling,
+        "single_rhs": single,
         "solves": solves,
         "serve": serve,
         "cpu_baseline": cpu,

@@ -38,6 +38,20 @@ qxd_status qxd_debug_set_step_graphs(int enable);
  * configuration repeats).  QXD_EINVAL if either pointer is NULL. */
 qxd_status qxd_debug_step_graph_counts(int64_t *captures, int64_t *replays);
 
+/* Streaming probe on the current device, the practical bandwidth ceiling the
+ * benchmark reports next to the kernels, shaped like the spinor traffic of
+ * the block-major fields.  dst is cut into chunks of 12 planes of 4 KB, src
+ * into chunks of 12 r planes (r = reads_per_write: 1, 2, 4, 7 or 8); plane p
+ * of dst chunk c is the bytewise xor of planes p, p + 12, ..., p + 12 (r - 1)
+ * of src chunk c, with non-temporal loads and stores, so r bytes are read
+ * per byte written (the FP64 Dirac operator reads about 7 per byte it
+ * writes).  src holds r * dst_bytes bytes; both buffers are device memory,
+ * 16-byte aligned and disjoint; dst_bytes a multiple of 49152 (QXD_EINVAL
+ * otherwise).  Asynchronous on `stream` (a hipStream_t, NULL =
+ * default stream). */
+qxd_status qxd_debug_stream(const void *src_dev, void *dst_dev, size_t dst_bytes, int reads_per_write,
+                            void *stream);
+
 /* The variant the autotuner chose for the full operator D (phase folded into
  * the links) on this field's lattice in precision prec, in the encoding of
  * qxd_debug_set_dirac_variant; 0 if D has not been applied yet. */

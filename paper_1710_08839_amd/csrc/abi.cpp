@@ -10,6 +10,7 @@
 #include "../../include/qxd_debug.h"
 #include "host.h"
 #include "batch_solver.h"
+#include "blas.h"
 #include "launch.h"
 #include "solver.h"
 
@@ -260,6 +261,19 @@ qxd_status qxd_debug_step_graph_counts(int64_t *captures, int64_t *replays) {
     return QXD_EINVAL;
   }
   step_graph_counts(captures, replays);
+  return QXD_OK;
+}
+
+qxd_status qxd_debug_stream(const void *src_dev, void *dst_dev, size_t dst_bytes, int reads_per_write,
+                            void *stream) {
+  const int r = reads_per_write;
+  if (!src_dev || !dst_dev || (((uintptr_t)src_dev | (uintptr_t)dst_dev) & 15) || dst_bytes % 49152 ||
+      !(r == 1 || r == 2 || r == 4 || r == 7 || r == 8)) {
+    set_error("stream probe needs non-NULL 16-byte-aligned buffers, a multiple of 49152 bytes and "
+              "reads_per_write in {1, 2, 4, 7, 8}");
+    return QXD_EINVAL;
+  }
+  QXD_HIP_CHECK(launch_stream(src_dev, dst_dev, dst_bytes, r, (hipStream_t)stream));
   return QXD_OK;
 }
 

@@ -29,6 +29,12 @@ struct MaxpyHost {
   SpinorArg w{nullptr, 0, 0, RunDiv{}};     // optional: also (z_0, w)
 };
 
+// Streaming probe, the reference point for the kernels' bandwidth: per 48 KB
+// chunk (12 planes of 4 KB) of dst (16-byte aligned, dst_bytes a multiple of
+// 49152), plane p = xor of planes p, p + 12, ... of the 12 reads_per_write
+// planes of the matching src chunk (reads_per_write 1, 2, 4, 7 or 8)
+hipError_t launch_stream(const void *src, void *dst, size_t dst_bytes, int reads_per_write, hipStream_t st);
+
 // Partial-sum scratch needed by any call: 3 * 2 * MAXV * RED_BLOCKS doubles
 inline size_t blas_partial_doubles() { return (size_t)2 * MAXV * RED_BLOCKS + 8; }
 

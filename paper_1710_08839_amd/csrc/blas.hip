@@ -577,7 +577,47 @@ __global__ void gs_finish_kernel(const GsSlot<P> *slots, int gx, const double *p
   }
 }
 
+// Shaped like one FP64 spinor site of the block-major fields: thread (c, t)
+// of 4 KB-plane chunk c reads the 12 NR planes of src chunk c at position t
+// and writes 12 planes of dst chunk c, plane p = xor of input planes
+// p, p + 12, ..., p + 12 (NR - 1); every byte read or written once, streamed
+template <int NR>
+__global__ void __launch_bounds__(256) stream_kernel(const typename RawOf<16>::type *src,
+                                                     typename RawOf<16>::type *dst, int64_t nchunk) {
+  using R = typename RawOf<16>::type;
+  const int64_t c = blockIdx.x;
+  if (c >= nchunk) return;
+  const R *s = src + c * 12 * NR * 256 + threadIdx.x;
+  R acc[12];
+#pragma unroll
+  for (int p = 0; p < 12; p++) acc[p] = __builtin_nontemporal_load(s + p * 256);
+#pragma unroll
+  for (int k = 12; k < 12 * NR; k++) acc[k % 12] ^= __builtin_nontemporal_load(s + k * 256);
+  R *d = dst + c * 12 * 256 + threadIdx.x;
+#pragma unroll
+  for (int p = 0; p < 12; p++) __builtin_nontemporal_store(acc[p], d + p * 256);
+}
+
 }  // namespace
+
+hipError_t launch_stream(const void *src, void *dst, size_t dst_bytes, int reads_per_write, hipStream_t st) {
+  using R = typename RawOf<16>::type;
+  const int64_t nchunk = (int64_t)(dst_bytes / (12 * 4096));
+  if (nchunk == 0) return hipSuccess;
+  if (nchunk > 0x7fffffff) return hipErrorInvalidValue;
+  const R *s = (const R *)src;
+  R *d = (R *)dst;
+  const unsigned grid = (unsigned)nchunk;
+  switch (reads_per_write) {
+    case 1: stream_kernel<1><<<grid, 256, 0, st>>>(s, d, nchunk); break;
+    case 2: stream_kernel<2><<<grid, 256, 0, st>>>(s, d, nchunk); break;
+    case 4: stream_kernel<4><<<grid, 256, 0, st>>>(s, d, nchunk); break;
+    case 7: stream_kernel<7><<<grid, 256, 0, st>>>(s, d, nchunk); break;
+    case 8: stream_kernel<8><<<grid, 256, 0, st>>>(s, d, nchunk); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
 hipError_t finish(const double *partial, int nblk, int nred, double *out, const double *div,
                   int div_stride, hipStream_t st) {

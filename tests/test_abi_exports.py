@@ -43,6 +43,7 @@ def test_header_parses():
     assert fns["qxd_debug_get_dirac_variant"] == 3
     assert fns["qxd_debug_set_step_graphs"] == 1
     assert fns["qxd_debug_step_graph_counts"] == 2
+    assert fns["qxd_debug_stream"] == 5
     assert fns["qxd_abi_version"] == 0
     assert fns["qxd_dirac_apply"] == 10
     assert fns["qxd_solve"] == 10

@@ -172,3 +172,28 @@ def test_cfg2_shape_sampled_sites(ctx):
     sites = np.concatenate([rng.choice(lat.V, 64, replace=False), [0, lat.V - 1]])
     expect = od.apply_at_sites(lat, ue, ae, x, sites, 0.1365, q=-1 / 3, csw=1.9, csw_u1=1.0)
     assert rel(yh[sites], expect) < 1e-12
+
+
+def test_stream_probe_exact(ctx):
+    """The streaming probe the benchmark times as its bandwidth ceiling reads
+    every input byte: dst = xor of the r planes, bit for bit, for sizes below
+    and above one pass of the grid."""
+    import torch
+    from paper_1710_08839_amd import qxd
+    for r in (1, 7):
+        for nchunk in (1, 3, 900):
+            nbytes = nchunk * 49152
+            n = nbytes // 4
+            a = torch.randint(-2**31, 2**31 - 1, (r * n,), dtype=torch.int32, device="cuda")
+            b = torch.zeros(n, dtype=torch.int32, device="cuda")
+            qxd.stream_probe(a, b, nbytes, r)
+            planes = a.view(nchunk, r, 12, 1024)  # [chunk][k][plane][4 KB]: input plane 12 k + p
+            want = planes[:, 0].clone()
+            for k in range(1, r):
+                want ^= planes[:, k]
+            torch.cuda.synchronize()
+            assert torch.equal(b, want.reshape(-1)), (r, nbytes)
+    with pytest.raises(qxd.QxdError):
+        qxd.stream_probe(a, b, 4096, 1)
+    with pytest.raises(qxd.QxdError):
+        qxd.stream_probe(a, b, 16, 3)
