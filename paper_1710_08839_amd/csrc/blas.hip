@@ -480,16 +480,19 @@ template <int P>
 __global__ void gs_axpy_kernel(const GsSlot<P> *slots, int64_t ng, double *partial) {
   constexpr int W = VW<P>;
   __shared__ double sh[12];
+  __shared__ double cfs[2 * MAXV];  // the coefficients ak, read once per work-group
   const GsSlot<P> s = slots[blockIdx.y];
   const int k = s.k, gx = gridDim.x;
   typename St<P>::pair_t *xk = s.chi0 + (int64_t)k * s.vstride;
+  for (int j = threadIdx.x; j < 2 * k; j += BT) cfs[j] = gld(s.ak, j);
+  __syncthreads();
   double nn = 0.0, wr = 0.0, wi = 0.0;
   for (int64_t t = (int64_t)blockIdx.x * BT + threadIdx.x; t < ng; t += (int64_t)gx * BT) {
     cx<double> z[W];
     gld_grp<P>(xk, t, z);
 #pragma unroll 4
     for (int l = 0; l < k; l++) {
-      const cx<double> cf{gld(s.ak, 2 * l), gld(s.ak, 2 * l + 1)};
+      const cx<double> cf{cfs[2 * l], cfs[2 * l + 1]};
       cx<double> y[W];
       gld_grp<P>(s.chi0 + (int64_t)l * s.vstride, t, y);
 #pragma unroll
