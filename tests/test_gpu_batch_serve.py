@@ -50,7 +50,7 @@ def _ops(case, quarks):
 QUARKS = [(0.13, 2 / 3, 1.9), (0.1300, -1 / 3, 1.9), (0.126, 2 / 3, 1.2)]
 
 
-@pytest.mark.parametrize("prec", [1, 2], ids=["f32", "f16s"])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3], ids=["f64", "f32", "f16s", "bf16"])
 def test_batched_solve_matches_alone(big, prec):
     import torch
     from paper_1710_08839_amd import qxd
