@@ -33,7 +33,10 @@ constexpr int QP_XOR2 = 0x4E;  // DPP quad_perm(2,3,0,1)
 
 template <int CTRL>
 __device__ __forceinline__ float qperm(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+  // bound_ctrl set: the source lane is always in the same quad, and the four
+  // lanes of a quad (one site pair) are active together, so no lane reads a
+  // disabled one; it lets the compiler fold the move into the add that uses it
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
 }
 template <int CTRL>
 __device__ __forceinline__ cx<float> qperm(cx<float> z) {
