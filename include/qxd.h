@@ -76,7 +76,9 @@ typedef enum {
                         sites of the output are set to 0 (Sec. 2.4)           */
   QXD_OP_HOP = 2,    /* hopping part of D only (D minus its diagonal)         */
   QXD_OP_PAULI = 3,  /* diagonal part P(x) = 4 + m0 + dD_sw only              */
-  QXD_OP_OOINV = 4   /* D_oo^-1 on odd sites, even sites set to 0             */
+  QXD_OP_OOINV = 4,  /* D_oo^-1 on odd sites, even sites set to 0             */
+  QXD_OP_G5D = 5     /* gamma5 D (Hermitian: D is gamma5-hermitian, Sec. 2.3;
+                        gamma5 = diag(1, 1, -1, -1) in the chiral basis)     */
 } qxd_op;
 
 #define QXD_NATIVE 1u  /* in/out are native-layout buffers of precision prec */

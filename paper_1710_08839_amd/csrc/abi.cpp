@@ -224,6 +224,10 @@ qxd_status apply_native(Field *fd, const Operator &op, qxd_op which, int prec, v
       QXD_HIP_CHECK(launch_dirac(prec, DK_ODD, g, f, full_in, full_in, full_out, 0.0, st));
       QXD_HIP_CHECK(launch_zero_sites(prec, full_out, 0, g.Vh, st));
       break;
+    case QXD_OP_G5D:
+      QXD_HIP_CHECK(launch_dirac(prec, DK_FULL, g, f, full_in, full_in, full_out, -0.5, st));
+      QXD_HIP_CHECK(launch_g5_sites(prec, full_out, 0, g.V, st));
+      break;
     default:
       set_error("unknown operator %d", (int)which);
       return QXD_EINVAL;
@@ -430,7 +434,7 @@ qxd_status qxd_dirac_apply(qxd_field *field, const qxd_quark *quarks, int nquark
                            qxd_prec prec, const void *in_dev, void *out_dev, int nrhs, unsigned flags,
                            void *stream) {
   if (!field || !quarks || !in_dev || !out_dev || nquark < 1 || nrhs < 1 || nrhs % nquark ||
-      !valid_prec(prec) || op < QXD_OP_D || op > QXD_OP_OOINV || (flags & ~QXD_NATIVE)) {
+      !valid_prec(prec) || op < QXD_OP_D || op > QXD_OP_G5D || (flags & ~QXD_NATIVE)) {
     set_error("invalid arguments to qxd_dirac_apply");
     return QXD_EINVAL;
   }

@@ -293,7 +293,36 @@ __global__ void zero_sites_kernel(Spinor<P> v, int64_t first, int64_t count) {
   store_spinor<P, typename St<P>::comp_t>(v, i, z);
 }
 
+// gamma5 of the chiral basis, diag(1, 1, -1, -1) in spin, in place: flips the
+// sign of the stored components 6..11 (spins 2 and 3); exact in every storage
+// format, and the FP16 site scale (a magnitude) is unchanged.  Thread t
+// handles component 6 + t / count of site first + t % count.
+template <int P>
+__global__ void g5_sites_kernel(Spinor<P> v, int64_t first, int64_t count) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 6 * count) return;
+  const int k = 6 + (int)(t / count);
+  const int64_t i = first + t % count;
+  const uint32_t j = (uint32_t)(i - v.off);
+  typename St<P>::pair_t *p = v.data + v.rd.base(j, 12, VW<P>) + v.rd.comp_off(k, VW<P>);
+  const auto z = St<P>::ld(p, 0);
+  St<P>::st(p, 0, {-z.re, -z.im});
+}
+
 }  // namespace
+
+hipError_t launch_g5_sites(int prec, SpinorArg v, int64_t first, int64_t count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  unsigned gr = grid_for(6 * count, 256);
+  switch (prec) {
+    case QXD_F64: g5_sites_kernel<QXD_F64><<<gr, 256, 0, st>>>(spinor_view<QXD_F64>(v.ptr, v.sites, v.off, v.rd), first, count); break;
+    case QXD_F32: g5_sites_kernel<QXD_F32><<<gr, 256, 0, st>>>(spinor_view<QXD_F32>(v.ptr, v.sites, v.off, v.rd), first, count); break;
+    case QXD_F16S: g5_sites_kernel<QXD_F16S><<<gr, 256, 0, st>>>(spinor_view<QXD_F16S>(v.ptr, v.sites, v.off, v.rd), first, count); break;
+    case QXD_BF16: g5_sites_kernel<QXD_BF16><<<gr, 256, 0, st>>>(spinor_view<QXD_BF16>(v.ptr, v.sites, v.off, v.rd), first, count); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_zero_sites(int prec, SpinorArg v, int64_t first, int64_t count, hipStream_t st) {
   unsigned gr = grid_for(count, 256);

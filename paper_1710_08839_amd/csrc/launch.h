@@ -43,6 +43,8 @@ hipError_t launch_unpack(int prec, const Geom &g, const void *native, double *ap
 struct SpinorArg;
 // Zero native sites [first, first + count) of a spinor.
 hipError_t launch_zero_sites(int prec, SpinorArg v, int64_t first, int64_t count, hipStream_t st);
+// v = gamma5 v on sites [first, first + count), in place
+hipError_t launch_g5_sites(int prec, SpinorArg v, int64_t first, int64_t count, hipStream_t st);
 
 // ---- Dirac operator (dirac.hip) -----------------------------------------
 struct OpFields {

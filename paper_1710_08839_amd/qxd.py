@@ -14,7 +14,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libqxd.so"
 
 F64, F32, F16S, BF16 = 0, 1, 2, 3
 PREC = {"f64": F64, "f32": F32, "f16": F16S, "f16s": F16S, "bf16": BF16}
-OP_D, OP_DHAT, OP_HOP, OP_PAULI, OP_OOINV = 0, 1, 2, 3, 4
+OP_D, OP_DHAT, OP_HOP, OP_PAULI, OP_OOINV, OP_G5D = 0, 1, 2, 3, 4, 5
 NATIVE = 1
 EO_GCR, SAP_GCR = 0, 1
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ENOCONV", -4: "EFLOAT", -5: "EDEVICE",

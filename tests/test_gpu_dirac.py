@@ -103,6 +103,37 @@ def test_every_kernel_variant(case, choice):
         qxd.set_dirac_variant(0)
 
 
+@pytest.mark.parametrize("prec", [0, 1, 2, 3], ids=["f64", "f32", "f16s", "bf16"])
+def test_g5d(case, prec):
+    """gamma5 D against the oracle's gamma5 applied to its D; in FP64 also
+    gamma5-hermiticity on the GPU: (eta, g5 D psi) = conj((psi, g5 D eta))."""
+    import torch
+    from paper_1710_08839_amd import qxd
+    x, e = case.source(21), case.source(22)
+    y = torch.empty_like(to_dev(x))
+    case.field.apply(case.quark, qxd.OP_G5D, prec, to_dev(x), y)
+    torch.cuda.synchronize()
+    ref = case.op.apply_g5(case.op.apply(x))
+    assert rel(to_host(y), ref) < TOL[prec]
+    if prec == 0:
+        ye = torch.empty_like(y)
+        case.field.apply(case.quark, qxd.OP_G5D, 0, to_dev(e), ye)
+        torch.cuda.synchronize()
+        a = np.vdot(e, to_host(y))
+        b = np.conj(np.vdot(x, to_host(ye)))
+        assert abs(a - b) <= 1e-13 * np.linalg.norm(e) * np.linalg.norm(to_host(y))
+
+
+def test_apply_rejects_unknown_operator(case):
+    import torch
+    from paper_1710_08839_amd import qxd
+    x = to_dev(case.source(23))
+    y = torch.empty_like(x)
+    for op in (-1, qxd.OP_G5D + 1):
+        with pytest.raises(qxd.QxdError):
+            case.field.apply(case.quark, op, 0, x, y)
+
+
 def test_pack_roundtrip_and_native(case):
     """API -> native -> API is exact in FP64; the native-layout apply equals
     the API-layout apply bit for bit."""
