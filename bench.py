@@ -461,7 +461,7 @@ def main():
         "config": {"workload": "Wilson-clover D (hop + Pauli), SU(3)xU(1), C* in x,y,z, "
                                "64x32^3 physical = 64x64x32x32 extended (4194304 sites), "
                                "q=-1/3, kappa=0.1365, csw=1.9, eps=0.25, A~N(0,0.15)",
-                   "global_batch": 1, "seq_len": V, "parallelism": "single GPU"},
+                   "extended_sites": V, "rhs_per_application": 1, "gpus": 1},
         "roofline": {"bound": "hbm", "achieved": round(value, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(value / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get((kernel_hash(), kernel)),
                      "kernel": kernel,
