@@ -101,12 +101,6 @@ size_t BatchSolver::slot_bytes(const Field *f, int prec, const qxd_solver &s) {
          scal_doubles(nkv) * 8;
 }
 
-// 16-byte groups of one inner-precision vector (flat layouts)
-int64_t BatchSolver::ngroups() const {
-  const int w = prec_ == QXD_F64 ? 1 : (prec_ == QXD_F32 ? 2 : 4);
-  return f_->g.V * 12 / w;
-}
-
 int BatchSolver::active() const {
   int n = 0;
   for (auto &s : slots_) n += s->active;
@@ -141,10 +135,8 @@ qxd_status BatchSolver::reserve(int n) {
   BCK(dslots_.ensure(nslot * sizeof(DSlot<QXD_F64>)));
   BCK(sslots_.ensure(nslot * sizeof(SapSlot<QXD_F64>)));
   BCK(act_.ensure(2 * nslot * sizeof(int)));
-  if (gs_batch_ok(prec_)) {
-    BCK(gsslots_.ensure(nslot * sizeof(GsSlot<QXD_F64>)));
-    BCK(gspart_.ensure(gs_batch_partial_doubles((int)nslot, ngroups()) * 8));
-  }
+  BCK(gsslots_.ensure(nslot * sizeof(GsSlot<QXD_F64>)));
+  BCK(gspart_.ensure(gs_batch_partial_doubles((int)nslot, prec_, g.V) * 8));
   // graphs name the tables by address: none survives a reallocation
   if (old[0] != dslots_.p || old[1] != sslots_.p || old[2] != act_.p || old[3] != gsslots_.p ||
       old[4] != gspart_.p)
@@ -176,27 +168,6 @@ struct BImpl {
     sl.r2 = b2;
     sl.k = 0;
     sl.inner_it = 0;
-    return QXD_OK;
-  }
-
-  // Gram-Schmidt of chi_k and the residual update, for one slot
-  static qxd_status gs(BatchSolver::Slot &sl, const Geom &g, double *partial, int nkv, hipStream_t st,
-                       double *norm_out) {
-    int k = sl.k;
-    std::vector<SpinorArg> chi(k + 1);
-    for (int l = 0; l <= k; l++) chi[l] = F(g, sl.chi(nkv, l));
-    double *ak = sl.amat() + 2 * k * nkv;
-    double *rec = sl.rec(nkv);
-    if (k > 0) BCK(blas_mdot<P>(chi.data(), k, chi[k], 0, g.V, partial, ak, rec, 3, st));
-    MaxpyHost m;
-    m.n = k;
-    m.src[0] = chi[k];
-    m.dst[0] = chi[k];
-    m.ys[0] = chi.data();
-    m.coef = ak;
-    m.w = F(g, sl.rho());
-    BCK(blas_maxpy<P>(m, 0, g.V, partial, rec + 3 * k, st));
-    BCK(blas_update<P>(F(g, sl.rho()), chi[k], rec + 3 * k + 1, rec + 3 * k, 0, 0, g.V, partial, norm_out, st));
     return QXD_OK;
   }
 
@@ -269,7 +240,7 @@ struct BImpl {
   // the batched part of a step: phi_k = M_SAP rho, chi_k = D phi_k
   static qxd_status batched(BatchSolver &bs, std::vector<BatchSolver::Slot *> &act, hipStream_t st,
                             DevBuf &sslots, DevBuf &dslots, DevBuf &actbuf, DevBuf &gsslots, DevBuf &gspart,
-                            int64_t ngroups, double *norms, void *stage, int ncy, int nmr, int nkv) {
+                            double *norms, void *stage, int ncy, int nmr, int nkv) {
     Field *f = bs.field();
     const Geom &g = f->g;
     int n = (int)act.size();
@@ -318,21 +289,18 @@ struct BImpl {
     BCK(hipMemcpyAsync(dslots.p, hd, n * sizeof(DSlot<P>), hipMemcpyHostToDevice, st));
     BCK(hipMemcpyAsync(actbuf.p, ha, 2 * n * sizeof(int), hipMemcpyHostToDevice, st));
     // Gram-Schmidt table (chi_k = D phi_k is orthogonalised in the same step)
-    constexpr bool gs_batched = gs_batch_ok(P);
-    if constexpr (gs_batched) {
-      GsSlot<P> *hg = (GsSlot<P> *)(((uintptr_t)(ha + 2 * n) + 15) & ~(uintptr_t)15);
-      for (int j = 0; j < n; j++) {
-        BatchSolver::Slot &sl = *act[j];
-        hg[j].chi0 = (typename St<P>::pair_t *)sl.chi(nkv, 0);
-        hg[j].vstride = (int64_t)(sl.fbP / sizeof(typename St<P>::pair_t));
-        hg[j].rho = (typename St<P>::pair_t *)sl.rho();
-        hg[j].ak = sl.amat() + 2 * sl.k * nkv;
-        hg[j].rec = sl.rec(nkv);
-        hg[j].norm = norms + j;
-        hg[j].k = sl.k;
-      }
-      BCK(hipMemcpyAsync(gsslots.p, hg, n * sizeof(GsSlot<P>), hipMemcpyHostToDevice, st));
+    GsSlot<P> *hg = (GsSlot<P> *)(((uintptr_t)(ha + 2 * n) + 15) & ~(uintptr_t)15);
+    for (int j = 0; j < n; j++) {
+      BatchSolver::Slot &sl = *act[j];
+      hg[j].chi0 = (typename St<P>::pair_t *)sl.chi(nkv, 0);
+      hg[j].vstride_bytes = (int64_t)sl.fbP;
+      hg[j].rho = (typename St<P>::pair_t *)sl.rho();
+      hg[j].ak = sl.amat() + 2 * sl.k * nkv;
+      hg[j].rec = sl.rec(nkv);
+      hg[j].norm = norms + j;
+      hg[j].k = sl.k;
     }
+    BCK(hipMemcpyAsync(gsslots.p, hg, n * sizeof(GsSlot<P>), hipMemcpyHostToDevice, st));
     const int *dsingle = actbuf.as<int>() + n, *dpair = dsingle + nsingle;
     const int *lists[2];
     int nper;
@@ -350,8 +318,7 @@ struct BImpl {
                                     cy == 0 && c == 0, nmr, st));
         }
       BCK(launch_dirac_batch<P>(g, dslots.as<DSlot<P>>(), actbuf.as<int>(), n, 2, st));
-      if constexpr (gs_batched)
-        BCK(blas_gs_batch<P>(gsslots.as<GsSlot<P>>(), n, ngroups, gspart.as<double>(), st));
+      BCK(blas_gs_batch<P>(gsslots.as<GsSlot<P>>(), n, g.V, g.rd, gspart.as<double>(), st));
       return QXD_OK;
     };
     const std::array<int64_t, 10> key{P, n, npair, (int64_t)ncy * 256 + nmr, (int64_t)(intptr_t)sslots.p,
@@ -541,22 +508,14 @@ qxd_status BatchSolver::step() {
   int n = (int)act.size();
   // batched: phi_k = M_SAP rho, chi_k = D phi_k
   switch (prec_) {
-    case QXD_F64: BCS(BImpl<QXD_F64>::batched(*this, act, st_, sslots_, dslots_, act_, gsslots_, gspart_, ngroups(), d_norms_.as<double>(), h_stage_, ncy_, nmr_, nkv_)); break;
-    case QXD_F32: BCS(BImpl<QXD_F32>::batched(*this, act, st_, sslots_, dslots_, act_, gsslots_, gspart_, ngroups(), d_norms_.as<double>(), h_stage_, ncy_, nmr_, nkv_)); break;
-    case QXD_F16S: BCS(BImpl<QXD_F16S>::batched(*this, act, st_, sslots_, dslots_, act_, gsslots_, gspart_, ngroups(), d_norms_.as<double>(), h_stage_, ncy_, nmr_, nkv_)); break;
-    default: BCS(BImpl<QXD_BF16>::batched(*this, act, st_, sslots_, dslots_, act_, gsslots_, gspart_, ngroups(), d_norms_.as<double>(), h_stage_, ncy_, nmr_, nkv_)); break;
+    case QXD_F64: BCS(BImpl<QXD_F64>::batched(*this, act, st_, sslots_, dslots_, act_, gsslots_, gspart_, d_norms_.as<double>(), h_stage_, ncy_, nmr_, nkv_)); break;
+    case QXD_F32: BCS(BImpl<QXD_F32>::batched(*this, act, st_, sslots_, dslots_, act_, gsslots_, gspart_, d_norms_.as<double>(), h_stage_, ncy_, nmr_, nkv_)); break;
+    case QXD_F16S: BCS(BImpl<QXD_F16S>::batched(*this, act, st_, sslots_, dslots_, act_, gsslots_, gspart_, d_norms_.as<double>(), h_stage_, ncy_, nmr_, nkv_)); break;
+    default: BCS(BImpl<QXD_BF16>::batched(*this, act, st_, sslots_, dslots_, act_, gsslots_, gspart_, d_norms_.as<double>(), h_stage_, ncy_, nmr_, nkv_)); break;
   }
-  // per right-hand side: Gram-Schmidt and residual update (done for the whole
-  // batch inside the step's launches where the layout is flat)
+  // the batched Gram-Schmidt of the step left |rho|^2 of right-hand side j in
+  // d_norms_[j]
   double *dn = d_norms_.as<double>();
-  for (int j = 0; j < n && !gs_batch_ok(prec_); j++) {
-    switch (prec_) {
-      case QXD_F64: BCS(BImpl<QXD_F64>::gs(*act[j], g, partial_.as<double>(), nkv_, st_, dn + j)); break;
-      case QXD_F32: BCS(BImpl<QXD_F32>::gs(*act[j], g, partial_.as<double>(), nkv_, st_, dn + j)); break;
-      case QXD_F16S: BCS(BImpl<QXD_F16S>::gs(*act[j], g, partial_.as<double>(), nkv_, st_, dn + j)); break;
-      default: BCS(BImpl<QXD_BF16>::gs(*act[j], g, partial_.as<double>(), nkv_, st_, dn + j)); break;
-    }
-  }
   BCK(hipMemcpyAsync(h_norms_, dn, n * sizeof(double), hipMemcpyDeviceToHost, st_));
   BCK(hipStreamSynchronize(st_));
   const int maxiter = s_.maxiter > 0 ? s_.maxiter : 100000;

@@ -77,10 +77,8 @@ class BatchSolver {
   std::vector<Finished> done_;
   // device/pinned staging of slot descriptors and the active list
   DevBuf dslots_, sslots_, act_, partial_;
-  // batched Gram-Schmidt: per-slot table and partial sums (all precisions but
-  // FP16 + scale, which orthogonalise one right-hand side at a time)
+  // batched Gram-Schmidt: per-slot table and partial sums
   DevBuf gsslots_, gspart_;
-  int64_t ngroups() const;
   void *h_stage_ = nullptr;
   size_t h_stage_bytes_ = 0;
   double *h_norms_ = nullptr;

@@ -64,8 +64,9 @@ hipError_t blas_norm2(SpinorArg x, int64_t first, int64_t count, double *partial
                       hipStream_t st);
 
 // Batched Gram-Schmidt step of the flexible GCR for many right-hand sides at
-// once (one launch per phase for the whole batch; every precision but FP16 +
-// scale, whose vectors are not flat).  For each slot, with k = slot.k:
+// once (one launch per phase for the whole batch; flat 16-byte streams, or
+// one site per thread for FP16 + scale vectors with their per-site scales).
+// For each slot, with k = slot.k:
 //   ak_l = (chi_l, chi_k) / |chi_l|^2            (l < k; |chi_l|^2 = rec[3l])
 //   chi_k -= sum_l ak_l chi_l                     (stored in place)
 //   rec[3k] = |chi_k|^2, rec[3k+1..2] = (chi_k, rho)
@@ -74,23 +75,22 @@ hipError_t blas_norm2(SpinorArg x, int64_t first, int64_t count, double *partial
 // not depend on the other slots of the batch.
 template <int P>
 struct GsSlot {
-  typename St<P>::pair_t *chi0;  // chi_0 (flat native vector); chi_l = chi0 + l * vstride
-  int64_t vstride;               // stored pairs from chi_l to chi_l+1
+  typename St<P>::pair_t *chi0;  // chi_0 (full-lattice native vector)
+  int64_t vstride_bytes;         // bytes from chi_l to chi_l+1
   typename St<P>::pair_t *rho;
   double *ak;                    // complex, l < k
   double *rec;                   // 3 per vector
   double *norm;                  // |rho|^2 out
   int k;
 };
-constexpr bool gs_batch_ok(int prec) { return prec != QXD_F16S; }
-// work-groups per slot of the batched kernels, and the partial-sum scratch
-// they need for n slots
-unsigned gs_batch_grid(int64_t ngroups);
-inline size_t gs_batch_partial_doubles(int n, int64_t ngroups) {
-  return (size_t)n * 2 * MAXV * gs_batch_grid(ngroups) + 8;
+// work-groups per slot of the batched kernels for vectors of nsites sites,
+// and the partial-sum scratch they need for n slots
+unsigned gs_batch_grid(int prec, int64_t nsites);
+inline size_t gs_batch_partial_doubles(int n, int prec, int64_t nsites) {
+  return (size_t)n * 2 * MAXV * gs_batch_grid(prec, nsites) + 8;
 }
-// ngroups = 16-byte groups per vector (12 V / pairs per group)
 template <int P>
-hipError_t blas_gs_batch(const GsSlot<P> *slots, int n, int64_t ngroups, double *partial, hipStream_t st);
+hipError_t blas_gs_batch(const GsSlot<P> *slots, int n, int64_t nsites, const RunDiv &rd, double *partial,
+                         hipStream_t st);
 
 }  // namespace qxd

@@ -425,6 +425,15 @@ __device__ __forceinline__ void gst_grp(typename St<P>::pair_t *base, int64_t gi
 
 constexpr int GS_CH = 8;  // vectors per sweep of the dot kernel
 
+template <int P>
+__device__ __forceinline__ typename St<P>::pair_t *vec_at(const GsSlot<P> &s, int l) {
+  return (typename St<P>::pair_t *)((char *)s.chi0 + (int64_t)l * s.vstride_bytes);
+}
+template <int P>
+__device__ __forceinline__ Spinor<P> vec_view(const GsSlot<P> &s, int l, int64_t nsites, const RunDiv &rd) {
+  return spinor_view<P>(vec_at(s, l), nsites, 0, rd);
+}
+
 // partial[(y * 2 MAXV + 2l (+1)) * gx + bx] = block sums of (chi_l, chi_k)
 template <int P>
 __global__ void gs_dot_kernel(const GsSlot<P> *slots, int64_t ng, double *partial) {
@@ -433,7 +442,7 @@ __global__ void gs_dot_kernel(const GsSlot<P> *slots, int64_t ng, double *partia
   const GsSlot<P> s = slots[blockIdx.y];
   const int k = s.k, gx = gridDim.x;
   double *pp = partial + (int64_t)blockIdx.y * 2 * MAXV * gx + blockIdx.x;
-  const typename St<P>::pair_t *xk = s.chi0 + (int64_t)k * s.vstride;
+  const typename St<P>::pair_t *xk = vec_at(s, k);
   for (int c0 = 0; c0 < k; c0 += GS_CH) {
     const int m = k - c0 < GS_CH ? k - c0 : GS_CH;
     double acc[2 * GS_CH];
@@ -446,7 +455,7 @@ __global__ void gs_dot_kernel(const GsSlot<P> *slots, int64_t ng, double *partia
       for (int l = 0; l < GS_CH; l++) {
         if (l < m) {
           cx<double> yv[W];
-          gld_grp<P>(s.chi0 + (int64_t)(c0 + l) * s.vstride, t, yv);
+          gld_grp<P>(vec_at(s, c0 + l), t, yv);
 #pragma unroll
           for (int w = 0; w < W; w++) {
             acc[2 * l] = fmat(yv[w].re, xv[w].re, acc[2 * l]);
@@ -483,7 +492,7 @@ __global__ void gs_axpy_kernel(const GsSlot<P> *slots, int64_t ng, double *parti
   __shared__ double cfs[2 * MAXV];  // the coefficients ak, read once per work-group
   const GsSlot<P> s = slots[blockIdx.y];
   const int k = s.k, gx = gridDim.x;
-  typename St<P>::pair_t *xk = s.chi0 + (int64_t)k * s.vstride;
+  typename St<P>::pair_t *xk = vec_at(s, k);
   for (int j = threadIdx.x; j < 2 * k; j += BT) cfs[j] = gld(s.ak, j);
   __syncthreads();
   double nn = 0.0, wr = 0.0, wi = 0.0;
@@ -494,7 +503,7 @@ __global__ void gs_axpy_kernel(const GsSlot<P> *slots, int64_t ng, double *parti
     for (int l = 0; l < k; l++) {
       const cx<double> cf{cfs[2 * l], cfs[2 * l + 1]};
       cx<double> y[W];
-      gld_grp<P>(s.chi0 + (int64_t)l * s.vstride, t, y);
+      gld_grp<P>(vec_at(s, l), t, y);
 #pragma unroll
       for (int w = 0; w < W; w++) z[w] = z[w] - cf * y[w];
     }
@@ -520,7 +529,7 @@ __global__ void gs_update_kernel(const GsSlot<P> *slots, int64_t ng, double *par
   __shared__ double sh[4];
   const GsSlot<P> s = slots[blockIdx.y];
   const int k = s.k, gx = gridDim.x;
-  const typename St<P>::pair_t *xk = s.chi0 + (int64_t)k * s.vstride;
+  const typename St<P>::pair_t *xk = vec_at(s, k);
   const double d = gld(s.rec, 3 * k);
   const cx<double> c{gld(s.rec, 3 * k + 1) / d, gld(s.rec, 3 * k + 2) / d};
   double nn = 0.0;
@@ -533,6 +542,128 @@ __global__ void gs_update_kernel(const GsSlot<P> *slots, int64_t ng, double *par
     gst_grp<P>(s.rho, t, r, rs);
 #pragma unroll
     for (int w = 0; w < W; w++) nn += norm2(rs[w]);
+  }
+  const double v1[1] = {nn};
+  block_sums<1>(v1, sh, partial + (int64_t)blockIdx.y * 2 * MAXV * gx + blockIdx.x, gx);
+}
+
+// One site per thread (vectors with per-site scales): the three phases of
+// gs_dot_kernel, gs_axpy_kernel and gs_update_kernel, with whole spinors
+// loaded and stored through the scaled format.
+template <int P>
+__global__ void gs_dot_site_kernel(const GsSlot<P> *slots, int64_t nsites, RunDiv rd, double *partial) {
+  __shared__ double sh[4 * 2 * GS_CH];
+  const GsSlot<P> s = slots[blockIdx.y];
+  const int k = s.k, gx = gridDim.x;
+  double *pp = partial + (int64_t)blockIdx.y * 2 * MAXV * gx + blockIdx.x;
+  const Spinor<P> xk = vec_view(s, k, nsites, rd);
+  for (int c0 = 0; c0 < k; c0 += GS_CH) {
+    const int m = k - c0 < GS_CH ? k - c0 : GS_CH;
+    double acc[2 * GS_CH];
+#pragma unroll
+    for (int j = 0; j < 2 * GS_CH; j++) acc[j] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < nsites; i += (int64_t)gx * BT) {
+      cx<double> x[4][3];
+      load_spinor<P, double>(xk, i, x);
+#pragma unroll
+      for (int l = 0; l < GS_CH; l++) {
+        if (l < m) {
+          cx<double> y[4][3];
+          load_spinor<P, double>(vec_view(s, c0 + l, nsites, rd), i, y);
+#pragma unroll
+          for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+              acc[2 * l] = fmat(y[a][c].re, x[a][c].re, acc[2 * l]);
+              acc[2 * l] = fmat(y[a][c].im, x[a][c].im, acc[2 * l]);
+              acc[2 * l + 1] = fmat(y[a][c].re, x[a][c].im, acc[2 * l + 1]);
+              acc[2 * l + 1] = fmat(-y[a][c].im, x[a][c].re, acc[2 * l + 1]);
+            }
+        }
+      }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < 2 * GS_CH; j++) {
+      double x = acc[j];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+      if (lane == 0) sh[4 * j + wv] = x;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < 2 * m) {
+      const int j = threadIdx.x;
+      pp[(int64_t)(2 * c0 + j) * gx] = (sh[4 * j] + sh[4 * j + 1]) + (sh[4 * j + 2] + sh[4 * j + 3]);
+    }
+    __syncthreads();
+  }
+}
+
+template <int P>
+__global__ void gs_axpy_site_kernel(const GsSlot<P> *slots, int64_t nsites, RunDiv rd, double *partial) {
+  __shared__ double sh[12];
+  __shared__ double cfs[2 * MAXV];
+  const GsSlot<P> s = slots[blockIdx.y];
+  const int k = s.k, gx = gridDim.x;
+  const Spinor<P> xk = vec_view(s, k, nsites, rd);
+  const Spinor<P> rho = spinor_view<P>(s.rho, nsites, 0, rd);
+  for (int j = threadIdx.x; j < 2 * k; j += BT) cfs[j] = gld(s.ak, j);
+  __syncthreads();
+  double nn = 0.0, wr = 0.0, wi = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < nsites; i += (int64_t)gx * BT) {
+    cx<double> z[4][3];
+    load_spinor<P, double>(xk, i, z);
+    for (int l = 0; l < k; l++) {
+      const cx<double> cf{cfs[2 * l], cfs[2 * l + 1]};
+      cx<double> y[4][3];
+      load_spinor<P, double>(vec_view(s, l, nsites, rd), i, y);
+#pragma unroll
+      for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) z[a][c] = z[a][c] - cf * y[a][c];
+    }
+    store_spinor<P, double>(xk, i, z);
+    cx<double> zs[4][3], rv[4][3];
+    load_spinor<P, double>(xk, i, zs);  // the stored value, as a later read sees it
+    load_spinor<P, double>(rho, i, rv);
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        nn += norm2(zs[a][c]);
+        const cx<double> q = cmulc(zs[a][c], rv[a][c]);
+        wr += q.re;
+        wi += q.im;
+      }
+  }
+  const double v3[3] = {nn, wr, wi};
+  block_sums<3>(v3, sh, partial + (int64_t)blockIdx.y * 2 * MAXV * gx + blockIdx.x, gx);
+}
+
+template <int P>
+__global__ void gs_update_site_kernel(const GsSlot<P> *slots, int64_t nsites, RunDiv rd, double *partial) {
+  __shared__ double sh[4];
+  const GsSlot<P> s = slots[blockIdx.y];
+  const int k = s.k, gx = gridDim.x;
+  const Spinor<P> xk = vec_view(s, k, nsites, rd);
+  const Spinor<P> rho = spinor_view<P>(s.rho, nsites, 0, rd);
+  const double d = gld(s.rec, 3 * k);
+  const cx<double> c{gld(s.rec, 3 * k + 1) / d, gld(s.rec, 3 * k + 2) / d};
+  double nn = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < nsites; i += (int64_t)gx * BT) {
+    cx<double> r[4][3], x[4][3];
+    load_spinor<P, double>(rho, i, r);
+    load_spinor<P, double>(xk, i, x);
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int b = 0; b < 3; b++) r[a][b] = r[a][b] - c * x[a][b];
+    store_spinor<P, double>(rho, i, r);
+    load_spinor<P, double>(rho, i, r);
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int b = 0; b < 3; b++) nn += norm2(r[a][b]);
   }
   const double v1[1] = {nn};
   block_sums<1>(v1, sh, partial + (int64_t)blockIdx.y * 2 * MAXV * gx + blockIdx.x, gx);
@@ -765,27 +896,43 @@ QXD_INST2(QXD_F16S, QXD_F16S)
 QXD_INST2(QXD_BF16, QXD_BF16)
 #undef QXD_INST2
 
-unsigned gs_batch_grid(int64_t ngroups) { return red_grid(ngroups); }
+// flat forms: one 16-byte group per thread; scaled vectors: one site per thread
+unsigned gs_batch_grid(int prec, int64_t nsites) {
+  if (prec == QXD_F16S) return red_grid(nsites);
+  const int w = prec == QXD_F64 ? 1 : (prec == QXD_F32 ? 2 : 4);
+  return red_grid(nsites * 12 / w);
+}
 
 template <int P>
-hipError_t blas_gs_batch(const GsSlot<P> *slots, int n, int64_t ngroups, double *partial, hipStream_t st) {
+hipError_t blas_gs_batch(const GsSlot<P> *slots, int n, int64_t nsites, const RunDiv &rd, double *partial,
+                         hipStream_t st) {
   if (n < 1) return hipSuccess;
+  const unsigned gx = gs_batch_grid(P, nsites);
+  const dim3 grid(gx, (unsigned)n);
   if constexpr (St<P>::scaled) {
-    return hipErrorInvalidValue;
-  } else {
-    const unsigned gx = red_grid(ngroups);
-    const dim3 grid(gx, (unsigned)n);
-    gs_dot_kernel<P><<<grid, BT, 0, st>>>(slots, ngroups, partial);
+    gs_dot_site_kernel<P><<<grid, BT, 0, st>>>(slots, nsites, rd, partial);
     gs_finish_kernel<P><<<(unsigned)n, BT, 0, st>>>(slots, (int)gx, partial, 0);
-    gs_axpy_kernel<P><<<grid, BT, 0, st>>>(slots, ngroups, partial);
+    gs_axpy_site_kernel<P><<<grid, BT, 0, st>>>(slots, nsites, rd, partial);
     gs_finish_kernel<P><<<(unsigned)n, BT, 0, st>>>(slots, (int)gx, partial, 1);
-    gs_update_kernel<P><<<grid, BT, 0, st>>>(slots, ngroups, partial);
+    gs_update_site_kernel<P><<<grid, BT, 0, st>>>(slots, nsites, rd, partial);
     gs_finish_kernel<P><<<(unsigned)n, BT, 0, st>>>(slots, (int)gx, partial, 2);
-    return hipGetLastError();
+  } else {
+    const int64_t ng = nsites * 12 / VW<P>;
+    gs_dot_kernel<P><<<grid, BT, 0, st>>>(slots, ng, partial);
+    gs_finish_kernel<P><<<(unsigned)n, BT, 0, st>>>(slots, (int)gx, partial, 0);
+    gs_axpy_kernel<P><<<grid, BT, 0, st>>>(slots, ng, partial);
+    gs_finish_kernel<P><<<(unsigned)n, BT, 0, st>>>(slots, (int)gx, partial, 1);
+    gs_update_kernel<P><<<grid, BT, 0, st>>>(slots, ng, partial);
+    gs_finish_kernel<P><<<(unsigned)n, BT, 0, st>>>(slots, (int)gx, partial, 2);
   }
+  return hipGetLastError();
 }
-template hipError_t blas_gs_batch<QXD_F64>(const GsSlot<QXD_F64> *, int, int64_t, double *, hipStream_t);
-template hipError_t blas_gs_batch<QXD_F32>(const GsSlot<QXD_F32> *, int, int64_t, double *, hipStream_t);
-template hipError_t blas_gs_batch<QXD_BF16>(const GsSlot<QXD_BF16> *, int, int64_t, double *, hipStream_t);
+#define QXD_INST(P)                                                                                       \
+  template hipError_t blas_gs_batch<P>(const GsSlot<P> *, int, int64_t, const RunDiv &, double *, hipStream_t);
+QXD_INST(QXD_F64)
+QXD_INST(QXD_F32)
+QXD_INST(QXD_F16S)
+QXD_INST(QXD_BF16)
+#undef QXD_INST
 
 }  // namespace qxd
