@@ -140,7 +140,10 @@ def solve_rates(ctx, nsrc, nsrc_fp64, dims=(48, 24, 24, 24)):
         return [synth.point_source(V, 0, s // 3 % 4, s % 3) for s in range(n)]
 
     out = {}
-    legs = [("mixed_sap_gcr_f32", qxd.solver(kind=qxd.SAP_GCR, tol=1e-10, nkv=24, ncy=4, nmr=4,
+    # Krylov lengths: the measured best for each inner precision on this
+    # batch (FP32 slots are twice the size of FP16 ones, so 48 of them do not
+    # all fit in HBM at once and the longer cycle pays off)
+    legs = [("mixed_sap_gcr_f32", qxd.solver(kind=qxd.SAP_GCR, tol=1e-10, nkv=32, ncy=4, nmr=4,
                                               inner_prec=qxd.F32), nsrc),
             ("mixed_sap_gcr_f16s", qxd.solver(kind=qxd.SAP_GCR, tol=1e-10, nkv=24, ncy=4, nmr=4,
                                                inner_prec=qxd.F16S), nsrc),
@@ -161,6 +164,7 @@ def solve_rates(ctx, nsrc, nsrc_fp64, dims=(48, 24, 24, 24)):
         dt = time.perf_counter() - t0
         log(f"solve {name}: {nrhs} rhs in {dt:.2f} s, status {st}")
         out[name] = {"solves_per_s": round(nrhs / dt, 4), "seconds": round(dt, 3), "nrhs": nrhs,
+                     "nkv_ncy_nmr": [s.nkv, s.ncy, s.nmr],
                      "status": st, "max_true_resid": max(i.true_resid for i in info),
                      "inner_iters_per_operator": [i.inner_iters for i in info][::ns],
                      "outer_iters_per_operator": [i.outer_iters for i in info][::ns]}
@@ -265,7 +269,7 @@ def stream_gbs(reads_per_write, dst_bytes=49152 * 21845, reps=10):
 SERVE_SIZES = [(8, 8, 8, 8), (32, 16, 16, 16), (48, 24, 24, 24), (64, 32, 32, 32)]
 
 
-def serve_stream(ctx, nreq, max_rhs, rate, inner_prec, seed=4242):
+def serve_stream(ctx, nreq, max_rhs, rate, inner_prec, seed=4242, nkv=32):
     """Poisson arrivals of solve requests on resident fields of the four
     lattice sizes (C*), random charge, kappa ~ U[0.130, 0.1365], Gaussian or
     point sources, 1..max_rhs right-hand sides; returns latency statistics."""
@@ -277,7 +281,7 @@ def serve_stream(ctx, nreq, max_rhs, rate, inner_prec, seed=4242):
         u, a = synth.gauge_field(d, 20171010 + i, 0.25, 0.15)
         fields.append(qxd.Field(ctx, d, u, a, cstar=3))
         del u, a
-    s = qxd.solver(kind=qxd.SAP_GCR, tol=1e-10, nkv=16, ncy=4, nmr=4, inner_prec=inner_prec)
+    s = qxd.solver(kind=qxd.SAP_GCR, tol=1e-10, nkv=nkv, ncy=4, nmr=4, inner_prec=inner_prec)
     reqs = []
     t = 0.0
     for j in range(nreq):

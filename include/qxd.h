@@ -212,8 +212,15 @@ typedef struct {
   double true_resid;       /* max over right-hand sides                       */
 } qxd_result;
 
-/* Start the serving scheduler of ctx with a device-memory budget (bytes) for
- * request workspaces; 0 means 80% of the free device memory. */
+/* Start the serving scheduler of ctx with a device-memory budget (bytes);
+ * 0 means 70% of the device memory free at this call.  Charged against it:
+ * per group of requests (same field, inner precision and solver parameters)
+ * the larger of the solver workspaces the group holds and those its admitted
+ * right-hand sides need, plus for every admitted request the operator
+ * (clover term, its inverse, hopping links) it may build.  Requests are
+ * admitted in arrival order while the charge fits; one request always runs
+ * when nothing else is charged.  max_active (0 = no limit) caps the
+ * right-hand sides in flight. */
 qxd_status qxd_serve_start(qxd_ctx *ctx, size_t budget_bytes, int max_active);
 
 /* Queue a request; *ticket identifies it.  Buffers must stay valid until

@@ -112,6 +112,14 @@ qxd_status Field::ensure_links(int prec, hipStream_t st) {
   return QXD_OK;
 }
 
+size_t Field::op_bytes(int prec) const {
+  // Pauli term (all sites), its odd-site inverse and the folded links, in FP64
+  // and (if different) in precision prec
+  size_t b = (size_t)36 * (2 * g.V + g.Vh) * 16;
+  if (prec != QXD_F64) b += (size_t)36 * (2 * g.V + g.Vh) * pair_bytes(prec);
+  return b;
+}
+
 qxd_status Field::get_op(const qxd_quark &q, int prec, Operator **out, hipStream_t st) {
   if (!(q.kappa > 0.0) || !isfinite(q.kappa) || !isfinite(q.csw) || !isfinite(q.csw_u1) || !isfinite(q.q)) {
     set_error("quark parameters must be finite with kappa > 0");
@@ -130,6 +138,17 @@ qxd_status Field::get_op(const qxd_quark &q, int prec, Operator **out, hipStream
   auto it = ops.find(key);
   Operator *op;
   if (it == ops.end()) {
+    // bounded cache: drop the least recently used operators no solver slot
+    // holds (freeing device memory synchronises the device, so no queued
+    // kernel still reads them)
+    while (ops.size() >= kMaxCachedOps) {
+      auto victim = ops.end();
+      for (auto jt = ops.begin(); jt != ops.end(); ++jt)
+        if (jt->second->users == 0 && (victim == ops.end() || jt->second->last_use < victim->second->last_use))
+          victim = jt;
+      if (victim == ops.end()) break;
+      ops.erase(victim);
+    }
     std::unique_ptr<Operator> nop(new Operator());
     nop->quark = q;
     nop->qhat = qhat;
@@ -170,6 +189,7 @@ qxd_status Field::get_op(const qxd_quark &q, int prec, Operator **out, hipStream
   }
   qxd_status s = ensure_links(prec, st);
   if (s != QXD_OK) return s;
+  op->last_use = ++op_clock;
   *out = op;
   return QXD_OK;
 }

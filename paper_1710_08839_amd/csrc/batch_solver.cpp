@@ -89,6 +89,10 @@ BatchSolver::BatchSolver(Field *f, int prec, const qxd_solver &s, hipStream_t st
 
 BatchSolver::~BatchSolver() {
   (void)hipStreamSynchronize(st_);
+  {
+    std::lock_guard<std::recursive_mutex> lk(f_->mu);
+    for (auto &s : slots_) release_ops(*s);
+  }
   drop_graphs();
   if (cap_st_) (void)hipStreamDestroy(cap_st_);
   if (h_stage_) (void)hipHostFree(h_stage_);
@@ -437,6 +441,23 @@ qxd_status BatchSolver::finish(Slot &sl, int status) {
     if (slots_[j].get() == &sl) fin.slot = (int)j;
   done_.push_back(fin);
   sl.active = false;
+  release_ops(sl);
+  return QXD_OK;
+}
+
+void BatchSolver::release_ops(Slot &sl) {
+  if (sl.op64) sl.op64->users--;
+  if (sl.opP && sl.opP != sl.op64) sl.opP->users--;
+  sl.op64 = sl.opP = nullptr;
+}
+
+qxd_status BatchSolver::release_slots() {
+  if (active() != 0) {
+    set_error("release_slots with right-hand sides in flight");
+    return QXD_EBUSY;
+  }
+  BCK(hipStreamSynchronize(st_));
+  slots_.clear();
   return QXD_OK;
 }
 
@@ -454,7 +475,13 @@ qxd_status BatchSolver::add(const qxd_quark &q, const double *eta_api, double *p
   }
   const Geom &g = f_->g;
   BCS(f_->get_op(q, QXD_F64, &sl->op64, st_));
-  BCS(f_->get_op(q, prec_, &sl->opP, st_));
+  sl->op64->users++;  // held until finish(): the operator cache keeps it
+  qxd_status so = f_->get_op(q, prec_, &sl->opP, st_);
+  if (so != QXD_OK) {
+    release_ops(*sl);
+    return so;
+  }
+  if (sl->opP != sl->op64) sl->opP->users++;
   sl->q = q;
   sl->tag = tag;
   sl->eta_api = eta_api;

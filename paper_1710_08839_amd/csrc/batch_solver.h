@@ -36,6 +36,8 @@ class BatchSolver {
   int capacity() const { return (int)slots_.size(); }
   int active() const;
   int free_slots() const { return capacity() - active(); }
+  // free every slot's memory (no right-hand side may be in flight)
+  qxd_status release_slots();
   // start solving D psi = eta for one right-hand side (API-layout FP64
   // device buffers); may finish at once (zero or converged guess)
   qxd_status add(const qxd_quark &q, const double *eta_api, double *psi_api, bool use_guess, void *tag);
@@ -64,6 +66,7 @@ class BatchSolver {
 
  private:
   qxd_status finish(Slot &sl, int status);
+  void release_ops(Slot &sl);
   qxd_status new_inner(Slot &sl);
   qxd_status cycle_end(Slot &sl);
   qxd_status outer_update(Slot &sl);

@@ -49,6 +49,8 @@ struct DevBuf {
 struct Operator {
   qxd_quark quark;
   int qhat = 0;
+  int users = 0;           // solver slots holding it (guarded by the field's mutex)
+  uint64_t last_use = 0;   // for least-recently-used eviction
   DevBuf pauli[4];   // indexed by qxd_prec
   DevBuf pinv[4];
   DevBuf wl[4];      // hopping links W = U z^qhat with the phase folded in
@@ -64,7 +66,14 @@ struct Field {
   DevBuf links[4];   // indexed by qxd_prec (links[F64] is the master copy)
   DevBuf angles[4];  // F64: double, others: float (same buffer for F32/F16S/BF16)
   bool links_ready[4] = {false, false, false, false};
+  // operators by (kappa, q, c_sw, c_sw^U(1)); at most kMaxCachedOps are kept
+  // once unused (a serve stream draws a new kappa per request, and at 64x32^3
+  // one operator holds several GB)
   std::map<std::tuple<double, double, double, double>, std::unique_ptr<Operator>> ops;
+  uint64_t op_clock = 0;
+  static constexpr size_t kMaxCachedOps = 4;
+  // device bytes one operator of this field holds in FP64 plus precision prec
+  size_t op_bytes(int prec) const;
   std::map<std::string, std::unique_ptr<DevBuf>> work;  // named workspaces
   std::recursive_mutex mu;
 

@@ -9,6 +9,13 @@
 // its right-hand sides by one inner iteration (BatchSolver::step) and hands
 // finished ones back; a finished right-hand side frees its slot at once.
 // Gauge fields stay resident: requests refer to fields uploaded beforehand.
+//
+// Memory charged against the budget: for every group, the larger of the
+// solver slots its worker holds (slots are pooled for reuse and released when
+// the group runs idle) and the slots its admitted right-hand sides need; plus,
+// for every admitted request, the operator (Pauli term, inverse, folded links)
+// it may build.
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -39,7 +46,7 @@ struct Req {
   int status = QXD_OK;
   int max_iters = 0;
   double max_res = 0;
-  size_t bytes = 0;
+  size_t op_bytes = 0;  // operator memory charged for this request
 };
 
 struct Rhs {  // one right-hand side handed to a worker
@@ -70,7 +77,7 @@ struct qxd_serve {
   std::map<uint64_t, std::unique_ptr<Req>> reqs;
   std::map<uint64_t, qxd_result> results;
   std::map<GroupKey, std::unique_ptr<Worker>> workers;
-  size_t used = 0;
+  size_t op_used = 0;  // operator memory charged for admitted requests
   int active_rhs = 0;
   std::thread sched;
   std::string error;
@@ -84,6 +91,10 @@ struct Worker {
   std::deque<Rhs> inbox;  // guarded by sv->mu
   std::thread th;
   bool quit = false;      // guarded by sv->mu
+  size_t slot_b = 0;      // bytes of one solver slot of this group
+  size_t held = 0;        // slot bytes the worker's solver holds (guarded by sv->mu)
+  int admitted = 0;       // admitted right-hand sides not yet finished (guarded by sv->mu)
+  size_t charge() const { return std::max(held, (size_t)admitted * slot_b); }
 
   void run() {
     (void)hipSetDevice(sv->ctx->device);
@@ -108,6 +119,10 @@ struct Worker {
         // already charged its memory to the budget)
         if (!take.empty() && bs->free_slots() < (int)take.size()) {
           qxd_status s = bs->reserve(bs->active() + (int)take.size());
+          {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            held = (size_t)bs->capacity() * slot_b;
+          }
           if (s != QXD_OK) {
             for (auto &x : take) {
               Finished e;
@@ -147,6 +162,7 @@ struct Worker {
           if (x.info.inner_iters > q->max_iters) q->max_iters = x.info.inner_iters;
           if (x.info.true_resid > q->max_res) q->max_res = x.info.true_resid;
           sv->active_rhs--;
+          admitted--;
           if (--q->remaining == 0) {
             qxd_result res;
             res.status = q->status;
@@ -156,9 +172,24 @@ struct Worker {
             res.inner_iters = q->max_iters;
             res.true_resid = q->max_res;
             sv->results[q->ticket] = res;
-            sv->used -= q->bytes;
+            sv->op_used -= q->op_bytes;
           }
         }
+        sv->cv.notify_all();
+      }
+      // a group that has run idle gives its pooled slots back to the device
+      bool idle;
+      {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        idle = inbox.empty() && bs->active() == 0 && bs->capacity() > 0;
+      }
+      if (idle) {
+        qxd_status s = bs->release_slots();
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (s == QXD_OK)
+          held = 0;
+        else
+          sv->error = qxd_last_error();
         sv->cv.notify_all();
       }
     }
@@ -173,17 +204,26 @@ static void scheduler(qxd_serve *sv) {
     while (!sv->queue.empty()) {
       Req *q = sv->queue.front();
       qxd_field *f = q->r.field;
-      size_t need = (size_t)q->r.nrhs * BatchSolver::slot_bytes(f, q->r.solver.inner_prec, q->r.solver);
-      bool fits = sv->used + need <= sv->budget || sv->used == 0;
+      const size_t slot_b = BatchSolver::slot_bytes(f, q->r.solver.inner_prec, q->r.solver);
+      const size_t op_b = f->op_bytes(q->r.solver.inner_prec);
+      GroupKey gk = key_of(q->r);
+      auto wit = sv->workers.find(gk);
+      Worker *w0 = wit == sv->workers.end() ? nullptr : wit->second.get();
+      size_t used = sv->op_used;
+      for (auto &kv : sv->workers) used += kv.second->charge();
+      const size_t before = w0 ? w0->charge() : 0;
+      const size_t after = w0 ? std::max(w0->held, (size_t)(w0->admitted + q->r.nrhs) * slot_b)
+                              : (size_t)q->r.nrhs * slot_b;
+      bool fits = used - before + after + op_b <= sv->budget || used == 0;
       bool room = sv->max_active <= 0 || sv->active_rhs + q->r.nrhs <= sv->max_active || sv->active_rhs == 0;
       if (!fits || !room) break;
       sv->queue.pop_front();
-      GroupKey key = key_of(q->r);
-      auto &w = sv->workers[key];
+      auto &w = sv->workers[gk];
       if (!w) {
         w.reset(new Worker());
         w->sv = sv;
         w->proto = q->r;
+        w->slot_b = slot_b;
         lk.unlock();
         hipStream_t st = nullptr;
         hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
@@ -198,8 +238,9 @@ static void scheduler(qxd_serve *sv) {
       }
       q->t_admit = now_s();
       q->remaining = q->r.nrhs;
-      q->bytes = need;
-      sv->used += need;
+      q->op_bytes = op_b;
+      sv->op_used += op_b;
+      w->admitted += q->r.nrhs;
       sv->active_rhs += q->r.nrhs;
       for (int i = 0; i < q->r.nrhs; i++) w->inbox.push_back(Rhs{q, i});
       sv->cv.notify_all();
@@ -243,7 +284,9 @@ qxd_status qxd_serve_start(qxd_ctx *ctx, size_t budget_bytes, int max_active) {
   if (budget_bytes == 0) {
     size_t fr = 0, tot = 0;
     QXD_HIP_CHECK(hipMemGetInfo(&fr, &tot));
-    budget_bytes = (size_t)(0.8 * fr);
+    // the rest stays free for the runtime, the fields' operator caches (a few
+    // unused operators per field are kept) and other users of the device
+    budget_bytes = (size_t)(0.7 * fr);
   }
   qxd_serve *sv = new qxd_serve();
   sv->ctx = ctx;
