@@ -322,11 +322,16 @@ qxd_status solve(Field *f, const qxd_quark *quarks, int nquark, const qxd_solver
       return QXD_EINVAL;
     }
     // every right-hand side gets a slot of the batch while device memory
-    // allows; the others join as slots free up (continuous batching)
+    // allows; the others join as slots free up (continuous batching).  The
+    // operators of the call's quarks are built as their right-hand sides
+    // join, so their memory is set aside first.
     size_t freeb = 0, totalb = 0;
     CK(hipMemGetInfo(&freeb, &totalb));
     size_t per_slot = BatchSolver::slot_bytes(f, s.inner_prec, s);
-    int cap = (int)std::min<size_t>((size_t)nrhs, std::max<size_t>(1, (size_t)(0.8 * freeb) / per_slot));
+    size_t avail = (size_t)(0.8 * freeb);
+    const size_t ops_b = (size_t)nquark * f->op_bytes(s.inner_prec);
+    avail = avail > ops_b ? avail - ops_b : 0;
+    int cap = (int)std::min<size_t>((size_t)nrhs, std::max<size_t>(1, avail / per_slot));
     BatchSolver bs(f, s.inner_prec, s, st);
     CS(bs.reserve(cap));
     int next = 0, finished = 0;
