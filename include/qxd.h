@@ -106,9 +106,10 @@ typedef struct {
   int kind;           /* qxd_solver_kind                                       */
   double tol;         /* target |eta - D psi| / |eta| in FP64 (e.g. 1e-10)     */
   int maxiter;        /* EO_GCR: GCR iterations; SAP_GCR: inner iterations     */
-  int nkv;            /* Krylov vectors per restart cycle                      */
-  int ncy;            /* SAP cycles per preconditioner application             */
-  int nmr;            /* MR steps per SAP block solve                          */
+  int nkv;            /* Krylov vectors per restart cycle (0: 32 for SAP_GCR,
+                         16 for EO_GCR)                                        */
+  int ncy;            /* SAP cycles per preconditioner application (0: 4)      */
+  int nmr;            /* MR steps per SAP block solve (0: 4)                   */
   int inner_prec;     /* qxd_prec of the SAP-GCR inner solver                  */
   double inner_tol;   /* relative residual reduction per inner solve           */
   int max_outer;      /* outer defect-correction steps (SAP_GCR)              */

@@ -80,10 +80,10 @@ static size_t scal_doubles(int nkv) { return (size_t)2 * nkv * nkv + 3 * nkv + 2
 
 BatchSolver::BatchSolver(Field *f, int prec, const qxd_solver &s, hipStream_t st)
     : f_(f), prec_(prec), s_(s), st_(st) {
-  nkv_ = s.nkv > 0 ? s.nkv : 8;
+  nkv_ = s.nkv > 0 ? s.nkv : kDefaultNkv;
   if (nkv_ > MAXV) nkv_ = MAXV;
-  ncy_ = s.ncy > 0 ? s.ncy : 5;
-  nmr_ = s.nmr > 0 ? s.nmr : 4;
+  ncy_ = s.ncy > 0 ? s.ncy : kDefaultNcy;
+  nmr_ = s.nmr > 0 ? s.nmr : kDefaultNmr;
   inner_tol_ = s.inner_tol > 0 ? s.inner_tol : (prec == QXD_F64 ? 1e-6 : (prec == QXD_F32 ? 1e-5 : 1e-2));
 }
 
@@ -100,7 +100,8 @@ BatchSolver::~BatchSolver() {
 }
 
 size_t BatchSolver::slot_bytes(const Field *f, int prec, const qxd_solver &s) {
-  int nkv = s.nkv > 0 ? s.nkv : 8;
+  int nkv = s.nkv > 0 ? s.nkv : kDefaultNkv;
+  if (nkv > MAXV) nkv = MAXV;
   return 4 * spinor_bytes(QXD_F64, f->g.V) + (size_t)(5 + 2 * nkv) * spinor_bytes(prec, f->g.V) +
          scal_doubles(nkv) * 8;
 }

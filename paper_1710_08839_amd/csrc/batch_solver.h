@@ -96,6 +96,10 @@ class BatchSolver {
   void drop_graphs();
 };
 
+// SAP-GCR parameters taken when the caller passes 0: the measured best of
+// sweeps on the hardest synthetic operators (48x24^3 C*, q = -1/3)
+constexpr int kDefaultNkv = 32, kDefaultNcy = 4, kDefaultNmr = 4;
+
 // Process-wide switch for graph capture of the batched steps (testing hook).
 void set_step_graphs(bool on);
 // process-wide totals: step graphs captured, and step graphs launched

@@ -157,7 +157,7 @@ def quark(kappa, q=0.0, csw=0.0, csw_u1=1.0):
     return Quark(kappa, q, csw, csw_u1)
 
 
-def solver(kind=SAP_GCR, tol=1e-10, maxiter=0, nkv=16, ncy=5, nmr=4, inner_prec=F32, inner_tol=0.0,
+def solver(kind=SAP_GCR, tol=1e-10, maxiter=0, nkv=0, ncy=0, nmr=0, inner_prec=F32, inner_tol=0.0,
            max_outer=0):
     return Solver(kind, tol, maxiter, nkv, ncy, nmr, inner_prec, inner_tol, max_outer)
 
