@@ -32,14 +32,25 @@ HBM_PEAK_GBS = 8000.0
 # reals), Pauli term (2 x 36 reals); FP16S adds one fp32 scale per spinor site.
 BYTES_PER_SITE = {0: 48 * 8 + 72 * 8 + 72 * 8, 1: 48 * 4 + 72 * 4 + 72 * 4,
                   2: 48 * 2 + 8 + 72 * 2 + 72 * 2, 3: 48 * 2 + 72 * 2 + 72 * 2}
+# link bytes per extended site (4 x 18 reals): with the mirror-fused link
+# reads on a C* lattice (variant bit 64) the mirror half's links are read at
+# their physical partners, so one application needs half of them
+LINK_BYTES = {0: 72 * 8, 1: 72 * 4, 2: 72 * 2, 3: 72 * 2}
 FLOPS_PER_SITE = 1320 + 552 + 48   # hops + two 6x6 Hermitian blocks + combine
+
+
+def site_bytes(prec, choice):
+    """Algorithmic bytes per extended site for the kernel variant `choice`."""
+    mirror = (choice & 16) and (choice & 64)
+    return BYTES_PER_SITE[prec] - (LINK_BYTES[prec] // 2 if mirror else 0)
+
 
 # HBM bytes per FP64 launch from the calibrated FETCH_SIZE + WRITE_SIZE
 # counters (profiles/dirac_64x32c_hbm_counters.md), valid only for the kernel
 # sources they were taken on (hash of the files below) and for the variant
-# the autotuner picked there.
+# the autotuner picked there (hop group + 16 LDS + 32 non-temporal + 64 mirror).
 KERNEL_FILES = ["dirac.hip", "dirac_site.h", "qxd_impl.h"]
-TRAFFIC = {("248a3a0e70a6dbfd", "dirac_lds_kernel<0, 0, 1, true>"): 9.870e9}
+TRAFFIC = {("8c2a1154d768aed4", 113): 8.138e9}
 
 
 def kernel_hash():
@@ -59,7 +70,8 @@ def kernel_name(choice, prec):
         return "dirac_kernel (not tuned)"
     g, lds, nt = choice & 15, bool(choice & 16), bool(choice & 32)
     if lds:
-        return f"dirac_lds_kernel<{prec}, 0, {g}, {'true' if nt else 'false'}>"
+        return (f"dirac_lds_kernel<{prec}, 0, {g}, {'true' if nt else 'false'}>"
+                + (" (mirror-fused links)" if choice & 64 else ""))
     return f"dirac_kernel<{prec}, 0, {g}>"
 _T0 = time.perf_counter()
 
@@ -407,23 +419,27 @@ def main():
         ms = time_applies(field, q, p, 3, 2, 1)
         ms = time_applies(field, q, p, 3, args.steps if p == 0 else max(10, args.steps // 2),
                           args.warmup)
-        gbs = BYTES_PER_SITE[p] * V / (ms * 1e-3) / 1e9
+        choice = args.dirac_variant or field.dirac_variant(p)
+        gbs = site_bytes(p, choice) * V / (ms * 1e-3) / 1e9
         log(f"D {PREC_NAME[p]}: {ms:.4f} ms per application")
         dw[PREC_NAME[p]] = {"ms": round(ms, 4), "GB/s": round(gbs, 1),
-                            "kernel": kernel_name(args.dirac_variant or field.dirac_variant(p), p),
+                            "kernel": kernel_name(choice, p),
                             "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
                             "GFLOP/s": round(FLOPS_PER_SITE * V / (ms * 1e-3) / 1e9, 1),
-                            "bytes_per_site": BYTES_PER_SITE[p]}
+                            "bytes_per_site": site_bytes(p, choice)}
 
     # the timed leg of the contract: K FP64 applications between barriers
     torch.cuda.synchronize()
     ms = time_applies(field, q, 0, 3, args.steps, args.warmup)
-    value = BYTES_PER_SITE[0] * V / (ms * 1e-3) / 1e9
-    kernel = kernel_name(args.dirac_variant or field.dirac_variant(0), 0)
-    stream_ceiling = {"read7_write1_GB/s": stream_gbs(7), "copy_GB/s": stream_gbs(1),
+    choice = args.dirac_variant or field.dirac_variant(0)
+    value = site_bytes(0, choice) * V / (ms * 1e-3) / 1e9
+    kernel = kernel_name(choice, 0)
+    stream_ceiling = {"read7_write1_GB/s": stream_gbs(7), "read5_write1_GB/s": stream_gbs(5),
+                      "read6_write1_GB/s": stream_gbs(6), "copy_GB/s": stream_gbs(1),
                       "what": "library streaming probe: per thread 12 r 16-byte non-temporal loads folded "
                               "into 12 stores, 4 KB planes as in the block-major fields, 1 GiB written; "
-                              "r = 7 is the FP64 D kernel's read/write mix"}
+                              "the FP64 D kernel reads 7 bytes per byte written, 5.5 with the mirror-fused "
+                              "link reads"}
     log(f"streaming ceiling: {stream_ceiling}")
 
     single = None
@@ -467,9 +483,9 @@ def main():
                                "q=-1/3, kappa=0.1365, csw=1.9, eps=0.25, A~N(0,0.15)",
                    "extended_sites": V, "rhs_per_application": 1, "gpus": 1},
         "roofline": {"bound": "hbm", "achieved": round(value, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(value / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get((kernel_hash(), kernel)),
+                     "frac": round(value / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get((kernel_hash(), choice)),
                      "kernel": kernel,
-                     "bytes_per_launch": BYTES_PER_SITE[0] * V},
+                     "bytes_per_launch": site_bytes(0, choice) * V},
         "dw": dw,
         "stream_ceiling": stream_ceiling,
         "single_rhs": single,

@@ -5,7 +5,8 @@
  * additions: the number of hops whose loads are issued together (1, 2, 4 or
  * 8), whether the input spinors of a lattice block are first staged in
  * LDS, and whether the Pauli term and the output are streamed with
- * non-temporal loads and stores.  An autotuner picks the fastest variant per (precision, kernel,
+ * non-temporal loads and stores, and whether the links of the C* mirror half
+ * are read at their physical partners.  An autotuner picks the fastest variant per (precision, kernel,
  * lattice volume) on first use.  Tests force each variant in turn to check
  * all of them against the reference.
  */
@@ -21,7 +22,9 @@ extern "C" {
 /* Force the Dirac kernel variant of every later application in this process:
  * choice = group (1, 2, 4 or 8), plus 16 for the LDS-staged variant (ignored
  * where a block does not fit one work-group), plus 32 for non-temporal Pauli
- * and output streams (with the LDS-staged variant only); 0 returns to the
+ * and output streams, plus 64 for mirror-fused link reads on C* lattices
+ * (links of the mirror half read at the physical partner and conjugated,
+ * Sec. 2.1; both with the LDS-staged variant only); 0 returns to the
  * autotuner.
  * Process-wide; not synchronised with applications in flight on other
  * threads.  QXD_EINVAL for any other value. */
@@ -41,11 +44,11 @@ qxd_status qxd_debug_step_graph_counts(int64_t *captures, int64_t *replays);
 /* Streaming probe on the current device, the practical bandwidth ceiling the
  * benchmark reports next to the kernels, shaped like the spinor traffic of
  * the block-major fields.  dst is cut into chunks of 12 planes of 4 KB, src
- * into chunks of 12 r planes (r = reads_per_write: 1, 2, 4, 7 or 8); plane p
+ * into chunks of 12 r planes (r = reads_per_write: 1, 2 or 4 to 8); plane p
  * of dst chunk c is the bytewise xor of planes p, p + 12, ..., p + 12 (r - 1)
  * of src chunk c, with non-temporal loads and stores, so r bytes are read
  * per byte written (the FP64 Dirac operator reads about 7 per byte it
- * writes).  src holds r * dst_bytes bytes; both buffers are device memory,
+ * writes, 5.5 with the mirror-fused link reads).  src holds r * dst_bytes bytes; both buffers are device memory,
  * 16-byte aligned and disjoint; dst_bytes a multiple of 49152 (QXD_EINVAL
  * otherwise).  Asynchronous on `stream` (a hipStream_t, NULL =
  * default stream). */

@@ -292,9 +292,9 @@ qxd_status qxd_debug_stream(const void *src_dev, void *dst_dev, size_t dst_bytes
                             void *stream) {
   const int r = reads_per_write;
   if (!src_dev || !dst_dev || (((uintptr_t)src_dev | (uintptr_t)dst_dev) & 15) || dst_bytes % 49152 ||
-      !(r == 1 || r == 2 || r == 4 || r == 7 || r == 8)) {
+      !(r == 1 || r == 2 || (r >= 4 && r <= 8))) {
     set_error("stream probe needs non-NULL 16-byte-aligned buffers, a multiple of 49152 bytes and "
-              "reads_per_write in {1, 2, 4, 7, 8}");
+              "reads_per_write in {1, 2, 4, 5, 6, 7, 8}");
     return QXD_EINVAL;
   }
   QXD_HIP_CHECK(launch_stream(src_dev, dst_dev, dst_bytes, r, (hipStream_t)stream));

@@ -746,6 +746,8 @@ hipError_t launch_stream(const void *src, void *dst, size_t dst_bytes, int reads
     case 1: stream_kernel<1><<<grid, 256, 0, st>>>(s, d, nchunk); break;
     case 2: stream_kernel<2><<<grid, 256, 0, st>>>(s, d, nchunk); break;
     case 4: stream_kernel<4><<<grid, 256, 0, st>>>(s, d, nchunk); break;
+    case 5: stream_kernel<5><<<grid, 256, 0, st>>>(s, d, nchunk); break;
+    case 6: stream_kernel<6><<<grid, 256, 0, st>>>(s, d, nchunk); break;
     case 7: stream_kernel<7><<<grid, 256, 0, st>>>(s, d, nchunk); break;
     case 8: stream_kernel<8><<<grid, 256, 0, st>>>(s, d, nchunk); break;
     default: return hipErrorInvalidValue;

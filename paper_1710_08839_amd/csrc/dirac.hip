@@ -19,6 +19,7 @@ namespace {
 
 constexpr int LDS_VARIANT = 16;
 constexpr int NT_VARIANT = 32;
+constexpr int MIRROR_VARIANT = 64;
 
 template <int P, int KIND, int GROUP>
 __global__ void __launch_bounds__(256) dirac_kernel(Geom g, const typename St<P>::pair_t *links,
@@ -98,13 +99,22 @@ __global__ void __launch_bounds__(256) dirac_kernel(Geom g, const typename St<P>
 // Pauli term are read as in dirac_kernel.  Requires whole blocks per
 // work-group and hopping links with the U(1) phase folded in (qhat = 0);
 // LDS: 12 complex per staged site.
+//
+// Mirror-fused link reads (mb > 0, C* lattices only): the orbifold makes the
+// link of a mirror site x + L1 e1 the complex conjugate of the link of x
+// (Sec. 2.1), also with the U(1) phase folded in (the mirror angle is -A).
+// Consecutive logical blocks are then a block of the physical half and its
+// mirror (mb = L1 / b1 blocks further in direction 1), and every link of a
+// mirror site is read at its physical partner and conjugated: the two reads
+// of a link line come from neighbouring work-groups of one XCD, so the second
+// is served by its L2, and the mirror half of the link array is never read.
 template <int P, int KIND, int GROUP, bool NT>
 __global__ void __launch_bounds__(256) dirac_lds_kernel(Geom g, const typename St<P>::pair_t *links,
                                                         const typename St<P>::real_t *angles, int qhat,
                                                         const typename St<P>::pair_t *pauli,
                                                         const typename St<P>::pair_t *pinv,
                                                         Spinor<P> in, Spinor<P> self, Spinor<P> out,
-                                                        typename St<P>::comp_t c) {
+                                                        typename St<P>::comp_t c, int mb) {
   using T = typename St<P>::comp_t;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T> *lds = (cx<T> *)smem_raw;
@@ -115,8 +125,15 @@ __global__ void __launch_bounds__(256) dirac_lds_kernel(Geom g, const typename S
   const int wg = xcd_order(blockIdx.x, gridDim.x);
   const int lb = threadIdx.x / per_block;
   const int r = threadIdx.x - lb * per_block;
-  const int blk = wg * bpw + lb;
-  const bool valid = blk < g.nblocks;
+  const int lblk = wg * bpw + lb;
+  const bool valid = lblk < g.nblocks;
+  const int n23 = g.nb[2] * g.nb[3];
+  int blk = lblk;
+  if (mb) {
+    // logical pair m = (B0, B1 < mb, B2, B3) lexicographic: the block, then its mirror
+    const int m = lblk >> 1, q = m / n23;
+    blk = ((q / mb) * g.nb[1] + q % mb + (lblk & 1) * mb) * n23 + (m - q * n23);
+  }
   const int par = half ? (KIND == DK_ODD ? 1 : 0) : (r >= g.Vbh);
   const int h = r >= g.Vbh ? r - g.Vbh : r;
   const int i = par * g.Vh + blk * g.Vbh + h;
@@ -177,7 +194,17 @@ __global__ void __launch_bounds__(256) dirac_lds_kernel(Geom g, const typename S
         } else {
           load_spinor<P, T>(in, j, psi);
         }
-        load_link<P, T>(links, g, mu, dir > 0 ? (int64_t)i : (int64_t)j, w);
+        int64_t li = dir > 0 ? (int64_t)i : (int64_t)j;
+        bool cj = false;
+        if (mb && (dir > 0 ? s.B(1) : t.B(1)) >= mb) {
+          li -= (int64_t)mb * n23 * g.Vbh;  // the physical partner, same parity and block position
+          cj = true;
+        }
+        load_link<P, T>(links, g, mu, li, w);
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+          for (int b = 0; b < 3; b++) w[a][b].im = cj ? -w[a][b].im : w[a][b].im;
         if (dir > 0)
           hop_fwd<T>(mu, w, psi, c * (T)sg, res);
         else
@@ -208,11 +235,11 @@ template <int P, int KIND, int G>
 void launch_k(unsigned gr, int threads, size_t lds, bool nt, hipStream_t st, const Geom &g,
               const typename St<P>::pair_t *links, const typename St<P>::real_t *angles, int qhat,
               const typename St<P>::pair_t *pauli, const typename St<P>::pair_t *pinv, Spinor<P> vin,
-              Spinor<P> vself, Spinor<P> vout, typename St<P>::comp_t c) {
+              Spinor<P> vself, Spinor<P> vout, typename St<P>::comp_t c, int mb) {
   if (lds && nt)
-    dirac_lds_kernel<P, KIND, G, true><<<gr, threads, lds, st>>>(g, links, angles, qhat, pauli, pinv, vin, vself, vout, c);
+    dirac_lds_kernel<P, KIND, G, true><<<gr, threads, lds, st>>>(g, links, angles, qhat, pauli, pinv, vin, vself, vout, c, mb);
   else if (lds)
-    dirac_lds_kernel<P, KIND, G, false><<<gr, threads, lds, st>>>(g, links, angles, qhat, pauli, pinv, vin, vself, vout, c);
+    dirac_lds_kernel<P, KIND, G, false><<<gr, threads, lds, st>>>(g, links, angles, qhat, pauli, pinv, vin, vself, vout, c, mb);
   else
     dirac_kernel<P, KIND, G><<<gr, threads, 0, st>>>(g, links, angles, qhat, pauli, pinv, vin, vself, vout, c);
 }
@@ -221,12 +248,12 @@ template <int P, int KIND>
 void launch_g(int group, unsigned gr, int threads, size_t lds, bool nt, hipStream_t st, const Geom &g,
               const typename St<P>::pair_t *links, const typename St<P>::real_t *angles, int qhat,
               const typename St<P>::pair_t *pauli, const typename St<P>::pair_t *pinv, Spinor<P> vin,
-              Spinor<P> vself, Spinor<P> vout, typename St<P>::comp_t c) {
+              Spinor<P> vself, Spinor<P> vout, typename St<P>::comp_t c, int mb) {
   switch (group) {
-    case 1: launch_k<P, KIND, 1>(gr, threads, lds, nt, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
-    case 4: launch_k<P, KIND, 4>(gr, threads, lds, nt, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
-    case 8: launch_k<P, KIND, 8>(gr, threads, lds, nt, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
-    default: launch_k<P, KIND, 2>(gr, threads, lds, nt, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c); break;
+    case 1: launch_k<P, KIND, 1>(gr, threads, lds, nt, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c, mb); break;
+    case 4: launch_k<P, KIND, 4>(gr, threads, lds, nt, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c, mb); break;
+    case 8: launch_k<P, KIND, 8>(gr, threads, lds, nt, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c, mb); break;
+    default: launch_k<P, KIND, 2>(gr, threads, lds, nt, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c, mb); break;
   }
 }
 
@@ -264,15 +291,17 @@ hipError_t launch_p(DiracKind kind, int choice, const Geom &g, const OpFields &f
   // blocks per work-group only)
   const bool use_lds = (choice & LDS_VARIANT) && per_block <= 256 && kind != DK_PAULI && f.qhat == 0;
   const bool nt = use_lds && (choice & NT_VARIANT);
+  // mirror-fused link reads: C* lattices (extended direction 1 twice L1), pairs of whole blocks
+  const int mb = use_lds && (choice & MIRROR_VARIANT) && g.N[1] == 2 * g.L1 ? g.L1b : 0;
   const int group = choice & (LDS_VARIANT - 1);
   const size_t lds = use_lds ? 12 * (size_t)threads * sizeof(cx<T>) : 0;
   switch (kind) {
-    case DK_FULL: launch_g<P, DK_FULL>(group, gr, threads, lds, nt, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
-    case DK_HOP: launch_g<P, DK_HOP>(group, gr, threads, lds, nt, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
-    case DK_PAULI: launch_g<P, DK_PAULI>(1, gr, threads, 0, false, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
-    case DK_ODD: launch_g<P, DK_ODD>(group, gr, threads, lds, nt, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
-    case DK_EVEN: launch_g<P, DK_EVEN>(group, gr, threads, lds, nt, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
-    case DK_EVEN_ID: launch_g<P, DK_EVEN_ID>(group, gr, threads, lds, nt, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc); break;
+    case DK_FULL: launch_g<P, DK_FULL>(group, gr, threads, lds, nt, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc, mb); break;
+    case DK_HOP: launch_g<P, DK_HOP>(group, gr, threads, lds, nt, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc, mb); break;
+    case DK_PAULI: launch_g<P, DK_PAULI>(1, gr, threads, 0, false, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc, mb); break;
+    case DK_ODD: launch_g<P, DK_ODD>(group, gr, threads, lds, nt, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc, mb); break;
+    case DK_EVEN: launch_g<P, DK_EVEN>(group, gr, threads, lds, nt, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc, mb); break;
+    case DK_EVEN_ID: launch_g<P, DK_EVEN_ID>(group, gr, threads, lds, nt, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc, mb); break;
   }
   return hipGetLastError();
 }
@@ -311,9 +340,12 @@ int tune_group(int prec, DiracKind kind, const Geom &g, const OpFields &f, Spino
     if (it != g_tuned.end()) return it->second;
   }
   constexpr int L = LDS_VARIANT, N = NT_VARIANT;
-  static const int cand[] = {1, 2, 4, 8, L | 1, L | 2, L | 4, L | N | 1, L | N | 2, L | N | 4};
+  constexpr int M = MIRROR_VARIANT;
+  static const int cand[] = {1, 2, 4, 8, L | 1, L | 2, L | 4, L | N | 1, L | N | 2, L | N | 4,
+                             L | M | 1, L | N | M | 1, L | N | M | 2};
   const bool half = kind == DK_ODD || kind == DK_EVEN || kind == DK_EVEN_ID;
-  const int ncand = (half ? g.Vbh : 2 * g.Vbh) <= 256 ? 10 : 4;
+  const bool fits = (half ? g.Vbh : 2 * g.Vbh) <= 256;
+  const int ncand = !fits ? 4 : g.N[1] == 2 * g.L1 ? 13 : 10;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return 2;
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -365,7 +397,7 @@ hipError_t launch_dirac(int prec, DiracKind kind, const Geom &g, const OpFields 
 
 bool force_dirac_variant(int choice) {
   const int group = choice & (LDS_VARIANT - 1);
-  if (choice != 0 && ((choice & ~(NT_VARIANT | LDS_VARIANT | 15)) ||
+  if (choice != 0 && ((choice & ~(MIRROR_VARIANT | NT_VARIANT | LDS_VARIANT | 15)) ||
                       (group != 1 && group != 2 && group != 4 && group != 8)))
     return false;
   g_forced_choice.store(choice);

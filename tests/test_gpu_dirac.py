@@ -77,15 +77,18 @@ def test_operator_low_precision(case, prec):
         assert rel(to_host(y), oracle_op(case, which, x)) < TOL[prec]
 
 
-VARIANTS = [1, 2, 4, 8, 17, 18, 20, 24, 49, 50, 52, 56]
+VARIANTS = [1, 2, 4, 8, 17, 18, 20, 24, 49, 50, 52, 56, 81, 113, 114, 120]
 
 
 @pytest.mark.parametrize("choice", VARIANTS,
-                         ids=[f"g{v & 15}{'-lds' if v & 16 else ''}{'-nt' if v & 32 else ''}" for v in VARIANTS])
+                         ids=[f"g{v & 15}{'-lds' if v & 16 else ''}{'-nt' if v & 32 else ''}"
+                              f"{'-mir' if v & 64 else ''}" for v in VARIANTS])
 def test_every_kernel_variant(case, choice):
-    """Each hop-group size, the LDS-staged input and the non-temporal Pauli
-    and output streams, forced in turn (the autotuner would otherwise pick
-    one), for D, D^ and the hopping term in FP64 and FP32."""
+    """Each hop-group size, the LDS-staged input, the non-temporal Pauli
+    and output streams and the mirror-fused link reads (C* lattices: mirror
+    links read at the physical partner and conjugated), forced in turn (the
+    autotuner would otherwise pick one), for D, D^ and the hopping term in
+    FP64 and FP32."""
     import torch
     from paper_1710_08839_amd import qxd
     x = case.source(9)
@@ -211,7 +214,7 @@ def test_stream_probe_exact(ctx):
     and above one pass of the grid."""
     import torch
     from paper_1710_08839_amd import qxd
-    for r in (1, 7):
+    for r in (1, 5, 7):
         for nchunk in (1, 3, 900):
             nbytes = nchunk * 49152
             n = nbytes // 4
