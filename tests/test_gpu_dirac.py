@@ -88,14 +88,16 @@ def test_every_kernel_variant(case, choice):
     and output streams and the mirror-fused link reads (C* lattices: mirror
     links read at the physical partner and conjugated), forced in turn (the
     autotuner would otherwise pick one), for D, D^ and the hopping term in
-    FP64 and FP32."""
+    FP64 and FP32 (mirror-fused variants in all four storages)."""
     import torch
     from paper_1710_08839_amd import qxd
     x = case.source(9)
     refs = {w: oracle_op(case, w, x) for w in (0, 1, 2)}
     qxd.set_dirac_variant(choice)
     try:
-        for prec in (0, 1):
+        # the mirror-fused reads also in the 16-bit storages (conjugation of
+        # FP16 / BF16 link components)
+        for prec in ((0, 1, 2, 3) if choice & 64 else (0, 1)):
             for which in (0, 1, 2):
                 y = torch.empty_like(to_dev(x))
                 case.field.apply(case.quark, which, prec, to_dev(x), y)
