@@ -5,8 +5,10 @@
 Prints one JSON line.  `value` is the achieved bandwidth of the Dirac
 operator D = hop + Pauli in FP64 on the 64 x 32^3 lattice with C* boundaries
 in x, y, z (4,194,304 extended sites): algorithmic bytes of one application
-(each field read once: in and out spinors, the hopping links W = U z^qhat and
-the Pauli term) divided by the average time of one application, measured with
+(each field read once: in and out spinors, the hopping links W = U z^qhat --
+only the physical half's when the kernel reads the C* mirror links at their
+physical partners -- and the Pauli term) divided by the average time of one
+application, measured with
 HIP events over K back-to-back applications on the launch stream.  A "step"
 is one such application; inputs are resident in HBM.  The other precisions,
 the mixed-precision versus FP64 solve rates and the oracle timed on the host
