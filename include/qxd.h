@@ -111,7 +111,8 @@ typedef struct {
   int ncy;            /* SAP cycles per preconditioner application (0: 4)      */
   int nmr;            /* MR steps per SAP block solve (0: 4)                   */
   int inner_prec;     /* qxd_prec of the SAP-GCR inner solver                  */
-  double inner_tol;   /* relative residual reduction per inner solve           */
+  double inner_tol;   /* relative residual reduction per inner solve (0: 1e-6
+                         F64, 1e-5 F32, 2e-2 F16S, 1e-2 BF16)                  */
   int max_outer;      /* outer defect-correction steps (SAP_GCR)              */
 } qxd_solver;
 

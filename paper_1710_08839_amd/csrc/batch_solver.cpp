@@ -84,7 +84,7 @@ BatchSolver::BatchSolver(Field *f, int prec, const qxd_solver &s, hipStream_t st
   if (nkv_ > MAXV) nkv_ = MAXV;
   ncy_ = s.ncy > 0 ? s.ncy : kDefaultNcy;
   nmr_ = s.nmr > 0 ? s.nmr : kDefaultNmr;
-  inner_tol_ = s.inner_tol > 0 ? s.inner_tol : (prec == QXD_F64 ? 1e-6 : (prec == QXD_F32 ? 1e-5 : 1e-2));
+  inner_tol_ = s.inner_tol > 0 ? s.inner_tol : kDefaultInnerTol[prec >= QXD_F64 && prec <= QXD_BF16 ? prec : 0];
 }
 
 BatchSolver::~BatchSolver() {
