@@ -5,6 +5,7 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <algorithm>
 #include <cstring>
 
 #include "../../include/qxd_debug.h"
@@ -117,6 +118,24 @@ size_t Field::op_bytes(int prec) const {
   // and (if different) in precision prec
   size_t b = (size_t)36 * (2 * g.V + g.Vh) * 16;
   if (prec != QXD_F64) b += (size_t)36 * (2 * g.V + g.Vh) * pair_bytes(prec);
+  return b;
+}
+
+size_t Field::pending_op_bytes(const qxd_quark *quarks, int n, int prec) {
+  std::lock_guard<std::recursive_mutex> lk(mu);
+  size_t b = 0;
+  std::vector<std::tuple<double, double, double, double>> seen;
+  for (int k = 0; k < n; k++) {
+    const qxd_quark &q = quarks[k];
+    auto key = std::make_tuple(q.kappa, has_u1 ? q.q : 0.0, q.csw, has_u1 ? q.csw_u1 : 0.0);
+    if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
+    seen.push_back(key);
+    auto it = ops.find(key);
+    if (it == ops.end())
+      b += op_bytes(prec);
+    else if (!it->second->ready[prec])
+      b += (size_t)36 * (2 * g.V + g.Vh) * pair_bytes(prec);
+  }
   return b;
 }
 

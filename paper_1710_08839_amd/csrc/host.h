@@ -74,6 +74,9 @@ struct Field {
   static constexpr size_t kMaxCachedOps = 4;
   // device bytes one operator of this field holds in FP64 plus precision prec
   size_t op_bytes(int prec) const;
+  // device bytes still to be allocated for the operators of these quarks
+  // (distinct ones, not yet built in FP64 and precision prec)
+  size_t pending_op_bytes(const qxd_quark *quarks, int n, int prec);
   std::map<std::string, std::unique_ptr<DevBuf>> work;  // named workspaces
   std::recursive_mutex mu;
 

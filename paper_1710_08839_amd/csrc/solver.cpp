@@ -324,12 +324,13 @@ qxd_status solve(Field *f, const qxd_quark *quarks, int nquark, const qxd_solver
     // every right-hand side gets a slot of the batch while device memory
     // allows; the others join as slots free up (continuous batching).  The
     // operators of the call's quarks are built as their right-hand sides
-    // join, so their memory is set aside first.
+    // join, so the memory of those not built yet is set aside first (built
+    // ones are already out of the free memory).
     size_t freeb = 0, totalb = 0;
     CK(hipMemGetInfo(&freeb, &totalb));
     size_t per_slot = BatchSolver::slot_bytes(f, s.inner_prec, s);
     size_t avail = (size_t)(0.8 * freeb);
-    const size_t ops_b = (size_t)nquark * f->op_bytes(s.inner_prec);
+    const size_t ops_b = f->pending_op_bytes(quarks, nquark, s.inner_prec);
     avail = avail > ops_b ? avail - ops_b : 0;
     int cap = (int)std::min<size_t>((size_t)nrhs, std::max<size_t>(1, avail / per_slot));
     BatchSolver bs(f, s.inner_prec, s, st);
