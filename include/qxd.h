@@ -166,7 +166,11 @@ qxd_status qxd_spinor_pack(qxd_field *field, qxd_prec prec, const double *in_dev
 qxd_status qxd_spinor_unpack(qxd_field *field, qxd_prec prec, const void *in_dev,
                              double *out_dev, int nrhs, void *stream);
 
-/* out = op(in) for nrhs spinors.  quarks: nquark entries; right-hand side r
+/* out = op(in) for nrhs spinors: D = m0 + Dw + dD_sw with the covariant
+ * derivatives carrying U z^qhat and the SW term of both gauge groups (Sec.
+ * 2.3), its diagonal and hopping parts, the even-odd blocks and the Schur
+ * complement D^ = D_ee - D_eo D_oo^-1 D_oe (Sec. 2.4), or gamma5 D.
+ * quarks: nquark entries; right-hand side r
  * uses quarks[r * nquark / nrhs] (nrhs must be a multiple of nquark).  With
  * flags & QXD_NATIVE, in_dev/out_dev are nrhs consecutive native spinors of
  * precision prec; otherwise they are API-layout FP64 buffers and the operator
@@ -177,7 +181,14 @@ qxd_status qxd_dirac_apply(qxd_field *field, const qxd_quark *quarks, int nquark
                            int nrhs, unsigned flags, void *stream);
 
 /* Solve D psi = eta for nrhs right-hand sides (API-layout FP64, device), each
- * to |eta - D psi| / |eta| <= s->tol with the residual computed in FP64.
+ * to |eta - D psi| / |eta| <= s->tol with the residual computed in FP64.  D
+ * is the operator of qxd_dirac_apply (Sec. 2.3); psi lives on the whole
+ * extended lattice (Sec. 2.1).  The solvers are the ones the paper names in
+ * its abstract and in the feature list of Sec. 2: QXD_SOLVER_EO_GCR is GCR on
+ * the even-odd preconditioned D^ of Sec. 2.4 with psi_o reconstructed from
+ * psi_e; QXD_SOLVER_SAP_GCR is flexible GCR right-preconditioned by the
+ * Schwarz alternating procedure (qxd_sap_apply) inside an FP64 defect
+ * correction.
  * quarks as in qxd_dirac_apply.  psi_dev is the initial guess if use_guess,
  * else it is overwritten.  info: nrhs entries (may be NULL).  Returns
  * QXD_ENOCONV if any right-hand side missed tol (best iterate written),
@@ -186,10 +197,12 @@ qxd_status qxd_solve(qxd_field *field, const qxd_quark *quarks, int nquark,
                      const qxd_solver *s, const double *eta_dev, double *psi_dev,
                      int nrhs, int use_guess, qxd_solve_info *info, void *stream);
 
-/* Apply the SAP preconditioner M_SAP of the SAP_GCR solver (ncy cycles of
- * black and white block solves, each by nmr minimal-residual steps on the
- * even-odd block operator with Dirichlet faces) to nrhs API-layout FP64
- * spinors, computing in precision prec with the field's blocks.  out = M in.
+/* Apply the SAP preconditioner M_SAP of the SAP_GCR solver (the Schwarz
+ * preconditioner the paper's SAP-GCR is named after, abstract and Sec. 2):
+ * ncy cycles of black and white block solves, each by nmr minimal-residual
+ * steps on the even-odd (Sec. 2.4) block operator with Dirichlet faces, to
+ * nrhs API-layout FP64 spinors, computing in precision prec with the field's
+ * blocks.  out = M in.
  * Asynchronous on `stream`. */
 qxd_status qxd_sap_apply(qxd_field *field, const qxd_quark *quark, qxd_prec prec, int ncy,
                          int nmr, const double *in_dev, double *out_dev, int nrhs, void *stream);

@@ -41,6 +41,14 @@ qxd_status qxd_debug_set_step_graphs(int enable);
  * configuration repeats).  QXD_EINVAL if either pointer is NULL. */
 qxd_status qxd_debug_step_graph_counts(int64_t *captures, int64_t *replays);
 
+/* Make the next n steps of the batched SAP-GCR solver (qxd_solve with
+ * QXD_SOLVER_SAP_GCR, and the serve loop) fail with QXD_EDEVICE before any
+ * device work; 0 cancels.  For testing the error paths: qxd_solve returns the
+ * error with every unfinished right-hand side's info.status set to it, and a
+ * serve request whose batch fails completes with that status (its psi is not
+ * written).  Process-wide.  QXD_EINVAL for n < 0. */
+qxd_status qxd_debug_fail_steps(int n);
+
 /* Streaming probe on the current device, the practical bandwidth ceiling the
  * benchmark reports next to the kernels, shaped like the spinor traffic of
  * the block-major fields.  dst is cut into chunks of 12 planes of 4 KB, src

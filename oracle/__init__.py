@@ -21,9 +21,10 @@ code for QCD+QED", Lattice 2017):
   dense.py    dense matrices and brute-force tools for tiny lattices
 
 Parity status: every function is pinned by a CPU test against closed forms,
-identities of the paper or brute force, except the open time boundary
-(parity unpinned beyond gamma5-hermiticity, gauge covariance and the dense
-solve) and the solver iteration counts (the paper prints none).
+identities of the paper or brute force (the open time boundary by closed forms
+of the boundary clover: a field whose only non-trivial links are the cut ones,
+and a uniform flux whose boundary leaves are half missing), except the solver
+iteration counts (the paper prints none).
 """
 
 from .lattice import Lattice  # noqa: F401

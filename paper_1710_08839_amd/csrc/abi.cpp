@@ -298,6 +298,15 @@ qxd_status qxd_debug_set_step_graphs(int enable) {
   return QXD_OK;
 }
 
+qxd_status qxd_debug_fail_steps(int n) {
+  if (n < 0) {
+    set_error("n must be >= 0");
+    return QXD_EINVAL;
+  }
+  inject_step_failures(n);
+  return QXD_OK;
+}
+
 qxd_status qxd_debug_step_graph_counts(int64_t *captures, int64_t *replays) {
   if (!captures || !replays) {
     set_error("captures and replays must be non-NULL");

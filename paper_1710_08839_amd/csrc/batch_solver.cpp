@@ -337,6 +337,7 @@ struct BImpl {
 };
 
 std::atomic<bool> g_step_graphs{true};
+std::atomic<int> g_inject_failures{0};
 std::atomic<int64_t> g_graph_captures{0}, g_graph_replays{0};
 
 #define DISPATCH(call)                                          \
@@ -348,6 +349,7 @@ std::atomic<int64_t> g_graph_captures{0}, g_graph_replays{0};
   }
 
 void set_step_graphs(bool on) { g_step_graphs.store(on); }
+void inject_step_failures(int n) { g_inject_failures.store(n > 0 ? n : 0); }
 void step_graph_counts(int64_t *captures, int64_t *replays) {
   *captures = g_graph_captures.load();
   *replays = g_graph_replays.load();
@@ -527,11 +529,34 @@ qxd_status BatchSolver::add(const qxd_quark &q, const double *eta_api, double *p
   return new_inner(*sl);
 }
 
+void BatchSolver::abort_all(int status) {
+  for (size_t j = 0; j < slots_.size(); j++) {
+    Slot &sl = *slots_[j];
+    if (!sl.active) continue;
+    Finished fin;
+    fin.slot = (int)j;
+    fin.tag = sl.tag;
+    fin.info.status = status;
+    fin.info.outer_iters = sl.outer;
+    fin.info.inner_iters = sl.total_it;
+    fin.info.true_resid = INFINITY;
+    fin.info.seconds = now_s() - sl.t0;
+    done_.push_back(fin);
+    sl.active = false;
+    release_ops(sl);
+  }
+}
+
 qxd_status BatchSolver::step() {
   std::vector<Slot *> act;
   for (auto &s : slots_)
     if (s->active) act.push_back(s.get());
   if (act.empty()) return QXD_OK;
+  for (int left = g_inject_failures.load(); left > 0;)
+    if (g_inject_failures.compare_exchange_weak(left, left - 1)) {
+      set_error("injected failure of a batched solver step (testing hook)");
+      return QXD_EDEVICE;
+    }
   const Geom &g = f_->g;
   int n = (int)act.size();
   // batched: phi_k = M_SAP rho, chi_k = D phi_k

@@ -43,6 +43,10 @@ class BatchSolver {
   qxd_status add(const qxd_quark &q, const double *eta_api, double *psi_api, bool use_guess, void *tag);
   // one inner iteration for every active right-hand side
   qxd_status step();
+  // end every active right-hand side with `status` after a failed step: no
+  // device work (the device may be unusable), the solutions are not written
+  // back, their operators are released and take_finished() reports them
+  void abort_all(int status);
   // right-hand sides finished since the last call
   std::vector<Finished> take_finished();
   // the solver parameters this batch runs with
@@ -105,6 +109,9 @@ constexpr double kDefaultInnerTol[4] = {1e-6, 1e-5, 2e-2, 1e-2};
 
 // Process-wide switch for graph capture of the batched steps (testing hook).
 void set_step_graphs(bool on);
+// Make the next n batched steps of any solver fail before any launch
+// (testing hook for the error paths of qxd_solve and the serve loop).
+void inject_step_failures(int n);
 // process-wide totals: step graphs captured, and step graphs launched
 void step_graph_counts(int64_t *captures, int64_t *replays);
 

@@ -148,8 +148,13 @@ struct Worker {
         if (bs->active() > 0) {
           qxd_status s = bs->step();
           if (s != QXD_OK) {
-            std::lock_guard<std::mutex> lk(sv->mu);
-            sv->error = qxd_last_error();
+            // the batch cannot go on: every right-hand side in it ends with
+            // the error, so their requests complete and stop() can join
+            {
+              std::lock_guard<std::mutex> lk(sv->mu);
+              sv->error = qxd_last_error();
+            }
+            bs->abort_all(s);
           }
         }
         for (auto &x : bs->take_finished()) fin.push_back(x);

@@ -343,7 +343,14 @@ qxd_status solve(Field *f, const qxd_quark *quarks, int nquark, const qxd_solver
                   (void *)(intptr_t)next));
         next++;
       }
-      CS(bs.step());
+      qxd_status ss = bs.step();
+      if (ss != QXD_OK) {
+        // report the right-hand sides still in flight with the error
+        bs.abort_all(ss);
+        for (auto &fin : bs.take_finished())
+          if (info) info[(int)(intptr_t)fin.tag] = fin.info;
+        return ss;
+      }
       for (auto &fin : bs.take_finished()) {
         int r = (int)(intptr_t)fin.tag;
         if (info) info[r] = fin.info;

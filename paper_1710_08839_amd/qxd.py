@@ -84,6 +84,7 @@ SIGNATURES = {
     # testing hooks (include/qxd_debug.h)
     "qxd_debug_set_dirac_variant": ([_I], _I),
     "qxd_debug_set_step_graphs": ([_I], _I),
+    "qxd_debug_fail_steps": ([_I], _I),
     "qxd_debug_stream": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, _I, ctypes.c_void_p], _I),
     "qxd_debug_step_graph_counts": ([ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], _I),
     "qxd_debug_get_dirac_variant": ([_VP, _I, ctypes.POINTER(_I)], _I),
@@ -136,6 +137,12 @@ def set_step_graphs(enable=True):
     """Replay batched SAP-GCR steps from captured HIP graphs (default) or
     issue every launch directly.  A testing hook."""
     _check(lib().qxd_debug_set_step_graphs(1 if enable else 0))
+
+
+def fail_steps(n):
+    """Make the next n batched SAP-GCR steps fail before any device work
+    (0 cancels).  A testing hook for the error paths."""
+    _check(lib().qxd_debug_fail_steps(int(n)))
 
 
 def stream_probe(src, dst, dst_bytes, reads_per_write, stream=None):

@@ -83,3 +83,5 @@ def test_library_loads_and_reports(libpath):
     assert lib.qxd_debug_set_dirac_variant(3) != 0
     assert lib.qxd_debug_set_dirac_variant(16 | 4) == 0
     assert lib.qxd_debug_set_dirac_variant(0) == 0
+    assert lib.qxd_debug_fail_steps(-1) != 0
+    assert lib.qxd_debug_fail_steps(0) == 0

@@ -252,3 +252,39 @@ def test_operator_cache_eviction(ctx, small):
     ph = to_host(psi)
     for r in range(6):
         assert od.norm(etas[r] - ops[r].apply(ph[r])) / od.norm(etas[r]) <= 1.05e-10, r
+
+
+def test_failed_step_ends_solves_and_requests(ctx, small):
+    """A batched step that fails (forced from the host before any launch)
+    ends every right-hand side in flight with the error: qxd_solve returns it
+    with each info.status set, a served request completes with it, and the
+    serve loop still stops.  Afterwards the same solve succeeds."""
+    import torch
+    from paper_1710_08839_amd import qxd
+    c = small
+    s = qxd.solver(kind=qxd.SAP_GCR, tol=1e-10, nkv=6, ncy=2, nmr=3, inner_prec=qxd.F32)
+    etas = to_dev(np.stack([c.source(60 + r) for r in range(3)]))
+    psi = torch.empty_like(etas)
+    qxd.fail_steps(1)
+    try:
+        st, info = c.field.solve(c.quark, s, etas, psi, nrhs=3, check=False)
+    finally:
+        qxd.fail_steps(0)
+    assert st == -5 and all(i.status == -5 for i in info)
+    ctx.serve_start()
+    try:
+        qxd.fail_steps(1)
+        t = ctx.serve_submit(c.field, c.quark, s, etas, psi, 3)
+        r, t0 = None, time.time()
+        while r is None and time.time() - t0 < 30:
+            r = ctx.serve_poll(t)
+            time.sleep(0.005)
+    finally:
+        qxd.fail_steps(0)
+        ctx.serve_stop()
+    assert r is not None and r.status == -5
+    st, info = c.field.solve(c.quark, s, etas, psi, nrhs=3)
+    assert st == 0
+    ph, eh = to_host(psi), to_host(etas)
+    for k in range(3):
+        assert od.norm(eh[k] - c.op.apply(ph[k])) / od.norm(eh[k]) <= 1.05e-10

@@ -33,6 +33,14 @@ def cstar_case(ctx):
 
 
 @pytest.fixture(scope="module")
+def open_case(ctx):
+    # as cstar_case with an open time boundary: the links across x0 = T-1 -> 0
+    # are absent in the block solves, the face updates and the Dirac operator
+    return Case(ctx, (8, 8, 8, 8), cstar=3, time_bc=1, q=-1 / 3, kappa=0.1365, csw=1.9, eps=0.25,
+                seed=20171004)
+
+
+@pytest.fixture(scope="module")
 def periodic_case(ctx):
     return Case(ctx, (8, 8, 8, 8), cstar=0, u1=False, kappa=0.124, csw=1.0, eps=0.3, seed=20171000)
 
@@ -40,9 +48,10 @@ def periodic_case(ctx):
 @pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5), (2, 1e-2), (3, 1e-2)],
                          ids=["f64", "f32", "f16s", "bf16"])
 @pytest.mark.parametrize("ncy,nmr", [(1, 0), (1, 1), (2, 4)])
-def test_sap_matches_oracle(cstar_case, prec, tol, ncy, nmr):
+@pytest.mark.parametrize("which", ["cstar_case", "open_case"], ids=["antiperiodic", "open"])
+def test_sap_matches_oracle(request, which, prec, tol, ncy, nmr):
     import torch
-    c = cstar_case
+    c = request.getfixturevalue(which)
     blocks = osv.Blocks(c.lat, (4, 4, 4, 4))
     assert blocks.check_colouring()
     rho = c.source(31)
@@ -85,10 +94,11 @@ def test_eo_gcr_f64(periodic_case):
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2, 3], ids=["f64", "f32", "f16s", "bf16"])
-def test_sap_gcr(cstar_case, prec):
+@pytest.mark.parametrize("which", ["cstar_case", "open_case"], ids=["antiperiodic", "open"])
+def test_sap_gcr(request, which, prec):
     import torch
     from paper_1710_08839_amd import qxd
-    c = cstar_case
+    c = request.getfixturevalue(which)
     eta = c.source(1001)
     psi = torch.empty_like(to_dev(eta))
     s = qxd.solver(kind=qxd.SAP_GCR, tol=1e-10, nkv=8, ncy=4, nmr=4, inner_prec=prec)
@@ -96,6 +106,52 @@ def test_sap_gcr(cstar_case, prec):
     assert st == 0, info[0].status
     assert info[0].true_resid <= 1e-10
     _check_solution(c, eta, to_host(psi))
+
+
+def test_eo_gcr_open_time(open_case):
+    """Plain FP64 even-odd GCR with the open time boundary on a C* lattice."""
+    import torch
+    from paper_1710_08839_amd import qxd
+    c = open_case
+    eta = c.source(1005)
+    psi = torch.empty_like(to_dev(eta))
+    st, info = c.field.solve(c.quark, qxd.solver(kind=qxd.EO_GCR, tol=1e-10, nkv=32), to_dev(eta), psi)
+    assert st == 0 and info[0].true_resid <= 1e-10
+    _check_solution(c, eta, to_host(psi))
+
+
+_FGCR_REF = {}
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 1e-5), (2, 1e-2), (3, 1e-2)],
+                         ids=["f64", "f32", "f16s", "bf16"])
+@pytest.mark.parametrize("k", [1, 3, 8])
+def test_fgcr_steps_match_oracle(cstar_case, prec, tol, k):
+    """The iterate after k flexible-GCR steps (SAP preconditioner, one outer
+    defect-correction step) equals the oracle's k-step FGCR on the same source
+    to the bar of the inner precision: the per-step error of the mixed-
+    precision solver against FP64.  The library orthogonalises by one
+    classical Gram-Schmidt pass with FP64 sums, the oracle by modified
+    Gram-Schmidt with normalised vectors; the two agree in exact arithmetic."""
+    import torch
+    from paper_1710_08839_amd import qxd
+    c = cstar_case
+    eta = c.source(1003)
+    if k not in _FGCR_REF:
+        blocks = osv.Blocks(c.lat, (4, 4, 4, 4))
+        en = od.norm(eta)
+        ref, it = osv.fgcr(c.op.apply, lambda r: osv.sap(c.op, blocks, r, ncy=2, nmr=4), eta / en, 1e-14,
+                           nkv=8, maxiter=k)
+        assert it == k
+        _FGCR_REF[k] = en * ref
+    ref = _FGCR_REF[k]
+    psi = torch.empty_like(to_dev(eta))
+    s = qxd.solver(kind=qxd.SAP_GCR, tol=1e-14, maxiter=k, nkv=8, ncy=2, nmr=4, inner_prec=prec,
+                   inner_tol=1e-14, max_outer=1)
+    st, info = c.field.solve(c.quark, s, to_dev(eta), psi, check=False)
+    assert st == -3 and info[0].inner_iters == k and info[0].outer_iters == 1
+    err = rel(to_host(psi), ref)
+    assert err < tol, err
 
 
 def test_solve_with_guess_and_point_source(cstar_case):

@@ -512,3 +512,104 @@ def test_apply_at_sites_matches_full_operator():
     sites = np.array([0, 5, 77, 300, lat.V - 1])
     got = od.apply_at_sites(lat, ue, ae, psi, sites, 0.13, q=-1 / 3, csw=1.9, csw_u1=1.2)
     assert rel(got, op.apply(psi)[sites]) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Open time boundary (Sec. 2 features list; the boundary term dD_b is only
+# named in Sec. 2.3).  Reading: the links across x0 = T-1 -> 0 do not exist,
+# the boundary coefficient is 1 (dD_b = 0) and every clover leaf that contains
+# a missing link counts as zero, with the remaining leaves not reweighted.
+# ---------------------------------------------------------------------------
+def cut_only_field(lat, seed):
+    """Unit links everywhere except the time links at x0 = T-1 (random SU(3)
+    and random U(1) angles there)."""
+    rng = synth.rng_from_seed(seed)
+    u = np.broadcast_to(np.eye(3, dtype=complex), (lat.Vphs, 4, 3, 3)).copy()
+    a = np.zeros((lat.Vphs, 4))
+    c = lat.coords[lat.phys_index()]
+    cut = c[:, 0] == lat.phys[0] - 1
+    u[cut, 0] = synth.su3_links(rng, int(cut.sum()), 0.9)[:, 0]
+    a[cut, 0] = synth.u1_angles(rng, int(cut.sum()), 1.0)[:, 0]
+    return u, a
+
+
+@pytest.mark.parametrize("cstar", [0, 3])
+def test_open_time_cut_links_leave_no_field_strength(cstar):
+    """Only the links that the open boundary removes are non-trivial: every
+    leaf through them is dropped, so P(x) = 1/(2 kappa) at every site.  The
+    same field with periodic time has field strength at x0 = 0 and T-1, which
+    shows the check tells dropped leaves from kept ones."""
+    kappa = 0.13
+    for time_bc, expect_trivial in ((1, True), (0, False)):
+        lat = Lattice((4, 4, 2, 2), cstar=cstar, time_bc=time_bc)
+        u, a = cut_only_field(lat, 17)
+        ue, ae = of.extend_gauge(lat, u, a)
+        op = od.build_operator(lat, ue, ae, kappa, q=2 / 3, csw=1.9, csw_u1=1.3)
+        dev = np.max(np.abs(op.pauli - np.eye(12) / (2 * kappa)), axis=(1, 2))
+        if expect_trivial:
+            assert np.max(dev) < 1e-15
+        else:
+            x0 = lat.coords[:, 0]
+            assert np.min(dev[(x0 == 0) | (x0 == lat.phys[0] - 1)]) > 1e-2
+            assert np.max(dev[(x0 > 0) & (x0 < lat.phys[0] - 1)]) < 1e-15
+
+
+def test_open_time_boundary_flux_is_halved():
+    """Uniform abelian flux phi per (0,1) plaquette, A_1(x) = phi x0, with open
+    time: in the bulk the field tensors are the closed forms of the periodic
+    torus; on the slices x0 = 0 and x0 = T-1 two of the four leaves contain a
+    missing link, so the field strength is exactly half (no reweighting of the
+    remaining leaves)."""
+    t = 6
+    lat = Lattice((t, 4, 2, 2), cstar=0, time_bc=1)
+    phi = 0.37
+    c = lat.coords[lat.phys_index()]
+    a = np.zeros((lat.Vphs, 4))
+    a[:, 1] = phi * c[:, 0]
+    ca, cb = 1, 2
+    ph = np.stack([np.exp(1j * ca * a), np.exp(1j * cb * a), np.exp(-1j * (ca + cb) * a)], axis=-1)
+    u = np.zeros((lat.Vphs, 4, 3, 3), complex)
+    for i in range(3):
+        u[:, :, i, i] = ph[..., i]
+    ue, ae = of.extend_gauge(lat, u, a)
+    kappa, csw, cu1, q = 0.12, 1.6, 1.4, -1.0 / 3.0
+    qhat = -2
+    op = od.build_operator(lat, ue, ae, kappa, q=q, csw=csw, csw_u1=cu1)
+    s01 = 0.5j * (G[0] @ G[1] - G[1] @ G[0])
+    f01 = np.diag([np.sin(ca * phi), np.sin(cb * phi), -np.sin((ca + cb) * phi)])
+    x0 = lat.coords[:, 0]
+    for w, sel in ((1.0, (x0 > 0) & (x0 < t - 1)), (0.5, (x0 == 0) | (x0 == t - 1))):
+        expect = (np.eye(12) / (2 * kappa) - w * (csw / 2) * np.kron(s01, f01)
+                  - w * (qhat * cu1 / 2) * np.sin(phi) * np.kron(s01, np.eye(3)))
+        assert np.max(np.abs(op.pauli[sel] - expect[None])) < 1e-13
+
+
+def test_colouring_check_rejects_bad_decompositions():
+    """Two colours need an even number of blocks per direction and, across a
+    shifted C* boundary, an even block shift L1 / b1: the check must say no
+    when a wrap or a shift joins blocks of one colour."""
+    assert osv.Blocks(Lattice((4, 4, 4, 4), cstar=0), (2, 2, 2, 2)).check_colouring()
+    assert not osv.Blocks(Lattice((6, 4, 4, 4), cstar=0), (2, 2, 2, 2)).check_colouring()
+    assert osv.Blocks(Lattice((4, 4, 4, 4), cstar=3), (2, 2, 2, 2)).check_colouring()
+    # L1 / b1 = 1: crossing x2 moves the block coordinates by (0, 1, nb2 - 1, 0)
+    assert not osv.Blocks(Lattice((4, 2, 4, 4), cstar=3), (2, 2, 2, 2)).check_colouring()
+    # a wrap alone is harmless with C* in direction 1 only
+    assert osv.Blocks(Lattice((4, 2, 4, 4), cstar=1), (2, 2, 2, 2)).check_colouring()
+
+
+def test_dense_open_time():
+    """Open time on a C* lattice: Schur complement and determinant identity,
+    and the even-odd and SAP-FGCR solves against numpy.linalg.solve."""
+    lat = Lattice((4, 2, 2, 2), cstar=3, time_bc=1)
+    ue, ae = random_field(lat, 29, eps=0.5, sigma=0.4)
+    op = od.build_operator(lat, ue, ae, 0.125, q=-1 / 3, csw=1.5)
+    d = dense_matrix(op.apply, lat.V)
+    _check_schur_det(lat, op, d)
+    eta = rand_spinor(lat, 8)
+    exact = np.linalg.solve(d, eta.reshape(-1)).reshape(eta.shape)
+    psi, _ = osv.solve_eo(op, eta, 1e-12, nkv=16)
+    assert rel(psi, exact) < 1e-10
+    blocks = osv.Blocks(lat, (2, 2, 2, 2))
+    assert blocks.check_colouring()
+    x, _ = osv.fgcr(op.apply, lambda r: osv.sap(op, blocks, r, ncy=3, nmr=4), eta, 1e-12, nkv=8)
+    assert rel(x, exact) < 1e-10
