@@ -180,6 +180,35 @@ qxd_status qxd_dirac_apply(qxd_field *field, const qxd_quark *quarks, int nquark
                            qxd_op op, qxd_prec prec, const void *in_dev, void *out_dev,
                            int nrhs, unsigned flags, void *stream);
 
+/* Bytes of the device scratch buffer of qxd_dirac_apply_noalloc, one per GPU. */
+#define QXD_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation, arguments and results as qxd_dirac_apply, but the call performs
+ * no hipMalloc, hipFree or other allocation.  Limits:
+ *   - every quark's operator must already be built on this field in precision
+ *     prec (an earlier qxd_dirac_apply or qxd_solve in that precision builds
+ *     it); otherwise QXD_EINVAL and nothing is queued;
+ *   - its temporaries live in one library-owned device buffer of
+ *     QXD_NOALLOC_SCRATCH_BYTES per GPU, created when the library's code is
+ *     loaded on that GPU (resolved by qxd_init) and held until the process
+ *     ends.  Needed: nothing for native-layout D, HOP, PAULI, OOINV and G5D;
+ *     one half-lattice native spinor of precision prec for QXD_OP_DHAT; two
+ *     full-lattice native spinors of precision prec (each rounded up to 256
+ *     bytes) more for API-layout buffers.  A call that needs more returns
+ *     QXD_EINVAL before any device work;
+ *   - all calls on one GPU share that buffer and it keeps the last call's
+ *     contents: calls queued on one stream are ordered, but calls that
+ *     overlap in time on one GPU (other streams, other threads) race;
+ *   - the kernel variant is the one the autotuner already chose for the
+ *     lattice and precision (a fixed default if none was chosen); nothing is
+ *     timed.
+ * Asynchronous on `stream`. */
+qxd_status qxd_dirac_apply_noalloc(qxd_field *field, const qxd_quark *quarks, int nquark, qxd_op op,
+                                   qxd_prec prec, const void *in_dev, void *out_dev, int nrhs,
+                                   unsigned flags, void *stream);
+
 /* Solve D psi = eta for nrhs right-hand sides (API-layout FP64, device), each
  * to |eta - D psi| / |eta| <= s->tol with the residual computed in FP64.  D
  * is the operator of qxd_dirac_apply (Sec. 2.3); psi lives on the whole

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 
 #include "../../include/qxd_debug.h"
 #include "host.h"
@@ -213,6 +214,14 @@ qxd_status Field::get_op(const qxd_quark &q, int prec, Operator **out, hipStream
   return QXD_OK;
 }
 
+Operator *Field::find_op(const qxd_quark &q, int prec) {
+  std::lock_guard<std::recursive_mutex> lk(mu);
+  if (!links_ready[prec]) return nullptr;
+  auto it = ops.find(std::make_tuple(q.kappa, has_u1 ? q.q : 0.0, q.csw, has_u1 ? q.csw_u1 : 0.0));
+  if (it == ops.end() || !it->second->ready[prec]) return nullptr;
+  return it->second.get();
+}
+
 OpFields Field::op_fields(const Operator &op, int prec) const {
   OpFields f;
   f.links = op.wl[prec].p;
@@ -235,36 +244,40 @@ OpFields Field::op_fields_u(const Operator &op, int prec) const {
 
 // Apply `op` to one native spinor (full-lattice buffers).
 qxd_status apply_native(Field *fd, const Operator &op, qxd_op which, int prec, void *in, void *out,
-                        hipStream_t st) {
+                        hipStream_t st, void *dhat_tmp, bool may_tune) {
   const Geom &g = fd->g;
   OpFields f = fd->op_fields(op, prec);
   SpinorArg full_in{in, g.V, 0, g.rd}, full_out{out, g.V, 0, g.rd}, none{nullptr, 0, 0, g.rd};
+  const bool mt = may_tune;
   switch (which) {
     case QXD_OP_D:
-      QXD_HIP_CHECK(launch_dirac(prec, DK_FULL, g, f, full_in, full_in, full_out, -0.5, st));
+      QXD_HIP_CHECK(launch_dirac(prec, DK_FULL, g, f, full_in, full_in, full_out, -0.5, st, mt));
       break;
     case QXD_OP_HOP:
-      QXD_HIP_CHECK(launch_dirac(prec, DK_HOP, g, f, full_in, none, full_out, -0.5, st));
+      QXD_HIP_CHECK(launch_dirac(prec, DK_HOP, g, f, full_in, none, full_out, -0.5, st, mt));
       break;
     case QXD_OP_PAULI:
-      QXD_HIP_CHECK(launch_dirac(prec, DK_PAULI, g, f, full_in, full_in, full_out, 0.0, st));
+      QXD_HIP_CHECK(launch_dirac(prec, DK_PAULI, g, f, full_in, full_in, full_out, 0.0, st, mt));
       break;
     case QXD_OP_DHAT: {
-      hipError_t e;
-      void *tmp = fd->workspace("dhat_tmp", spinor_bytes(prec, g.Vh), &e);
-      QXD_HIP_CHECK(e);
+      void *tmp = dhat_tmp;
+      if (!tmp) {
+        hipError_t e;
+        tmp = fd->workspace("dhat_tmp", spinor_bytes(prec, g.Vh), &e);
+        QXD_HIP_CHECK(e);
+      }
       SpinorArg t_o{tmp, g.Vh, g.Vh, g.rd};
-      QXD_HIP_CHECK(launch_dirac(prec, DK_ODD, g, f, full_in, none, t_o, -0.5, st));
-      QXD_HIP_CHECK(launch_dirac(prec, DK_EVEN, g, f, t_o, full_in, full_out, 0.5, st));
+      QXD_HIP_CHECK(launch_dirac(prec, DK_ODD, g, f, full_in, none, t_o, -0.5, st, mt));
+      QXD_HIP_CHECK(launch_dirac(prec, DK_EVEN, g, f, t_o, full_in, full_out, 0.5, st, mt));
       QXD_HIP_CHECK(launch_zero_sites(prec, full_out, g.Vh, g.Vh, st));
       break;
     }
     case QXD_OP_OOINV:
-      QXD_HIP_CHECK(launch_dirac(prec, DK_ODD, g, f, full_in, full_in, full_out, 0.0, st));
+      QXD_HIP_CHECK(launch_dirac(prec, DK_ODD, g, f, full_in, full_in, full_out, 0.0, st, mt));
       QXD_HIP_CHECK(launch_zero_sites(prec, full_out, 0, g.Vh, st));
       break;
     case QXD_OP_G5D:
-      QXD_HIP_CHECK(launch_dirac(prec, DK_FULL, g, f, full_in, full_in, full_out, -0.5, st));
+      QXD_HIP_CHECK(launch_dirac(prec, DK_FULL, g, f, full_in, full_in, full_out, -0.5, st, mt));
       QXD_HIP_CHECK(launch_g5_sites(prec, full_out, 0, g.V, st));
       break;
     default:
@@ -272,6 +285,45 @@ qxd_status apply_native(Field *fd, const Operator &op, qxd_op which, int prec, v
       return QXD_EINVAL;
   }
   return QXD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Scratch memory of the allocation-free entry point (qxd_dirac_apply_noalloc):
+// one buffer per GPU, part of the library's code object, so the runtime
+// creates it when the code is loaded on a device and it lives until the
+// process ends.  Host code never passes `scratch` itself to a kernel (in host
+// code the name is only a stand-in for the symbol): qxd_init resolves the
+// device address of each GPU's copy once, with that GPU current, and every
+// later use goes through that address.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[QXD_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+
+// Resolve this device's copy of the scratch array (the device is current).
+static qxd_status init_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) {
+    set_error("device %d beyond the %d devices the library supports", device, kMaxDevices);
+    return QXD_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return QXD_OK;
+  void *ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    set_error("cannot resolve the scratch buffer of device %d: %s", device, hipGetErrorString(e));
+    return QXD_EDEVICE;
+  }
+  g_scratch_ptr[device] = ptr;
+  return QXD_OK;
+}
+
+static void *scratch_of(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
 
 }  // namespace qxd
@@ -351,6 +403,8 @@ qxd_status qxd_init(int device, qxd_ctx **ctx) {
     return QXD_EINVAL;
   }
   QXD_HIP_CHECK(hipSetDevice(device));
+  qxd_status ss = init_scratch(device);
+  if (ss != QXD_OK) return ss;
   qxd_ctx *c = new qxd_ctx();
   c->device = device;
   *ctx = c;
@@ -520,6 +574,73 @@ qxd_status qxd_dirac_apply(qxd_field *field, const qxd_quark *quarks, int nquark
       QXD_HIP_CHECK(launch_pack(prec, field->g, src, nin, 1, st));
       s = apply_native(field, *o, op, prec, nin, nout, st);
       if (s == QXD_OK) QXD_HIP_CHECK(launch_unpack(prec, field->g, nout, dst, 1, st));
+    }
+    if (s != QXD_OK) return s;
+  }
+  return QXD_OK;
+}
+
+static size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+qxd_status qxd_dirac_apply_noalloc(qxd_field *field, const qxd_quark *quarks, int nquark, qxd_op op,
+                                   qxd_prec prec, const void *in_dev, void *out_dev, int nrhs, unsigned flags,
+                                   void *stream) {
+  if (!field || !quarks || !in_dev || !out_dev || nquark < 1 || nrhs < 1 || nrhs % nquark ||
+      !valid_prec(prec) || op < QXD_OP_D || op > QXD_OP_G5D || (flags & ~QXD_NATIVE)) {
+    set_error("invalid arguments to qxd_dirac_apply_noalloc");
+    return QXD_EINVAL;
+  }
+  if (in_dev == out_dev) {
+    set_error("in and out must not overlap");
+    return QXD_EINVAL;
+  }
+  const bool native = flags & QXD_NATIVE;
+  if (native && (!aligned16(in_dev) || !aligned16(out_dev))) {
+    set_error("native spinors must be 16-byte aligned");
+    return QXD_EINVAL;
+  }
+  const Geom &g = field->g;
+  const size_t nb = field->spinor_bytes(prec);
+  // scratch layout: [API staging in | API staging out] [odd-site temporary of D^]
+  const size_t stage = native ? 0 : 2 * align256(nb);
+  const size_t need = stage + (op == QXD_OP_DHAT ? spinor_bytes(prec, g.Vh) : 0);
+  if (need > QXD_NOALLOC_SCRATCH_BYTES) {
+    set_error("qxd_dirac_apply_noalloc needs %zu bytes of scratch on this lattice, more than the %zu it has",
+              need, (size_t)QXD_NOALLOC_SCRATCH_BYTES);
+    return QXD_EINVAL;
+  }
+  std::lock_guard<std::recursive_mutex> lk(field->mu);
+  const int device = field->ctx->device;
+  char *ptr = (char *)scratch_of(device);
+  if (!ptr) {
+    set_error("the scratch buffer of device %d is not resolved (no qxd_init on it)", device);
+    return QXD_EDEVICE;
+  }
+  // every operator must exist already: building one allocates
+  const int per = nrhs / nquark;
+  for (int k = 0; k < nquark; k++)
+    if (!field->find_op(quarks[k], prec)) {
+      set_error("the operator of quark %d (kappa %g, q %g) is not built in precision %d on this field; "
+                "apply it once with qxd_dirac_apply first",
+                k, quarks[k].kappa, quarks[k].q, (int)prec);
+      return QXD_EINVAL;
+    }
+  hipStream_t st = (hipStream_t)stream;
+  QXD_HIP_CHECK(hipSetDevice(device));
+  void *nin = ptr, *nout = ptr + align256(nb);
+  void *tmp = op == QXD_OP_DHAT ? ptr + stage : nullptr;
+  for (int r = 0; r < nrhs; r++) {
+    Operator *o = field->find_op(quarks[r / per], prec);
+    qxd_status s;
+    if (native) {
+      s = apply_native(field, *o, op, prec, (char *)const_cast<void *>(in_dev) + r * nb, (char *)out_dev + r * nb,
+                       st, tmp, false);
+    } else {
+      const double *src = (const double *)in_dev + (int64_t)r * 24 * g.V;
+      double *dst = (double *)out_dev + (int64_t)r * 24 * g.V;
+      QXD_HIP_CHECK(launch_pack(prec, g, src, nin, 1, st));
+      s = apply_native(field, *o, op, prec, nin, nout, st, tmp, false);
+      if (s == QXD_OK) QXD_HIP_CHECK(launch_unpack(prec, g, nout, dst, 1, st));
     }
     if (s != QXD_OK) return s;
   }

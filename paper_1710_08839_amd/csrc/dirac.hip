@@ -388,10 +388,20 @@ int tune_group(int prec, DiracKind kind, const Geom &g, const OpFields &f, Spino
 std::atomic<int> g_forced_choice{0};
 
 hipError_t launch_dirac(int prec, DiracKind kind, const Geom &g, const OpFields &f, SpinorArg in,
-                        SpinorArg self, SpinorArg out, double c, hipStream_t st) {
+                        SpinorArg self, SpinorArg out, double c, hipStream_t st, bool may_tune) {
   if (prec < QXD_F64 || prec > QXD_BF16) return hipErrorInvalidValue;
   const int forced = g_forced_choice.load(std::memory_order_relaxed);
-  int choice = kind == DK_PAULI ? 1 : forced ? forced : tune_group(prec, kind, g, f, in, self, out, c, st);
+  int choice = 1;
+  if (kind != DK_PAULI) {
+    if (forced) {
+      choice = forced;
+    } else if (may_tune) {
+      choice = tune_group(prec, kind, g, f, in, self, out, c, st);
+    } else {
+      choice = tuned_group(prec, (int)kind, g.V, f.qhat != 0);
+      if (!choice) choice = 2;
+    }
+  }
   return launch_any(prec, kind, choice, g, f, in, self, out, c, st);
 }
 

@@ -84,6 +84,9 @@ struct Field {
   void *workspace(const std::string &name, size_t bytes, hipError_t *err);
   // operator for a quark in precision prec (built on first use)
   qxd_status get_op(const qxd_quark &q, int prec, Operator **out, hipStream_t st);
+  // the operator if it is already built in precision prec (nothing is
+  // allocated), else nullptr
+  Operator *find_op(const qxd_quark &q, int prec);
   qxd_status ensure_links(int prec, hipStream_t st);
   // operator fields for the kernels: links with the U(1) phase folded in
   OpFields op_fields(const Operator &op, int prec) const;

@@ -76,9 +76,12 @@ struct SpinorArg {
 };
 
 // Autotuned on first use per (prec, kind, volume, phase-on-the-fly): the
-// first call times the hop-group variants on its own operands.
+// first call times the hop-group variants on its own operands.  With
+// may_tune = false nothing is timed: the variant already chosen for the key
+// is used, or a fixed default if none has been chosen yet.
 hipError_t launch_dirac(int prec, DiracKind kind, const Geom &g, const OpFields &f,
-                        SpinorArg in, SpinorArg self, SpinorArg out, double c, hipStream_t st);
+                        SpinorArg in, SpinorArg self, SpinorArg out, double c, hipStream_t st,
+                        bool may_tune = true);
 
 // Kernel variant chosen by the autotuner for a key (0 if not tuned yet):
 // hop group size, plus 16 for the LDS-staged variant.

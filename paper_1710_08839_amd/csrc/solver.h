@@ -9,9 +9,12 @@ qxd_status solve(Field *f, const qxd_quark *quarks, int nquark, const qxd_solver
                  const double *eta_dev, double *psi_dev, int nrhs, int use_guess,
                  qxd_solve_info *info, hipStream_t st);
 
-// Apply the operator `which` to one native spinor (abi.cpp).
+// Apply the operator `which` to one native spinor (abi.cpp).  The odd-site
+// temporary of the Schur complement is dhat_tmp if given (a half-lattice
+// spinor of precision prec), else a field workspace; with may_tune = false
+// no kernel variant is timed.
 qxd_status apply_native(Field *fd, const Operator &op, qxd_op which, int prec, void *in, void *out,
-                        hipStream_t st);
+                        hipStream_t st, void *dhat_tmp = nullptr, bool may_tune = true);
 
 // M_SAP on native spinors of precision prec: psi = M_SAP rho (ncy cycles,
 // nmr MR steps per block solve).

@@ -74,6 +74,8 @@ SIGNATURES = {
     "qxd_spinor_pack": ([_VP, _I, _VP, _VP, _I, _VP], _I),
     "qxd_spinor_unpack": ([_VP, _I, _VP, _VP, _I, _VP], _I),
     "qxd_dirac_apply": ([_VP, ctypes.POINTER(Quark), _I, _I, _I, _VP, _VP, _I, ctypes.c_uint, _VP], _I),
+    "qxd_dirac_apply_noalloc": ([_VP, ctypes.POINTER(Quark), _I, _I, _I, _VP, _VP, _I, ctypes.c_uint, _VP],
+                                _I),
     "qxd_solve": ([_VP, ctypes.POINTER(Quark), _I, ctypes.POINTER(Solver), _VP, _VP, _I, _I,
                    ctypes.POINTER(SolveInfo), _VP], _I),
     "qxd_sap_apply": ([_VP, ctypes.POINTER(Quark), _I, _I, _I, _VP, _VP, _I, _VP], _I),
@@ -248,6 +250,14 @@ class Field:
         arr = (Quark * len(qs))(*qs)
         _check(lib().qxd_dirac_apply(self.h, arr, len(qs), op, prec, _ptr(x), _ptr(y), nrhs,
                                      NATIVE if native else 0, _stream(stream)))
+
+    def apply_noalloc(self, quarks, op, prec, x, y, nrhs=1, native=False, stream=None):
+        """As apply, through the allocation-free entry point (the operators
+        must already be built in precision prec)."""
+        qs = quarks if isinstance(quarks, (list, tuple)) else [quarks]
+        arr = (Quark * len(qs))(*qs)
+        _check(lib().qxd_dirac_apply_noalloc(self.h, arr, len(qs), op, prec, _ptr(x), _ptr(y), nrhs,
+                                             NATIVE if native else 0, _stream(stream)))
 
     def solve(self, quarks, s, eta, psi, nrhs=1, use_guess=False, stream=None, check=True):
         qs = quarks if isinstance(quarks, (list, tuple)) else [quarks]
