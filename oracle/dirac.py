@@ -122,19 +122,20 @@ class DiracOperator:
         return self.restrict(psi_e, self.lat.even) + odd_part
 
 
-def build_operator(lat, u_ext, a_ext, kappa, q=0.0, csw=0.0, csw_u1=1.0, q_el=1.0 / 6.0):
-    """D for one flavour from extended-lattice U, A (a_ext may be None)."""
+def build_operator(lat, u_ext, a_ext, kappa, q=0.0, csw=0.0, csw_u1=1.0, q_el=1.0 / 6.0, theta=None):
+    """D for one flavour from extended-lattice U, A (a_ext may be None);
+    theta: fermion boundary phases (fields.theta_phases)."""
     from .fields import charge_hat, hopping_links, pauli_term
     qhat = charge_hat(q, q_el) if a_ext is not None else 0
     a = a_ext if a_ext is not None else np.zeros((lat.V, 4))
-    w = hopping_links(lat, u_ext, a, qhat)
+    w = hopping_links(lat, u_ext, a, qhat, theta)
     p = pauli_term(lat, u_ext, a_ext, kappa, q if a_ext is not None else 0.0, csw, csw_u1, q_el)
     return DiracOperator(lat, w, p)
 
 
 def apply_at_sites(lat, u_ext, a_ext, psi, sites, kappa, q=0.0, csw=0.0, csw_u1=1.0, q_el=1.0 / 6.0):
     """(D psi)(x) at the listed sites only, by the same site formula, for
-    lattices too large to build the whole operator."""
+    lattices too large to build the whole operator (no boundary phases)."""
     from .fields import charge_hat, pauli_term
     sites = np.asarray(sites)
     qhat = charge_hat(q, q_el) if a_ext is not None else 0

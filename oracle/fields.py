@@ -59,9 +59,36 @@ def charge_hat(q, q_el):
     return int(r)
 
 
-def hopping_links(lat, u, a, qhat):
-    """W(x, mu) = U(x, mu) exp(i qhat A(x, mu))."""
-    return u * np.exp(1j * qhat * a)[:, :, None, None]
+def theta_phases(lat, theta):
+    """Fermion boundary phases [V, 4] (Sec. 2 feature list: theta-periodic
+    fermions in periodic space directions).  psi(x + L_mu e_mu) = e^{i theta_mu}
+    psi(x) is realised as the factor e^{i theta_mu} on every link (x, mu) whose
+    forward hop crosses the boundary of direction mu.  Reading for C* lattices:
+    on the mirror half the phase is conjugated, e^{-i theta_mu}, as the
+    orbifold constraint conjugates every U(1) field there (Sec. 2.1); this
+    keeps D[U,z] T = T D[U*,z*] and the antisymmetry of C T D (Sec. 2.4).
+    theta_0 multiplies the antiperiodic sign of the time hop; it must vanish
+    with open time, and theta_k must vanish in C* directions (direction 1 is
+    C* whenever any is)."""
+    ph = np.ones((lat.V, 4), dtype=np.complex128)
+    if theta is None:
+        return ph
+    theta = np.asarray(theta, dtype=float)
+    for mu in range(4):
+        if theta[mu] == 0.0:
+            continue
+        if (mu == 0 and lat.time_bc != 0) or (mu >= 1 and mu in lat.cstar_dirs):
+            raise ValueError(f"theta_{mu} must be 0 for this boundary condition")
+        cross = lat.coords[:, mu] == lat.ext[mu] - 1
+        sgn = np.where(lat.is_phys, 1.0, -1.0)
+        ph[cross, mu] = np.exp(1j * theta[mu] * sgn[cross])
+    return ph
+
+
+def hopping_links(lat, u, a, qhat, theta=None):
+    """W(x, mu) = U(x, mu) exp(i qhat A(x, mu)), times the fermion boundary
+    phase of theta_phases on the links that cross a boundary."""
+    return u * (np.exp(1j * qhat * a) * theta_phases(lat, theta))[:, :, None, None]
 
 
 def _existing(lat):

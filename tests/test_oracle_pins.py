@@ -613,3 +613,79 @@ def test_dense_open_time():
     assert blocks.check_colouring()
     x, _ = osv.fgcr(op.apply, lambda r: osv.sap(op, blocks, r, ncy=3, nmr=4), eta, 1e-12, nkv=8)
     assert rel(x, exact) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# theta-periodic fermions in periodic directions (Sec. 2 feature list):
+# psi(x + L_mu e_mu) = e^{i theta_mu} psi(x), so the free-field momenta are
+# p_mu = (2 pi n + theta_mu) / L_mu in space and (pi (2n + 1) + theta_0) / T in
+# antiperiodic time.  Reading for C* lattices: the phase is conjugated on the
+# mirror half; the mirror identities of Sec. 2.4 hold for that reading and
+# fail for the same phase on both halves.
+# ---------------------------------------------------------------------------
+THETA = np.array([0.31, 0.57, -1.13, 2.2])
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (4, 2, 4, 6)])
+def test_theta_free_field_spectrum(dims):
+    lat = Lattice(dims, cstar=0)
+    kappa = 0.125
+    m0 = 1 / (2 * kappa) - 4
+    u = np.broadcast_to(np.eye(3, dtype=complex), (lat.Vphs, 4, 3, 3)).copy()
+    ue, _ = of.extend_gauge(lat, u, None)
+    op = od.build_operator(lat, ue, None, kappa, csw=1.3, theta=THETA)
+    shift = THETA / np.array(dims)
+    moms = allowed_momenta(dims, 0)
+    rng = np.random.default_rng(1)
+    for p in moms[rng.choice(len(moms), size=24, replace=False)]:
+        m = plane_wave_matrix(op, lat, p + shift)
+        ev = np.linalg.eigvals(m)
+        assert eig_mismatch(ev, closed_form_eigs(m0, p + shift)) < 1e-13
+        # e^{-i theta} on the crossing links would give p - theta / L
+        assert eig_mismatch(ev, closed_form_eigs(m0, p - shift)) > 1e-3
+
+
+@pytest.mark.parametrize("cstar,time_bc,theta", [(1, 0, (0.4, 0, 0.9, -0.6)), (2, 0, (-0.7, 0, 0, 1.1)),
+                                                 (1, 1, (0, 0, 0.5, 0.25))])
+def test_theta_identities_cstar(cstar, time_bc, theta):
+    """gamma5-hermiticity, the mirror identities D[U,z] T = T D[U*,z*] (the
+    conjugate field carrying -theta), the antisymmetry of C T D and the
+    antilinear symmetry S, with theta phases in the periodic directions of a
+    C* lattice."""
+    lat = Lattice((4, 4, 4, 4), cstar=cstar, time_bc=time_bc)
+    rng = synth.rng_from_seed(23)
+    u = synth.su3_links(rng, lat.Vphs, 0.8)
+    a = synth.u1_angles(rng, lat.Vphs, 0.5)
+    ue, ae = of.extend_gauge(lat, u, a)
+    kw = dict(q=2 / 3, csw=1.9, csw_u1=1.0)
+    th = np.array(theta)
+    op = od.build_operator(lat, ue, ae, 0.13, theta=th, **kw)
+    opc = od.build_operator(lat, np.conj(ue), -ae, 0.13, theta=-th, **kw)
+    psi, chi = rand_spinor(lat, 33), rand_spinor(lat, 34)
+    lhs = od.dot(chi, op.apply_g5(op.apply(psi)))
+    rhs = np.conj(od.dot(psi, op.apply_g5(op.apply(chi))))
+    assert abs(lhs - rhs) / (od.norm(chi) * od.norm(op.apply(psi))) < 1e-13
+    tr = lambda v: v[lat.mirror()]
+    assert rel(op.apply(tr(psi)), tr(opc.apply(psi))) < 1e-13
+    ctd = lambda o, v: np.einsum("st,xtc->xsc", G[0] @ G[2], tr(o.apply(v)))
+    anti = lambda o: abs(np.sum(chi * ctd(o, psi)) + np.sum(psi * ctd(o, chi))) / (
+        od.norm(chi) * od.norm(o.apply(psi)))
+    assert anti(op) < 1e-13
+    cinv = np.linalg.inv(G[0] @ G[2])
+    g5 = G[0] @ G[1] @ G[2] @ G[3]
+    sop = lambda v: tr(np.einsum("st,xtc->xsc", g5 @ cinv, np.conj(v)))
+    assert rel(op.apply(sop(psi)), sop(op.apply(psi))) < 1e-13
+    # the same phase on both halves breaks the antisymmetry of C T D
+    wrong = od.build_operator(lat, ue, ae, 0.13, **kw)
+    k = [m for m in range(4) if th[m] != 0][0]
+    cross = lat.coords[:, k] == lat.ext[k] - 1
+    wrong.w[cross, k] *= np.exp(1j * th[k])
+    wrong.wd = np.conj(np.swapaxes(wrong.w, -1, -2))
+    assert anti(wrong) > 1e-6
+
+
+def test_theta_rejected_where_undefined():
+    for cstar, time_bc, theta in [(1, 0, (0, 0.3, 0, 0)), (3, 0, (0, 0, 0, 0.2)), (0, 1, (0.1, 0, 0, 0))]:
+        lat = Lattice((4, 4, 4, 4), cstar=cstar, time_bc=time_bc)
+        with pytest.raises(ValueError):
+            of.theta_phases(lat, theta)
