@@ -107,33 +107,158 @@ def time_applies(field, q, prec, nrhs_bufs, steps, warmup):
     return ms
 
 
-def cpu_baseline(budget_s=15.0):
-    """The FP64 oracle's D on a bounded sample: 16 x 8^3 with C* (16,384
-    extended sites), repeated for about budget_s seconds."""
+CPU_DIMS = (16, 8, 8, 8)       # the bounded sample of the 64x32^3 C* workload for the oracle's D
+CFG2 = dict(dims=(64, 32, 32, 32), seed=20171002, eps=0.25, sigma=0.15, kappa=0.1365, q=-1 / 3, csw=1.9,
+            src_seed=1003)
+SAMPLE_SEED = 5
+
+
+def cfg2_sample_sites(V):
+    """Sampled extended sites of the 64x32^3 C* lattice at which the GPU's D
+    is compared with the oracle (and the first and last site)."""
+    rng = np.random.default_rng(SAMPLE_SEED)
+    return np.concatenate([rng.choice(V, 64, replace=False), [0, V - 1]])
+
+
+def _cpu_share():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _oracle_d_worker(args):
+    """One process: apply the oracle's D to its own source for budget_s
+    seconds (single-threaded numpy); returns (applications, seconds)."""
+    seed, budget_s = args
     from threadpoolctl import threadpool_limits
 
     from oracle import Lattice
     from oracle import dirac as od
     from oracle import fields as of
     from paper_1710_08839_amd import synth
-    dims = (16, 8, 8, 8)
-    lat = Lattice(dims, cstar=3)
-    u, a = synth.gauge_field(dims, 20171002, 0.25, 0.15)
-    ue, ae = of.extend_gauge(lat, u, a)
-    op = od.build_operator(lat, ue, ae, 0.1365, q=-1 / 3, csw=1.9)
-    x = synth.source(dims, 3, 1003)
     with threadpool_limits(limits=1):
+        lat = Lattice(CPU_DIMS, cstar=3)
+        u, a = synth.gauge_field(CPU_DIMS, 20171002, 0.25, 0.15)
+        ue, ae = of.extend_gauge(lat, u, a)
+        op = od.build_operator(lat, ue, ae, 0.1365, q=-1 / 3, csw=1.9)
+        x = synth.source(CPU_DIMS, 3, seed)
         op.apply(x)
-        n = 0
-        t0 = time.perf_counter()
+        n, t0 = 0, time.perf_counter()
         while time.perf_counter() - t0 < budget_s:
             op.apply(x)
             n += 1
+        return n, time.perf_counter() - t0, lat.V
+
+
+def cpu_baseline_child(out_npy, budget_s=8.0):
+    """The CPU leg, run in a child process that never touches the GPU: the
+    oracle's D timed on one core and on every core of the CPU share, the
+    per-site D at the 64x32^3 C* shape (clover term evaluated on the fly, as
+    the oracle's per-site form does), the even-odd GCR solve of the 8x8^3
+    periodic SU(3) workload, and the oracle's D at the sampled 64x32^3 sites
+    (saved to out_npy for the GPU error report)."""
+    import multiprocessing as mp
+
+    from threadpoolctl import threadpool_limits
+
+    from oracle import Lattice
+    from oracle import dirac as od
+    from oracle import fields as of
+    from oracle import solvers as osv
+    from paper_1710_08839_amd import synth
+    res = {"cpu_model": _cpu_model()}
+    ncores = _cpu_share()
+    ctx = mp.get_context("fork")
+    with ctx.Pool(1) as pool:
+        n1, t1, V = pool.map(_oracle_d_worker, [(1003, budget_s)])[0]
+    with ctx.Pool(ncores) as pool:
+        outs = pool.map(_oracle_d_worker, [(1003 + k, budget_s) for k in range(ncores)])
+    napp = sum(o[0] for o in outs)
+    wall = max(o[1] for o in outs)
+    gb1 = BYTES_PER_SITE[0] * V * n1 / t1 / 1e9
+    gbn = BYTES_PER_SITE[0] * V * napp / wall / 1e9
+    res["one_core"] = {"value": round(gb1, 4), "unit": "GB/s", "cores": 1,
+                       "msites_per_s": round(V * n1 / t1 / 1e6, 4), "applications": n1, "seconds": round(t1, 2)}
+    res["all_cores"] = {"value": round(gbn, 4), "unit": "GB/s", "cores": ncores,
+                        "msites_per_s": round(V * napp / wall / 1e6, 4), "applications": napp,
+                        "seconds": round(wall, 2)}
+    with threadpool_limits(limits=1):
+        # the 64x32^3 C* lattice: oracle D at sampled sites (error report and
+        # per-site cost with the clover term built on the fly)
+        c = CFG2
+        lat = Lattice(c["dims"], cstar=3)
+        u, a = synth.gauge_field(c["dims"], c["seed"], c["eps"], c["sigma"])
+        ue, ae = of.extend_gauge(lat, u, a)
+        del u, a
+        x = synth.source(c["dims"], 3, c["src_seed"])
+        sites = cfg2_sample_sites(lat.V)
+        kw = dict(q=c["q"], csw=c["csw"], csw_u1=1.0)
+        expect = od.apply_at_sites(lat, ue, ae, x, sites, c["kappa"], **kw)
+        np.save(out_npy, expect)
+        rng = np.random.default_rng(7)
+        probe = rng.choice(lat.V, 4096, replace=False)
+        t0 = time.perf_counter()
+        od.apply_at_sites(lat, ue, ae, x, probe, c["kappa"], **kw)
         dt = time.perf_counter() - t0
-    gbs = BYTES_PER_SITE[0] * lat.V * n / dt / 1e9
-    return {"value": round(gbs, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 oracle D on 16x8^3 C* (16384 extended sites), {n} applications in "
-                      f"{dt:.1f} s ({dt / n * 1e3:.1f} ms each, {lat.V * n / dt / 1e6:.3f} Msite/s)"}
+        res["cfg2_per_site"] = {"us_per_site": round(dt / len(probe) * 1e6, 2), "sites": len(probe), "cores": 1,
+                                "what": "oracle per-site D at 64x32^3 C* (hops + clover term built per site)"}
+        del ue, ae, x, lat
+        # the 8x8^3 periodic SU(3) even-odd GCR solve to 1e-10
+        d0 = (8, 8, 8, 8)
+        lat0 = Lattice(d0, cstar=0)
+        u0, _ = synth.gauge_field(d0, 20171000, 0.3)
+        ue0, _ = of.extend_gauge(lat0, u0, None)
+        op0 = od.build_operator(lat0, ue0, None, 0.124, csw=1.0)
+        eta0 = synth.source(d0, 0, 1000)
+        t0 = time.perf_counter()
+        psi0, it0 = osv.solve_eo(op0, eta0, 1e-10, nkv=16)
+        dt0 = time.perf_counter() - t0
+        r0 = od.norm(eta0 - op0.apply(psi0)) / od.norm(eta0)
+        res["eo_gcr_8x8c3"] = {"seconds": round(dt0, 3), "gcr_iterations": int(it0), "true_resid": float(r0),
+                               "cores": 1}
+    return res
+
+
+def cpu_baseline_run():
+    """Run the CPU leg in a child process (forked workers need a parent that
+    has not touched the GPU); returns (cpu_baseline record, oracle values at
+    the sampled 64x32^3 sites or None)."""
+    import subprocess
+    import tempfile
+    fd, path = tempfile.mkstemp(suffix=".npy")
+    os.close(fd)
+    try:
+        p = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-child", path],
+                           capture_output=True, text=True, timeout=900)
+        if p.returncode != 0:
+            log(f"cpu baseline child failed: {p.stderr[-2000:]}")
+            return None, None
+        res = json.loads(p.stdout.strip().splitlines()[-1])
+        expect = np.load(path)
+    finally:
+        os.unlink(path)
+    one, alln = res["one_core"], res["all_cores"]
+    rec = {"value": alln["value"], "unit": "GB/s", "cores": alln["cores"], "kind": "oracle",
+           "sample": f"FP64 numpy oracle D (stored clover term) on 16x8^3 C* (16384 extended sites), one "
+                     f"source per process in {alln['cores']} single-threaded processes for "
+                     f"{alln['seconds']} s: {alln['applications']} applications, {alln['msites_per_s']} Msite/s; "
+                     f"algorithmic bytes as for the GPU FP64 D without mirror fusion (1536 B/site)",
+           "cpu_model": res["cpu_model"], "one_core": one,
+           "cfg2_per_site": res["cfg2_per_site"], "eo_gcr_8x8c3": res["eo_gcr_8x8c3"]}
+    return rec, expect
 
 
 def solve_rates(ctx, nsrc, nsrc_fp64, dims=(48, 24, 24, 24)):
@@ -217,25 +342,79 @@ def single_solve(f, q, s, eta):
 
 def single_rhs_32x16(ctx):
     """32 x 16^3 with C* in x, y, z (eps 0.3, A ~ N(0, 0.15), kappa 0.124,
-    csw 1.0), one Gaussian source per charge: SAP-GCR with 4^4 blocks and an
-    FP32 or an FP64 inner solver."""
+    csw 1.0), periodic and open time, one Gaussian source per charge:
+    SAP-GCR with 4^4 blocks and an FP32 or an FP64 inner solver."""
     import torch
     from paper_1710_08839_amd import qxd, synth
     dims = (32, 16, 16, 16)
     u, a = synth.gauge_field(dims, 20171001, 0.3, 0.15)
-    f = qxd.Field(ctx, dims, u, a, cstar=3)
-    del u, a
     out = {}
-    for q, seed in ((2 / 3, 1001), (-1 / 3, 1002)):
-        eta = torch.from_numpy(synth.source(dims, 3, seed)).cuda()
-        for name, prec in (("f32_inner", qxd.F32), ("f64_inner", qxd.F64)):
-            s = qxd.solver(kind=qxd.SAP_GCR, tol=1e-10, nkv=24, ncy=4, nmr=4, inner_prec=prec)
-            r = single_solve(f, qxd.quark(0.124, q, 1.0, 1.0), s, eta)
-            out[f"q={q:+.3f} {name}"] = r
-            log(f"32x16^3 q={q:+.3f} {name}: {r['seconds']} s, outer {r['outer_iters']}, "
-                f"inner {r['inner_iters']}, resid {r['true_resid']:.2e}")
-    f.release()
+    for tbc, tname in ((0, "periodic"), (1, "open")):
+        f = qxd.Field(ctx, dims, u, a, cstar=3, time_bc=tbc)
+        for q, seed in ((2 / 3, 1001), (-1 / 3, 1002)):
+            eta = torch.from_numpy(synth.source(dims, 3, seed)).cuda()
+            for name, prec in (("f32_inner", qxd.F32), ("f64_inner", qxd.F64)):
+                s = qxd.solver(kind=qxd.SAP_GCR, tol=1e-10, nkv=24, ncy=4, nmr=4, inner_prec=prec)
+                r = single_solve(f, qxd.quark(0.124, q, 1.0, 1.0), s, eta)
+                out[f"{tname} q={q:+.3f} {name}"] = r
+                log(f"32x16^3 {tname} q={q:+.3f} {name}: {r['seconds']} s, outer {r['outer_iters']}, "
+                    f"inner {r['inner_iters']}, resid {r['true_resid']:.2e}")
+        f.release()
     return out
+
+
+def single_rhs_8x8(ctx):
+    """8 x 8^3 periodic SU(3) (eps 0.3, kappa 0.124, csw 1.0), one Gaussian
+    source: the plain FP64 even-odd GCR to 1e-10, the workload the oracle's
+    solve is timed on."""
+    import torch
+    from paper_1710_08839_amd import qxd, synth
+    dims = (8, 8, 8, 8)
+    u, _ = synth.gauge_field(dims, 20171000, 0.3)
+    f = qxd.Field(ctx, dims, u, None, cstar=0)
+    eta = torch.from_numpy(synth.source(dims, 0, 1000)).cuda()
+    r = single_solve(f, qxd.quark(0.124, 0.0, 1.0, 1.0), qxd.solver(kind=qxd.EO_GCR, tol=1e-10, nkv=16), eta)
+    f.release()
+    log(f"8x8^3 EO-GCR: {r['seconds']} s, {r['inner_iters']} iterations, resid {r['true_resid']:.2e}")
+    return {"fp64_eo_gcr": r}
+
+
+# zeros and poles of the rational approximation of the QCD2 / QCD3 runs
+# (Table 2 of the paper), for the multi-shift leg
+TABLE2_MU = [1.2383e+01, 4.8370e+00, 2.3515e+00, 1.1994e+00, 6.1927e-01, 3.2079e-01, 1.6632e-01, 8.6246e-02,
+             4.4718e-02, 2.3170e-02, 1.1973e-02, 6.1273e-03, 3.0301e-03, 1.3855e-03]
+
+
+def multishift_leg(f, iters=(20, 60)):
+    """Multi-shift CG on D^dag D^ of the 64 x 32^3 field with the 14 poles
+    mu_j^2 of Table 2 as shifts: two runs capped at iters[0] and iters[1]
+    iterations (no shift converges that early on this operator), timed with
+    wall clock around the synchronising calls; the difference over the extra
+    iterations is the cost of one iteration with all 14 shifts active."""
+    import torch
+    from paper_1710_08839_amd import qxd, synth
+    dims = f.lat.dims[:]
+    q = qxd.quark(CFG2["kappa"], CFG2["q"], CFG2["csw"], 1.0)
+    eta = torch.from_numpy(synth.source(tuple(dims), 3, CFG2["src_seed"])).cuda()
+    shifts = np.array(TABLE2_MU) ** 2
+    psi = torch.empty((len(shifts),) + tuple(eta.shape), dtype=eta.dtype, device="cuda")
+    f.multishift(q, shifts, eta, psi, tol=1e-10, maxiter=3, check=False)  # builds and tunes
+    t = []
+    for k in iters:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, info = f.multishift(q, shifts, eta, psi, tol=1e-10, maxiter=k, check=False)
+        t.append(time.perf_counter() - t0)
+    ms_it = (t[1] - t[0]) / (iters[1] - iters[0]) * 1e3
+    V = f.volume
+    # per iteration: the shifted update reads r, p, x_j, p_j and writes p,
+    # x_j, p_j (FP64 even-site spinors of 192 B per site)
+    upd = (3 + 4 * len(shifts)) * (V // 2) * 192
+    del psi, eta
+    log(f"multi-shift CG, 14 shifts: {ms_it:.2f} ms per iteration")
+    return {"shifts": len(shifts), "ms_per_iteration": round(ms_it, 3),
+            "update_bytes_per_iteration": upd,
+            "workload": "64x32^3 C*, q=-1/3, kappa=0.1365, csw=1.9, shifts mu_j^2 of Table 2 (14), FP64"}
 
 
 def single_rhs_64x32(f):
@@ -382,7 +561,13 @@ def main():
                     help="force a Dirac kernel variant (0: autotune), e.g. to profile the tuned one")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (profiler counter calibration)")
+    ap.add_argument("--no-multishift", action="store_true")
+    ap.add_argument("--cpu-child", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_child:
+        # the CPU leg's own process: it never touches the GPU
+        print(json.dumps(cpu_baseline_child(args.cpu_child)))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not part "
               f"of this build", file=sys.stderr)
@@ -430,6 +615,18 @@ def main():
                             "GFLOP/s": round(FLOPS_PER_SITE * V / (ms * 1e-3) / 1e9, 1),
                             "bytes_per_site": site_bytes(p, choice)}
 
+    # D at the sampled sites in every precision (API layout from the FP64
+    # source), compared with the oracle after the timed legs
+    sites = cfg2_sample_sites(V)
+    x_dev = torch.from_numpy(synth.source(dims, 3, CFG2["src_seed"])).cuda()
+    y_dev = torch.empty_like(x_dev)
+    dw_at_sites = {}
+    for p in precs:
+        field.apply(q, qxd.OP_D, p, x_dev, y_dev)
+        torch.cuda.synchronize()
+        dw_at_sites[PREC_NAME[p]] = y_dev[torch.from_numpy(sites).cuda()].cpu().numpy()
+    del x_dev, y_dev
+
     # the timed leg of the contract: K FP64 applications between barriers
     torch.cuda.synchronize()
     ms = time_applies(field, q, 0, 3, args.steps, args.warmup)
@@ -444,12 +641,16 @@ def main():
                               "link reads"}
     log(f"streaming ceiling: {stream_ceiling}")
 
+    multishift = None
+    if not args.no_multishift:
+        multishift = multishift_leg(field)
     single = None
     if not args.no_single:
         single = {"64x32^3": single_rhs_64x32(field)}
     field.release()
     if single is not None:
         single["32x16^3"] = single_rhs_32x16(ctx)
+        single["8x8^3"] = single_rhs_8x8(ctx)
 
     solves = None
     if not args.no_solve:
@@ -463,9 +664,17 @@ def main():
             serve[name] = serve_stream(ctx, args.serve_requests, args.serve_max_rhs, args.serve_rate, prec)
             log(f"serving {name}: p50 {serve[name]['p50_s']} s, p99 {serve[name]['p99_s']} s")
 
-    log("timing the oracle on the host")
-    cpu = None if args.no_cpu else cpu_baseline()
     ctx.close()
+    cpu, dw_error = None, None
+    if not args.no_cpu:
+        log("timing the oracle on the host (child process)")
+        cpu, expect = cpu_baseline_run()
+        if expect is not None:
+            dw_error = {k: float(np.linalg.norm(v - expect) / np.linalg.norm(expect))
+                        for k, v in dw_at_sites.items()}
+            dw_error["what"] = (f"|D_gpu - D_oracle| / |D_oracle| over {len(sites)} sampled sites of the "
+                                f"64x32^3 C* lattice, FP64 source, autotuned kernels; bars 1e-12 (f64), "
+                                f"1e-5 (f32), 1e-2 (f16s, bf16)")
 
     rec = {
         "metric": METRIC,
@@ -489,6 +698,8 @@ def main():
                      "kernel": kernel,
                      "bytes_per_launch": site_bytes(0, choice) * V},
         "dw": dw,
+        "dw_error_vs_oracle": dw_error,
+        "multishift": multishift,
         "stream_ceiling": stream_ceiling,
         "single_rhs": single,
         "solves": solves,

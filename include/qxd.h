@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define QXD_ABI_VERSION 1
+#define QXD_ABI_VERSION 2
 
 typedef enum {
   QXD_OK = 0,
@@ -72,13 +72,20 @@ typedef enum { QXD_F64 = 0, QXD_F32 = 1, QXD_F16S = 2, QXD_BF16 = 3 } qxd_prec;
 
 typedef enum {
   QXD_OP_D = 0,      /* full D on all of the extended lattice (Sec. 2.3)      */
-  QXD_OP_DHAT = 1,   /* D^ = D_ee - D_eo D_oo^-1 D_oe on even sites; odd
-                        sites of the output are set to 0 (Sec. 2.4)           */
+  QXD_OP_DHAT = 1,   /* D^ + i mu gamma5 on even sites, D^ = D_ee - D_eo
+                        D_oo^-1 D_oe (Sec. 2.4) and mu the quark's twisted
+                        mass (0: plain D^); odd sites of the output are 0    */
   QXD_OP_HOP = 2,    /* hopping part of D only (D minus its diagonal)         */
   QXD_OP_PAULI = 3,  /* diagonal part P(x) = 4 + m0 + dD_sw only              */
   QXD_OP_OOINV = 4,  /* D_oo^-1 on odd sites, even sites set to 0             */
-  QXD_OP_G5D = 5     /* gamma5 D (Hermitian: D is gamma5-hermitian, Sec. 2.3;
+  QXD_OP_G5D = 5,    /* gamma5 D (Hermitian: D is gamma5-hermitian, Sec. 2.3;
                         gamma5 = diag(1, 1, -1, -1) in the chiral basis)     */
+  QXD_OP_DHAT_DAG = 6, /* (D^ + i mu gamma5)^dag = gamma5 (D^ - i mu gamma5)
+                        gamma5 on even sites, odd sites 0                    */
+  QXD_OP_NORMAL = 7  /* (D^ + i mu gamma5)^dag (D^ + i mu gamma5) = D^dag D^ +
+                        mu^2 on even sites (Sec. 2.4: the operator of the
+                        twisted-mass regulator and of the rational
+                        approximation), odd sites 0                           */
 } qxd_op;
 
 #define QXD_NATIVE 1u  /* in/out are native-layout buffers of precision prec */
@@ -98,6 +105,18 @@ typedef struct {
   double q;       /* charge in units of e; q / q_el must be an integer       */
   double csw;     /* SU(3) clover coefficient                                */
   double csw_u1;  /* U(1) clover coefficient                                 */
+  double mu;      /* twisted mass of the even-odd operators QXD_OP_DHAT,
+                     QXD_OP_DHAT_DAG, QXD_OP_NORMAL and of the multi-shift
+                     solver and rational functions (Sec. 2.4); D itself and
+                     the D solvers do not use it                             */
+  double theta[4];/* fermion boundary phases psi(x + L_mu e_mu) =
+                     e^{i theta_mu} psi(x) in periodic directions (Sec. 2
+                     feature list), entering as e^{i theta_mu} on the links
+                     whose forward hop crosses the boundary; on a C* lattice
+                     the mirror half carries e^{-i theta_mu} (the orbifold
+                     conjugates every U(1) field).  theta_0 multiplies the
+                     antiperiodic sign of the time hop.  Must be 0 in C*
+                     directions and, with open time, for mu = 0 (QXD_EINVAL) */
 } qxd_quark;
 
 typedef enum { QXD_SOLVER_EO_GCR = 0, QXD_SOLVER_SAP_GCR = 1 } qxd_solver_kind;
@@ -185,8 +204,9 @@ qxd_status qxd_dirac_apply(qxd_field *field, const qxd_quark *quarks, int nquark
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
- * operation, arguments and results as qxd_dirac_apply, but the call performs
- * no hipMalloc, hipFree or other allocation.  Limits:
+ * operation, arguments and results as qxd_dirac_apply for the operators
+ * QXD_OP_D to QXD_OP_G5D, but the call performs no hipMalloc, hipFree or
+ * other allocation (QXD_OP_DHAT_DAG and QXD_OP_NORMAL: QXD_EINVAL).  Limits:
  *   - every quark's operator must already be built on this field in precision
  *     prec (an earlier qxd_dirac_apply or qxd_solve in that precision builds
  *     it); otherwise QXD_EINVAL and nothing is queued;
@@ -225,6 +245,37 @@ qxd_status qxd_dirac_apply_noalloc(qxd_field *field, const qxd_quark *quarks, in
 qxd_status qxd_solve(qxd_field *field, const qxd_quark *quarks, int nquark,
                      const qxd_solver *s, const double *eta_dev, double *psi_dev,
                      int nrhs, int use_guess, qxd_solve_info *info, void *stream);
+
+/* Multi-shift conjugate gradient (the paper's solver for the factors of the
+ * rational approximation, feature list of Sec. 2 and Table 2): solves
+ *     (D^dag D^ + mu^2 + shifts[j]) psi_j = eta_e,   j < nshift,
+ * on the even sites for one quark (mu its twisted mass, Sec. 2.4), all shifts
+ * in one Krylov space: CG on the smallest shift, the others from the
+ * collinear residuals.  FP64 throughout.  eta_dev: one API-layout FP64
+ * spinor (its odd sites are ignored); psi_dev: nshift API-layout FP64
+ * spinors, written with zero odd sites.  shifts >= 0, 1 <= nshift <= 64.
+ * Shift j stops once its residual |eta_e - (X + shift_j) psi_j| <= tol
+ * |eta_e| (X = D^dag D^ + mu^2); info (nshift entries, may be NULL) gets each
+ * shift's iterations and true FP64 residual.  QXD_ENOCONV if maxiter (0:
+ * 100000) ends first (iterates written).  Synchronises `stream`. */
+qxd_status qxd_multishift_solve(qxd_field *field, const qxd_quark *quark, const double *shifts, int nshift,
+                                double tol, int maxiter, const double *eta_dev, double *psi_dev,
+                                qxd_solve_info *info, void *stream);
+
+/* Rational function of the even-odd normal operator (Sec. 2.4):
+ *     out_e = A prod_{j<n} (X + nu_j^2) / (X + mu_j^2) eta_e,  X = D^dag D^ + mu^2
+ * (mu the quark's twisted mass), evaluated as A (eta_e + sum_j rho_j (X +
+ * mu_j^2)^-1 eta_e) with the partial-fraction residues rho_j and one
+ * multi-shift CG over the poles.  A whole approximation R (Table 2) or one
+ * frequency-splitting factor P_k (A = 1 and the zeros and poles of its index
+ * range) or a twisted-mass Hasenbusch ratio (n = 1) are all of this form.
+ * The mu_j must be distinct; 1 <= n <= 64.  tol, maxiter, info (n entries,
+ * one per pole) as for qxd_multishift_solve.  eta_dev, out_dev: API-layout
+ * FP64 spinors (odd sites of eta ignored, of out set to 0).  Synchronises
+ * `stream`. */
+qxd_status qxd_rational_apply(qxd_field *field, const qxd_quark *quark, double A, const double *nu,
+                              const double *mu, int n, double tol, int maxiter, const double *eta_dev,
+                              double *out_dev, qxd_solve_info *info, void *stream);
 
 /* Apply the SAP preconditioner M_SAP of the SAP_GCR solver (the Schwarz
  * preconditioner the paper's SAP-GCR is named after, abstract and Sec. 2):

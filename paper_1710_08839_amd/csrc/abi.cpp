@@ -122,13 +122,18 @@ size_t Field::op_bytes(int prec) const {
   return b;
 }
 
+Field::OpKey Field::op_key(const qxd_quark &q) const {
+  return OpKey{q.kappa, has_u1 ? q.q : 0.0, q.csw, has_u1 ? q.csw_u1 : 0.0,
+               q.theta[0], q.theta[1], q.theta[2], q.theta[3]};
+}
+
 size_t Field::pending_op_bytes(const qxd_quark *quarks, int n, int prec) {
   std::lock_guard<std::recursive_mutex> lk(mu);
   size_t b = 0;
-  std::vector<std::tuple<double, double, double, double>> seen;
+  std::vector<OpKey> seen;
   for (int k = 0; k < n; k++) {
     const qxd_quark &q = quarks[k];
-    auto key = std::make_tuple(q.kappa, has_u1 ? q.q : 0.0, q.csw, has_u1 ? q.csw_u1 : 0.0);
+    const OpKey key = op_key(q);
     if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
     seen.push_back(key);
     auto it = ops.find(key);
@@ -140,10 +145,30 @@ size_t Field::pending_op_bytes(const qxd_quark *quarks, int n, int prec) {
   return b;
 }
 
-qxd_status Field::get_op(const qxd_quark &q, int prec, Operator **out, hipStream_t st) {
-  if (!(q.kappa > 0.0) || !isfinite(q.kappa) || !isfinite(q.csw) || !isfinite(q.csw_u1) || !isfinite(q.q)) {
+// Quark parameters that the lattice admits: finite values, kappa > 0, theta
+// only in periodic directions (not C*, not open time).
+static qxd_status check_quark(const Field &f, const qxd_quark &q) {
+  bool fin = isfinite(q.kappa) && isfinite(q.csw) && isfinite(q.csw_u1) && isfinite(q.q) && isfinite(q.mu);
+  for (int m = 0; m < 4; m++) fin = fin && isfinite(q.theta[m]);
+  if (!fin || !(q.kappa > 0.0)) {
     set_error("quark parameters must be finite with kappa > 0");
     return QXD_EINVAL;
+  }
+  for (int m = 0; m < 4; m++) {
+    if (q.theta[m] == 0.0) continue;
+    const bool cstar_dir = m >= 1 && m <= f.lat.cstar;
+    if (cstar_dir || (m == 0 && f.lat.time_bc != 0)) {
+      set_error("theta[%d] must be 0: direction %d has %s boundaries", m, m, cstar_dir ? "C*" : "open");
+      return QXD_EINVAL;
+    }
+  }
+  return QXD_OK;
+}
+
+qxd_status Field::get_op(const qxd_quark &q, int prec, Operator **out, hipStream_t st) {
+  {
+    qxd_status cs = check_quark(*this, q);
+    if (cs != QXD_OK) return cs;
   }
   int qhat = 0;
   if (has_u1) {
@@ -154,7 +179,7 @@ qxd_status Field::get_op(const qxd_quark &q, int prec, Operator **out, hipStream
       return QXD_EINVAL;
     }
   }
-  auto key = std::make_tuple(q.kappa, has_u1 ? q.q : 0.0, q.csw, has_u1 ? q.csw_u1 : 0.0);
+  const OpKey key = op_key(q);
   auto it = ops.find(key);
   Operator *op;
   if (it == ops.end()) {
@@ -191,7 +216,7 @@ qxd_status Field::get_op(const qxd_quark &q, int prec, Operator **out, hipStream
     }
     QXD_HIP_CHECK(nop->wl[QXD_F64].ensure((size_t)36 * g.V * 16));
     QXD_HIP_CHECK(launch_fold_phase(g, links[QXD_F64].as<double2>(), angles[QXD_F64].as<double>(), qhat,
-                                    nop->wl[QXD_F64].as<double2>(), st));
+                                    q.theta, nop->wl[QXD_F64].as<double2>(), st));
     nop->ready[QXD_F64] = true;
     op = nop.get();
     ops[key] = std::move(nop);
@@ -217,7 +242,7 @@ qxd_status Field::get_op(const qxd_quark &q, int prec, Operator **out, hipStream
 Operator *Field::find_op(const qxd_quark &q, int prec) {
   std::lock_guard<std::recursive_mutex> lk(mu);
   if (!links_ready[prec]) return nullptr;
-  auto it = ops.find(std::make_tuple(q.kappa, has_u1 ? q.q : 0.0, q.csw, has_u1 ? q.csw_u1 : 0.0));
+  auto it = ops.find(op_key(q));
   if (it == ops.end() || !it->second->ready[prec]) return nullptr;
   return it->second.get();
 }
@@ -242,8 +267,21 @@ OpFields Field::op_fields_u(const Operator &op, int prec) const {
   return f;
 }
 
+// out_e = (D^ + i mu gamma5) in_e on the even half of full-lattice native
+// spinors (odd half of out untouched); tmp: an odd-half spinor.
+hipError_t schur_tm(Field *fd, const OpFields &f, int prec, double mu, SpinorArg in, SpinorArg out, void *tmp,
+                    hipStream_t st, bool may_tune) {
+  const Geom &g = fd->g;
+  SpinorArg t_o{tmp, g.Vh, g.Vh, g.rd}, none{nullptr, 0, 0, g.rd};
+  hipError_t e = launch_dirac(prec, DK_ODD, g, f, in, none, t_o, -0.5, st, may_tune);
+  if (e == hipSuccess) e = launch_dirac(prec, DK_EVEN, g, f, t_o, in, out, 0.5, st, may_tune);
+  if (e == hipSuccess && mu != 0.0)
+    e = launch_lincomb_sites(prec, out, out, 1.0, 0.0, false, in, 0.0, mu, true, 0, g.Vh, st);
+  return e;
+}
+
 // Apply `op` to one native spinor (full-lattice buffers).
-qxd_status apply_native(Field *fd, const Operator &op, qxd_op which, int prec, void *in, void *out,
+qxd_status apply_native(Field *fd, const Operator &op, double mu, qxd_op which, int prec, void *in, void *out,
                         hipStream_t st, void *dhat_tmp, bool may_tune) {
   const Geom &g = fd->g;
   OpFields f = fd->op_fields(op, prec);
@@ -266,9 +304,29 @@ qxd_status apply_native(Field *fd, const Operator &op, qxd_op which, int prec, v
         tmp = fd->workspace("dhat_tmp", spinor_bytes(prec, g.Vh), &e);
         QXD_HIP_CHECK(e);
       }
-      SpinorArg t_o{tmp, g.Vh, g.Vh, g.rd};
-      QXD_HIP_CHECK(launch_dirac(prec, DK_ODD, g, f, full_in, none, t_o, -0.5, st, mt));
-      QXD_HIP_CHECK(launch_dirac(prec, DK_EVEN, g, f, t_o, full_in, full_out, 0.5, st, mt));
+      QXD_HIP_CHECK(schur_tm(fd, f, prec, mu, full_in, full_out, tmp, st, mt));
+      QXD_HIP_CHECK(launch_zero_sites(prec, full_out, g.Vh, g.Vh, st));
+      break;
+    }
+    case QXD_OP_DHAT_DAG:
+    case QXD_OP_NORMAL: {
+      hipError_t e;
+      void *tmp = fd->workspace("dhat_tmp", spinor_bytes(prec, g.Vh), &e);
+      QXD_HIP_CHECK(e);
+      void *t2 = fd->workspace("normal_tmp", spinor_bytes(prec, g.V), &e);
+      QXD_HIP_CHECK(e);
+      SpinorArg full_t2{t2, g.V, 0, g.rd};
+      const double m = mu;
+      SpinorArg src = full_in;
+      if (which == QXD_OP_NORMAL) {  // t2 = (D^ + i mu g5) in
+        QXD_HIP_CHECK(schur_tm(fd, f, prec, m, full_in, full_t2, tmp, st, mt));
+        src = full_t2;
+      }
+      // (D^ + i mu g5)^dag src = g5 (D^ - i mu g5) g5 src: out = g5 src,
+      // out = (D^ - i mu g5) out through t2, out = g5 out
+      QXD_HIP_CHECK(launch_lincomb_sites(prec, full_out, src, 1.0, 0.0, true, none, 0, 0, false, 0, g.Vh, st));
+      QXD_HIP_CHECK(schur_tm(fd, f, prec, -m, full_out, full_t2, tmp, st, mt));
+      QXD_HIP_CHECK(launch_lincomb_sites(prec, full_out, full_t2, 1.0, 0.0, true, none, 0, 0, false, 0, g.Vh, st));
       QXD_HIP_CHECK(launch_zero_sites(prec, full_out, g.Vh, g.Vh, st));
       break;
     }
@@ -536,7 +594,7 @@ qxd_status qxd_dirac_apply(qxd_field *field, const qxd_quark *quarks, int nquark
                            qxd_prec prec, const void *in_dev, void *out_dev, int nrhs, unsigned flags,
                            void *stream) {
   if (!field || !quarks || !in_dev || !out_dev || nquark < 1 || nrhs < 1 || nrhs % nquark ||
-      !valid_prec(prec) || op < QXD_OP_D || op > QXD_OP_G5D || (flags & ~QXD_NATIVE)) {
+      !valid_prec(prec) || op < QXD_OP_D || op > QXD_OP_NORMAL || (flags & ~QXD_NATIVE)) {
     set_error("invalid arguments to qxd_dirac_apply");
     return QXD_EINVAL;
   }
@@ -567,12 +625,13 @@ qxd_status qxd_dirac_apply(qxd_field *field, const qxd_quark *quarks, int nquark
     qxd_status s = field->get_op(quarks[r / per], prec, &o, st);
     if (s != QXD_OK) return s;
     if (native) {
-      s = apply_native(field, *o, op, prec, (char *)in_dev + r * nb, (char *)out_dev + r * nb, st);
+      s = apply_native(field, *o, quarks[r / per].mu, op, prec, (char *)in_dev + r * nb, (char *)out_dev + r * nb,
+                       st);
     } else {
       const double *src = (const double *)in_dev + (int64_t)r * 24 * field->g.V;
       double *dst = (double *)out_dev + (int64_t)r * 24 * field->g.V;
       QXD_HIP_CHECK(launch_pack(prec, field->g, src, nin, 1, st));
-      s = apply_native(field, *o, op, prec, nin, nout, st);
+      s = apply_native(field, *o, quarks[r / per].mu, op, prec, nin, nout, st);
       if (s == QXD_OK) QXD_HIP_CHECK(launch_unpack(prec, field->g, nout, dst, 1, st));
     }
     if (s != QXD_OK) return s;
@@ -633,13 +692,13 @@ qxd_status qxd_dirac_apply_noalloc(qxd_field *field, const qxd_quark *quarks, in
     Operator *o = field->find_op(quarks[r / per], prec);
     qxd_status s;
     if (native) {
-      s = apply_native(field, *o, op, prec, (char *)const_cast<void *>(in_dev) + r * nb, (char *)out_dev + r * nb,
-                       st, tmp, false);
+      s = apply_native(field, *o, quarks[r / per].mu, op, prec, (char *)const_cast<void *>(in_dev) + r * nb,
+                       (char *)out_dev + r * nb, st, tmp, false);
     } else {
       const double *src = (const double *)in_dev + (int64_t)r * 24 * g.V;
       double *dst = (double *)out_dev + (int64_t)r * 24 * g.V;
       QXD_HIP_CHECK(launch_pack(prec, g, src, nin, 1, st));
-      s = apply_native(field, *o, op, prec, nin, nout, st, tmp, false);
+      s = apply_native(field, *o, quarks[r / per].mu, op, prec, nin, nout, st, tmp, false);
       if (s == QXD_OK) QXD_HIP_CHECK(launch_unpack(prec, g, nout, dst, 1, st));
     }
     if (s != QXD_OK) return s;
@@ -657,6 +716,43 @@ qxd_status qxd_solve(qxd_field *field, const qxd_quark *quarks, int nquark, cons
   std::lock_guard<std::recursive_mutex> lk(field->mu);
   QXD_HIP_CHECK(hipSetDevice(field->ctx->device));
   return solve(field, quarks, nquark, *s, eta_dev, psi_dev, nrhs, use_guess, info, (hipStream_t)stream);
+}
+
+qxd_status qxd_multishift_solve(qxd_field *field, const qxd_quark *quark, const double *shifts, int nshift,
+                                double tol, int maxiter, const double *eta_dev, double *psi_dev,
+                                qxd_solve_info *info, void *stream) {
+  if (!field || !quark || !shifts || !eta_dev || !psi_dev || nshift < 1 || nshift > 64 || !(tol > 0.0) ||
+      tol >= 1.0 || maxiter < 0) {
+    set_error("invalid arguments to qxd_multishift_solve");
+    return QXD_EINVAL;
+  }
+  for (int j = 0; j < nshift; j++)
+    if (!(shifts[j] >= 0.0) || !isfinite(shifts[j])) {
+      set_error("shift %d must be finite and >= 0", j);
+      return QXD_EINVAL;
+    }
+  std::lock_guard<std::recursive_mutex> lk(field->mu);
+  QXD_HIP_CHECK(hipSetDevice(field->ctx->device));
+  return multishift_solve(field, *quark, shifts, nshift, tol, maxiter, eta_dev, psi_dev, info,
+                          (hipStream_t)stream);
+}
+
+qxd_status qxd_rational_apply(qxd_field *field, const qxd_quark *quark, double A, const double *nu,
+                              const double *mu, int n, double tol, int maxiter, const double *eta_dev,
+                              double *out_dev, qxd_solve_info *info, void *stream) {
+  if (!field || !quark || !nu || !mu || !eta_dev || !out_dev || n < 1 || n > 64 || !isfinite(A) ||
+      !(tol > 0.0) || tol >= 1.0 || maxiter < 0) {
+    set_error("invalid arguments to qxd_rational_apply");
+    return QXD_EINVAL;
+  }
+  for (int j = 0; j < n; j++)
+    if (!isfinite(nu[j]) || !isfinite(mu[j])) {
+      set_error("zeros and poles must be finite");
+      return QXD_EINVAL;
+    }
+  std::lock_guard<std::recursive_mutex> lk(field->mu);
+  QXD_HIP_CHECK(hipSetDevice(field->ctx->device));
+  return rational_apply(field, *quark, A, nu, mu, n, tol, maxiter, eta_dev, out_dev, info, (hipStream_t)stream);
 }
 
 qxd_status qxd_sap_apply(qxd_field *field, const qxd_quark *quark, qxd_prec prec, int ncy, int nmr,

@@ -264,16 +264,30 @@ __global__ void unpack_kernel(Geom g, const void *native, double *api, size_t by
     }
 }
 
-// W(x,mu) = U(x,mu) exp(i qhat A(x,mu)) in FP64; one thread per (site, mu)
-__global__ void fold_phase_kernel(Geom g, const double2 *links, const double *angles, int qhat,
+struct Theta {
+  double t[4];
+};
+
+// W(x,mu) = U(x,mu) exp(i qhat A(x,mu)) in FP64, times exp(+-i theta_mu) on
+// the links whose forward hop crosses the boundary of direction mu (the sign
+// is - on the C* mirror half, x1 >= L1 of an extended direction 1); one
+// thread per (site, mu)
+__global__ void fold_phase_kernel(Geom g, const double2 *links, const double *angles, int qhat, Theta th,
                                   double2 *w) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 4 * (int64_t)g.V) return;
   int mu = (int)(t / g.V);
   uint32_t i = (uint32_t)(t - (int64_t)mu * g.V);
   const uint32_t el = g.rd.base(i, 36);
+  double phase = qhat * angles[g.rd.base(i, 4) + mu * g.Vbh];
+  if (th.t[mu] != 0.0) {
+    const Site s = decode(g, (int)i);
+    int x[4];
+    global_coords(g, s, x);
+    if (x[mu] == g.N[mu] - 1) phase += (g.N[1] != g.L1 && x[1] >= g.L1) ? -th.t[mu] : th.t[mu];
+  }
   double sn, cs;
-  sincos(qhat * angles[g.rd.base(i, 4) + mu * g.Vbh], &sn, &cs);
+  sincos(phase, &sn, &cs);
   cx<double> z{cs, sn};
   for (int k = 0; k < 9; k++) {
     double2 u = links[el + (mu * 9 + k) * g.Vbh];
@@ -337,9 +351,60 @@ hipError_t launch_zero_sites(int prec, SpinorArg v, int64_t first, int64_t count
 }
 
 hipError_t launch_fold_phase(const Geom &g, const double2 *links, const double *angles, int qhat,
-                             double2 *w, hipStream_t st) {
-  fold_phase_kernel<<<grid_for(4 * (int64_t)g.V, 256), 256, 0, st>>>(g, links, angles, qhat, w);
+                             const double theta[4], double2 *w, hipStream_t st) {
+  Theta th;
+  for (int m = 0; m < 4; m++) th.t[m] = theta ? theta[m] : 0.0;
+  fold_phase_kernel<<<grid_for(4 * (int64_t)g.V, 256), 256, 0, st>>>(g, links, angles, qhat, th, w);
   return hipGetLastError();
+}
+
+namespace {
+// out = ca G_a a + cb G_b b per site (G = gamma5 or 1), one thread per site
+template <int P>
+__global__ void lincomb_sites_kernel(Spinor<P> out, Spinor<P> a, cx<typename St<P>::comp_t> ca, int g5a,
+                                     Spinor<P> b, cx<typename St<P>::comp_t> cb, int g5b, int64_t first,
+                                     int64_t count) {
+  using T = typename St<P>::comp_t;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  const int64_t i = first + k;
+  cx<T> va[4][3], res[4][3];
+  load_spinor<P, T>(a, i, va);
+  for (int s = 0; s < 4; s++)
+    for (int c = 0; c < 3; c++) res[s][c] = ca * ((g5a && s >= 2) ? -va[s][c] : va[s][c]);
+  if (b.data) {
+    cx<T> vb[4][3];
+    load_spinor<P, T>(b, i, vb);
+    for (int s = 0; s < 4; s++)
+      for (int c = 0; c < 3; c++) res[s][c] = res[s][c] + cb * ((g5b && s >= 2) ? -vb[s][c] : vb[s][c]);
+  }
+  store_spinor<P, T>(out, i, res);
+}
+
+template <int P>
+hipError_t lincomb_p(SpinorArg out, SpinorArg a, double car, double cai, bool g5a, SpinorArg b, double cbr,
+                     double cbi, bool g5b, int64_t first, int64_t count, hipStream_t st) {
+  using T = typename St<P>::comp_t;
+  Spinor<P> vo = spinor_view<P>(out.ptr, out.sites, out.off, out.rd);
+  Spinor<P> va = spinor_view<P>(a.ptr, a.sites, a.off, a.rd);
+  Spinor<P> vb = b.ptr ? spinor_view<P>(b.ptr, b.sites, b.off, b.rd) : Spinor<P>{nullptr, nullptr, 0, out.rd};
+  lincomb_sites_kernel<P><<<grid_for(count, 256), 256, 0, st>>>(vo, va, cx<T>{(T)car, (T)cai}, g5a, vb,
+                                                                cx<T>{(T)cbr, (T)cbi}, g5b, first, count);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_lincomb_sites(int prec, SpinorArg out, SpinorArg a, double ca_re, double ca_im, bool g5a,
+                                SpinorArg b, double cb_re, double cb_im, bool g5b, int64_t first, int64_t count,
+                                hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  switch (prec) {
+    case QXD_F64: return lincomb_p<QXD_F64>(out, a, ca_re, ca_im, g5a, b, cb_re, cb_im, g5b, first, count, st);
+    case QXD_F32: return lincomb_p<QXD_F32>(out, a, ca_re, ca_im, g5a, b, cb_re, cb_im, g5b, first, count, st);
+    case QXD_F16S: return lincomb_p<QXD_F16S>(out, a, ca_re, ca_im, g5a, b, cb_re, cb_im, g5b, first, count, st);
+    case QXD_BF16: return lincomb_p<QXD_BF16>(out, a, ca_re, ca_im, g5a, b, cb_re, cb_im, g5b, first, count, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_orbifold(const Geom &g, const double *u_phs, const double *a_phs, double2 *links,

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -47,7 +48,7 @@ struct DevBuf {
 // One Dirac operator (one quark flavour) on one gauge field: its Pauli term
 // and the inverse odd-site blocks, in FP64 and in each storage precision.
 struct Operator {
-  qxd_quark quark;
+  qxd_quark quark;         // the quark that built it (its mu is not part of the operator)
   int qhat = 0;
   int users = 0;           // solver slots holding it (guarded by the field's mutex)
   uint64_t last_use = 0;   // for least-recently-used eviction
@@ -66,10 +67,12 @@ struct Field {
   DevBuf links[4];   // indexed by qxd_prec (links[F64] is the master copy)
   DevBuf angles[4];  // F64: double, others: float (same buffer for F32/F16S/BF16)
   bool links_ready[4] = {false, false, false, false};
-  // operators by (kappa, q, c_sw, c_sw^U(1)); at most kMaxCachedOps are kept
-  // once unused (a serve stream draws a new kappa per request, and at 64x32^3
-  // one operator holds several GB)
-  std::map<std::tuple<double, double, double, double>, std::unique_ptr<Operator>> ops;
+  // operators by (kappa, q, c_sw, c_sw^U(1), theta[4]); at most
+  // kMaxCachedOps are kept once unused (a serve stream draws a new kappa per
+  // request, and at 64x32^3 one operator holds several GB)
+  using OpKey = std::array<double, 8>;
+  OpKey op_key(const qxd_quark &q) const;
+  std::map<OpKey, std::unique_ptr<Operator>> ops;
   uint64_t op_clock = 0;
   static constexpr size_t kMaxCachedOps = 4;
   // device bytes one operator of this field holds in FP64 plus precision prec

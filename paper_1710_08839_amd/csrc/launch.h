@@ -23,9 +23,11 @@ hipError_t launch_pauli_build(const Geom &g, const double2 *links, const double 
 hipError_t launch_pauli_invert(const Geom &g, const double2 *pauli, double2 *pinv,
                                int *bad, hipStream_t st);
 
-// W = U exp(i qhat A) in FP64 ([4][9][V] pairs).
+// W = U exp(i qhat A) in FP64 ([4][9][V] pairs), times the fermion boundary
+// phase e^{+-i theta_mu} on the links whose forward hop crosses the boundary
+// of direction mu (+ on the physical half, - on the C* mirror half).
 hipError_t launch_fold_phase(const Geom &g, const double2 *links, const double *angles, int qhat,
-                             double2 *w, hipStream_t st);
+                             const double theta[4], double2 *w, hipStream_t st);
 
 // FP64 pairs -> storage precision `prec` (n pairs).
 // FP64 block-major field with K pairs per site over `sites` sites -> the
@@ -45,6 +47,12 @@ struct SpinorArg;
 hipError_t launch_zero_sites(int prec, SpinorArg v, int64_t first, int64_t count, hipStream_t st);
 // v = gamma5 v on sites [first, first + count), in place
 hipError_t launch_g5_sites(int prec, SpinorArg v, int64_t first, int64_t count, hipStream_t st);
+// out = ca G_a a + cb G_b b on sites [first, first + count), G = gamma5 if
+// the flag is set else 1, complex coefficients; b may be null (cb ignored);
+// out may be a or b (site-local)
+hipError_t launch_lincomb_sites(int prec, SpinorArg out, SpinorArg a, double ca_re, double ca_im, bool g5a,
+                                SpinorArg b, double cb_re, double cb_im, bool g5b, int64_t first, int64_t count,
+                                hipStream_t st);
 
 // ---- Dirac operator (dirac.hip) -----------------------------------------
 struct OpFields {

@@ -14,7 +14,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libqxd.so"
 
 F64, F32, F16S, BF16 = 0, 1, 2, 3
 PREC = {"f64": F64, "f32": F32, "f16": F16S, "f16s": F16S, "bf16": BF16}
-OP_D, OP_DHAT, OP_HOP, OP_PAULI, OP_OOINV, OP_G5D = 0, 1, 2, 3, 4, 5
+OP_D, OP_DHAT, OP_HOP, OP_PAULI, OP_OOINV, OP_G5D, OP_DHAT_DAG, OP_NORMAL = 0, 1, 2, 3, 4, 5, 6, 7
 NATIVE = 1
 EO_GCR, SAP_GCR = 0, 1
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ENOCONV", -4: "EFLOAT", -5: "EDEVICE",
@@ -34,7 +34,7 @@ class Lattice(ctypes.Structure):
 
 class Quark(ctypes.Structure):
     _fields_ = [("kappa", ctypes.c_double), ("q", ctypes.c_double), ("csw", ctypes.c_double),
-                ("csw_u1", ctypes.c_double)]
+                ("csw_u1", ctypes.c_double), ("mu", ctypes.c_double), ("theta", ctypes.c_double * 4)]
 
 
 class Solver(ctypes.Structure):
@@ -79,6 +79,10 @@ SIGNATURES = {
     "qxd_solve": ([_VP, ctypes.POINTER(Quark), _I, ctypes.POINTER(Solver), _VP, _VP, _I, _I,
                    ctypes.POINTER(SolveInfo), _VP], _I),
     "qxd_sap_apply": ([_VP, ctypes.POINTER(Quark), _I, _I, _I, _VP, _VP, _I, _VP], _I),
+    "qxd_multishift_solve": ([_VP, ctypes.POINTER(Quark), _VP, _I, _D, _I, _VP, _VP, ctypes.POINTER(SolveInfo),
+                              _VP], _I),
+    "qxd_rational_apply": ([_VP, ctypes.POINTER(Quark), _D, _VP, _VP, _I, _D, _I, _VP, _VP,
+                            ctypes.POINTER(SolveInfo), _VP], _I),
     "qxd_serve_start": ([_VP, _SZ, _I], _I),
     "qxd_serve_submit": ([_VP, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], _I),
     "qxd_serve_poll": ([_VP, ctypes.c_uint64, ctypes.POINTER(Result)], _I),
@@ -162,8 +166,10 @@ def step_graph_counts():
     return c.value, r.value
 
 
-def quark(kappa, q=0.0, csw=0.0, csw_u1=1.0):
-    return Quark(kappa, q, csw, csw_u1)
+def quark(kappa, q=0.0, csw=0.0, csw_u1=1.0, mu=0.0, theta=(0.0, 0.0, 0.0, 0.0)):
+    """Quark parameters: hopping parameter, charge, clover coefficients,
+    twisted mass of the even-odd normal operators, fermion boundary phases."""
+    return Quark(kappa, q, csw, csw_u1, mu, (ctypes.c_double * 4)(*theta))
 
 
 def solver(kind=SAP_GCR, tol=1e-10, maxiter=0, nkv=0, ncy=0, nmr=0, inner_prec=F32, inner_tol=0.0,
@@ -266,6 +272,29 @@ class Field:
         st = lib().qxd_solve(self.h, arr, len(qs), ctypes.byref(s), _ptr(eta), _ptr(psi), nrhs,
                              int(use_guess), info, _stream(stream))
         if check and st not in (0,):
+            _check(st)
+        return st, list(info)
+
+    def multishift(self, q, shifts, eta, psi, tol=1e-10, maxiter=0, stream=None, check=True):
+        """(D^dag D^ + mu^2 + shifts[j]) psi[j] = eta on the even sites; psi
+        holds len(shifts) API-layout spinors.  Returns (status, infos)."""
+        sh = np.ascontiguousarray(shifts, dtype=np.float64)
+        info = (SolveInfo * len(sh))()
+        st = lib().qxd_multishift_solve(self.h, ctypes.byref(q), sh.ctypes.data, len(sh), float(tol), int(maxiter),
+                                        _ptr(eta), _ptr(psi), info, _stream(stream))
+        if check and st != 0:
+            _check(st)
+        return st, list(info)
+
+    def rational(self, q, A, nu, mu, eta, out, tol=1e-10, maxiter=0, stream=None, check=True):
+        """out = A prod_j (X + nu_j^2) / (X + mu_j^2) eta, X = D^dag D^ +
+        q.mu^2, on the even sites.  Returns (status, infos per pole)."""
+        nu = np.ascontiguousarray(nu, dtype=np.float64)
+        mu = np.ascontiguousarray(mu, dtype=np.float64)
+        info = (SolveInfo * len(mu))()
+        st = lib().qxd_rational_apply(self.h, ctypes.byref(q), float(A), nu.ctypes.data, mu.ctypes.data, len(mu),
+                                      float(tol), int(maxiter), _ptr(eta), _ptr(out), info, _stream(stream))
+        if check and st != 0:
             _check(st)
         return st, list(info)
 

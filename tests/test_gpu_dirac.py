@@ -134,7 +134,7 @@ def test_apply_rejects_unknown_operator(case):
     from paper_1710_08839_amd import qxd
     x = to_dev(case.source(23))
     y = torch.empty_like(x)
-    for op in (-1, qxd.OP_G5D + 1):
+    for op in (-1, qxd.OP_NORMAL + 1):
         with pytest.raises(qxd.QxdError):
             case.field.apply(case.quark, op, 0, x, y)
 
