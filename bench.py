@@ -72,7 +72,8 @@ def kernel_name(choice, prec):
         return "dirac_kernel (not tuned)"
     g, lds, nt = choice & 15, bool(choice & 16), bool(choice & 32)
     if lds:
-        return (f"dirac_lds_kernel<{prec}, 0, {g}, {'true' if nt else 'false'}>"
+        name = "dirac_wave_kernel" if choice & 128 else "dirac_lds_kernel"
+        return (f"{name}<{prec}, 0, {g}, {'true' if nt else 'false'}>"
                 + (" (mirror-fused links)" if choice & 64 else ""))
     return f"dirac_kernel<{prec}, 0, {g}>"
 _T0 = time.perf_counter()

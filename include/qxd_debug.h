@@ -24,8 +24,10 @@ extern "C" {
  * where a block does not fit one work-group), plus 32 for non-temporal Pauli
  * and output streams, plus 64 for mirror-fused link reads on C* lattices
  * (links of the mirror half read at the physical partner and conjugated,
- * Sec. 2.1; both with the LDS-staged variant only); 0 returns to the
- * autotuner.
+ * Sec. 2.1), plus 128 for wavefront-uniform addressing on 4^4 blocks (the
+ * neighbour blocks, boundary signs and C* shifts of each hop computed once
+ * per wavefront; ignored on other block shapes); 32, 64 and 128 with the
+ * LDS-staged variant only; 0 returns to the autotuner.
  * Process-wide; not synchronised with applications in flight on other
  * threads.  QXD_EINVAL for any other value. */
 qxd_status qxd_debug_set_dirac_variant(int choice);

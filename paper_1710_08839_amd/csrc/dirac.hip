@@ -9,6 +9,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <vector>
 
 #include "dirac_site.h"
 #include "launch.h"
@@ -20,6 +21,7 @@ namespace {
 constexpr int LDS_VARIANT = 16;
 constexpr int NT_VARIANT = 32;
 constexpr int MIRROR_VARIANT = 64;
+constexpr int WAVE_VARIANT = 128;
 
 template <int P, int KIND, int GROUP>
 __global__ void __launch_bounds__(256) dirac_kernel(Geom g, const typename St<P>::pair_t *links,
@@ -231,12 +233,219 @@ __global__ void __launch_bounds__(256) dirac_lds_kernel(Geom g, const typename S
   }
 }
 
+
+// The LDS-staged kernel for 4^4 lattice blocks with wavefront-uniform
+// addressing.  A wavefront then lies inside one block and one parity (128
+// sites of each parity per block, 64 lanes per wavefront), so everything a
+// hop needs beyond the lane's local coordinates is the same for the whole
+// wavefront and is computed once in scalar registers: the block across the
+// face in direction (mu, dir) with its wrap, the fermion sign of the time
+// boundary and the C* shift in directions 2 and 3 (Sec. 2.1), the block
+// runs of the neighbour spinors and of the links, and the physical partner
+// block for mirror-fused link reads.  A lane finds its neighbour by adding
+// +-stride_mu to its local lexicographic index (wrapping across the face),
+// with no division.  Neighbour spinors read from memory are loaded as stored
+// and the FP16 site scale is folded into the hop's sign.  Same results as
+// dirac_lds_kernel up to the order of additions.
+template <int P, int KIND, int GROUP, bool NT>
+__global__ void __launch_bounds__(256) dirac_wave_kernel(Geom g, const typename St<P>::pair_t *links,
+                                                         const typename St<P>::pair_t *pauli,
+                                                         const typename St<P>::pair_t *pinv,
+                                                         Spinor<P> in, Spinor<P> self, Spinor<P> out,
+                                                         typename St<P>::comp_t c, int mb) {
+  using T = typename St<P>::comp_t;
+  using C = typename St<P>::comp_t;
+  constexpr int W = VW<P>;
+  constexpr int R = 128;  // sites of one parity of a 4^4 block
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T> *lds = (cx<T> *)smem_raw;
+  constexpr bool half = KIND == DK_ODD || KIND == DK_EVEN || KIND == DK_EVEN_ID;
+  constexpr int per_block = half ? R : 2 * R;
+  const int bpw = blockDim.x / per_block;
+  const int ns = bpw * per_block;
+  const int wg = xcd_order(blockIdx.x, gridDim.x);
+  const int lb = (int)threadIdx.x / per_block;
+  const int r = (int)threadIdx.x - lb * per_block;
+  const int lblk = wg * bpw + lb;
+  const bool valid = lblk < g.nblocks;
+  const int n23 = g.nb[2] * g.nb[3];
+  int blk = lblk;
+  if (mb) {
+    const int m = lblk >> 1, q = m / n23;
+    blk = ((q / mb) * g.nb[1] + q % mb + (lblk & 1) * mb) * n23 + (m - q * n23);
+  }
+  blk = __builtin_amdgcn_readfirstlane(blk);
+  const int par = half ? (KIND == DK_ODD ? 1 : 0) : __builtin_amdgcn_readfirstlane(r >> 7);
+  const int h = r & (R - 1);
+  const int i = par * g.Vh + blk * R + h;
+  constexpr bool pauli_first = KIND == DK_FULL || KIND == DK_PAULI || KIND == DK_EVEN;
+  const bool self_in_lds = !half && self.data == in.data && self.off == in.off;
+  cx<T> res[4][3];
+  if (valid) {
+    const int spar = half ? 1 - par : par;
+    cx<T> v[4][3];
+    load_spinor<P, T>(in, (int64_t)spar * g.Vh + (int64_t)blk * R + h, v);
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int b = 0; b < 3; b++) lds[(a * 3 + b) * ns + threadIdx.x] = v[a][b];
+    if constexpr (pauli_first) {
+      if (!self_in_lds) load_spinor<P, T>(self, i, v);
+      pauli_mul<P, T, NT>(pauli, g, i, v, res);
+    }
+  }
+  __syncthreads();
+  if (!valid) return;
+  const int base = lb * per_block;
+  if constexpr (!pauli_first) {
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int b = 0; b < 3; b++) res[a][b] = {0, 0};
+  }
+  if (KIND != DK_PAULI) {
+    // the lane's local coordinates in its 4^4 block and its local index
+    const int q = h >> 1;
+    const int y2 = q & 3, y1 = (q >> 2) & 3, y0 = q >> 4;
+    const int y3 = 2 * (h & 1) + ((par + y0 + y1 + y2) & 1);
+    const int l = (y0 << 6) | (y1 << 4) | (y2 << 2) | y3;
+    const uint32_t ypk = pack4(y0, y1, y2, y3);
+    // the block's coordinates (wavefront-uniform)
+    int bb = blk;
+    const int B3 = bb % g.nb[3];
+    bb /= g.nb[3];
+    const int B2 = bb % g.nb[2];
+    bb /= g.nb[2];
+    const int B1 = bb % g.nb[1];
+    const int B0 = bb / g.nb[1];
+    const uint32_t Bpk = pack4(B0, B1, B2, B3);
+    const int npar = 1 - par;
+    const int in_run0 = (int)(in.off / R);
+    const uint32_t mshift = (uint32_t)mb * (uint32_t)n23;  // block-index offset of a mirror block's partner
+#pragma unroll 1
+    for (int k0 = 0; k0 < 8; k0 += GROUP) {
+#pragma unroll
+      for (int k = k0; k < k0 + GROUP; k++) {
+        const int mu = k >> 1, dir = ((k & 1) ^ (half ? 0 : par)) ? -1 : 1;
+        // wavefront-uniform: the block across the face, sign and C* shift
+        int nb_mu = (int)((Bpk >> (8 * mu)) & 0xff) + dir;
+        const int nbm = (int)((g.nbpk >> (8 * mu)) & 0xff);
+        int sg = 1;
+        uint32_t nBpk = Bpk;
+        bool wrap = false;
+        if (nb_mu == nbm) {
+          nb_mu = 0;
+          wrap = true;
+        } else if (nb_mu < 0) {
+          nb_mu = nbm - 1;
+          wrap = true;
+        }
+        nBpk = (nBpk & ~(0xffu << (8 * mu))) | ((uint32_t)nb_mu << (8 * mu));
+        if (wrap) {
+          if (mu == 0) {
+            sg = g.time_bc == 0 ? -1 : 0;
+          } else if ((g.shift_mask >> mu) & 1) {
+            int b1 = (int)((nBpk >> 8) & 0xff) + g.L1b;
+            if (b1 >= g.nb[1]) b1 -= g.nb[1];
+            nBpk = (nBpk & ~0xff00u) | ((uint32_t)b1 << 8);
+          }
+        }
+        const int nB1 = (int)((nBpk >> 8) & 0xff);
+        const int nbk = ((int)(nBpk & 0xff) * g.nb[1] + nB1) * n23 + (int)((nBpk >> 16) & 0xff) * g.nb[3] +
+                        (int)(nBpk >> 24);
+        // the lane's neighbour: inside the block (LDS) or across the face
+        const int ym = (int)((ypk >> (8 * mu)) & 0xff);
+        const bool inside = (unsigned)(ym + dir) < 4u;
+        const int stride = 1 << (6 - 2 * mu);
+        const int lp = inside ? l + dir * stride : l - 3 * dir * stride;
+        const int hn = lp >> 1;
+        cx<T> psi[4][3];
+        T hs = (T)1;
+        if (inside) {
+          const int slot = base + (half ? 0 : npar * R) + hn;
+#pragma unroll
+          for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int b = 0; b < 3; b++) psi[a][b] = lds[(a * 3 + b) * ns + slot];
+        } else {
+          const uint32_t jrel = (uint32_t)((npar * g.nblocks + nbk - in_run0) * R + hn);
+          const uint32_t e = (uint32_t)((npar * g.nblocks + nbk - in_run0) * 12 * R) + (uint32_t)hn * W;
+#pragma unroll
+          for (int gk = 0; gk < 12 / W; gk++) {
+            cx<C> z[W];
+            ld_group<P>(at32(in.data + gk * W * R, e), z);
+#pragma unroll
+            for (int w = 0; w < W; w++) psi[(gk * W + w) / 3][(gk * W + w) % 3] = {(T)z[w].re, (T)z[w].im};
+          }
+          if constexpr (St<P>::scaled) hs = (T)*at32(in.scale, jrel);
+          hs *= (T)sg;
+        }
+        // the link: the site's own for a forward hop, the neighbour's for a
+        // backward one; a mirror block's links are read at its physical
+        // partner and conjugated
+        int lblkk, lrun_par, lh;
+        bool cj = false;
+        if (dir > 0) {
+          lblkk = blk;
+          lrun_par = par;
+          lh = h;
+          if (mb && B1 >= mb) {
+            lblkk -= (int)mshift;
+            cj = true;
+          }
+        } else {
+          const int ob1 = inside ? B1 : nB1;
+          lblkk = inside ? blk : nbk;
+          lrun_par = npar;
+          lh = hn;
+          if (mb && ob1 >= mb) {
+            lblkk -= (int)mshift;
+            cj = true;
+          }
+        }
+        const uint32_t el = (uint32_t)((lrun_par * g.nblocks + lblkk) * 36 * R) + (uint32_t)lh * W;
+        cx<T> w[3][3];
+        load_link_at<P, T>(links, g, mu, el, w);
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+          for (int b = 0; b < 3; b++) w[a][b].im = cj ? -w[a][b].im : w[a][b].im;
+        if (dir > 0)
+          hop_fwd<T>(mu, w, psi, c * hs, res);
+        else
+          hop_bwd<T>(mu, w, psi, c * hs, res);
+      }
+    }
+  }
+  if (KIND == DK_EVEN_ID || KIND == DK_ODD) {
+    if (self.data != nullptr) {
+      cx<T> v[4][3];
+      load_spinor<P, T>(self, i, v);
+#pragma unroll
+      for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 3; b++) res[a][b] = res[a][b] + v[a][b];
+    }
+  }
+  if (KIND == DK_ODD) {
+    cx<T> pv[4][3];
+    pauli_mul<P, T, NT>(pinv, g, i - g.Vh, res, pv);
+    store_spinor<P, T, NT>(out, i, pv);
+  } else {
+    store_spinor<P, T, NT>(out, i, res);
+  }
+}
+
 template <int P, int KIND, int G>
-void launch_k(unsigned gr, int threads, size_t lds, bool nt, hipStream_t st, const Geom &g,
+void launch_k(unsigned gr, int threads, size_t lds, bool nt, bool wave, hipStream_t st, const Geom &g,
               const typename St<P>::pair_t *links, const typename St<P>::real_t *angles, int qhat,
               const typename St<P>::pair_t *pauli, const typename St<P>::pair_t *pinv, Spinor<P> vin,
               Spinor<P> vself, Spinor<P> vout, typename St<P>::comp_t c, int mb) {
-  if (lds && nt)
+  if (lds && wave && nt)
+    dirac_wave_kernel<P, KIND, G, true><<<gr, threads, lds, st>>>(g, links, pauli, pinv, vin, vself, vout, c, mb);
+  else if (lds && wave)
+    dirac_wave_kernel<P, KIND, G, false><<<gr, threads, lds, st>>>(g, links, pauli, pinv, vin, vself, vout, c, mb);
+  else if (lds && nt)
     dirac_lds_kernel<P, KIND, G, true><<<gr, threads, lds, st>>>(g, links, angles, qhat, pauli, pinv, vin, vself, vout, c, mb);
   else if (lds)
     dirac_lds_kernel<P, KIND, G, false><<<gr, threads, lds, st>>>(g, links, angles, qhat, pauli, pinv, vin, vself, vout, c, mb);
@@ -245,15 +454,15 @@ void launch_k(unsigned gr, int threads, size_t lds, bool nt, hipStream_t st, con
 }
 
 template <int P, int KIND>
-void launch_g(int group, unsigned gr, int threads, size_t lds, bool nt, hipStream_t st, const Geom &g,
+void launch_g(int group, unsigned gr, int threads, size_t lds, bool nt, bool wave, hipStream_t st, const Geom &g,
               const typename St<P>::pair_t *links, const typename St<P>::real_t *angles, int qhat,
               const typename St<P>::pair_t *pauli, const typename St<P>::pair_t *pinv, Spinor<P> vin,
               Spinor<P> vself, Spinor<P> vout, typename St<P>::comp_t c, int mb) {
   switch (group) {
-    case 1: launch_k<P, KIND, 1>(gr, threads, lds, nt, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c, mb); break;
-    case 4: launch_k<P, KIND, 4>(gr, threads, lds, nt, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c, mb); break;
-    case 8: launch_k<P, KIND, 8>(gr, threads, lds, nt, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c, mb); break;
-    default: launch_k<P, KIND, 2>(gr, threads, lds, nt, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c, mb); break;
+    case 1: launch_k<P, KIND, 1>(gr, threads, lds, nt, wave, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c, mb); break;
+    case 4: launch_k<P, KIND, 4>(gr, threads, lds, nt, wave, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c, mb); break;
+    case 8: launch_k<P, KIND, 8>(gr, threads, lds, nt, wave, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c, mb); break;
+    default: launch_k<P, KIND, 2>(gr, threads, lds, nt, wave, st, g, links, angles, qhat, pauli, pinv, vin, vself, vout, c, mb); break;
   }
 }
 
@@ -295,13 +504,15 @@ hipError_t launch_p(DiracKind kind, int choice, const Geom &g, const OpFields &f
   const int mb = use_lds && (choice & MIRROR_VARIANT) && g.N[1] == 2 * g.L1 ? g.L1b : 0;
   const int group = choice & (LDS_VARIANT - 1);
   const size_t lds = use_lds ? 12 * (size_t)threads * sizeof(cx<T>) : 0;
+  // wavefront-uniform addressing: LDS-staged kernel on 4^4 blocks
+  const bool wave = use_lds && (choice & WAVE_VARIANT) && g.b[0] == 4 && g.b[1] == 4 && g.b[2] == 4 && g.b[3] == 4;
   switch (kind) {
-    case DK_FULL: launch_g<P, DK_FULL>(group, gr, threads, lds, nt, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc, mb); break;
-    case DK_HOP: launch_g<P, DK_HOP>(group, gr, threads, lds, nt, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc, mb); break;
-    case DK_PAULI: launch_g<P, DK_PAULI>(1, gr, threads, 0, false, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc, mb); break;
-    case DK_ODD: launch_g<P, DK_ODD>(group, gr, threads, lds, nt, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc, mb); break;
-    case DK_EVEN: launch_g<P, DK_EVEN>(group, gr, threads, lds, nt, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc, mb); break;
-    case DK_EVEN_ID: launch_g<P, DK_EVEN_ID>(group, gr, threads, lds, nt, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc, mb); break;
+    case DK_FULL: launch_g<P, DK_FULL>(group, gr, threads, lds, nt, wave, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc, mb); break;
+    case DK_HOP: launch_g<P, DK_HOP>(group, gr, threads, lds, nt, wave, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc, mb); break;
+    case DK_PAULI: launch_g<P, DK_PAULI>(1, gr, threads, 0, false, false, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc, mb); break;
+    case DK_ODD: launch_g<P, DK_ODD>(group, gr, threads, lds, nt, wave, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc, mb); break;
+    case DK_EVEN: launch_g<P, DK_EVEN>(group, gr, threads, lds, nt, wave, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc, mb); break;
+    case DK_EVEN_ID: launch_g<P, DK_EVEN_ID>(group, gr, threads, lds, nt, wave, st, g, links, angles, f.qhat, pauli, pinv, vin, vself, vout, cc, mb); break;
   }
   return hipGetLastError();
 }
@@ -340,19 +551,31 @@ int tune_group(int prec, DiracKind kind, const Geom &g, const OpFields &f, Spino
     if (it != g_tuned.end()) return it->second;
   }
   constexpr int L = LDS_VARIANT, N = NT_VARIANT;
-  constexpr int M = MIRROR_VARIANT;
-  static const int cand[] = {1, 2, 4, 8, L | 1, L | 2, L | 4, L | N | 1, L | N | 2, L | N | 4,
-                             L | M | 1, L | N | M | 1, L | N | M | 2};
+  constexpr int M = MIRROR_VARIANT, Wv = WAVE_VARIANT;
   const bool half = kind == DK_ODD || kind == DK_EVEN || kind == DK_EVEN_ID;
   const bool fits = (half ? g.Vbh : 2 * g.Vbh) <= 256;
-  const int ncand = !fits ? 4 : g.N[1] == 2 * g.L1 ? 13 : 10;
+  const bool cstar = g.N[1] == 2 * g.L1;
+  const bool b44 = g.b[0] == 4 && g.b[1] == 4 && g.b[2] == 4 && g.b[3] == 4;
+  std::vector<int> cands = {1, 2, 4, 8};
+  if (fits) {
+    for (int c : {L | 1, L | 2, L | 4, L | N | 1, L | N | 2, L | N | 4}) cands.push_back(c);
+    if (cstar)
+      for (int c : {L | M | 1, L | N | M | 1, L | N | M | 2}) cands.push_back(c);
+    if (b44) {
+      for (int c : {L | N | Wv | 1, L | N | Wv | 2, L | N | Wv | 4}) cands.push_back(c);
+      if (cstar)
+        for (int c : {L | N | M | Wv | 1, L | N | M | Wv | 2, L | N | M | Wv | 4}) cands.push_back(c);
+    }
+  }
+  const int ncand = (int)cands.size();
+  const int *cand = cands.data();
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return 2;
   if (hipEventCreate(&e1) != hipSuccess) {
     (void)hipEventDestroy(e0);
     return 2;
   }
-  float ms_of[16];
+  std::vector<float> ms_of(cands.size());
   for (float &m : ms_of) m = 1e30f;
   for (int ci = 0; ci < ncand; ci++) {
     const int gsz = cand[ci];
@@ -407,7 +630,7 @@ hipError_t launch_dirac(int prec, DiracKind kind, const Geom &g, const OpFields 
 
 bool force_dirac_variant(int choice) {
   const int group = choice & (LDS_VARIANT - 1);
-  if (choice != 0 && ((choice & ~(MIRROR_VARIANT | NT_VARIANT | LDS_VARIANT | 15)) ||
+  if (choice != 0 && ((choice & ~(WAVE_VARIANT | MIRROR_VARIANT | NT_VARIANT | LDS_VARIANT | 15)) ||
                       (group != 1 && group != 2 && group != 4 && group != 8)))
     return false;
   g_forced_choice.store(choice);

@@ -134,8 +134,9 @@ def _ptr(t):
 
 def set_dirac_variant(choice=0):
     """Force a Dirac kernel variant (hop group 1/2/4/8, +16 for LDS staging,
-    +32 for non-temporal Pauli/output streams with LDS staging); 0 returns to
-    the autotuner.  A testing hook."""
+    +32 for non-temporal Pauli/output streams, +64 for mirror-fused link
+    reads, +128 for wavefront-uniform addressing on 4^4 blocks, the last three
+    with LDS staging); 0 returns to the autotuner.  A testing hook."""
     _check(lib().qxd_debug_set_dirac_variant(int(choice)))
 
 

@@ -47,6 +47,7 @@ def test_kernel_name():
     assert bench.kernel_name(2, 0) == "dirac_kernel<0, 0, 2>"
     assert bench.kernel_name(49, 0) == "dirac_lds_kernel<0, 0, 1, true>"
     assert bench.kernel_name(113, 1) == "dirac_lds_kernel<1, 0, 1, true> (mirror-fused links)"
+    assert bench.kernel_name(241, 2) == "dirac_wave_kernel<2, 0, 1, true> (mirror-fused links)"
 
 
 def test_refuses_several_gpus():

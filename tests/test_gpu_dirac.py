@@ -77,18 +77,19 @@ def test_operator_low_precision(case, prec):
         assert rel(to_host(y), oracle_op(case, which, x)) < TOL[prec]
 
 
-VARIANTS = [1, 2, 4, 8, 17, 18, 20, 24, 49, 50, 52, 56, 81, 113, 114, 120]
+VARIANTS = [1, 2, 4, 8, 17, 18, 20, 24, 49, 50, 52, 56, 81, 113, 114, 120, 146, 177, 178, 241, 242, 244]
 
 
 @pytest.mark.parametrize("choice", VARIANTS,
                          ids=[f"g{v & 15}{'-lds' if v & 16 else ''}{'-nt' if v & 32 else ''}"
-                              f"{'-mir' if v & 64 else ''}" for v in VARIANTS])
+                              f"{'-mir' if v & 64 else ''}{'-wave' if v & 128 else ''}" for v in VARIANTS])
 def test_every_kernel_variant(case, choice):
     """Each hop-group size, the LDS-staged input, the non-temporal Pauli
-    and output streams and the mirror-fused link reads (C* lattices: mirror
-    links read at the physical partner and conjugated), forced in turn (the
-    autotuner would otherwise pick one), for D, D^ and the hopping term in
-    FP64 and FP32 (mirror-fused variants in all four storages)."""
+    and output streams, the mirror-fused link reads (C* lattices: mirror
+    links read at the physical partner and conjugated) and the wavefront-
+    uniform addressing of 4^4 blocks, forced in turn (the autotuner would
+    otherwise pick one), for D, D^ and the hopping term in FP64 and FP32
+    (mirror-fused and wavefront-uniform variants in all four storages)."""
     import torch
     from paper_1710_08839_amd import qxd
     x = case.source(9)
@@ -97,7 +98,7 @@ def test_every_kernel_variant(case, choice):
     try:
         # the mirror-fused reads also in the 16-bit storages (conjugation of
         # FP16 / BF16 link components)
-        for prec in ((0, 1, 2, 3) if choice & 64 else (0, 1)):
+        for prec in ((0, 1, 2, 3) if choice & (64 | 128) else (0, 1)):
             for which in (0, 1, 2):
                 y = torch.empty_like(to_dev(x))
                 case.field.apply(case.quark, which, prec, to_dev(x), y)
@@ -187,7 +188,8 @@ def test_cfg2_shape_sampled_sites(ctx):
     evaluated at those sites only, in every storage precision, with the
     autotuned kernel variant and with the mirror-fused link reads forced (on
     this lattice the mirror half's links are 8 blocks away from their
-    physical partners in direction 1)."""
+    physical partners in direction 1), with and without the wavefront-uniform
+    addressing."""
     import torch
     from paper_1710_08839_amd import qxd, synth
     from oracle import Lattice
@@ -206,7 +208,7 @@ def test_cfg2_shape_sampled_sites(ctx):
     got = {}
     try:
         for prec in (0, 1, 2, 3):
-            for choice in (0, 113):
+            for choice in (0, 113, 241):
                 qxd.set_dirac_variant(choice)
                 f.apply(q, 0, prec, xd, y)
                 torch.cuda.synchronize()
