@@ -1,6 +1,6 @@
 """Wilson-clover Dirac operator and its even-odd Schur complement.
 
-Paper Sec. 2.3: D = m0 + Dw + dD_sw (+ dD_b, zero here), with
+Paper Sec. 2.3: D = m0 + Dw + dD_sw + dD_b (dD_b: fields.boundary_term), with
     Dw = sum_mu (1/2) { gamma_mu (nabla_mu + nabla*_mu) - nabla*_mu nabla_mu },
     nabla_mu psi(x)  = W(x,mu) psi(x+mu) - psi(x),
     nabla*_mu psi(x) = psi(x) - W(x-mu,mu)^dag psi(x-mu).
@@ -145,8 +145,10 @@ def apply_at_sites(lat, u_ext, a_ext, psi, sites, kappa, q=0.0, csw=0.0, csw_u1=
     for mu in range(4):
         yf = lat.fwd[mu][sites]
         yb = lat.bwd[mu][sites]
-        wf = u_ext[sites, mu] * (np.exp(1j * qhat * a_ext[sites, mu])[:, None, None] if qhat else 1.0)
-        wb = u_ext[yb, mu] * (np.exp(1j * qhat * a_ext[yb, mu])[:, None, None] if qhat else 1.0)
+        live_f = (~lat.frozen[sites]).astype(float)[:, None, None]
+        live_b = (~lat.frozen[yb]).astype(float)[:, None, None]
+        wf = live_f * u_ext[sites, mu] * (np.exp(1j * qhat * a_ext[sites, mu])[:, None, None] if qhat else 1.0)
+        wb = live_b * u_ext[yb, mu] * (np.exp(1j * qhat * a_ext[yb, mu])[:, None, None] if qhat else 1.0)
         fw = np.einsum("xab,xsb->xsa", wf, psi[yf]) * lat.sign[mu][sites][:, None, None]
         bw = np.einsum("xba,xsb->xsa", np.conj(wb), psi[yb]) * lat.bsign[mu][sites][:, None, None]
         acc += np.einsum("st,xtc->xsc", EYE4 - GAMMA[mu], fw)

@@ -87,13 +87,20 @@ def theta_phases(lat, theta):
 
 def hopping_links(lat, u, a, qhat, theta=None):
     """W(x, mu) = U(x, mu) exp(i qhat A(x, mu)), times the fermion boundary
-    phase of theta_phases on the links that cross a boundary."""
-    return u * (np.exp(1j * qhat * a) * theta_phases(lat, theta))[:, :, None, None]
+    phase of theta_phases on the links that cross a boundary.  With SF or
+    open-SF time boundaries the links of the fixed slice x0 = 0 carry no hop
+    (the fermion field vanishes there), so that slice is decoupled."""
+    w = u * (np.exp(1j * qhat * a) * theta_phases(lat, theta))[:, :, None, None]
+    if lat.frozen.any():
+        w = w.copy()
+        w[lat.frozen] = 0.0
+    return w
 
 
 def _existing(lat):
-    """1 for links that exist, 0 for the links cut by open time boundaries."""
-    return np.abs(lat.sign)  # [4, V]
+    """1 for links that exist in the gauge field, 0 for the links an open time
+    end cuts (open and open-SF; with SF the links into x0 = T exist)."""
+    return lat.link_exists  # [4, V]
 
 
 def su3_field_tensor(lat, u, sites=None):
@@ -152,8 +159,35 @@ def u1_field_tensor(lat, a, q_el, sites=None):
     return ah
 
 
+def boundary_term(lat, sites=None):
+    """The coefficient of dD_b per site (Sec. 2.3): with open time (c_F - 1) on
+    x0 = 0 and T-1; with SF (c_F - 1) on x0 = 1 and T-1; with open-SF
+    (c_F - 1) on x0 = 1 and (c_F' - 1) on x0 = T-1; zero with periodic time."""
+    x0 = lat.coords[:, 0] if sites is None else lat.coords[np.asarray(sites), 0]
+    t = lat.phys[0]
+    d = np.zeros(len(x0))
+    if lat.time_bc == 1:
+        d[(x0 == 0) | (x0 == t - 1)] = lat.cF - 1.0
+    elif lat.time_bc == 2:
+        d[(x0 == 1) | (x0 == t - 1)] = lat.cF - 1.0
+    elif lat.time_bc == 3:
+        d[x0 == 1] = lat.cF - 1.0
+        d[x0 == t - 1] = lat.cF_prime - 1.0
+    return d
+
+
 def pauli_term(lat, u, a, kappa, q, csw, csw_u1, q_el, sites=None):
-    """P[x, 12, 12] on spin (x) colour, index s*3 + c (all or listed sites)."""
+    """P[x, 12, 12] on spin (x) colour, index s*3 + c (all or listed sites):
+    4 + m0 + dD_sw + dD_b, and the identity on the fixed slice of SF and
+    open-SF time boundaries."""
+    p = _pauli_bulk(lat, u, a, kappa, q, csw, csw_u1, q_el, sites)
+    p += boundary_term(lat, sites)[:, None, None] * np.eye(12)
+    fz = lat.frozen if sites is None else lat.frozen[np.asarray(sites)]
+    p[fz] = np.eye(12)
+    return p
+
+
+def _pauli_bulk(lat, u, a, kappa, q, csw, csw_u1, q_el, sites=None):
     m0 = 1.0 / (2.0 * kappa) - 4.0
     f = su3_field_tensor(lat, u, sites)
     n = f.shape[1]

@@ -7,9 +7,17 @@ with period 2L1 in direction 1 (eq. "periodic"); a C* direction k = 2, 3 is
 realised by shifted boundary conditions: a step across x_k = L_k - 1 -> 0
 also moves x1 by L1 (eq. "shifted", Fig. 1).
 
-Time: periodic gauge field with antiperiodic fermions (time_bc=0), or open
-boundaries (time_bc=1), where the hop across x0 = T-1 -> 0 is absent and the
-boundary improvement coefficient is 1, so the boundary term vanishes (Sec. 2.3).
+Time (Sec. 2 feature list: open, SF, open-SF, periodic; Sec. 2.3: the
+boundary improvement term dD_b):
+  time_bc = 0  periodic gauge field, antiperiodic fermions;
+  time_bc = 1  open: the hop across x0 = T-1 -> 0 is absent;
+  time_bc = 2  Schroedinger functional (SF): the fermion field is fixed to zero
+               on the boundary slice x0 = 0 (stored as a slice whose rows and
+               columns of D are the identity), the hop across x0 = T-1 -> 0 is
+               absent;
+  time_bc = 3  open-SF: SF at x0 = 0, open at x0 = T-1.
+The improvement coefficients cF (and cF_prime at the open end of open-SF)
+enter dD_b (fields.pauli_term).
 
 Site index: ((x0*N1 + x1)*L2 + x2)*L3 + x3 with N1 = 2L1 under C*, else L1.
 """
@@ -18,17 +26,19 @@ import numpy as np
 
 
 class Lattice:
-    def __init__(self, dims, cstar=0, time_bc=0):
+    def __init__(self, dims, cstar=0, time_bc=0, cF=1.0, cF_prime=1.0):
         dims = tuple(int(d) for d in dims)
         if len(dims) != 4:
             raise ValueError("dims must be (T, L1, L2, L3)")
         if cstar not in (0, 1, 2, 3):
             raise ValueError("cstar must be 0..3")
-        if time_bc not in (0, 1):
-            raise ValueError("time_bc must be 0 (antiperiodic) or 1 (open)")
+        if time_bc not in (0, 1, 2, 3):
+            raise ValueError("time_bc must be 0 (antiperiodic), 1 (open), 2 (SF) or 3 (open-SF)")
         self.phys = dims
         self.cstar = cstar
         self.time_bc = time_bc
+        self.cF = float(cF)
+        self.cF_prime = float(cF_prime)
         t, l1, l2, l3 = dims
         self.L1 = l1
         n1 = 2 * l1 if cstar else l1
@@ -64,6 +74,15 @@ class Lattice:
             self.bwd[mu, self.fwd[mu]] = idx
         # the sign of the hop x -> x - mu belongs to the link (x - mu, mu)
         self.bsign = np.stack([self.sign[mu, self.bwd[mu]] for mu in range(4)])
+
+        # SF and open-SF: the slice x0 = 0 is the fixed (zero) boundary field
+        self.frozen = (self.coords[:, 0] == 0) if time_bc in (2, 3) else np.zeros(self.V, dtype=bool)
+        # links that exist in the gauge field: the time links across
+        # x0 = T-1 -> 0 are absent at an open end (open, open-SF); with SF
+        # they connect the bulk to the boundary at x0 = T
+        self.link_exists = np.ones((4, self.V))
+        if time_bc in (1, 3):
+            self.link_exists[0, self.coords[:, 0] == t - 1] = 0.0
 
         self.even = np.nonzero(self.parity == 0)[0]
         self.odd = np.nonzero(self.parity == 1)[0]

@@ -689,3 +689,109 @@ def test_theta_rejected_where_undefined():
         lat = Lattice((4, 4, 4, 4), cstar=cstar, time_bc=time_bc)
         with pytest.raises(ValueError):
             of.theta_phases(lat, theta)
+
+
+# ---------------------------------------------------------------------------
+# SF and open-SF time boundaries and the boundary term dD_b (Sec. 2 feature
+# list, Sec. 2.3), in the conventions of the openQCD code the paper inherits:
+# dD_b = (c_F - 1) on x0 = 0, T-1 (open), on x0 = 1, T-1 (SF), and
+# (c_F - 1) on x0 = 1, (c_F' - 1) on x0 = T-1 (open-SF); with SF the fermion
+# field is fixed to zero on x0 = 0 (a decoupled slice where D is the identity).
+# ---------------------------------------------------------------------------
+BOUNDARY_SLICES = {1: {0: "cF", 5: "cF"}, 2: {1: "cF", 5: "cF"}, 3: {1: "cF", 5: "cFp"}}
+
+
+@pytest.mark.parametrize("time_bc", [1, 2, 3])
+def test_boundary_term_closed_form(time_bc):
+    """D(c_F, c_F') - D(1, 1) is (c_F - 1) or (c_F' - 1) times the identity on
+    exactly the slices the boundary type names, and zero elsewhere."""
+    cF, cFp = 1.37, 0.81
+    ops = []
+    for a, b in ((cF, cFp), (1.0, 1.0)):
+        lat = Lattice((6, 4, 2, 2), cstar=1, time_bc=time_bc, cF=a, cF_prime=b)
+        ue, ae = random_field(lat, 13)
+        ops.append(od.build_operator(lat, ue, ae, 0.13, q=2 / 3, csw=1.9))
+    psi = rand_spinor(lat, 3)
+    diff = ops[0].apply(psi) - ops[1].apply(psi)
+    x0 = lat.coords[:, 0]
+    coef = {"cF": cF - 1, "cFp": cFp - 1}
+    expect = np.zeros_like(psi)
+    for t, which in BOUNDARY_SLICES[time_bc].items():
+        expect[x0 == t] = coef[which] * psi[x0 == t]
+    if time_bc in (2, 3):
+        expect[x0 == 0] = 0.0  # the fixed slice stays the identity
+    assert np.max(np.abs(diff - expect)) < 1e-13
+
+
+@pytest.mark.parametrize("time_bc", [2, 3])
+def test_sf_slice_decoupled(time_bc):
+    """With SF or open-SF the rows and the columns of the slice x0 = 0 of the
+    dense D are those of the identity; the rest is the operator of the bulk."""
+    lat = Lattice((4, 2, 2, 2), cstar=3, time_bc=time_bc, cF=1.2, cF_prime=0.9)
+    ue, ae = random_field(lat, 19, eps=0.5, sigma=0.4)
+    op = od.build_operator(lat, ue, ae, 0.125, q=-1 / 3, csw=1.5)
+    d = dense_matrix(op.apply, lat.V)
+    fz = site_dofs(np.nonzero(lat.frozen)[0])
+    assert len(fz) > 0
+    eye = np.eye(d.shape[0])
+    assert np.array_equal(d[fz, :], eye[fz, :]) and np.array_equal(d[:, fz], eye[:, fz])
+
+
+def test_sf_keeps_the_link_to_the_upper_boundary():
+    """Only the time links at x0 = T-1 non-trivial: with SF they reach the
+    boundary at x0 = T and enter the clover term of x0 = T-1; with an open end
+    they do not exist and P(x) = 1/(2 kappa) there."""
+    kappa = 0.13
+    devs = {}
+    for time_bc in (2, 1):
+        lat = Lattice((4, 4, 2, 2), cstar=0, time_bc=time_bc)
+        u, a = cut_only_field(lat, 27)
+        ue, ae = of.extend_gauge(lat, u, a)
+        op = od.build_operator(lat, ue, ae, kappa, q=2 / 3, csw=1.9, csw_u1=1.3)
+        top = lat.coords[:, 0] == lat.phys[0] - 1
+        devs[time_bc] = np.max(np.abs(op.pauli[top] - np.eye(12) / (2 * kappa)))
+    assert devs[1] < 1e-15 and devs[2] > 1e-2
+
+
+@pytest.mark.parametrize("cstar,time_bc", [(3, 2), (1, 3), (0, 3)])
+def test_sf_identities(cstar, time_bc):
+    """gamma5-hermiticity, gauge covariance and (C*) the mirror identities
+    with SF and open-SF time boundaries and c_F, c_F' != 1."""
+    lat = Lattice((4, 4, 2, 2), cstar=cstar, time_bc=time_bc, cF=1.3, cF_prime=0.7)
+    ue, ae = random_field(lat, 37)
+    kw = dict(q=-1 / 3, csw=1.9, csw_u1=1.2)
+    op = od.build_operator(lat, ue, ae, 0.13, **kw)
+    eta, psi = rand_spinor(lat, 1), rand_spinor(lat, 2)
+    lhs = od.dot(eta, op.apply_g5(op.apply(psi)))
+    rhs = np.conj(od.dot(psi, op.apply_g5(op.apply(eta))))
+    assert abs(lhs - rhs) / (od.norm(eta) * od.norm(op.apply(psi))) < 1e-13
+    rng = synth.rng_from_seed(55)
+    om = synth.su3_links(rng, lat.V, 3.0)[:, 0]
+    phi = rng.uniform(-np.pi, np.pi, lat.V)
+    up, ap = gauge_transform(lat, ue, ae, om, phi)
+    opp = od.build_operator(lat, up, ap, 0.13, **kw)
+    rot = lambda v: np.exp(1j * -2 * phi)[:, None, None] * np.einsum("xab,xsb->xsa", om, v)
+    assert rel(opp.apply(rot(psi)), rot(op.apply(psi))) < 1e-13
+    if cstar:
+        opc = od.build_operator(lat, np.conj(ue), -ae, 0.13, **kw)
+        tr = lambda v: v[lat.mirror()]
+        assert rel(op.apply(tr(psi)), tr(opc.apply(psi))) < 1e-13
+        ctd = lambda v: np.einsum("st,xtc->xsc", G[0] @ G[2], tr(op.apply(v)))
+        assert abs(np.sum(eta * ctd(psi)) + np.sum(psi * ctd(eta))) / (od.norm(eta) * od.norm(op.apply(psi))) < 1e-13
+
+
+@pytest.mark.parametrize("time_bc", [2, 3])
+def test_dense_sf_solves(time_bc):
+    lat = Lattice((4, 2, 2, 2), cstar=3, time_bc=time_bc, cF=1.15, cF_prime=0.95)
+    ue, ae = random_field(lat, 43, eps=0.5, sigma=0.4)
+    op = od.build_operator(lat, ue, ae, 0.125, q=-1 / 3, csw=1.5)
+    d = dense_matrix(op.apply, lat.V)
+    _check_schur_det(lat, op, d)
+    eta = rand_spinor(lat, 8)
+    exact = np.linalg.solve(d, eta.reshape(-1)).reshape(eta.shape)
+    psi, _ = osv.solve_eo(op, eta, 1e-12, nkv=16)
+    assert rel(psi, exact) < 1e-10
+    blocks = osv.Blocks(lat, (2, 2, 2, 2))
+    x, _ = osv.fgcr(op.apply, lambda r: osv.sap(op, blocks, r, ncy=3, nmr=4), eta, 1e-12, nkv=8)
+    assert rel(x, exact) < 1e-10
+    assert np.array_equal(x[lat.frozen], eta[lat.frozen]) or rel(x[lat.frozen], eta[lat.frozen]) < 1e-12
