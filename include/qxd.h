@@ -19,10 +19,10 @@
  *   Gamma matrices: chiral basis, gamma_0 = [[0,-1],[-1,0]],
  *   gamma_k = [[0,-i s_k],[i s_k,0]], gamma_5 = diag(1,1,-1,-1).
  *   Spinors in API layout: double [nrhs][V_ext][4 spin][3 colour][re,im].
- *   D = (4 + m0) + dD_sw - 1/2 sum_mu [(1-g_mu) W(x,mu) psi(x+mu)
+ *   D = (4 + m0) + dD_sw + dD_b - 1/2 sum_mu [(1-g_mu) W(x,mu) psi(x+mu)
  *       + (1+g_mu) W(x-mu,mu)^dag psi(x-mu)],  W = U exp(i qhat A),
  *   m0 = 1/(2 kappa) - 4.  Fermions are antiperiodic in time (time_bc = 0)
- *   or the time hop is absent (time_bc = 1, open, boundary coefficient 1).
+ *   or the time hop is absent (open, SF, open-SF: qxd_lattice.time_bc).
  *   Clover: F = (Q_munu - Q_munu^dag)/8 from the four plaquette leaves;
  *   Ahat = i/(4 q_el) Im(sum of the four U(1) plaquettes).
  *
@@ -92,12 +92,23 @@ typedef enum {
 
 typedef struct {
   int dims[4];    /* physical T, L1, L2, L3; all even                        */
-  int time_bc;    /* 0: periodic gauge, antiperiodic fermions; 1: open      */
+  int time_bc;    /* 0: periodic gauge, antiperiodic fermions; 1: open;
+                     2: Schroedinger functional (SF): the fermion field is
+                     fixed to zero on x0 = 0 (D is the identity on that slice,
+                     no hop enters or leaves it) and the hop across x0 = T-1
+                     -> T is absent, the time links into x0 = T staying in
+                     the clover term with the x0 = 0 slice's spatial links as
+                     the upper boundary field; 3: open-SF (SF at x0 = 0, open
+                     at x0 = T-1).  Sec. 2 feature list                      */
   int cstar;      /* 0: periodic space; k = 1..3: directions 1..k are C*    */
   double q_el;    /* elementary charge (Sec. 2.2); 1/6 is required with C*
                      for charged hadrons; 0 means 1/6                         */
   int block[4];   /* block size of the device layout and of SAP; each even,
                      dividing the extended extent (and L1); 0 means 4          */
+  double cF;      /* time-boundary improvement coefficient c_F of dD_b (Sec.
+                     2.3): dD_b = (c_F - 1) on x0 = 0 and T-1 (open), on x0 = 1
+                     and T-1 (SF), on x0 = 1 (open-SF); 0 means 1            */
+  double cF_prime;/* c_F' on x0 = T-1 of open-SF; 0 means 1                  */
 } qxd_lattice;
 
 typedef struct {
@@ -311,10 +322,12 @@ typedef struct {
  * 0 means 70% of the device memory free at this call.  Charged against it:
  * per group of requests (same field, inner precision and solver parameters)
  * the larger of the solver workspaces the group holds and those its admitted
- * right-hand sides need, plus for every admitted request the operator
- * (clover term, its inverse, hopping links) it may build.  Requests are
+ * right-hand sides need; the operators (clover term, its inverse, hopping
+ * links) the fields build or keep cached beyond what they held when their
+ * first request arrived; and for every admitted request whose operator is
+ * not built yet, that operator until the request completes.  Requests are
  * admitted in arrival order while the charge fits; one request always runs
- * when nothing else is charged.  max_active (0 = no limit) caps the
+ * when no other request is charged.  max_active (0 = no limit) caps the
  * right-hand sides in flight. */
 qxd_status qxd_serve_start(qxd_ctx *ctx, size_t budget_bytes, int max_active);
 

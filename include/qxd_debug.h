@@ -51,6 +51,16 @@ qxd_status qxd_debug_step_graph_counts(int64_t *captures, int64_t *replays);
  * written).  Process-wide.  QXD_EINVAL for n < 0. */
 qxd_status qxd_debug_fail_steps(int n);
 
+/* Measurement hook: time one colour pass (the blocks of colour 0, with the
+ * face update) of the SAP block solver that the batched SAP-GCR runs on pairs
+ * of right-hand sides sharing an operator, for npair pairs of synthetic
+ * vectors in storage precision prec (QXD_F32, QXD_F16S or QXD_BF16), with nmr
+ * MR steps per block; *ms receives the average over reps launches, timed
+ * with HIP events on `stream`.  Builds the quark's operator if needed;
+ * allocates its vectors on the field.  Synchronises `stream`. */
+qxd_status qxd_debug_sap_pair_pass(qxd_field *field, const qxd_quark *quark, qxd_prec prec, int nmr, int npair,
+                                   int reps, float *ms, void *stream);
+
 /* Streaming probe on the current device, the practical bandwidth ceiling the
  * benchmark reports next to the kernels, shaped like the spinor traffic of
  * the block-major fields.  dst is cut into chunks of 12 planes of 4 KB, src
@@ -64,6 +74,13 @@ qxd_status qxd_debug_fail_steps(int n);
  * default stream). */
 qxd_status qxd_debug_stream(const void *src_dev, void *dst_dev, size_t dst_bytes, int reads_per_write,
                             void *stream);
+
+/* The serve loop's memory accounting on ctx (a snapshot): out[0] = operator
+ * bytes that admitted requests have still to build, out[1] = operator bytes
+ * the fields of its requests hold beyond what they held when first seen,
+ * out[2] = solver slot bytes charged to its groups, out[3] = the budget.
+ * QXD_EINVAL if out is NULL or serving is not started on ctx. */
+qxd_status qxd_debug_serve_charges(qxd_ctx *ctx, size_t out[4]);
 
 /* The variant the autotuner chose for the full operator D (phase folded into
  * the links) on this field's lattice in precision prec, in the encoding of

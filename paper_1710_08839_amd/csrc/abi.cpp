@@ -44,8 +44,12 @@ static qxd_status make_geom(const qxd_lattice *lat, Geom *g) {
     set_error("cstar must be 0..3 (got %d)", lat->cstar);
     return QXD_EINVAL;
   }
-  if (lat->time_bc != 0 && lat->time_bc != 1) {
-    set_error("time_bc must be 0 (antiperiodic) or 1 (open)");
+  if (lat->time_bc < 0 || lat->time_bc > 3) {
+    set_error("time_bc must be 0 (antiperiodic), 1 (open), 2 (SF) or 3 (open-SF)");
+    return QXD_EINVAL;
+  }
+  if (!isfinite(lat->cF) || !isfinite(lat->cF_prime)) {
+    set_error("cF and cF_prime must be finite");
     return QXD_EINVAL;
   }
   int N[4] = {lat->dims[0], lat->cstar ? 2 * lat->dims[1] : lat->dims[1], lat->dims[2], lat->dims[3]};
@@ -165,6 +169,13 @@ static qxd_status check_quark(const Field &f, const qxd_quark &q) {
   return QXD_OK;
 }
 
+size_t Field::pending_op_bytes_nowait(const qxd_quark &q, int prec) {
+  if (!mu.try_lock()) return op_bytes(prec);
+  size_t b = pending_op_bytes(&q, 1, prec);
+  mu.unlock();
+  return b;
+}
+
 qxd_status Field::get_op(const qxd_quark &q, int prec, Operator **out, hipStream_t st) {
   {
     qxd_status cs = check_quark(*this, q);
@@ -192,6 +203,7 @@ qxd_status Field::get_op(const qxd_quark &q, int prec, Operator **out, hipStream
         if (jt->second->users == 0 && (victim == ops.end() || jt->second->last_use < victim->second->last_use))
           victim = jt;
       if (victim == ops.end()) break;
+      op_mem -= victim->second->bytes;
       ops.erase(victim);
     }
     std::unique_ptr<Operator> nop(new Operator());
@@ -201,6 +213,7 @@ qxd_status Field::get_op(const qxd_quark &q, int prec, Operator **out, hipStream
     QXD_HIP_CHECK(nop->pinv[QXD_F64].ensure((size_t)36 * g.Vh * 16));
     QXD_HIP_CHECK(launch_pauli_build(g, links[QXD_F64].as<double2>(), angles[QXD_F64].as<double>(), has_u1,
                                      q.kappa, q.csw, has_u1 ? qhat * q.csw_u1 : 0.0,
+                                     lat.cF == 0.0 ? 1.0 : lat.cF, lat.cF_prime == 0.0 ? 1.0 : lat.cF_prime,
                                      nop->pauli[QXD_F64].as<double2>(), st));
     hipError_t e;
     int *bad = (int *)workspace("bad_count", sizeof(int), &e);
@@ -218,6 +231,8 @@ qxd_status Field::get_op(const qxd_quark &q, int prec, Operator **out, hipStream
     QXD_HIP_CHECK(launch_fold_phase(g, links[QXD_F64].as<double2>(), angles[QXD_F64].as<double>(), qhat,
                                     q.theta, nop->wl[QXD_F64].as<double2>(), st));
     nop->ready[QXD_F64] = true;
+    nop->bytes = (size_t)36 * (2 * g.V + g.Vh) * 16;
+    op_mem += nop->bytes;
     op = nop.get();
     ops[key] = std::move(nop);
   } else {
@@ -231,6 +246,9 @@ qxd_status Field::get_op(const qxd_quark &q, int prec, Operator **out, hipStream
     QXD_HIP_CHECK(op->wl[prec].ensure((size_t)36 * g.V * pair_bytes(prec)));
     QXD_HIP_CHECK(launch_convert_field(prec, g, 36, g.V, op->wl[QXD_F64].as<double2>(), op->wl[prec].p, st));
     op->ready[prec] = true;
+    const size_t nb = (size_t)36 * (2 * g.V + g.Vh) * pair_bytes(prec);
+    op->bytes += nb;
+    op_mem += nb;
   }
   qxd_status s = ensure_links(prec, st);
   if (s != QXD_OK) return s;
@@ -406,6 +424,17 @@ qxd_status qxd_debug_get_dirac_variant(const qxd_field *field, qxd_prec prec, in
 qxd_status qxd_debug_set_step_graphs(int enable) {
   set_step_graphs(enable != 0);
   return QXD_OK;
+}
+
+qxd_status qxd_debug_sap_pair_pass(qxd_field *field, const qxd_quark *quark, qxd_prec prec, int nmr, int npair,
+                                   int reps, float *ms, void *stream) {
+  if (!field || !quark || !ms || nmr < 0 || npair < 1 || reps < 1) {
+    set_error("invalid arguments to qxd_debug_sap_pair_pass");
+    return QXD_EINVAL;
+  }
+  std::lock_guard<std::recursive_mutex> lk(field->mu);
+  QXD_HIP_CHECK(hipSetDevice(field->ctx->device));
+  return debug_sap_pair_pass(field, *quark, (int)prec, nmr, npair, reps, ms, (hipStream_t)stream);
 }
 
 qxd_status qxd_debug_fail_steps(int n) {

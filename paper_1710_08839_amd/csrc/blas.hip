@@ -59,7 +59,7 @@ __device__ __forceinline__ void ld(const Spinor<P> &v, int64_t i, cx<double> a[4
 }
 
 // partial[k][blk] for k < nred
-__global__ void finish_kernel(const double *partial, int nblk, int nred, double *out,
+__global__ void __launch_bounds__(BT) finish_kernel(const double *partial, int nblk, int nred, double *out,
                               const double *div, int div_stride) {
   __shared__ double sh[4];
   for (int k = 0; k < nred; k++) {
@@ -76,7 +76,7 @@ __global__ void finish_kernel(const double *partial, int nblk, int nred, double 
 
 // partial[(base + 2l (+1)) * grid + blk] = block sums of (y_l, x), l < N
 template <int P, int N>
-__global__ void mdot_kernel(VecList<P> ys, Spinor<P> x, int64_t first, int64_t count,
+__global__ void __launch_bounds__(BT) mdot_kernel(VecList<P> ys, Spinor<P> x, int64_t first, int64_t count,
                             double *partial, int base) {
   __shared__ double sh[4];
   double acc[2 * N];
@@ -125,10 +125,47 @@ struct MaxpyArgs {
   Spinor<P> w;
 };
 
+// One triple of maxpy_kernel at site i.  TR is a template argument so that
+// the kernel-argument arrays are indexed by constants: a run-time index
+// would copy them to private memory.
+template <int P, int N, int TR>
+__device__ __forceinline__ void maxpy_triple(const MaxpyArgs<P> &a, int64_t i, const cx<double> *cf, double &nn,
+                                             double &wr, double &wi) {
+  cx<double> z[4][3];
+  ld<P>(a.src[TR], i, z);
+#pragma unroll
+  for (int l = 0; l < N; l++) {
+    cx<double> y[4][3];
+    ld<P>(a.ys[TR].v[l], i, y);
+#pragma unroll
+    for (int s = 0; s < 4; s++)
+#pragma unroll
+      for (int k = 0; k < 3; k++) z[s][k] = z[s][k] - cf[l] * y[s][k];
+  }
+  store_spinor<P, double>(a.dst[TR], i, z);
+  if (TR == 0 && a.want_norms) {
+    // re-read what was stored so that the norms match the stored vector
+    ld<P>(a.dst[0], i, z);
+    cx<double> w[4][3];
+    if (a.has_w) ld<P>(a.w, i, w);
+#pragma unroll
+    for (int s = 0; s < 4; s++)
+#pragma unroll
+      for (int k = 0; k < 3; k++) {
+        nn += norm2(z[s][k]);
+        if (a.has_w) {
+          cx<double> q = cmulc(z[s][k], w[s][k]);
+          wr += q.re;
+          wi += q.im;
+        }
+      }
+  }
+}
+
 // z_t = src_t - sum_{l<N} coef[l] / div[l] * ys_t[l] for t < ntriples; then
 // partial sums of (z_0, z_0) and (z_0, w).
 template <int P, int N>
-__global__ void maxpy_kernel(MaxpyArgs<P> a, int64_t first, int64_t count, double *partial) {
+__global__ void __launch_bounds__(BT) maxpy_kernel(MaxpyArgs<P> a, int64_t first, int64_t count, double *partial) {
   __shared__ double sh[4];
   cx<double> cf[N > 0 ? N : 1];
 #pragma unroll
@@ -140,37 +177,8 @@ __global__ void maxpy_kernel(MaxpyArgs<P> a, int64_t first, int64_t count, doubl
   double nn = 0.0, wr = 0.0, wi = 0.0;
   for (int64_t t = (int64_t)blockIdx.x * BT + threadIdx.x; t < count; t += (int64_t)gridDim.x * BT) {
     int64_t i = first + t;
-    for (int tr = 0; tr < a.ntriples; tr++) {
-      cx<double> z[4][3];
-      ld<P>(a.src[tr], i, z);
-#pragma unroll
-      for (int l = 0; l < N; l++) {
-        cx<double> y[4][3];
-        ld<P>(a.ys[tr].v[l], i, y);
-#pragma unroll
-        for (int s = 0; s < 4; s++)
-#pragma unroll
-          for (int k = 0; k < 3; k++) z[s][k] = z[s][k] - cf[l] * y[s][k];
-      }
-      store_spinor<P, double>(a.dst[tr], i, z);
-      if (tr == 0 && a.want_norms) {
-        // re-read what was stored so that the norms match the stored vector
-        ld<P>(a.dst[0], i, z);
-        cx<double> w[4][3];
-        if (a.has_w) ld<P>(a.w, i, w);
-#pragma unroll
-        for (int s = 0; s < 4; s++)
-#pragma unroll
-          for (int k = 0; k < 3; k++) {
-            nn += norm2(z[s][k]);
-            if (a.has_w) {
-              cx<double> q = cmulc(z[s][k], w[s][k]);
-              wr += q.re;
-              wi += q.im;
-            }
-          }
-      }
-    }
+    maxpy_triple<P, N, 0>(a, i, cf, nn, wr, wi);
+    if (a.ntriples > 1) maxpy_triple<P, N, 1>(a, i, cf, nn, wr, wi);
   }
   if (a.want_norms) {
     double s0 = block_sum(nn, sh);
@@ -184,7 +192,7 @@ __global__ void maxpy_kernel(MaxpyArgs<P> a, int64_t first, int64_t count, doubl
 
 // y -= (num / den) x  with num complex (device), den real (device); then |y|^2.
 template <int P>
-__global__ void update_kernel(Spinor<P> y, Spinor<P> x, const double *num, const double *den,
+__global__ void __launch_bounds__(BT) update_kernel(Spinor<P> y, Spinor<P> x, const double *num, const double *den,
                               int negate, int64_t first, int64_t count, double *partial) {
   __shared__ double sh[4];
   double d = den ? *den : 1.0;
@@ -214,7 +222,7 @@ __global__ void update_kernel(Spinor<P> y, Spinor<P> x, const double *num, const
 // y_Q = a * y_Q + b * x_P (a, b real; y may be absent: a = 0 and y not read);
 // optional |y|^2.
 template <int Q, int P>
-__global__ void axpby_kernel(Spinor<Q> y, double a, Spinor<P> x, double b, int64_t first,
+__global__ void __launch_bounds__(BT) axpby_kernel(Spinor<Q> y, double a, Spinor<P> x, double b, int64_t first,
                              int64_t count, double *partial) {
   __shared__ double sh[4];
   double nn = 0.0;
@@ -251,7 +259,7 @@ __global__ void axpby_kernel(Spinor<Q> y, double a, Spinor<P> x, double b, int64
 
 // |x|^2 and a finiteness check
 template <int P>
-__global__ void norm_kernel(Spinor<P> x, int64_t first, int64_t count, double *partial) {
+__global__ void __launch_bounds__(BT) norm_kernel(Spinor<P> x, int64_t first, int64_t count, double *partial) {
   __shared__ double sh[4];
   double nn = 0.0;
   for (int64_t t = (int64_t)blockIdx.x * BT + threadIdx.x; t < count; t += (int64_t)gridDim.x * BT) {
@@ -290,7 +298,7 @@ __device__ __forceinline__ void ldg_group(const typename St<P>::pair_t *base, in
 
 // partial[(base + 2l (+1)) * grid + blk] = block sums of (y_l, x) over groups [g0, g0 + ng)
 template <int P, int N>
-__global__ void mdot_flat_kernel(VecList<P> ys, Spinor<P> x, int64_t g0, int64_t ng, double *partial,
+__global__ void __launch_bounds__(BT) mdot_flat_kernel(VecList<P> ys, Spinor<P> x, int64_t g0, int64_t ng, double *partial,
                                  int base) {
   constexpr int W = VW<P>;
   __shared__ double sh[4 * 2 * N];
@@ -319,7 +327,7 @@ __global__ void mdot_flat_kernel(VecList<P> ys, Spinor<P> x, int64_t g0, int64_t
 // z_t = src_t - sum_l cf_l ys_t[l] over groups; norms of the stored z_0 (the
 // value rounded to the storage precision, as a later read would see it)
 template <int P, int N>
-__global__ void maxpy_flat_kernel(MaxpyArgs<P> a, int64_t g0, int64_t ng, double *partial) {
+__global__ void __launch_bounds__(BT) maxpy_flat_kernel(MaxpyArgs<P> a, int64_t g0, int64_t ng, double *partial) {
   constexpr int W = VW<P>;
   using C = typename St<P>::comp_t;
   __shared__ double sh[12];
@@ -436,7 +444,7 @@ __device__ __forceinline__ Spinor<P> vec_view(const GsSlot<P> &s, int l, int64_t
 
 // partial[(y * 2 MAXV + 2l (+1)) * gx + bx] = block sums of (chi_l, chi_k)
 template <int P>
-__global__ void gs_dot_kernel(const GsSlot<P> *slots, int64_t ng, double *partial) {
+__global__ void __launch_bounds__(BT) gs_dot_kernel(const GsSlot<P> *slots, int64_t ng, double *partial) {
   constexpr int W = VW<P>;
   __shared__ double sh[4 * 2 * GS_CH];
   const GsSlot<P> s = slots[blockIdx.y];
@@ -486,7 +494,7 @@ __global__ void gs_dot_kernel(const GsSlot<P> *slots, int64_t ng, double *partia
 
 // chi_k -= sum_l ak_l chi_l; partial values 0..2 = |chi_k|^2, (chi_k, rho)
 template <int P>
-__global__ void gs_axpy_kernel(const GsSlot<P> *slots, int64_t ng, double *partial) {
+__global__ void __launch_bounds__(BT) gs_axpy_kernel(const GsSlot<P> *slots, int64_t ng, double *partial) {
   constexpr int W = VW<P>;
   __shared__ double sh[12];
   __shared__ double cfs[2 * MAXV];  // the coefficients ak, read once per work-group
@@ -524,7 +532,7 @@ __global__ void gs_axpy_kernel(const GsSlot<P> *slots, int64_t ng, double *parti
 
 // rho -= (rec[3k+1..2] / rec[3k]) chi_k; partial value 0 = |rho|^2
 template <int P>
-__global__ void gs_update_kernel(const GsSlot<P> *slots, int64_t ng, double *partial) {
+__global__ void __launch_bounds__(BT) gs_update_kernel(const GsSlot<P> *slots, int64_t ng, double *partial) {
   constexpr int W = VW<P>;
   __shared__ double sh[4];
   const GsSlot<P> s = slots[blockIdx.y];
@@ -551,7 +559,7 @@ __global__ void gs_update_kernel(const GsSlot<P> *slots, int64_t ng, double *par
 // gs_dot_kernel, gs_axpy_kernel and gs_update_kernel, with whole spinors
 // loaded and stored through the scaled format.
 template <int P>
-__global__ void gs_dot_site_kernel(const GsSlot<P> *slots, int64_t nsites, RunDiv rd, double *partial) {
+__global__ void __launch_bounds__(BT) gs_dot_site_kernel(const GsSlot<P> *slots, int64_t nsites, RunDiv rd, double *partial) {
   __shared__ double sh[4 * 2 * GS_CH];
   const GsSlot<P> s = slots[blockIdx.y];
   const int k = s.k, gx = gridDim.x;
@@ -600,7 +608,7 @@ __global__ void gs_dot_site_kernel(const GsSlot<P> *slots, int64_t nsites, RunDi
 }
 
 template <int P>
-__global__ void gs_axpy_site_kernel(const GsSlot<P> *slots, int64_t nsites, RunDiv rd, double *partial) {
+__global__ void __launch_bounds__(BT) gs_axpy_site_kernel(const GsSlot<P> *slots, int64_t nsites, RunDiv rd, double *partial) {
   __shared__ double sh[12];
   __shared__ double cfs[2 * MAXV];
   const GsSlot<P> s = slots[blockIdx.y];
@@ -641,7 +649,7 @@ __global__ void gs_axpy_site_kernel(const GsSlot<P> *slots, int64_t nsites, RunD
 }
 
 template <int P>
-__global__ void gs_update_site_kernel(const GsSlot<P> *slots, int64_t nsites, RunDiv rd, double *partial) {
+__global__ void __launch_bounds__(BT) gs_update_site_kernel(const GsSlot<P> *slots, int64_t nsites, RunDiv rd, double *partial) {
   __shared__ double sh[4];
   const GsSlot<P> s = slots[blockIdx.y];
   const int k = s.k, gx = gridDim.x;
@@ -673,7 +681,7 @@ __global__ void gs_update_site_kernel(const GsSlot<P> *slots, int64_t nsites, Ru
 // order and write the results.  phase 0: ak_l = dot_l / rec[3l] (l < k);
 // phase 1: rec[3k..3k+2]; phase 2: *norm.
 template <int P>
-__global__ void gs_finish_kernel(const GsSlot<P> *slots, int gx, const double *partial, int phase) {
+__global__ void __launch_bounds__(BT) gs_finish_kernel(const GsSlot<P> *slots, int gx, const double *partial, int phase) {
   constexpr int K = 16;
   __shared__ double sh[4 * K], res[K];
   const GsSlot<P> s = slots[blockIdx.x];

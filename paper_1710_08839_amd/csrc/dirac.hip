@@ -556,7 +556,11 @@ int tune_group(int prec, DiracKind kind, const Geom &g, const OpFields &f, Spino
   const bool fits = (half ? g.Vbh : 2 * g.Vbh) <= 256;
   const bool cstar = g.N[1] == 2 * g.L1;
   const bool b44 = g.b[0] == 4 && g.b[1] == 4 && g.b[2] == 4 && g.b[3] == 4;
-  std::vector<int> cands = {1, 2, 4, 8};
+  // FP64 with groups of 8 hops exceeds the register file and spills to
+  // private memory (slower, and that memory is allocated at dispatch): it is
+  // left out of the search
+  std::vector<int> cands = {1, 2, 4};
+  if (prec != QXD_F64) cands.push_back(8);
   if (fits) {
     for (int c : {L | 1, L | 2, L | 4, L | N | 1, L | N | 2, L | N | 4}) cands.push_back(c);
     if (cstar)

@@ -45,7 +45,8 @@ __global__ void orbifold_kernel(Geom g, const double *u_phs, const double *a_phs
   int64_t j = phys_lex(g, x, mirror);
   const uint32_t el = g.rd.base((uint32_t)i, 36), ea = g.rd.base((uint32_t)i, 4);
   for (int mu = 0; mu < 4; mu++) {
-    bool cut = g.time_bc == 1 && mu == 0 && x[0] == g.N[0] - 1;
+    // an open time end (open, open-SF) cuts the links across x0 = T-1 -> 0
+    bool cut = (g.time_bc == 1 || g.time_bc == 3) && mu == 0 && x[0] == g.N[0] - 1;
     const double *u = u_phs + (j * 4 + mu) * 18;
     for (int k = 0; k < 9; k++) {
       double re = u[2 * k], im = u[2 * k + 1];
@@ -62,22 +63,53 @@ __global__ void orbifold_kernel(Geom g, const double *u_phs, const double *a_phs
 __device__ __forceinline__ cx<double> zlink(const Geom &g, const double *angles, int mu,
                                             int64_t i, const Site &s) {
   int x0 = s.B(0) * g.b[0] + s.y(0);
-  if (g.time_bc == 1 && mu == 0 && x0 == g.N[0] - 1) return {0.0, 0.0};
+  if ((g.time_bc == 1 || g.time_bc == 3) && mu == 0 && x0 == g.N[0] - 1) return {0.0, 0.0};
   double sn, cs;
   sincos(angles[g.rd.base((uint32_t)i, 4) + mu * g.Vbh], &sn, &cs);
   return {cs, sn};
 }
 
-__global__ void pauli_build_kernel(Geom g, const double2 *links, const double *angles, int has_u1,
-                                   double kappa, double csw, double u1coef, double2 *pauli) {
+__global__ void __launch_bounds__(128) pauli_build_kernel(Geom g, const double2 *links, const double *angles, int has_u1,
+                                   double kappa, double csw, double u1coef, double cF, double cFp,
+                                   double2 *pauli) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.V) return;
   Site s = decode(g, i);
-  // G_p = csw F_p + u1coef * Ahat'_p for the planes (01,02,03,12,13,23)
-  M3 gp[6];
-  int p = 0;
-  for (int mu = 0; mu < 4; mu++)
-    for (int nu = mu + 1; nu < 4; nu++, p++) {
+  const int x0 = s.B(0) * g.b[0] + s.y(0), t1 = g.N[0] - 1;
+  if ((g.time_bc == 2 || g.time_bc == 3) && x0 == 0) {
+    // the fixed slice of SF / open-SF: identity
+    const uint32_t e = g.rd.base((uint32_t)i, 36);
+    for (int blk = 0; blk < 2; blk++) {
+      for (int k = 0; k < 3; k++) pauli[e + (18 * blk + k) * g.Vbh] = make_double2(1.0, 1.0);
+      for (int k = 3; k < 18; k++) pauli[e + (18 * blk + k) * g.Vbh] = make_double2(0.0, 0.0);
+    }
+    return;
+  }
+  // dD_b = (c_F - 1) on x0 = 0, T-1 (open); x0 = 1, T-1 (SF); (c_F - 1) on
+  // x0 = 1 and (c_F' - 1) on x0 = T-1 (open-SF)
+  double dbt = 0.0;
+  if (g.time_bc == 1 && (x0 == 0 || x0 == t1)) dbt = cF - 1.0;
+  if (g.time_bc == 2 && (x0 == 1 || x0 == t1)) dbt = cF - 1.0;
+  if (g.time_bc == 3) dbt = x0 == t1 ? cFp - 1.0 : (x0 == 1 ? cF - 1.0 : 0.0);
+  // The chiral blocks are A = d + [[h3, h1 - i h2], [h1 + i h2, -h3]] with
+  // h_l = (i/2) M_l and M_l = +-G_0l - B_l, B = (G_23, -G_13, G_12), where
+  // G_p = csw F_p + u1coef * Ahat'_p.  The planes (01,02,03,12,13,23) are
+  // taken one at a time (a rolled loop: one plane's links live at once) and
+  // each adds its share to the upper triangles of both blocks, held in
+  // registers under compile-time indices (no private memory).
+  cx<double> ul[2][3][3], lr[2][3][3], ur[2][3][3];  // upper-left, lower-right (a <= b), upper-right
+#pragma unroll
+  for (int blk = 0; blk < 2; blk++)
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+      for (int b = 0; b < 3; b++) ul[blk][a][b] = lr[blk][a][b] = ur[blk][a][b] = cx<double>{0.0, 0.0};
+#pragma unroll 1
+  for (int p = 0; p < 6; p++) {
+    const int mu = p < 3 ? 0 : (p < 5 ? 1 : 2);
+    const int nu = p < 3 ? p + 1 : (p < 5 ? p - 1 : 3);
+    M3 gp;
+    {
       int sg;
       Site xpm = neighbour(g, s, mu, 1, sg), xpn = neighbour(g, s, nu, 1, sg);
       Site xmm = neighbour(g, s, mu, -1, sg), xmn = neighbour(g, s, nu, -1, sg);
@@ -86,14 +118,48 @@ __global__ void pauli_build_kernel(Geom g, const double2 *links, const double *a
       int64_t ixpm = encode(g, xpm), ixpn = encode(g, xpn), ixmm = encode(g, xmm),
               ixmn = encode(g, xmn), ixmm_pn = encode(g, xmm_pn), ixmm_mn = encode(g, xmm_mn),
               ixpm_mn = encode(g, xpm_mn);
-      M3 q1 = mul(mul(ld_u(links, g, mu, i), ld_u(links, g, nu, ixpm)),
-                  mul(dag(ld_u(links, g, mu, ixpn)), dag(ld_u(links, g, nu, i))));
-      M3 q2 = mul(mul(ld_u(links, g, nu, i), dag(ld_u(links, g, mu, ixmm_pn))),
-                  mul(dag(ld_u(links, g, nu, ixmm)), ld_u(links, g, mu, ixmm)));
-      M3 q3 = mul(mul(dag(ld_u(links, g, mu, ixmm)), dag(ld_u(links, g, nu, ixmm_mn))),
-                  mul(ld_u(links, g, mu, ixmm_mn), ld_u(links, g, nu, ixmn)));
-      M3 q4 = mul(mul(dag(ld_u(links, g, nu, ixmn)), ld_u(links, g, mu, ixmn)),
-                  mul(ld_u(links, g, nu, ixpm_mn), dag(ld_u(links, g, mu, i))));
+      // clover leaves q1..q4 (anticlockwise from x in the (mu, nu) plane),
+      // each the product of four links; the sixteen factors are taken in a
+      // rolled loop so that one link, the running product and the leaf sum
+      // are all that live at once
+      M3 qsum, prod;
+#pragma unroll
+      for (int a = 0; a < 3; a++)
+#pragma unroll
+        for (int b = 0; b < 3; b++) qsum.m[a][b] = prod.m[a][b] = cx<double>{0.0, 0.0};
+#pragma unroll 1
+      for (int t = 0; t < 16; t++) {
+        const int leaf = t >> 2, fct = t & 3;
+        int64_t y;
+        int dir;
+        bool dg;
+        if (leaf == 0) {         // U_mu(x) U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
+          y = fct == 0 ? (int64_t)i : fct == 1 ? ixpm : fct == 2 ? ixpn : (int64_t)i;
+          dir = (fct & 1) ? nu : mu;
+          dg = fct >= 2;
+        } else if (leaf == 1) {  // U_nu(x) U_mu(x-mu+nu)^+ U_nu(x-mu)^+ U_mu(x-mu)
+          y = fct == 0 ? (int64_t)i : fct == 1 ? ixmm_pn : ixmm;
+          dir = (fct & 1) ? mu : nu;
+          dg = fct == 1 || fct == 2;
+        } else if (leaf == 2) {  // U_mu(x-mu)^+ U_nu(x-mu-nu)^+ U_mu(x-mu-nu) U_nu(x-nu)
+          y = fct == 0 ? ixmm : fct == 3 ? ixmn : ixmm_mn;
+          dir = (fct & 1) ? nu : mu;
+          dg = fct <= 1;
+        } else {                 // U_nu(x-nu)^+ U_mu(x-nu) U_nu(x+mu-nu) U_mu(x)^+
+          y = fct <= 1 ? ixmn : fct == 2 ? ixpm_mn : (int64_t)i;
+          dir = (fct & 1) ? mu : nu;
+          dg = fct == 0 || fct == 3;
+        }
+        M3 u = ld_u(links, g, dir, y);
+        if (dg) u = dag(u);
+        prod = fct == 0 ? u : mul(prod, u);
+        if (fct == 3) {
+#pragma unroll
+          for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int b = 0; b < 3; b++) qsum.m[a][b] = qsum.m[a][b] + prod.m[a][b];
+        }
+      }
       double ah = 0.0;  // Ahat' = i * ah
       if (has_u1) {
         auto zp = [&](int64_t y, const Site &sy, int64_t ypm, const Site &sypm, int64_t ypn,
@@ -106,52 +172,65 @@ __global__ void pauli_build_kernel(Geom g, const double2 *links, const double *a
                         zp(ixmm_mn, xmm_mn, ixmn, xmn, ixmm, xmm);
         ah = 0.25 * zs.im;
       }
+#pragma unroll
       for (int a = 0; a < 3; a++)
+#pragma unroll
         for (int b = 0; b < 3; b++) {
-          cx<double> qs = q1.m[a][b] + q2.m[a][b] + q3.m[a][b] + q4.m[a][b];
-          cx<double> qt = q1.m[b][a] + q2.m[b][a] + q3.m[b][a] + q4.m[b][a];
-          cx<double> f = 0.125 * (qs - conj(qt));
-          gp[p].m[a][b] = csw * f;
+          cx<double> f = 0.125 * (qsum.m[a][b] - conj(qsum.m[b][a]));
+          gp.m[a][b] = csw * f;
         }
-      for (int a = 0; a < 3; a++) gp[p].m[a][a].im += u1coef * ah;
+#pragma unroll
+      for (int a = 0; a < 3; a++) gp.m[a][a].im += u1coef * ah;
     }
-  // chiral blocks: M_l = +-G_0l - B_l, B = (G_23, -G_13, G_12); H_l = (i/2) M_l
-  double d = 0.5 / kappa;
+    // plane p enters M_l (l = 1, 2, 3 for 01/23, 02/13, 03/12) with weight
+    // +-1 (the sign of the block) for the planes 0l, and -1, +1, -1 for
+    // 12, 13, 23
+    const int l = (p == 0 || p == 5) ? 1 : ((p == 1 || p == 4) ? 2 : 3);
+#pragma unroll
+    for (int blk = 0; blk < 2; blk++) {
+      const double c = p < 3 ? (blk == 0 ? 0.5 : -0.5) : (p == 4 ? 0.5 : -0.5);
+      const double w3 = l == 3 ? c : 0.0, w1 = l == 1 ? c : 0.0, w2 = l == 2 ? c : 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; a++)
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+          const cx<double> ig = times_i(gp.m[a][b]);
+          if (a <= b) {
+            ul[blk][a][b] = ul[blk][a][b] + w3 * ig;
+            lr[blk][a][b] = lr[blk][a][b] - w3 * ig;
+          }
+          ur[blk][a][b] = ur[blk][a][b] + w1 * ig + w2 * gp.m[a][b];
+        }
+    }
+  }
+  const double d = 0.5 / kappa + dbt;
+  const uint32_t e = g.rd.base((uint32_t)i, 36);
+#pragma unroll
   for (int blk = 0; blk < 2; blk++) {
-    double sgn = blk == 0 ? 1.0 : -1.0;
-    M3 h[3];
-    for (int a = 0; a < 3; a++)
-      for (int b = 0; b < 3; b++) {
-        cx<double> m1 = sgn * gp[0].m[a][b] - gp[5].m[a][b];
-        cx<double> m2 = sgn * gp[1].m[a][b] + gp[4].m[a][b];
-        cx<double> m3 = sgn * gp[2].m[a][b] - gp[3].m[a][b];
-        h[0].m[a][b] = 0.5 * times_i(m1);
-        h[1].m[a][b] = 0.5 * times_i(m2);
-        h[2].m[a][b] = 0.5 * times_i(m3);
-      }
-    cx<double> A[6][6];
-    for (int a = 0; a < 3; a++)
-      for (int b = 0; b < 3; b++) {
-        cx<double> dd{a == b ? d : 0.0, 0.0};
-        A[a][b] = dd + h[2].m[a][b];
-        A[a][3 + b] = h[0].m[a][b] - times_i(h[1].m[a][b]);
-        A[3 + a][b] = h[0].m[a][b] + times_i(h[1].m[a][b]);
-        A[3 + a][3 + b] = dd - h[2].m[a][b];
-      }
-    int base = 18 * blk;
-    const uint32_t e = g.rd.base((uint32_t)i, 36);
+    // A[r][c] for r <= c: rows/columns 0..2 upper, 3..5 lower chirality-block spin
+    auto entry = [&](int r, int c) -> cx<double> {
+      if (c < 3) return ul[blk][r][c];
+      if (r >= 3) return lr[blk][r - 3][c - 3];
+      return ur[blk][r][c - 3];
+    };
+    const int base = 18 * blk;
+#pragma unroll
     for (int k = 0; k < 3; k++)
-      pauli[e + (base + k) * g.Vbh] = make_double2(A[2 * k][2 * k].re, A[2 * k + 1][2 * k + 1].re);
+      pauli[e + (base + k) * g.Vbh] = make_double2(d + entry(2 * k, 2 * k).re, d + entry(2 * k + 1, 2 * k + 1).re);
+#pragma unroll
     for (int r = 0; r < 6; r++)
-      for (int c = r + 1; c < 6; c++)
-        pauli[e + (base + 3 + tri_index(r, c)) * g.Vbh] = make_double2(A[r][c].re, A[r][c].im);
+#pragma unroll
+      for (int c = r + 1; c < 6; c++) {
+        const cx<double> v = entry(r, c);
+        pauli[e + (base + 3 + tri_index(r, c)) * g.Vbh] = make_double2(v.re, v.im);
+      }
   }
 }
 
 // In-place Gauss-Jordan inverse of a Hermitian positive-definite 6x6 block
 // (no pivoting is needed for positive-definite matrices; a non-positive or
 // tiny pivot is reported as singular).
-__global__ void pauli_invert_kernel(Geom g, const double2 *pauli, double2 *pinv, int *bad) {
+__global__ void __launch_bounds__(128) pauli_invert_kernel(Geom g, const double2 *pauli, double2 *pinv, int *bad) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 2 * g.Vh) return;
   int blk = t / g.Vh;
@@ -280,15 +359,15 @@ __global__ void fold_phase_kernel(Geom g, const double2 *links, const double *an
   uint32_t i = (uint32_t)(t - (int64_t)mu * g.V);
   const uint32_t el = g.rd.base(i, 36);
   double phase = qhat * angles[g.rd.base(i, 4) + mu * g.Vbh];
-  if (th.t[mu] != 0.0) {
-    const Site s = decode(g, (int)i);
-    int x[4];
-    global_coords(g, s, x);
-    if (x[mu] == g.N[mu] - 1) phase += (g.N[1] != g.L1 && x[1] >= g.L1) ? -th.t[mu] : th.t[mu];
-  }
+  const Site s = decode(g, (int)i);
+  int x[4];
+  global_coords(g, s, x);
+  if (th.t[mu] != 0.0 && x[mu] == g.N[mu] - 1) phase += (g.N[1] != g.L1 && x[1] >= g.L1) ? -th.t[mu] : th.t[mu];
   double sn, cs;
   sincos(phase, &sn, &cs);
   cx<double> z{cs, sn};
+  // SF / open-SF: no hop enters or leaves the fixed slice x0 = 0
+  if ((g.time_bc == 2 || g.time_bc == 3) && x[0] == 0) z = {0.0, 0.0};
   for (int k = 0; k < 9; k++) {
     double2 u = links[el + (mu * 9 + k) * g.Vbh];
     cx<double> r = cx<double>{u.x, u.y} * z;
@@ -414,10 +493,10 @@ hipError_t launch_orbifold(const Geom &g, const double *u_phs, const double *a_p
 }
 
 hipError_t launch_pauli_build(const Geom &g, const double2 *links, const double *angles, int has_u1,
-                              double kappa, double csw, double u1coef, double2 *pauli,
-                              hipStream_t st) {
+                              double kappa, double csw, double u1coef, double cF, double cFp,
+                              double2 *pauli, hipStream_t st) {
   pauli_build_kernel<<<grid_for(g.V, 128), 128, 0, st>>>(g, links, angles, has_u1, kappa, csw,
-                                                         u1coef, pauli);
+                                                         u1coef, cF, cFp, pauli);
   return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <array>
+#include <atomic>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -52,6 +53,7 @@ struct Operator {
   int qhat = 0;
   int users = 0;           // solver slots holding it (guarded by the field's mutex)
   uint64_t last_use = 0;   // for least-recently-used eviction
+  size_t bytes = 0;        // device bytes of its fields built so far
   DevBuf pauli[4];   // indexed by qxd_prec
   DevBuf pinv[4];
   DevBuf wl[4];      // hopping links W = U z^qhat with the phase folded in
@@ -80,6 +82,13 @@ struct Field {
   // device bytes still to be allocated for the operators of these quarks
   // (distinct ones, not yet built in FP64 and precision prec)
   size_t pending_op_bytes(const qxd_quark *quarks, int n, int prec);
+  // as pending_op_bytes for one quark without waiting for the field's lock:
+  // if another thread holds it, the whole operator counts as pending (for
+  // callers that hold other locks the field's users may take after it)
+  size_t pending_op_bytes_nowait(const qxd_quark &q, int prec);
+  // device bytes of the operators resident on this field (built and cached),
+  // readable without the field's lock
+  std::atomic<size_t> op_mem{0};
   std::map<std::string, std::unique_ptr<DevBuf>> work;  // named workspaces
   std::recursive_mutex mu;
 

@@ -14,9 +14,11 @@ namespace qxd {
 hipError_t launch_orbifold(const Geom &g, const double *u_phs, const double *a_phs,
                            double2 *links, double *angles, hipStream_t st);
 
-// Pauli term P = 4 + m0 + dD_sw (Sec. 2.3) in FP64, packed Hermitian blocks.
+// Pauli term P = 4 + m0 + dD_sw + dD_b (Sec. 2.3) in FP64, packed Hermitian
+// blocks; dD_b from the time boundary type of g with the coefficients cF, cFp;
+// the identity on the fixed slice x0 = 0 of SF and open-SF boundaries.
 hipError_t launch_pauli_build(const Geom &g, const double2 *links, const double *angles,
-                              int has_u1, double kappa, double csw, double u1coef,
+                              int has_u1, double kappa, double csw, double u1coef, double cF, double cFp,
                               double2 *pauli, hipStream_t st);
 
 // Inverse blocks of P on odd sites (D_oo^-1); *bad counts singular blocks.

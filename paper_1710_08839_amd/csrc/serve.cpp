@@ -12,9 +12,21 @@
 //
 // Memory charged against the budget: for every group, the larger of the
 // solver slots its worker holds (slots are pooled for reuse and released when
-// the group runs idle) and the slots its admitted right-hand sides need; plus,
-// for every admitted request, the operator (Pauli term, inverse, folded links)
-// it may build.
+// the group runs idle) and the slots its admitted right-hand sides need; the
+// operators (Pauli term, inverse, folded links) the fields of the requests
+// have built and keep cached; and, for every admitted request whose operator
+// was not built at admission, that operator until its worker has built it
+// (from then on the field's cache accounts for it).  Operators a field
+// already held when the scheduler first saw it are not charged: they were
+// outside the free memory a default budget is taken from.
+//
+// Besides the budget, a request is admitted only while the device's free
+// memory, less what admitted work has still to allocate (slots and
+// operators), covers what the request will allocate plus a floor kept for
+// the runtime (kernels' private memory is allocated at dispatch, and a
+// dispatch that cannot get it ends the process) and other users of the
+// device.  Nothing else in the process is counted, so this check bounds what
+// the budget cannot see.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -28,6 +40,7 @@
 
 #include "batch_solver.h"
 #include "host.h"
+#include "qxd_debug.h"
 #include "solver.h"
 
 using namespace qxd;
@@ -46,7 +59,7 @@ struct Req {
   int status = QXD_OK;
   int max_iters = 0;
   double max_res = 0;
-  size_t op_bytes = 0;  // operator memory charged for this request
+  size_t op_bytes = 0;  // charged operator memory not yet built (cleared once built or done)
 };
 
 struct Rhs {  // one right-hand side handed to a worker
@@ -77,7 +90,11 @@ struct qxd_serve {
   std::map<uint64_t, std::unique_ptr<Req>> reqs;
   std::map<uint64_t, qxd_result> results;
   std::map<GroupKey, std::unique_ptr<Worker>> workers;
-  size_t op_used = 0;  // operator memory charged for admitted requests
+  size_t op_pending = 0;  // operators admitted requests still have to build
+  // fields of the requests seen, with the operator bytes they held when first
+  // seen (growth beyond that is charged: what they held is already outside
+  // the device memory the budget was taken from)
+  std::vector<std::pair<qxd_field *, size_t>> fields;
   int active_rhs = 0;
   std::thread sched;
   std::string error;
@@ -134,6 +151,7 @@ struct Worker {
             take.clear();
           }
         }
+        std::vector<Req *> built;  // requests whose operator now exists
         for (auto &x : take) {
           qxd_status s = bs->add(x.req->r.quark, x.req->r.eta_dev + (int64_t)x.idx * 24 * f->g.V,
                                  x.req->r.psi_dev + (int64_t)x.idx * 24 * f->g.V, false, x.req);
@@ -143,6 +161,16 @@ struct Worker {
             e.tag = x.req;
             e.info = qxd_solve_info{s, 0, 0, 0.0, 0.0};
             fin.push_back(e);
+          } else {
+            built.push_back(x.req);
+          }
+        }
+        if (!built.empty()) {
+          // the field's operator cache holds these operators now
+          std::lock_guard<std::mutex> lk(sv->mu);
+          for (Req *q : built) {
+            sv->op_pending -= q->op_bytes;
+            q->op_bytes = 0;
           }
         }
         if (bs->active() > 0) {
@@ -177,7 +205,8 @@ struct Worker {
             res.inner_iters = q->max_iters;
             res.true_resid = q->max_res;
             sv->results[q->ticket] = res;
-            sv->op_used -= q->op_bytes;
+            sv->op_pending -= q->op_bytes;
+            q->op_bytes = 0;
           }
         }
         sv->cv.notify_all();
@@ -201,6 +230,9 @@ struct Worker {
   }
 };
 
+// free device memory admission leaves untouched: 4 GiB plus 2% of the device
+static size_t device_floor(size_t total) { return ((size_t)4 << 30) + total / 50; }
+
 static void scheduler(qxd_serve *sv) {
   (void)hipSetDevice(sv->ctx->device);
   std::unique_lock<std::mutex> lk(sv->mu);
@@ -210,16 +242,40 @@ static void scheduler(qxd_serve *sv) {
       Req *q = sv->queue.front();
       qxd_field *f = q->r.field;
       const size_t slot_b = BatchSolver::slot_bytes(f, q->r.solver.inner_prec, q->r.solver);
-      const size_t op_b = f->op_bytes(q->r.solver.inner_prec);
+      const size_t op_b = f->pending_op_bytes_nowait(q->r.quark, q->r.solver.inner_prec);
+      if (std::find_if(sv->fields.begin(), sv->fields.end(), [&](const std::pair<qxd_field *, size_t> &x) {
+            return x.first == f;
+          }) == sv->fields.end())
+        sv->fields.emplace_back(f, f->op_mem.load());
       GroupKey gk = key_of(q->r);
       auto wit = sv->workers.find(gk);
       Worker *w0 = wit == sv->workers.end() ? nullptr : wit->second.get();
-      size_t used = sv->op_used;
-      for (auto &kv : sv->workers) used += kv.second->charge();
+      // work charged for admitted requests (slots, operators being built),
+      // and the operators resident on the fields (built and cached)
+      size_t work = sv->op_pending, resident = 0;
+      for (auto &kv : sv->workers) work += kv.second->charge();
+      for (auto &fd : sv->fields) {
+        const size_t now = fd.first->op_mem.load();
+        resident += now > fd.second ? now - fd.second : 0;
+      }
       const size_t before = w0 ? w0->charge() : 0;
       const size_t after = w0 ? std::max(w0->held, (size_t)(w0->admitted + q->r.nrhs) * slot_b)
                               : (size_t)q->r.nrhs * slot_b;
-      bool fits = used - before + after + op_b <= sv->budget || used == 0;
+      // what admitted work has still to allocate, with this request
+      size_t to_alloc = sv->op_pending + op_b;
+      for (auto &kv : sv->workers) {
+        const Worker *w = kv.second.get();
+        const size_t need = (size_t)(w->admitted + (w == w0 ? q->r.nrhs : 0)) * w->slot_b;
+        to_alloc += need > w->held ? need - w->held : 0;
+      }
+      if (!w0) to_alloc += (size_t)q->r.nrhs * slot_b;
+      size_t dev_free = 0, dev_total = 0;
+      bool dev_ok = hipMemGetInfo(&dev_free, &dev_total) == hipSuccess;
+      dev_ok = dev_ok && dev_free >= to_alloc && dev_free - to_alloc >= device_floor(dev_total);
+      // one request always runs when no other work is charged, whatever the
+      // cached operators hold (if the device cannot hold it, its solve ends
+      // with QXD_ENOMEM)
+      bool fits = (work - before + after + op_b + resident <= sv->budget && dev_ok) || work == 0;
       bool room = sv->max_active <= 0 || sv->active_rhs + q->r.nrhs <= sv->max_active || sv->active_rhs == 0;
       if (!fits || !room) break;
       sv->queue.pop_front();
@@ -244,7 +300,7 @@ static void scheduler(qxd_serve *sv) {
       q->t_admit = now_s();
       q->remaining = q->r.nrhs;
       q->op_bytes = op_b;
-      sv->op_used += op_b;
+      sv->op_pending += op_b;
       w->admitted += q->r.nrhs;
       sv->active_rhs += q->r.nrhs;
       for (int i = 0; i < q->r.nrhs; i++) w->inbox.push_back(Rhs{q, i});
@@ -275,6 +331,26 @@ static bool valid_request(const qxd_request *r) {
 }
 
 extern "C" {
+
+qxd_status qxd_debug_serve_charges(qxd_ctx *ctx, size_t out[4]) {
+  if (!ctx || !ctx->serve || !out) {
+    set_error("serving not started or out is NULL");
+    return QXD_EINVAL;
+  }
+  qxd_serve *sv = ctx->serve;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  size_t resident = 0, slots = 0;
+  for (auto &fd : sv->fields) {
+    const size_t now = fd.first->op_mem.load();
+    resident += now > fd.second ? now - fd.second : 0;
+  }
+  for (auto &kv : sv->workers) slots += kv.second->charge();
+  out[0] = sv->op_pending;
+  out[1] = resident;
+  out[2] = slots;
+  out[3] = sv->budget;
+  return QXD_OK;
+}
 
 qxd_status qxd_serve_start(qxd_ctx *ctx, size_t budget_bytes, int max_active) {
   if (!ctx) {

@@ -274,6 +274,72 @@ qxd_status sap_apply_t(Field *f, const Operator &op, int ncy, int nmr, void *rho
 
 }  // namespace
 
+namespace {
+template <int P>
+qxd_status sap_pair_pass_t(Field *f, const Operator &op, int nmr, int npair, int reps, float *ms, hipStream_t st) {
+  const Geom &g = f->g;
+  if (!sap_quad_pairs_ok(P, g)) {
+    set_error("the paired SAP kernel does not run on this lattice");
+    return QXD_EINVAL;
+  }
+  const int *lists[2];
+  int nper;
+  CS(sap_block_lists(f, lists, &nper));
+  const int nslot = 2 * npair;
+  const size_t fb = spinor_bytes(P, g.V);
+  Ws w{f, st};
+  char *vecs = (char *)w.get("sap_probe_vecs", fb * 4 * nslot);
+  SapSlot<P> *dslots = (SapSlot<P> *)w.get("sap_probe_slots", sizeof(SapSlot<P>) * nslot);
+  int *dpairs = (int *)w.get("sap_probe_pairs", sizeof(int) * nslot);
+  if (w.err) return w.err;
+  // finite, normal values in every storage format (bytes 0x3c: fp16 1.06,
+  // bfloat16 0.011, fp32 0.011; the FP16 site scales read 0.011)
+  CK(hipMemsetAsync(vecs, 0x3c, fb * 4 * nslot, st));
+  OpFields of = f->op_fields(op, P);
+  std::vector<SapSlot<P>> hs(nslot);
+  std::vector<int> hp(nslot);
+  for (int k = 0; k < nslot; k++) {
+    char *v = vecs + (size_t)4 * k * fb;
+    hs[k].op = SapOp<P>{(const typename St<P>::pair_t *)of.links, nullptr, 0,
+                        (const typename St<P>::pair_t *)of.pauli, (const typename St<P>::pair_t *)of.pinv};
+    hs[k].vec = SapVecs<P>{spinor_view<P>(v, g.V, 0, g), spinor_view<P>(v + fb, g.V, 0, g),
+                           spinor_view<P>(v + 2 * fb, g.V, 0, g), spinor_view<P>(v + 3 * fb, g.V, 0, g)};
+    hp[k] = k;
+  }
+  CK(hipMemcpyAsync(dslots, hs.data(), sizeof(SapSlot<P>) * nslot, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(dpairs, hp.data(), sizeof(int) * nslot, hipMemcpyHostToDevice, st));
+  // one untimed pass, then reps passes of colour 0 with the face update
+  CK(launch_sapq_pairs<P>(g, lists[0], nper, dslots, dpairs, npair, 0, 0, nmr, st));
+  hipEvent_t e0, e1;
+  CK(hipEventCreate(&e0));
+  CK(hipEventCreate(&e1));
+  CK(hipEventRecord(e0, st));
+  for (int r = 0; r < reps; r++) CK(launch_sapq_pairs<P>(g, lists[0], nper, dslots, dpairs, npair, 0, 0, nmr, st));
+  CK(hipEventRecord(e1, st));
+  CK(hipEventSynchronize(e1));
+  float t = 0;
+  CK(hipEventElapsedTime(&t, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = t / reps;
+  return QXD_OK;
+}
+}  // namespace
+
+qxd_status debug_sap_pair_pass(Field *f, const qxd_quark &q, int prec, int nmr, int npair, int reps, float *ms,
+                               hipStream_t st) {
+  CS(check_sap_blocks(f));
+  Operator *op;
+  CS(f->get_op(q, prec, &op, st));
+  switch (prec) {
+    case QXD_F32: return sap_pair_pass_t<QXD_F32>(f, *op, nmr, npair, reps, ms, st);
+    case QXD_F16S: return sap_pair_pass_t<QXD_F16S>(f, *op, nmr, npair, reps, ms, st);
+    case QXD_BF16: return sap_pair_pass_t<QXD_BF16>(f, *op, nmr, npair, reps, ms, st);
+  }
+  set_error("the paired SAP kernel runs in FP32, FP16+scale and BF16 storage");
+  return QXD_EINVAL;
+}
+
 qxd_status check_sap_blocks(const Field *f) {
   const Geom &g = f->g;
   for (int m = 0; m < 4; m++)

@@ -39,6 +39,12 @@ qxd_status rational_apply(Field *f, const qxd_quark &quark, double A, const doub
 qxd_status sap_apply(Field *f, const Operator &op, int prec, int ncy, int nmr, void *rho, void *psi,
                      hipStream_t st);
 
+// Time one colour pass of the paired SAP block solver (two right-hand sides
+// per work-group, as in the batched solve) for npair pairs of synthetic
+// vectors: *ms = average over reps launches (HIP events on st).
+qxd_status debug_sap_pair_pass(Field *f, const qxd_quark &q, int prec, int nmr, int npair, int reps, float *ms,
+                               hipStream_t st);
+
 // Device lists of the block indices of each SAP colour (built on first use).
 qxd_status sap_block_lists(Field *f, const int **lists, int *per_colour);
 

@@ -29,7 +29,8 @@ class QxdError(RuntimeError):
 
 class Lattice(ctypes.Structure):
     _fields_ = [("dims", ctypes.c_int * 4), ("time_bc", ctypes.c_int), ("cstar", ctypes.c_int),
-                ("q_el", ctypes.c_double), ("block", ctypes.c_int * 4)]
+                ("q_el", ctypes.c_double), ("block", ctypes.c_int * 4), ("cF", ctypes.c_double),
+                ("cF_prime", ctypes.c_double)]
 
 
 class Quark(ctypes.Structure):
@@ -91,6 +92,9 @@ SIGNATURES = {
     "qxd_debug_set_dirac_variant": ([_I], _I),
     "qxd_debug_set_step_graphs": ([_I], _I),
     "qxd_debug_fail_steps": ([_I], _I),
+    "qxd_debug_serve_charges": ([_VP, ctypes.POINTER(ctypes.c_size_t)], _I),
+    "qxd_debug_sap_pair_pass": ([_VP, ctypes.POINTER(Quark), _I, _I, _I, _I, ctypes.POINTER(ctypes.c_float), _VP],
+                                _I),
     "qxd_debug_stream": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, _I, ctypes.c_void_p], _I),
     "qxd_debug_step_graph_counts": ([ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], _I),
     "qxd_debug_get_dirac_variant": ([_VP, _I, ctypes.POINTER(_I)], _I),
@@ -210,13 +214,23 @@ class Context:
     def serve_stop(self):
         _check(lib().qxd_serve_stop(self.h))
 
+    def serve_charges(self):
+        """The serve loop's memory accounting (a testing hook): operator bytes
+        admitted requests have still to build, operator bytes the fields have
+        built since serving saw them, solver slot bytes, and the budget."""
+        out = (ctypes.c_size_t * 4)()
+        _check(lib().qxd_debug_serve_charges(self.h, out))
+        return {"op_pending": out[0], "op_resident": out[1], "slots": out[2], "budget": out[3]}
+
 
 class Field:
     """A resident gauge field (physical-lattice U and optional A, host numpy)."""
 
-    def __init__(self, ctx, dims, u, a=None, cstar=0, time_bc=0, q_el=1.0 / 6.0, block=(4, 4, 4, 4)):
+    def __init__(self, ctx, dims, u, a=None, cstar=0, time_bc=0, q_el=1.0 / 6.0, block=(4, 4, 4, 4), cF=1.0,
+                 cF_prime=1.0):
         self.ctx = ctx
-        self.lat = Lattice((ctypes.c_int * 4)(*dims), time_bc, cstar, q_el, (ctypes.c_int * 4)(*block))
+        self.lat = Lattice((ctypes.c_int * 4)(*dims), time_bc, cstar, q_el, (ctypes.c_int * 4)(*block), cF,
+                           cF_prime)
         u = np.ascontiguousarray(u, dtype=np.complex128)
         a_ptr = None
         if a is not None:
@@ -298,6 +312,14 @@ class Field:
         if check and st != 0:
             _check(st)
         return st, list(info)
+
+    def sap_pair_pass_ms(self, q, prec, nmr=4, npair=1, reps=20, stream=None):
+        """Average time (ms) of one colour pass of the paired SAP block
+        solver on synthetic vectors.  A measurement hook."""
+        t = ctypes.c_float(0)
+        _check(lib().qxd_debug_sap_pair_pass(self.h, ctypes.byref(q), int(prec), int(nmr), int(npair), int(reps),
+                                             ctypes.byref(t), _stream(stream)))
+        return t.value
 
     def sap_apply(self, q, prec, ncy, nmr, x, y, nrhs=1, stream=None):
         _check(lib().qxd_sap_apply(self.h, ctypes.byref(q), prec, ncy, nmr, _ptr(x), _ptr(y), nrhs,

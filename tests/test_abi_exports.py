@@ -44,6 +44,7 @@ def test_header_parses():
     assert fns["qxd_debug_set_step_graphs"] == 1
     assert fns["qxd_debug_step_graph_counts"] == 2
     assert fns["qxd_debug_stream"] == 5
+    assert fns["qxd_debug_serve_charges"] == 2
     assert fns["qxd_abi_version"] == 0
     assert fns["qxd_dirac_apply"] == 10
     assert fns["qxd_solve"] == 10
@@ -85,3 +86,5 @@ def test_library_loads_and_reports(libpath):
     assert lib.qxd_debug_set_dirac_variant(0) == 0
     assert lib.qxd_debug_fail_steps(-1) != 0
     assert lib.qxd_debug_fail_steps(0) == 0
+    out = (ctypes.c_size_t * 4)()
+    assert lib.qxd_debug_serve_charges(None, out) != 0

@@ -288,3 +288,46 @@ def test_failed_step_ends_solves_and_requests(ctx, small):
     ph, eh = to_host(psi), to_host(etas)
     for k in range(3):
         assert od.norm(eh[k] - c.op.apply(ph[k])) / od.norm(eh[k]) <= 1.05e-10
+
+
+def test_serve_charges_drain(ctx, small):
+    """Requests with distinct quarks (each builds its own operator) all
+    complete; while they run the operators being built are charged, and once
+    they are done nothing stays charged as pending, the operators left are
+    the field's bounded cache (at most four unused ones), and the groups give
+    their solver slots back when idle."""
+    import torch
+    from paper_1710_08839_amd import qxd
+    c = small
+    s = qxd.solver(kind=qxd.SAP_GCR, tol=1e-10, nkv=6, ncy=2, nmr=3, inner_prec=qxd.F32)
+    kappas = [0.1205 + 0.0007 * j for j in range(8)]
+    etas = [to_dev(c.source(700 + j)[None]) for j in range(len(kappas))]
+    outs = [torch.empty_like(e) for e in etas]
+    torch.cuda.synchronize()
+    ctx.serve_start()
+    try:
+        ts = [ctx.serve_submit(c.field, qxd.quark(k, -1 / 3, 1.5, 1.0), s, e, o, 1)
+              for k, e, o in zip(kappas, etas, outs)]
+        done, t0 = {}, time.time()
+        while len(done) < len(ts) and time.time() - t0 < 60:
+            for t in ts:
+                if t not in done:
+                    r = ctx.serve_poll(t)
+                    if r is not None:
+                        done[t] = r
+            time.sleep(0.005)
+        ch = ctx.serve_charges()
+        t0 = time.time()
+        while ch["slots"] and time.time() - t0 < 10:
+            time.sleep(0.02)
+            ch = ctx.serve_charges()
+    finally:
+        ctx.serve_stop()
+    assert len(done) == len(ts) and all(r.status == 0 for r in done.values())
+    assert ch["op_pending"] == 0 and ch["slots"] == 0
+    one_op = 36 * (2 * c.V + c.V // 2) * (16 + 8)  # Pauli term, inverse, links: FP64 and FP32
+    assert ch["op_resident"] <= 4 * one_op
+    ops = _ops(c, [(k, -1 / 3, 1.5) for k in kappas])
+    for e, o, op in zip(etas, outs, ops):
+        x = to_host(e)[0]
+        assert od.norm(x - op.apply(to_host(o)[0])) / od.norm(x) <= 1.05e-10

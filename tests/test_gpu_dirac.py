@@ -30,6 +30,10 @@ CASES = [
     dict(dims=(4, 4, 4, 4), cstar=1, q=-1 / 3, csw=1.3, block=(2, 4, 2, 2)),
     dict(dims=(6, 4, 4, 2), cstar=2, time_bc=1, q=2 / 3, csw=1.9, block=(2, 2, 2, 2)),
     dict(dims=(8, 4, 4, 4), cstar=3, time_bc=0, q=-1 / 3, csw=1.9, kappa=0.13, block=(4, 4, 4, 4)),
+    # Schroedinger-functional and open-SF time boundaries with c_F, c_F' != 1
+    dict(dims=(8, 4, 4, 4), cstar=3, time_bc=2, q=2 / 3, csw=1.9, kappa=0.13, block=(4, 4, 4, 4), cF=1.3),
+    dict(dims=(8, 8, 8, 8), cstar=0, time_bc=3, q=-1 / 3, csw=1.5, kappa=0.125, block=(4, 4, 4, 4), cF=1.2,
+         cF_prime=0.8),
 ]
 
 

@@ -41,6 +41,21 @@ def open_case(ctx):
 
 
 @pytest.fixture(scope="module")
+def sf_case(ctx):
+    # Schroedinger-functional time boundary: the slice x0 = 0 is fixed, dD_b
+    # with c_F = 1.25 on x0 = 1 and T-1
+    return Case(ctx, (8, 8, 8, 8), cstar=3, time_bc=2, q=-1 / 3, kappa=0.1365, csw=1.9, eps=0.25,
+                seed=20171005, cF=1.25)
+
+
+@pytest.fixture(scope="module")
+def osf_case(ctx):
+    # open-SF: SF at x0 = 0 (c_F on x0 = 1), open at x0 = T-1 (c_F')
+    return Case(ctx, (8, 8, 8, 8), cstar=1, time_bc=3, q=2 / 3, kappa=0.13, csw=1.7, eps=0.25,
+                seed=20171006, cF=1.1, cF_prime=0.85)
+
+
+@pytest.fixture(scope="module")
 def periodic_case(ctx):
     return Case(ctx, (8, 8, 8, 8), cstar=0, u1=False, kappa=0.124, csw=1.0, eps=0.3, seed=20171000)
 
@@ -48,7 +63,8 @@ def periodic_case(ctx):
 @pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5), (2, 1e-2), (3, 1e-2)],
                          ids=["f64", "f32", "f16s", "bf16"])
 @pytest.mark.parametrize("ncy,nmr", [(1, 0), (1, 1), (2, 4)])
-@pytest.mark.parametrize("which", ["cstar_case", "open_case"], ids=["antiperiodic", "open"])
+@pytest.mark.parametrize("which", ["cstar_case", "open_case", "sf_case", "osf_case"],
+                         ids=["antiperiodic", "open", "sf", "open-sf"])
 def test_sap_matches_oracle(request, which, prec, tol, ncy, nmr):
     import torch
     c = request.getfixturevalue(which)
@@ -94,7 +110,8 @@ def test_eo_gcr_f64(periodic_case):
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2, 3], ids=["f64", "f32", "f16s", "bf16"])
-@pytest.mark.parametrize("which", ["cstar_case", "open_case"], ids=["antiperiodic", "open"])
+@pytest.mark.parametrize("which", ["cstar_case", "open_case", "sf_case", "osf_case"],
+                         ids=["antiperiodic", "open", "sf", "open-sf"])
 def test_sap_gcr(request, which, prec):
     import torch
     from paper_1710_08839_amd import qxd
@@ -108,11 +125,12 @@ def test_sap_gcr(request, which, prec):
     _check_solution(c, eta, to_host(psi))
 
 
-def test_eo_gcr_open_time(open_case):
-    """Plain FP64 even-odd GCR with the open time boundary on a C* lattice."""
+@pytest.mark.parametrize("which", ["open_case", "sf_case", "osf_case"], ids=["open", "sf", "open-sf"])
+def test_eo_gcr_time_boundaries(request, which):
+    """Plain FP64 even-odd GCR with the open, SF and open-SF time boundaries."""
     import torch
     from paper_1710_08839_amd import qxd
-    c = open_case
+    c = request.getfixturevalue(which)
     eta = c.source(1005)
     psi = torch.empty_like(to_dev(eta))
     st, info = c.field.solve(c.quark, qxd.solver(kind=qxd.EO_GCR, tol=1e-10, nkv=32), to_dev(eta), psi)
