@@ -18,6 +18,11 @@ code for QCD+QED", Lattice 2017):
               procedure, flexible GCR, defect correction (solvers named in the
               abstract and Sec. 2; the steps follow the literature the paper
               builds on, see each docstring)
+  rational.py multi-shift CG on D^dag D^ + mu^2 and rational functions of it
+              (Sec. 2.4, Table 2)
+  deflation.py  local deflation of the SAP-GCR: deflation subspace, little
+              Dirac operator, deflated preconditioner (abstract, Sec. 2,
+              Appendix A; steps from the published method the paper cites)
   dense.py    dense matrices and brute-force tools for tiny lattices
 
 Parity status: every function is pinned by a CPU test against closed forms,
