@@ -52,7 +52,7 @@ def site_bytes(prec, choice):
 # sources they were taken on (hash of the files below) and for the variant
 # the autotuner picked there (hop group + 16 LDS + 32 non-temporal + 64 mirror).
 KERNEL_FILES = ["dirac.hip", "dirac_site.h", "qxd_impl.h"]
-TRAFFIC = {("8c2a1154d768aed4", 113): 8.138e9}
+TRAFFIC = {("34a0479e4cb9cdce", 113): 8.126e9}
 
 
 def kernel_hash():
@@ -380,6 +380,50 @@ def single_rhs_8x8(ctx):
     return {"fp64_eo_gcr": r}
 
 
+# Algorithmic flops of one SAP colour pass on one 4^4 block (256 sites, 128
+# of each parity) and one right-hand side, counted from the block algorithm
+# with the per-hop and per-Pauli costs of the D count: a hop (projection,
+# SU(3) product on the two-spin half spinor, reconstruction and
+# accumulation) 165 = 1320 / 8, a Pauli block application (two 6x6 Hermitian
+# blocks) 552; complex 12-component axpy 96, dot 96, norm 48, add 24.  An
+# interior site of a 4^4 block has 6 of its 8 neighbours in the block.
+HOP, PAULI = 165, 552
+
+
+def sap_block_flops(nmr):
+    face = 512 * HOP                                        # 8 faces x 64 sites, one hop each
+    prep = 128 * (PAULI + 6 * HOP + 24)                     # rho_e = r_e - D_eo D_oo^-1 r_o
+    mr = nmr * 128 * (12 * HOP + 2 * PAULI + 24 + 96 + 48 + 96 + 96)  # D^ s, dots, two axpys
+    recon = 128 * (6 * HOP + 24 + PAULI)                    # v_o = D_oo^-1 (r_o - D_oe v_e)
+    resid = 256 * (6 * HOP + PAULI + 24) + 256 * 24         # r -= D_Lambda v, psi += v
+    return face + prep + mr + recon + resid
+
+
+FP32_VALU_PEAK_TFLOPS = 78.6  # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz, no packed FP32
+
+
+def sap_leg(f, q, nmr=4, reps=20):
+    """One colour pass of the paired SAP block solver (two right-hand sides
+    sharing the operator per work-group, the kernel that dominates the batched
+    solve) on the 64 x 32^3 lattice, timed with HIP events over reps launches,
+    against the FP32 VALU peak."""
+    from paper_1710_08839_amd import qxd
+    nblocks = f.volume // 256
+    flops = sap_block_flops(nmr) * (nblocks // 2) * 2
+    out = {}
+    for name, prec in (("f32", qxd.F32), ("f16s", qxd.F16S)):
+        ms = f.sap_pair_pass_ms(q, prec, nmr=nmr, npair=1, reps=reps)
+        tf = flops / (ms * 1e-3) / 1e12
+        out[name] = {"kernel": f"sapq_pair_kernel<{prec}>", "ms_per_pass": round(ms, 4),
+                     "TFLOP/s": round(tf, 2), "frac": round(tf / FP32_VALU_PEAK_TFLOPS, 4)}
+        log(f"SAP pair pass {name}: {ms:.4f} ms, {tf:.1f} TFLOP/s")
+    out.update({"bound": "alu", "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "flops_per_pass": flops, "flops_per_block_rhs": sap_block_flops(nmr), "nmr": nmr,
+                "workload": "64x32^3 C*, q=-1/3, kappa=0.1365, csw=1.9; colour 0 (8192 blocks of 4^4), 2 right-hand "
+                            "sides, face update included, synthetic vectors"})
+    return out
+
+
 # zeros and poles of the rational approximation of the QCD2 / QCD3 runs
 # (Table 2 of the paper), for the multi-shift leg
 TABLE2_MU = [1.2383e+01, 4.8370e+00, 2.3515e+00, 1.1994e+00, 6.1927e-01, 3.2079e-01, 1.6632e-01, 8.6246e-02,
@@ -437,6 +481,32 @@ def single_rhs_64x32(f):
     return out
 
 
+def dfl_leg(f, ns=20, ninv=10, nkv=32):
+    """Locally deflated SAP-GCR on the 64 x 32^3 field of the D leg (q = -1/3,
+    kappa 0.1365, csw 1.9), one Gaussian source: the deflation subspace's
+    setup time, then the deflated solve and the plain SAP-GCR on the same
+    source, both with FP32 inner storage, FP64 defect correction and the same
+    Schwarz parameters (4^4 blocks, ncy 4, nmr 4, nkv 32)."""
+    import torch
+    from paper_1710_08839_amd import qxd, synth
+    dims = (64, 32, 32, 32)
+    eta = torch.from_numpy(synth.source(dims, 3, 1003)).cuda()
+    q = qxd.quark(0.1365, -1 / 3, 1.9, 1.0)
+    sap = single_solve(f, q, qxd.solver(kind=qxd.SAP_GCR, tol=1e-10, nkv=nkv, ncy=4, nmr=4, inner_prec=qxd.F32), eta)
+    log(f"64x32^3 SAP-GCR (fp32 inner): {sap}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f.dfl_setup(q, ns=ns, ninv=ninv, ncy=4, nmr=4, seed=2017)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    dfl = single_solve(f, q, qxd.solver(kind=qxd.DFL_SAP_GCR, tol=1e-10, nkv=nkv, ncy=4, nmr=4,
+                                        inner_prec=qxd.F32), eta)
+    log(f"64x32^3 deflated SAP-GCR: setup {setup_s:.2f} s, {dfl}")
+    return {"setup_s": round(setup_s, 3), "deflated": dfl, "sap_gcr": sap,
+            "subspace": {"ns": ns, "ninv": ninv, "ncy": 4, "nmr": 4, "little_tol": 1e-2, "little_nkv": 24},
+            "workload": "64x32^3 C*, q=-1/3, kappa=0.1365, csw=1.9, Gaussian source (seed 1003), tol 1e-10"}
+
+
 def stream_gbs(reads_per_write, dst_bytes=49152 * 21845, reps=10):
     """The library's streaming probe (reads_per_write bytes read per byte
     written, each once), timed with HIP events: the practical HBM ceiling for
@@ -463,84 +533,187 @@ def stream_gbs(reads_per_write, dst_bytes=49152 * 21845, reps=10):
 SERVE_SIZES = [(8, 8, 8, 8), (32, 16, 16, 16), (48, 24, 24, 24), (64, 32, 32, 32)]
 
 
-def serve_stream(ctx, nreq, max_rhs, rate, inner_prec, seed=4242, nkv=32):
-    """Poisson arrivals of solve requests on resident fields of the four
-    lattice sizes (C*), random charge, kappa ~ U[0.130, 0.1365], Gaussian or
-    point sources, 1..max_rhs right-hand sides; returns latency statistics."""
+def serve_fields(ctx, inner_prec, nkv):
+    """The resident fields of the four serving lattice sizes (C*), with one
+    loose solve per size first so that the kernels of each volume are tuned
+    before any stream is timed (operators are not built ahead: the stream's
+    requests build their own)."""
     import torch
     from paper_1710_08839_amd import qxd, synth
-    rng = np.random.default_rng(seed)
     fields = []
     for i, d in enumerate(SERVE_SIZES):
         u, a = synth.gauge_field(d, 20171010 + i, 0.25, 0.15)
         fields.append(qxd.Field(ctx, d, u, a, cstar=3))
         del u, a
+    for f in fields:
+        e = torch.from_numpy(synth.source(tuple(f.lat.dims[:]), 3, 7)[None]).cuda()
+        f.solve(qxd.quark(0.13, 2 / 3, 1.9, 1.0), qxd.solver(kind=qxd.SAP_GCR, tol=1e-3, nkv=nkv,
+                                                             inner_prec=inner_prec), e, torch.empty_like(e),
+                check=False)
+    torch.cuda.synchronize()
+    return fields
+
+
+def serve_stream(ctx, nreq, max_rhs, rate, inner_prec, seed=4242, nkv=32):
+    """A short serving stream: nreq Poisson requests at `rate`/s over the four
+    lattice sizes (C*), random charge, kappa ~ U[0.130, 0.1365], Gaussian or
+    point sources, 1..max_rhs right-hand sides; returns latency statistics."""
+    from paper_1710_08839_amd import qxd
+    fields = serve_fields(ctx, inner_prec, nkv)
     s = qxd.solver(kind=qxd.SAP_GCR, tol=1e-10, nkv=nkv, ncy=4, nmr=4, inner_prec=inner_prec)
-    reqs = []
-    t = 0.0
+    reqs = draw_requests(np.random.default_rng(seed), nreq, max_rhs, rate)
+    res, wall = run_stream(ctx, fields, reqs, s, limit_s=600)
+    for f in fields:
+        f.release()
+    out = stream_stats(reqs, res, wall)
+    out["stream"] = (f"{nreq} Poisson requests at {rate}/s over lattices "
+                     f"{[f'{d[0]}x{d[1]}^3' for d in SERVE_SIZES]} (C*), 1-{max_rhs} RHS each, "
+                     f"q in {{2/3,-1/3}}, kappa~U[0.130,0.1365], csw=1.9, Gaussian or point sources")
+    return out
+
+
+def draw_requests(rng, nreq, max_rhs, rate, t_start=0.0):
+    """Requests of the serving workload: Poisson arrivals at `rate` (all at
+    t_start if rate is None), lattice size ~U{4 sizes}, q ~U{2/3, -1/3},
+    kappa ~U[0.130, 0.1365], Gaussian or point sources (p = 1/2), 1..max_rhs
+    right-hand sides, source seed 5000 + j."""
+    reqs, t = [], t_start
     for j in range(nreq):
-        t += rng.exponential(1.0 / rate)
-        fi = int(rng.integers(len(SERVE_SIZES)))
-        q = float(rng.choice([2 / 3, -1 / 3]))
-        k = float(rng.uniform(0.130, 0.1365))
-        nrhs = int(rng.integers(1, max_rhs + 1))
-        point = bool(rng.integers(2))
-        reqs.append((t, fi, q, k, nrhs, point, 5000 + j))
-    # buffers (sources generated up front, outside the timed stream)
-    bufs = []
-    for (_, fi, q, k, nrhs, point, sd) in reqs:
-        V = fields[fi].volume
-        r = synth.rng_from_seed(sd)
-        if point:
-            eta = np.stack([synth.point_source(V, int(r.integers(V)), int(r.integers(4)), int(r.integers(3)))
-                            for _ in range(nrhs)])
-        else:
-            eta = np.stack([synth.gaussian_source(r, V) for _ in range(nrhs)])
-        e = torch.from_numpy(eta).cuda()
-        bufs.append((e, torch.empty_like(e)))
+        if rate:
+            t += rng.exponential(1.0 / rate)
+        reqs.append((t, int(rng.integers(len(SERVE_SIZES))), float(rng.choice([2 / 3, -1 / 3])),
+                     float(rng.uniform(0.130, 0.1365)), int(rng.integers(1, max_rhs + 1)), bool(rng.integers(2)),
+                     5000 + j))
+    return reqs
+
+
+def device_source(V, nrhs, point, seed):
+    """nrhs synthetic sources made on the device (a request's payload): spin-
+    colour point sources at a random site, or N(0, 1) real and imaginary
+    parts, from a torch generator seeded with `seed`."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    if point:
+        e = torch.zeros((nrhs, V * 12), dtype=torch.complex128, device="cuda")
+        idx = torch.randint(0, V * 12, (nrhs,), generator=g, device="cuda")
+        e[torch.arange(nrhs, device="cuda"), idx] = 1.0
+        return e.view(nrhs, V, 4, 3)
+    return torch.view_as_complex(torch.randn((nrhs, V, 4, 3, 2), dtype=torch.float64, generator=g,
+                                             device="cuda"))
+
+
+def run_stream(ctx, fields, reqs, s, budget_frac=0.6, limit_s=1e9):
+    """Submit the requests at their arrival times to the serve loop and poll
+    them.  A request's source and solution buffers are made on the device
+    when it is submitted and freed when it completes; a request whose
+    buffers do not fit waits at the client until completions free memory
+    (that wait counts in its latency).  The serve budget is budget_frac of
+    the device memory free at the start, leaving the rest to the buffers.
+    Returns {index: (result, client wait in s)} and the wall time."""
+    import torch
+    from paper_1710_08839_amd import qxd
     torch.cuda.synchronize()
-    # warm the operators of every request (Pauli terms are built per quark)
-    for (_, fi, q, k, nrhs, point, sd), (e, p) in zip(reqs, bufs):
-        fields[fi].apply(qxd.quark(k, q, 1.9, 1.0), qxd.OP_D, inner_prec, e[:1], p[:1])
-        fields[fi].apply(qxd.quark(k, q, 1.9, 1.0), qxd.OP_D, qxd.F64, e[:1], p[:1])
-    torch.cuda.synchronize()
-    ctx.serve_start()
-    tickets = {}
-    results = {}
+    free, _ = torch.cuda.mem_get_info()
+    ctx.serve_start(budget_bytes=int(budget_frac * free))
+    tickets, results, bufs, errors = {}, {}, {}, []
     t0 = time.perf_counter()
-    j = 0
+    j, t_log = 0, 0.0
     try:
         while len(results) < len(reqs):
             now = time.perf_counter() - t0
+            if now - t_log >= 20.0:
+                log(f"  stream: {j} submitted, {len(results)} of {len(reqs)} completed after {now:.0f} s")
+                t_log = now
             while j < len(reqs) and reqs[j][0] <= now:
-                (_, fi, q, k, nrhs, point, sd) = reqs[j]
-                e, p = bufs[j]
-                tickets[ctx.serve_submit(fields[fi], qxd.quark(k, q, 1.9, 1.0), s, e, p, nrhs)] = j
+                (t_arr, fi, q, k, nrhs, point, sd) = reqs[j]
+                try:
+                    e = device_source(fields[fi].volume, nrhs, point, sd)
+                    p = torch.empty_like(e)
+                except torch.OutOfMemoryError:
+                    break  # back-pressure: wait for completions
+                torch.cuda.synchronize()
+                tk = ctx.serve_submit(fields[fi], qxd.quark(k, q, 1.9, 1.0), s, e, p, nrhs)
+                tickets[tk] = (j, time.perf_counter() - t0 - t_arr)
+                bufs[tk] = (e, p)
                 j += 1
+            freed = False
             for tk in list(tickets):
-                if tickets[tk] not in results:
-                    r = ctx.serve_poll(tk)
-                    if r is not None:
-                        results[tickets[tk]] = (r, time.perf_counter() - t0)
-            if time.perf_counter() - t0 > 600:
+                r = ctx.serve_poll(tk)
+                if r is not None:
+                    i, wait = tickets.pop(tk)
+                    results[i] = (r, wait)
+                    if r.status != 0:
+                        errors.append(qxd.last_error()[:200])
+                    del bufs[tk]
+                    freed = True
+            if freed:
+                # hand the freed buffers back to the device (torch would keep
+                # them cached, out of the library's free memory)
+                torch.cuda.empty_cache()
+            if time.perf_counter() - t0 > limit_s:
                 break
             time.sleep(0.002)
     finally:
         ctx.serve_stop()
     wall = time.perf_counter() - t0
+    for m in sorted(set(errors)):
+        log(f"  failed request: {m}")
+    return results, wall
+
+
+def stream_stats(reqs, results, wall):
+    """Latency = time from arrival to completion (the library's latency from
+    submission plus the client's wait for buffer memory)."""
+    idx = sorted(results)
+    lat = np.array([results[i][0].latency_s + results[i][1] for i in idx])
+    nrhs_done = sum(reqs[i][4] for i in results)
+    big = [k for k, i in enumerate(idx) if reqs[i][1] == len(SERVE_SIZES) - 1]
+    return {"requests": len(reqs), "completed": len(results),
+            "all_ok": all(results[i][0].status == 0 for i in results),
+            "status_counts": {str(k): int(v) for k, v in zip(*np.unique([results[i][0].status for i in idx],
+                                                                        return_counts=True))},
+            "p50_s": round(float(np.percentile(lat, 50)), 3), "p90_s": round(float(np.percentile(lat, 90)), 3),
+            "p99_s": round(float(np.percentile(lat, 99)), 3), "max_s": round(float(lat.max()), 3),
+            "mean_s": round(float(lat.mean()), 3), "wall_s": round(wall, 2),
+            "requests_per_s": round(len(results) / wall, 4), "rhs_per_s": round(nrhs_done / wall, 3),
+            "rhs": int(nrhs_done), "max_true_resid": max(results[i][0].true_resid for i in results),
+            "max_client_wait_s": round(max(results[i][1] for i in results), 3),
+            "p50_64x32_s": round(float(np.percentile(lat[big], 50)), 3) if big else None}
+
+
+def serve_full(ctx, factors, nreq, nsat, sat_rate, inner_prec, max_rhs=12, seed=4242, nkv=32):
+    """The serving workload at its stated scale: the saturation throughput is
+    measured with a burst of nsat requests submitted at once (unless
+    sat_rate is given), then streams of nreq Poisson requests arrive at each
+    factor x saturation."""
+    from paper_1710_08839_amd import qxd
+    fields = serve_fields(ctx, inner_prec, nkv)
+    s = qxd.solver(kind=qxd.SAP_GCR, tol=1e-10, nkv=nkv, ncy=4, nmr=4, inner_prec=inner_prec)
+    out = {"inner_prec": PREC_NAME[inner_prec], "max_rhs": max_rhs,
+           "workload": f"lattices {[f'{d[0]}x{d[1]}^3' for d in SERVE_SIZES]} (C*), q in {{2/3,-1/3}}, "
+                       f"kappa~U[0.130,0.1365], csw=1.9, Gaussian or point sources, 1-{max_rhs} RHS, SAP-GCR "
+                       f"(nkv {nkv}, ncy 4, nmr 4) to 1e-10"}
+    rng = np.random.default_rng(seed)
+    if sat_rate is None:
+        reqs = draw_requests(rng, nsat, max_rhs, None)
+        log(f"saturation burst of {nsat} requests")
+        res, wall = run_stream(ctx, fields, reqs, s)
+        out["saturation"] = stream_stats(reqs, res, wall)
+        sat_rate = out["saturation"]["requests_per_s"]
+        log(f"saturation: {out['saturation']}")
+    out["saturation_requests_per_s"] = sat_rate
+    for fct in factors:
+        rate = fct * sat_rate
+        reqs = draw_requests(rng, nreq, max_rhs, rate)
+        log(f"stream at {fct} x saturation ({rate:.4f}/s), {nreq} requests")
+        res, wall = run_stream(ctx, fields, reqs, s)
+        out[f"stream_{fct}x"] = stream_stats(reqs, res, wall)
+        out[f"stream_{fct}x"]["rate_per_s"] = round(rate, 4)
+        log(f"stream {fct}x: {out[f'stream_{fct}x']}")
     for f in fields:
         f.release()
-    lat = np.array([results[i][0].latency_s for i in sorted(results)])
-    status = [results[i][0].status for i in sorted(results)]
-    nrhs_done = sum(reqs[i][4] for i in results)
-    return {"requests": len(reqs), "completed": len(results), "all_ok": all(x == 0 for x in status),
-            "p50_s": round(float(np.percentile(lat, 50)), 3), "p99_s": round(float(np.percentile(lat, 99)), 3),
-            "mean_s": round(float(lat.mean()), 3), "wall_s": round(wall, 2),
-            "requests_per_s": round(len(results) / wall, 3), "rhs_per_s": round(nrhs_done / wall, 3),
-            "max_true_resid": max(results[i][0].true_resid for i in results),
-            "stream": f"{nreq} Poisson requests at {rate}/s over lattices "
-                      f"{[f'{d[0]}x{d[1]}^3' for d in SERVE_SIZES]} (C*), 1-{max_rhs} RHS each, "
-                      f"q in {{2/3,-1/3}}, kappa~U[0.130,0.1365], csw=1.9, Gaussian or point sources"}
+    return out
 
 
 def main():
@@ -563,7 +736,15 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (profiler counter calibration)")
     ap.add_argument("--no-multishift", action="store_true")
+    ap.add_argument("--no-sap", action="store_true")
+    ap.add_argument("--no-dfl", action="store_true", help="skip the deflated SAP-GCR leg")
     ap.add_argument("--cpu-child", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--serve-full", action="store_true",
+                    help="only the serving workload at its stated scale (saturation burst, then Poisson streams)")
+    ap.add_argument("--serve-factors", default="0.8", help="arrival rates as fractions of saturation")
+    ap.add_argument("--serve-sat", type=float, default=None, help="known saturation throughput (requests/s)")
+    ap.add_argument("--serve-nsat", type=int, default=24, help="requests of the saturation burst")
+    ap.add_argument("--serve-prec", default="f32")
     args = ap.parse_args()
     if args.cpu_child:
         # the CPU leg's own process: it never touches the GPU
@@ -576,6 +757,14 @@ def main():
 
     import torch
     from paper_1710_08839_amd import qxd, synth
+
+    if args.serve_full:
+        ctx = qxd.Context(0)
+        res = serve_full(ctx, [float(x) for x in args.serve_factors.split(",")], args.serve_requests,
+                         args.serve_nsat, args.serve_sat, qxd.PREC[args.serve_prec])
+        ctx.close()
+        print(json.dumps({"serve_full": res}))
+        return
 
     dims = (64, 32, 32, 32)
     ctx = qxd.Context(0)
@@ -645,9 +834,11 @@ def main():
     multishift = None
     if not args.no_multishift:
         multishift = multishift_leg(field)
+    sap = None if args.no_sap else sap_leg(field, q)
     single = None
     if not args.no_single:
         single = {"64x32^3": single_rhs_64x32(field)}
+    deflation = None if args.no_dfl else dfl_leg(field)
     field.release()
     if single is not None:
         single["32x16^3"] = single_rhs_32x16(ctx)
@@ -701,6 +892,8 @@ def main():
         "dw": dw,
         "dw_error_vs_oracle": dw_error,
         "multishift": multishift,
+        "sap": sap,
+        "deflation": deflation,
         "stream_ceiling": stream_ceiling,
         "single_rhs": single,
         "solves": solves,

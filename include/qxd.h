@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define QXD_ABI_VERSION 2
+#define QXD_ABI_VERSION 3
 
 typedef enum {
   QXD_OK = 0,
@@ -130,17 +130,19 @@ typedef struct {
                      directions and, with open time, for mu = 0 (QXD_EINVAL) */
 } qxd_quark;
 
-typedef enum { QXD_SOLVER_EO_GCR = 0, QXD_SOLVER_SAP_GCR = 1 } qxd_solver_kind;
+typedef enum { QXD_SOLVER_EO_GCR = 0, QXD_SOLVER_SAP_GCR = 1, QXD_SOLVER_DFL_SAP_GCR = 2 } qxd_solver_kind;
 
 typedef struct {
   int kind;           /* qxd_solver_kind                                       */
   double tol;         /* target |eta - D psi| / |eta| in FP64 (e.g. 1e-10)     */
-  int maxiter;        /* EO_GCR: GCR iterations; SAP_GCR: inner iterations     */
+  int maxiter;        /* EO_GCR: GCR iterations; SAP_GCR, DFL_SAP_GCR: inner
+                         iterations                                            */
   int nkv;            /* Krylov vectors per restart cycle (0: 32 for SAP_GCR,
                          16 for EO_GCR)                                        */
   int ncy;            /* SAP cycles per preconditioner application (0: 4)      */
   int nmr;            /* MR steps per SAP block solve (0: 4)                   */
-  int inner_prec;     /* qxd_prec of the SAP-GCR inner solver                  */
+  int inner_prec;     /* qxd_prec of the SAP-GCR inner solver (DFL_SAP_GCR:
+                         QXD_F32 only)                                         */
   double inner_tol;   /* relative residual reduction per inner solve (0: 1e-6
                          F64, 1e-5 F32, 2e-2 F16S, 1e-2 BF16)                  */
   int max_outer;      /* outer defect-correction steps (SAP_GCR)              */
@@ -248,7 +250,9 @@ qxd_status qxd_dirac_apply_noalloc(qxd_field *field, const qxd_quark *quarks, in
  * the even-odd preconditioned D^ of Sec. 2.4 with psi_o reconstructed from
  * psi_e; QXD_SOLVER_SAP_GCR is flexible GCR right-preconditioned by the
  * Schwarz alternating procedure (qxd_sap_apply) inside an FP64 defect
- * correction.
+ * correction; QXD_SOLVER_DFL_SAP_GCR is the same with the deflated
+ * preconditioner of qxd_dfl_setup (one right-hand side at a time; QXD_EINVAL
+ * if no subspace was built for the quark).
  * quarks as in qxd_dirac_apply.  psi_dev is the initial guess if use_guess,
  * else it is overwritten.  info: nrhs entries (may be NULL).  Returns
  * QXD_ENOCONV if any right-hand side missed tol (best iterate written),
@@ -256,6 +260,44 @@ qxd_status qxd_dirac_apply_noalloc(qxd_field *field, const qxd_quark *quarks, in
 qxd_status qxd_solve(qxd_field *field, const qxd_quark *quarks, int nquark,
                      const qxd_solver *s, const double *eta_dev, double *psi_dev,
                      int nrhs, int use_guess, qxd_solve_info *info, void *stream);
+
+/* Parameters of the local deflation of the SAP-GCR (QXD_SOLVER_DFL_SAP_GCR).
+ * Zero means the default given in brackets. */
+typedef struct {
+  int ns;             /* deflation fields, i.e. basis vectors per SAP block
+                         (1..32) [20]                                          */
+  int ninv;           /* SAP-smoothed inverse-iteration steps that refine the
+                         random start fields [10]                              */
+  int ncy, nmr;       /* SAP cycles and MR steps of each such step [4, 4]      */
+  double little_tol;  /* relative residual of each little-system solve [1e-2] */
+  int little_nkv;     /* Krylov vectors of the little GCR (<= 64) [24]         */
+  int little_maxiter; /* iterations of one little solve [256]                  */
+  uint64_t seed;      /* seed of the random start fields                       */
+} qxd_dfl_params;
+
+/* Build the deflation subspace of the locally deflated SAP-GCR (the solver
+ * the paper inherits and uses for its most expensive factors: abstract,
+ * Sec. 2 feature list, Appendix A, Table 2) for one quark on this field, and
+ * its little Dirac operator:
+ *   - ns global fields, random (or the caller's start fields init_dev: ns
+ *     API-layout FP64 spinors, may be NULL), each refined by ninv steps
+ *     psi <- M_sap psi / |M_sap psi| with the Schwarz preconditioner (ncy,
+ *     nmr; FP32 storage) standing in for D^-1;
+ *   - on every SAP block the restricted fields are orthonormalised by
+ *     modified Gram-Schmidt in the order of the fields: the subspace has ns
+ *     basis vectors per block (stored FP32);
+ *   - the little operator A = V^dag D V on it (V: coefficients -> fields),
+ *     assembled in FP64: per block its ns x ns couplings to itself and to
+ *     its eight neighbours.
+ * A later qxd_solve with QXD_SOLVER_DFL_SAP_GCR for this quark then uses the
+ * preconditioner M_dfl r = V A^-1 V^dag r + M_sap (r - D V A^-1 V^dag r),
+ * with A^-1 applied by block-Jacobi right-preconditioned GCR to little_tol.
+ * A new call for the same quark replaces the subspace.  The subspace lives
+ * with the quark's operator in the field's operator cache (freed with it).
+ * Needs SAP blocks of at most 256 sites that admit the two-colour
+ * decomposition.  Synchronises `stream`. */
+qxd_status qxd_dfl_setup(qxd_field *field, const qxd_quark *quark, const qxd_dfl_params *params,
+                         const double *init_dev, void *stream);
 
 /* Multi-shift conjugate gradient (the paper's solver for the factors of the
  * rational approximation, feature list of Sec. 2 and Table 2): solves
@@ -325,9 +367,14 @@ typedef struct {
  * right-hand sides need; the operators (clover term, its inverse, hopping
  * links) the fields build or keep cached beyond what they held when their
  * first request arrived; and for every admitted request whose operator is
- * not built yet, that operator until the request completes.  Requests are
- * admitted in arrival order while the charge fits; one request always runs
- * when no other request is charged.  max_active (0 = no limit) caps the
+ * not built yet, that operator until it is built.  Requests are admitted in
+ * arrival order, each right-hand side while the charge fits and the
+ * device's free memory, less what admitted work has still to allocate,
+ * covers its allocations plus a floor of 4 GiB + 2% of the device; a
+ * request that does not fit whole is admitted in pieces (later requests
+ * wait until all of its right-hand sides are in); one right-hand side always
+ * runs when no other work is charged (QXD_ENOMEM as the request's status if
+ * the device cannot hold it).  max_active (0 = no limit) caps the
  * right-hand sides in flight. */
 qxd_status qxd_serve_start(qxd_ctx *ctx, size_t budget_bytes, int max_active);
 
@@ -336,7 +383,8 @@ qxd_status qxd_serve_start(qxd_ctx *ctx, size_t budget_bytes, int max_active);
 qxd_status qxd_serve_submit(qxd_ctx *ctx, const qxd_request *req, uint64_t *ticket);
 
 /* QXD_EBUSY while pending; otherwise fills *out (status of the solve) and
- * forgets the ticket.  QXD_ENOTFOUND for unknown tickets. */
+ * forgets the ticket; if the request failed, qxd_last_error() of the calling
+ * thread then says why.  QXD_ENOTFOUND for unknown tickets. */
 qxd_status qxd_serve_poll(qxd_ctx *ctx, uint64_t ticket, qxd_result *out);
 
 /* Stop the scheduler after finishing admitted requests. */

@@ -82,6 +82,37 @@ qxd_status qxd_debug_stream(const void *src_dev, void *dst_dev, size_t dst_bytes
  * QXD_EINVAL if out is NULL or serving is not started on ctx. */
 qxd_status qxd_debug_serve_charges(qxd_ctx *ctx, size_t out[4]);
 
+/* Deflation subspace that qxd_dfl_setup built for this quark: basis field k
+ * (its basis vector k on every SAP block) as one API-layout FP64 spinor on
+ * the device.  QXD_EINVAL if no subspace was built or k is out of range.
+ * Synchronises `stream`. */
+qxd_status qxd_debug_dfl_basis(qxd_field *field, const qxd_quark *quark, int k, double *out_dev, void *stream);
+
+/* Its little operator, copied to host memory: with the blocks numbered
+ * ((B0 nb1 + B1) nb2 + B2) nb3 + B3 over the extended lattice,
+ * a[2 (((b * 9 + d) * ns + k) * ns + l)] (re, im) = (phi_{b,k}, D phi_{n,l})
+ * restricted to the couplings of slot d, n = nbr[b * 9 + d]: d = 0 the
+ * couplings inside block b (n = b), d = 1 + 2 mu + s those through the
+ * face of b in direction mu, forward (s = 0) or backward (s = 1), n the
+ * block across it (the same block may appear in several slots).  a and nbr
+ * may be NULL to read *ns and *nblocks only.  QXD_EINVAL if no subspace was
+ * built. */
+qxd_status qxd_debug_dfl_little(qxd_field *field, const qxd_quark *quark, int *ns, int *nblocks, double *a,
+                                int *nbr);
+
+/* Counters of the deflated preconditioner of this quark since the last call
+ * (then reset): out[0] applications, out[1] little-system GCR iterations in
+ * total, out[2] the most iterations of one little solve.  QXD_EINVAL if no
+ * subspace was built. */
+qxd_status qxd_debug_dfl_stats(qxd_field *field, const qxd_quark *quark, int64_t out[3]);
+
+/* out = M_dfl in for one API-layout FP64 spinor: the deflated preconditioner
+ * of the DFL_SAP_GCR solver (FP32 storage inside), with the little system
+ * solved to relative residual little_tol (0: the setup's) and ncy, nmr SAP
+ * cycles and MR steps.  Synchronises `stream`. */
+qxd_status qxd_debug_dfl_precond(qxd_field *field, const qxd_quark *quark, double little_tol, int ncy, int nmr,
+                                 const double *in_dev, double *out_dev, void *stream);
+
 /* The variant the autotuner chose for the full operator D (phase folded into
  * the links) on this field's lattice in precision prec, in the encoding of
  * qxd_debug_set_dirac_variant; 0 if D has not been applied yet. */

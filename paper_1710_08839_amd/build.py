@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libqxd.so")
 SOURCES = ["abi.cpp", "solver.cpp", "serve.cpp", "field.hip", "dirac.hip", "blas.hip", "sap.hip",
-           "sap_quad.hip", "batch.hip", "batch_solver.cpp", "multishift.hip"]
+           "sap_quad.hip", "batch.hip", "batch_solver.cpp", "multishift.hip", "dfl.hip", "dfl_solver.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("QXD_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-x", "hip", f"--offload-arch={ARCH}",

@@ -1,0 +1,99 @@
+// Local deflation of the SAP-GCR solver (qxd_dfl_setup, QXD_SOLVER_DFL_SAP_GCR):
+// kernels in dfl.hip, host side in dfl_solver.cpp.
+//
+// The paper names the locally deflated SAP-GCR (abstract; Sec. 2 feature
+// list; Appendix A and Table 2, where it serves the expensive factors) and
+// cites the published method for its steps:
+//   - deflation fields: ns random fields refined by SAP-smoothed inverse
+//     iteration, psi <- M_sap psi / |M_sap psi|;
+//   - basis: on every SAP block the restricted fields, orthonormalised by
+//     modified Gram-Schmidt; V maps coefficients c[block][k] to fields;
+//   - little operator A = V^dag D V: per block its couplings to itself and,
+//     through each of its eight faces, to the block across;
+//   - preconditioner M_dfl r = V A^-1 V^dag r + M_sap (r - D V A^-1 V^dag r),
+//     A^-1 by GCR right-preconditioned with the inverse diagonal blocks.
+#pragma once
+
+#include "host.h"
+
+namespace qxd {
+
+constexpr int DFL_NSMAX = 32;  // basis vectors per block
+constexpr int DFL_SLOTS = 9;   // couplings of a block: itself, then faces 2 mu + (0 fwd, 1 bwd)
+
+struct Dfl {
+  qxd_dfl_params p{};     // with the defaults filled in
+  int ns = 0;
+  int nb = 0;              // blocks
+  size_t vbytes = 0;       // bytes of one basis field (FP32 native spinor)
+  DevBuf basis;            // ns FP32 native spinors; field k holds basis vector k of every block
+  DevBuf a;                // little operator [nb][9][ns][ns] double2
+  DevBuf ainv;             // inverses of the diagonal blocks A[b][0] [nb][ns][ns] double2
+  DevBuf nbr;              // [nb][9] int: the block each slot couples to
+  // little GCR: Krylov vectors z_k (preconditioned) and w_k = A z_k, work vectors, scalars
+  DevBuf lz, lw, lx, lr, lb, lpart, lscal;
+  // counters since the last read: preconditioner applications, little GCR
+  // iterations (total and the largest of one solve)
+  int64_t applications = 0, little_iters = 0, little_max = 0;
+  size_t bytes() const;
+};
+
+// ---- kernels (dfl.hip) ----------------------------------------------------
+// basis field k of `basis` is at basis + k * vbytes (FP32 native spinors)
+
+// ns Gaussian start fields (N(0,1) real and imaginary parts) from a
+// counter-based generator (splitmix64 of seed, field, site, component)
+hipError_t launch_dfl_random(const Geom &g, void *basis, size_t vbytes, int ns, uint64_t seed, hipStream_t st);
+// modified Gram-Schmidt of the ns restricted fields on every block, in place;
+// *bad counts blocks on which a field vanished
+hipError_t launch_dfl_ortho(const Geom &g, void *basis, size_t vbytes, int ns, int *bad, hipStream_t st);
+// c[b * ns + k] = (phi_{b,k}, r)_b for an FP32 native spinor r
+hipError_t launch_dfl_restrict(const Geom &g, const void *basis, size_t vbytes, int ns, const void *r,
+                               double2 *c, hipStream_t st);
+// out = sum_{b,k} c[b * ns + k] phi_{b,k} (FP32 native spinor)
+hipError_t launch_dfl_prolong(const Geom &g, const void *basis, size_t vbytes, int ns, const double2 *c,
+                              void *out, hipStream_t st);
+// face couplings of basis field l: a[b][1 + d][k][l] = (phi_{b,k}, H_d phi_l)_b for the
+// eight faces d of every block (H_d: the hops of D through that face), and nbr[b][1 + d]
+hipError_t launch_dfl_face(const Geom &g, const double2 *wl64, const void *basis, size_t vbytes, int ns, int l,
+                           double2 *a, int *nbr, hipStream_t st);
+// couplings inside the blocks: a[b][0][k][l] = (phi_{b,k}, y)_b - sum_d a[b][1 + d][k][l]
+// with y = D phi_l (FP64 native spinor); nbr[b][0] = b
+hipError_t launch_dfl_diag(const Geom &g, const void *basis, size_t vbytes, int ns, int l, const void *y64,
+                           double2 *a, int *nbr, hipStream_t st);
+// ainv[b] = a[b][0]^-1 (Gauss-Jordan with partial pivoting); *bad counts singular blocks
+hipError_t launch_little_invert(int nb, int ns, const double2 *a, double2 *ainv, int *bad, hipStream_t st);
+// y = A x over all blocks
+hipError_t launch_little_apply(int nb, int ns, const double2 *a, const int *nbr, const double2 *x, double2 *y,
+                               hipStream_t st);
+// y[b] = ainv[b] x[b]
+hipError_t launch_little_jacobi(int nb, int ns, const double2 *ainv, const double2 *x, double2 *y,
+                                hipStream_t st);
+// out[2j..2j+1] = (W_j, x) for j < k, W_j = W + j * n (complex vectors of length n)
+hipError_t launch_lv_dots(const double2 *W, int k, int64_t n, const double2 *x, double *partial, double *out,
+                          hipStream_t st);
+// x -= sum_{j<k} (d[2j] + i d[2j+1]) / wn[j] * W_j
+hipError_t launch_lv_maxpy(double2 *x, const double2 *W, int k, int64_t n, const double *d, const double *wn,
+                           hipStream_t st);
+// s[0] = |w|^2, s[1..2] = (w, r)
+hipError_t launch_lv_dot2(const double2 *w, const double2 *r, int64_t n, double *partial, double *s,
+                          hipStream_t st);
+// alpha = (s[1] + i s[2]) / s[0]: x += alpha z, r -= alpha w; out[0] = |r|^2
+hipError_t launch_lv_update(double2 *x, const double2 *z, double2 *r, const double2 *w, int64_t n,
+                            const double *s, double *partial, double *out, hipStream_t st);
+// partial-sum scratch of the little reductions (doubles)
+size_t lv_partial_doubles();
+
+// ---- host side (dfl_solver.cpp) ---------------------------------------------------
+// build the subspace and little operator of the quark's operator (replacing
+// any earlier one); init_api: ns API-layout FP64 start fields or null
+qxd_status dfl_setup(Field *f, const qxd_quark &q, const qxd_dfl_params *params, const double *init_api,
+                     hipStream_t st);
+// out = M_dfl r on FP32 native full-lattice spinors; little_tol 0: the setup's
+qxd_status dfl_precond(Field *f, Operator &op, double little_tol, int ncy, int nmr, void *r32, void *out32,
+                       hipStream_t st, int *little_iters = nullptr);
+// D psi = eta (FP64 native) by defect correction around flexible GCR(M_dfl) in FP32
+qxd_status dfl_solve(Field *f, Operator &op, const qxd_solver &s, void *eta64, void *psi64, bool guess,
+                     qxd_solve_info *info, hipStream_t st);
+
+}  // namespace qxd

@@ -1,0 +1,482 @@
+// Local deflation of the SAP-GCR, host side (the method in dfl.h).
+#include <math.h>
+
+#include <chrono>
+#include <memory>
+#include <vector>
+
+#include "blas.h"
+#include "dfl.h"
+#include "qxd_debug.h"
+#include "solver.h"
+
+namespace qxd {
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+#define DCK(...)                                                                      \
+  do {                                                                                 \
+    hipError_t _e = (__VA_ARGS__);                                                          \
+    if (_e != hipSuccess) {                                                            \
+      set_error("HIP error %s at %s:%d", hipGetErrorString(_e), __FILE__, __LINE__);  \
+      return _e == hipErrorOutOfMemory ? QXD_ENOMEM : QXD_EDEVICE;                     \
+    }                                                                                  \
+  } while (0)
+#define DCS(...)                        \
+  do {                                   \
+    qxd_status _s = (__VA_ARGS__);            \
+    if (_s != QXD_OK) return _s;         \
+  } while (0)
+
+qxd_status fetch(double *host, const double *dev, int n, hipStream_t st) {
+  DCK(hipMemcpyAsync(host, dev, n * sizeof(double), hipMemcpyDeviceToHost, st));
+  DCK(hipStreamSynchronize(st));
+  return QXD_OK;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// the field's workspace `name` of at least `bytes`
+qxd_status ws(Field *f, const char *name, size_t bytes, void **p) {
+  hipError_t e;
+  *p = f->workspace(name, bytes, &e);
+  if (e != hipSuccess) {
+    set_error("workspace allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? QXD_ENOMEM : QXD_EDEVICE;
+  }
+  return QXD_OK;
+}
+
+SpinorArg full(const Geom &g, void *p) { return SpinorArg{p, g.V, 0, g.rd}; }
+
+// scalars of the little GCR on the device
+constexpr int LS_S = 0, LS_RR = 4, LS_DOTS = 8, LS_WN = 8 + 2 * 64, LS_N = LS_WN + 64 + 8;
+
+// x = A^-1 b approximately: GCR right-preconditioned by the inverse diagonal
+// blocks, with p_k = J r (z) and w_k = A z_k made A-orthogonal, x and r
+// updated at every step; stops at |r| <= tol |b| or maxiter iterations
+qxd_status little_solve(Dfl &d, const double2 *b, double2 *x, double tol, int *iters, hipStream_t st) {
+  const int64_t n = (int64_t)d.nb * d.ns;
+  const int nkv = d.p.little_nkv;
+  double2 *Z = d.lz.as<double2>(), *W = d.lw.as<double2>(), *r = d.lr.as<double2>();
+  double *part = d.lpart.as<double>(), *sc = d.lscal.as<double>();
+  const double2 *A = d.a.as<double2>(), *Ai = d.ainv.as<double2>();
+  const int *nbr = d.nbr.as<int>();
+  DCK(hipMemsetAsync(x, 0, n * sizeof(double2), st));
+  DCK(hipMemcpyAsync(r, b, n * sizeof(double2), hipMemcpyDeviceToDevice, st));
+  DCK(launch_lv_dot2(r, r, n, part, sc + LS_S, st));
+  double bn2;
+  DCS(fetch(&bn2, sc + LS_S, 1, st));
+  int it = 0;
+  if (!isfinite(bn2)) {
+    set_error("little system: right-hand side is NaN/Inf");
+    return QXD_EFLOAT;
+  }
+  if (bn2 > 0.0) {
+    bool done = false;
+    while (!done && it < d.p.little_maxiter) {
+      for (int k = 0; k < nkv && !done; k++) {
+        double2 *zk = Z + (int64_t)k * n, *wk = W + (int64_t)k * n;
+        DCK(launch_little_jacobi(d.nb, d.ns, Ai, r, zk, st));
+        DCK(launch_little_apply(d.nb, d.ns, A, nbr, zk, wk, st));
+        if (k > 0) {
+          DCK(launch_lv_dots(W, k, n, wk, part, sc + LS_DOTS, st));
+          DCK(launch_lv_maxpy(wk, W, k, n, sc + LS_DOTS, sc + LS_WN, st));
+          DCK(launch_lv_maxpy(zk, Z, k, n, sc + LS_DOTS, sc + LS_WN, st));
+        }
+        DCK(launch_lv_dot2(wk, r, n, part, sc + LS_S, st));
+        DCK(hipMemcpyAsync(sc + LS_WN + k, sc + LS_S, sizeof(double), hipMemcpyDeviceToDevice, st));
+        DCK(launch_lv_update(x, zk, r, wk, n, sc + LS_S, part, sc + LS_RR, st));
+        double rr;
+        DCS(fetch(&rr, sc + LS_RR, 1, st));
+        it++;
+        if (!isfinite(rr)) {
+          set_error("little system: residual is NaN/Inf");
+          return QXD_EFLOAT;
+        }
+        if (rr <= tol * tol * bn2 || it >= d.p.little_maxiter) done = true;
+      }
+    }
+  }
+  if (iters) *iters = it;
+  return QXD_OK;
+}
+
+qxd_status fill_params(qxd_dfl_params *p) {
+  if (p->ns == 0) p->ns = 20;
+  if (p->ninv == 0) p->ninv = 10;
+  if (p->ncy == 0) p->ncy = 4;
+  if (p->nmr == 0) p->nmr = 4;
+  if (p->little_tol == 0.0) p->little_tol = 1e-2;
+  if (p->little_nkv == 0) p->little_nkv = 24;
+  if (p->little_maxiter == 0) p->little_maxiter = 256;
+  if (p->ns < 1 || p->ns > DFL_NSMAX || p->ninv < 0 || p->ncy < 1 || p->nmr < 0 || !(p->little_tol > 0.0) ||
+      p->little_tol >= 1.0 || p->little_nkv < 1 || p->little_nkv > 64 || p->little_maxiter < 1) {
+    set_error("invalid deflation parameters (ns 1..%d, ncy >= 1, 0 < little_tol < 1, little_nkv 1..64)",
+              DFL_NSMAX);
+    return QXD_EINVAL;
+  }
+  return QXD_OK;
+}
+
+// the quark's operator with its deflation subspace, or QXD_EINVAL
+qxd_status op_with_dfl(Field *f, const qxd_quark &q, Operator **op, hipStream_t st) {
+  DCS(f->get_op(q, QXD_F64, op, st));
+  DCS(f->get_op(q, QXD_F32, op, st));
+  if (!(*op)->dfl) {
+    set_error("no deflation subspace for this quark: call qxd_dfl_setup first");
+    return QXD_EINVAL;
+  }
+  return QXD_OK;
+}
+
+}  // namespace
+
+size_t Dfl::bytes() const {
+  return basis.n + a.n + ainv.n + nbr.n + lz.n + lw.n + lx.n + lr.n + lb.n + lpart.n + lscal.n;
+}
+
+qxd_status dfl_setup(Field *f, const qxd_quark &q, const qxd_dfl_params *pin, const double *init_api,
+                     hipStream_t st) {
+  qxd_dfl_params p = pin ? *pin : qxd_dfl_params{};
+  DCS(fill_params(&p));
+  DCS(check_sap_blocks(f));
+  const Geom &g = f->g;
+  if (2 * g.Vbh > 256) {
+    set_error("deflation needs SAP blocks of at most 256 sites");
+    return QXD_EINVAL;
+  }
+  Operator *op;
+  DCS(f->get_op(q, QXD_F64, &op, st));
+  DCS(f->get_op(q, QXD_F32, &op, st));
+  op->dfl.reset();  // free an earlier subspace first
+  std::shared_ptr<Dfl> d = std::make_shared<Dfl>();
+  d->p = p;
+  d->ns = p.ns;
+  d->nb = g.nblocks;
+  d->vbytes = align256(spinor_bytes(QXD_F32, g.V));
+  const int ns = d->ns;
+  DCK(d->basis.ensure(d->vbytes * ns));
+  char *basis = (char *)d->basis.p;
+  void *t32, *partial, *scal;
+  DCS(ws(f, "dfl_t32", spinor_bytes(QXD_F32, g.V), &t32));
+  DCS(ws(f, "partial", blas_partial_doubles() * 8, &partial));
+  DCS(ws(f, "dfl_scal", 64 * 8, &scal));
+  double *misc = (double *)scal;
+  // start fields
+  if (init_api) {
+    for (int k = 0; k < ns; k++)
+      DCK(launch_pack(QXD_F32, g, init_api + (int64_t)k * 24 * g.V, basis + (size_t)k * d->vbytes, 1, st));
+  } else {
+    DCK(launch_dfl_random(g, basis, d->vbytes, ns, p.seed, st));
+  }
+  // SAP-smoothed inverse iteration: psi <- psi / |psi|, then ninv times
+  // psi <- M_sap psi / |M_sap psi|
+  for (int k = 0; k < ns; k++) {
+    void *v = basis + (size_t)k * d->vbytes;
+    for (int it = 0; it <= p.ninv; it++) {
+      if (it > 0) {
+        DCS(sap_apply(f, *op, QXD_F32, p.ncy, p.nmr, v, t32, st));
+        DCK(hipMemcpyAsync(v, t32, spinor_bytes(QXD_F32, g.V), hipMemcpyDeviceToDevice, st));
+      }
+      DCK(blas_norm2<QXD_F32>(full(g, v), 0, g.V, (double *)partial, misc, st));
+      double n2;
+      DCS(fetch(&n2, misc, 1, st));
+      if (!(n2 > 0.0) || !isfinite(n2)) {
+        set_error("deflation field %d vanished or is not finite in inverse iteration", k);
+        return QXD_EFLOAT;
+      }
+      DCK(blas_axpby<QXD_F32, QXD_F32>(full(g, v), 1.0 / sqrt(n2), full(g, v), 0.0, 0, g.V, (double *)partial,
+                                       nullptr, st));
+    }
+  }
+  // block orthonormalisation
+  int *bad = (int *)misc;
+  DCK(hipMemsetAsync(bad, 0, sizeof(int), st));
+  DCK(launch_dfl_ortho(g, basis, d->vbytes, ns, bad, st));
+  int nbad = 0;
+  DCK(hipMemcpyAsync(&nbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+  DCK(hipStreamSynchronize(st));
+  if (nbad) {
+    set_error("a deflation field vanishes on %d blocks (ns too large for the block?)", nbad);
+    return QXD_EFLOAT;
+  }
+  // little operator in FP64
+  const size_t nn = (size_t)ns * ns;
+  DCK(d->a.ensure((size_t)d->nb * DFL_SLOTS * nn * sizeof(double2)));
+  DCK(d->nbr.ensure((size_t)d->nb * DFL_SLOTS * sizeof(int)));
+  DCK(d->ainv.ensure((size_t)d->nb * nn * sizeof(double2)));
+  void *x64, *y64;
+  DCS(ws(f, "dfl_x64", spinor_bytes(QXD_F64, g.V), &x64));
+  DCS(ws(f, "dfl_y64", spinor_bytes(QXD_F64, g.V), &y64));
+  const OpFields of64 = f->op_fields(*op, QXD_F64);
+  for (int l = 0; l < ns; l++) {
+    const void *bl = basis + (size_t)l * d->vbytes;
+    DCK(launch_dfl_face(g, (const double2 *)of64.links, basis, d->vbytes, ns, l, d->a.as<double2>(),
+                        d->nbr.as<int>(), st));
+    DCK(blas_axpby<QXD_F64, QXD_F32>(full(g, x64), 0.0, full(g, (void *)bl), 1.0, 0, g.V, (double *)partial,
+                                     nullptr, st));
+    DCS(apply_native(f, *op, 0.0, QXD_OP_D, QXD_F64, x64, y64, st));
+    DCK(launch_dfl_diag(g, basis, d->vbytes, ns, l, y64, d->a.as<double2>(), d->nbr.as<int>(), st));
+  }
+  DCK(hipMemsetAsync(bad, 0, sizeof(int), st));
+  DCK(launch_little_invert(d->nb, ns, d->a.as<double2>(), d->ainv.as<double2>(), bad, st));
+  DCK(hipMemcpyAsync(&nbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+  DCK(hipStreamSynchronize(st));
+  if (nbad) {
+    set_error("the little operator has %d singular diagonal blocks", nbad);
+    return QXD_EFLOAT;
+  }
+  // little GCR workspace
+  const size_t n = (size_t)d->nb * ns;
+  DCK(d->lz.ensure((size_t)p.little_nkv * n * sizeof(double2)));
+  DCK(d->lw.ensure((size_t)p.little_nkv * n * sizeof(double2)));
+  DCK(d->lx.ensure(n * sizeof(double2)));
+  DCK(d->lr.ensure(n * sizeof(double2)));
+  DCK(d->lb.ensure(n * sizeof(double2)));
+  DCK(d->lpart.ensure(lv_partial_doubles() * sizeof(double)));
+  DCK(d->lscal.ensure(LS_N * sizeof(double)));
+  op->dfl = d;
+  return QXD_OK;
+}
+
+qxd_status dfl_precond(Field *f, Operator &op, double little_tol, int ncy, int nmr, void *r32, void *out32,
+                       hipStream_t st, int *little_iters) {
+  Dfl &d = *op.dfl;
+  const Geom &g = f->g;
+  void *u, *t, *partial;
+  DCS(ws(f, "dfl_u", spinor_bytes(QXD_F32, g.V), &u));
+  DCS(ws(f, "dfl_t", spinor_bytes(QXD_F32, g.V), &t));
+  DCS(ws(f, "partial", blas_partial_doubles() * 8, &partial));
+  // u = V A^-1 V^dag r
+  DCK(launch_dfl_restrict(g, d.basis.p, d.vbytes, d.ns, r32, d.lb.as<double2>(), st));
+  int lit = 0;
+  DCS(little_solve(d, d.lb.as<double2>(), d.lx.as<double2>(), little_tol > 0.0 ? little_tol : d.p.little_tol,
+                   &lit, st));
+  if (little_iters) *little_iters = lit;
+  d.applications++;
+  d.little_iters += lit;
+  if (lit > d.little_max) d.little_max = lit;
+  DCK(launch_dfl_prolong(g, d.basis.p, d.vbytes, d.ns, d.lx.as<double2>(), u, st));
+  // out = u + M_sap (r - D u)
+  DCS(apply_native(f, op, 0.0, QXD_OP_D, QXD_F32, u, t, st));
+  DCK(blas_axpby<QXD_F32, QXD_F32>(full(g, t), -1.0, full(g, r32), 1.0, 0, g.V, (double *)partial, nullptr, st));
+  DCS(sap_apply(f, op, QXD_F32, ncy, nmr, t, out32, st));
+  DCK(blas_axpby<QXD_F32, QXD_F32>(full(g, out32), 1.0, full(g, u), 1.0, 0, g.V, (double *)partial, nullptr,
+                                   st));
+  return QXD_OK;
+}
+
+qxd_status dfl_solve(Field *f, Operator &op, const qxd_solver &s, void *eta, void *psi, bool guess,
+                     qxd_solve_info *info, hipStream_t st) {
+  const Geom &g = f->g;
+  const int nkv = s.nkv > 0 ? s.nkv : 32;
+  const int ncy = s.ncy > 0 ? s.ncy : 4, nmr = s.nmr > 0 ? s.nmr : 4;
+  const double inner_tol = s.inner_tol > 0.0 ? s.inner_tol : 1e-5;
+  const int maxiter = s.maxiter > 0 ? s.maxiter : 100000;
+  const int max_outer = s.max_outer > 0 ? s.max_outer : 100;
+  if (nkv > MAXV) {
+    set_error("nkv must be <= %d", MAXV);
+    return QXD_EINVAL;
+  }
+  const size_t fb32 = spinor_bytes(QXD_F32, g.V), fb64 = spinor_bytes(QXD_F64, g.V);
+  void *pv, *qv, *x32, *rho, *rho0, *z, *r64, *t64, *partial, *scal;
+  DCS(ws(f, "dfl_p", fb32 * nkv, &pv));
+  DCS(ws(f, "dfl_q", fb32 * nkv, &qv));
+  DCS(ws(f, "dfl_x32", fb32, &x32));
+  DCS(ws(f, "dfl_rho", fb32, &rho));
+  DCS(ws(f, "dfl_rho0", fb32, &rho0));
+  DCS(ws(f, "dfl_z", fb32, &z));
+  DCS(ws(f, "dfl_r64", fb64, &r64));
+  DCS(ws(f, "dfl_t64", fb64, &t64));
+  DCS(ws(f, "partial", blas_partial_doubles() * 8, &partial));
+  DCS(ws(f, "dfl_solve_scal", (size_t)(2 * MAXV + 3 * MAXV + 16) * 8, &scal));
+  double *beta = (double *)scal, *rec = beta + 2 * MAXV, *rn2 = rec + 3 * MAXV, *misc = rn2 + 4;
+  double *part = (double *)partial;
+  std::vector<SpinorArg> ps(nkv), qs(nkv);
+  for (int k = 0; k < nkv; k++) {
+    ps[k] = full(g, (char *)pv + k * fb32);
+    qs[k] = full(g, (char *)qv + k * fb32);
+  }
+  const SpinorArg E = full(g, eta), X = full(g, psi), R64 = full(g, r64), T64 = full(g, t64);
+  const SpinorArg X32 = full(g, x32), RHO = full(g, rho), RHO0 = full(g, rho0), Z = full(g, z);
+  DCK(blas_norm2<QXD_F64>(E, 0, g.V, part, misc, st));
+  double eta2;
+  DCS(fetch(&eta2, misc, 1, st));
+  if (!isfinite(eta2)) {
+    set_error("source contains NaN/Inf");
+    return QXD_EFLOAT;
+  }
+  if (eta2 == 0.0) {
+    DCK(hipMemsetAsync(psi, 0, fb64, st));
+    if (info) *info = qxd_solve_info{QXD_OK, 0, 0, 0.0, 0.0};
+    return QXD_OK;
+  }
+  const double eta_n = sqrt(eta2);
+  if (!guess) DCK(hipMemsetAsync(psi, 0, fb64, st));
+  int outer = 0, inner = 0;
+  double res = INFINITY;
+  for (;;) {
+    // r = eta - D psi in FP64
+    DCS(apply_native(f, op, 0.0, QXD_OP_D, QXD_F64, psi, t64, st));
+    DCK(blas_axpby<QXD_F64, QXD_F64>(R64, 0.0, E, 1.0, 0, g.V, part, nullptr, st));
+    DCK(blas_axpby<QXD_F64, QXD_F64>(R64, 1.0, T64, -1.0, 0, g.V, part, misc, st));
+    double r2;
+    DCS(fetch(&r2, misc, 1, st));
+    if (!isfinite(r2)) {
+      set_error("residual is NaN/Inf");
+      return QXD_EFLOAT;
+    }
+    res = sqrt(r2) / eta_n;
+    if (res <= s.tol || outer >= max_outer || inner >= maxiter) break;
+    // inner: D x = r / |r| by flexible GCR(M_dfl) in FP32, to inner_tol
+    const double sc = sqrt(r2);
+    DCK(blas_axpby<QXD_F32, QXD_F64>(RHO0, 0.0, R64, 1.0 / sc, 0, g.V, part, nullptr, st));
+    DCK(blas_axpby<QXD_F32, QXD_F32>(RHO, 0.0, RHO0, 1.0, 0, g.V, part, rn2, st));
+    DCK(hipMemsetAsync(x32, 0, fb32, st));
+    double rr;
+    DCS(fetch(&rr, rn2, 1, st));
+    while (sqrt(rr) > inner_tol && inner < maxiter) {
+      for (int k = 0; k < nkv && inner < maxiter; k++) {
+        DCS(dfl_precond(f, op, 0.0, ncy, nmr, rho, z, st));
+        DCS(apply_native(f, op, 0.0, QXD_OP_D, QXD_F32, z, qs[k].ptr, st));
+        if (k > 0) DCK(blas_mdot<QXD_F32>(qs.data(), k, qs[k], 0, g.V, part, beta, rec, 3, st));
+        MaxpyHost m;
+        m.n = k;
+        m.ntriples = 2;
+        m.src[0] = qs[k];
+        m.dst[0] = qs[k];
+        m.ys[0] = qs.data();
+        m.src[1] = Z;
+        m.dst[1] = ps[k];
+        m.ys[1] = ps.data();
+        m.coef = beta;
+        m.w = RHO;
+        DCK(blas_maxpy<QXD_F32>(m, 0, g.V, part, rec + 3 * k, st));
+        DCK(blas_update<QXD_F32>(X32, ps[k], rec + 3 * k + 1, rec + 3 * k, 1, 0, g.V, part, misc, st));
+        DCK(blas_update<QXD_F32>(RHO, qs[k], rec + 3 * k + 1, rec + 3 * k, 0, 0, g.V, part, rn2, st));
+        DCS(fetch(&rr, rn2, 1, st));
+        inner++;
+        if (!isfinite(rr)) {
+          set_error("inner GCR residual is NaN/Inf");
+          return QXD_EFLOAT;
+        }
+        if (sqrt(rr) <= inner_tol) break;
+      }
+      // restart: rho = rho0 - D x
+      DCS(apply_native(f, op, 0.0, QXD_OP_D, QXD_F32, x32, z, st));
+      DCK(blas_axpby<QXD_F32, QXD_F32>(RHO, 0.0, RHO0, 1.0, 0, g.V, part, nullptr, st));
+      DCK(blas_axpby<QXD_F32, QXD_F32>(RHO, 1.0, Z, -1.0, 0, g.V, part, rn2, st));
+      DCS(fetch(&rr, rn2, 1, st));
+    }
+    // psi += |r| x
+    DCK(blas_axpby<QXD_F64, QXD_F32>(X, 1.0, X32, sc, 0, g.V, part, nullptr, st));
+    outer++;
+  }
+  if (info) {
+    info->outer_iters = outer;
+    info->inner_iters = inner;
+    info->true_resid = res;
+  }
+  return res <= s.tol ? QXD_OK : QXD_ENOCONV;
+}
+
+}  // namespace qxd
+
+using namespace qxd;
+
+extern "C" {
+
+qxd_status qxd_dfl_setup(qxd_field *field, const qxd_quark *quark, const qxd_dfl_params *params,
+                         const double *init_dev, void *stream) {
+  if (!field || !quark) {
+    set_error("field or quark is NULL");
+    return QXD_EINVAL;
+  }
+  std::lock_guard<std::recursive_mutex> lk(field->mu);
+  DCK(hipSetDevice(field->ctx->device));
+  return dfl_setup(field, *quark, params, init_dev, (hipStream_t)stream);
+}
+
+qxd_status qxd_debug_dfl_basis(qxd_field *field, const qxd_quark *quark, int k, double *out_dev, void *stream) {
+  if (!field || !quark || !out_dev) {
+    set_error("invalid arguments to qxd_debug_dfl_basis");
+    return QXD_EINVAL;
+  }
+  std::lock_guard<std::recursive_mutex> lk(field->mu);
+  hipStream_t st = (hipStream_t)stream;
+  DCK(hipSetDevice(field->ctx->device));
+  Operator *op;
+  DCS(op_with_dfl(field, *quark, &op, st));
+  const Dfl &d = *op->dfl;
+  if (k < 0 || k >= d.ns) {
+    set_error("basis field %d out of range (ns = %d)", k, d.ns);
+    return QXD_EINVAL;
+  }
+  DCK(launch_unpack(QXD_F32, field->g, (const char *)d.basis.p + (size_t)k * d.vbytes, out_dev, 1, st));
+  DCK(hipStreamSynchronize(st));
+  return QXD_OK;
+}
+
+qxd_status qxd_debug_dfl_little(qxd_field *field, const qxd_quark *quark, int *ns, int *nblocks, double *a,
+                                int *nbr) {
+  if (!field || !quark || !ns || !nblocks) {
+    set_error("invalid arguments to qxd_debug_dfl_little");
+    return QXD_EINVAL;
+  }
+  std::lock_guard<std::recursive_mutex> lk(field->mu);
+  DCK(hipSetDevice(field->ctx->device));
+  Operator *op;
+  DCS(op_with_dfl(field, *quark, &op, nullptr));
+  const Dfl &d = *op->dfl;
+  *ns = d.ns;
+  *nblocks = d.nb;
+  DCK(hipDeviceSynchronize());
+  if (a) DCK(hipMemcpy(a, d.a.p, (size_t)d.nb * DFL_SLOTS * d.ns * d.ns * sizeof(double2), hipMemcpyDeviceToHost));
+  if (nbr) DCK(hipMemcpy(nbr, d.nbr.p, (size_t)d.nb * DFL_SLOTS * sizeof(int), hipMemcpyDeviceToHost));
+  return QXD_OK;
+}
+
+qxd_status qxd_debug_dfl_stats(qxd_field *field, const qxd_quark *quark, int64_t out[3]) {
+  if (!field || !quark || !out) {
+    set_error("invalid arguments to qxd_debug_dfl_stats");
+    return QXD_EINVAL;
+  }
+  std::lock_guard<std::recursive_mutex> lk(field->mu);
+  DCK(hipSetDevice(field->ctx->device));
+  Operator *op;
+  DCS(op_with_dfl(field, *quark, &op, nullptr));
+  Dfl &d = *op->dfl;
+  out[0] = d.applications;
+  out[1] = d.little_iters;
+  out[2] = d.little_max;
+  d.applications = d.little_iters = d.little_max = 0;
+  return QXD_OK;
+}
+
+qxd_status qxd_debug_dfl_precond(qxd_field *field, const qxd_quark *quark, double little_tol, int ncy, int nmr,
+                                 const double *in_dev, double *out_dev, void *stream) {
+  if (!field || !quark || !in_dev || !out_dev || ncy < 1 || nmr < 0 || little_tol < 0.0 || little_tol >= 1.0) {
+    set_error("invalid arguments to qxd_debug_dfl_precond");
+    return QXD_EINVAL;
+  }
+  std::lock_guard<std::recursive_mutex> lk(field->mu);
+  hipStream_t st = (hipStream_t)stream;
+  DCK(hipSetDevice(field->ctx->device));
+  Operator *op;
+  DCS(op_with_dfl(field, *quark, &op, st));
+  void *r32, *o32;
+  DCS(ws(field, "dfl_dbg_in", spinor_bytes(QXD_F32, field->g.V), &r32));
+  DCS(ws(field, "dfl_dbg_out", spinor_bytes(QXD_F32, field->g.V), &o32));
+  DCK(launch_pack(QXD_F32, field->g, in_dev, r32, 1, st));
+  DCS(dfl_precond(field, *op, little_tol, ncy, nmr, r32, o32, st));
+  DCK(launch_unpack(QXD_F32, field->g, o32, out_dev, 1, st));
+  DCK(hipStreamSynchronize(st));
+  return QXD_OK;
+}
+
+}  // extern "C"

@@ -46,6 +46,8 @@ struct DevBuf {
   template <class T> T *as() const { return (T *)p; }
 };
 
+struct Dfl;  // deflation subspace of an operator (dfl.h)
+
 // One Dirac operator (one quark flavour) on one gauge field: its Pauli term
 // and the inverse odd-site blocks, in FP64 and in each storage precision.
 struct Operator {
@@ -58,6 +60,7 @@ struct Operator {
   DevBuf pinv[4];
   DevBuf wl[4];      // hopping links W = U z^qhat with the phase folded in
   bool ready[4] = {false, false, false, false};
+  std::shared_ptr<Dfl> dfl;  // local deflation subspace (qxd_dfl_setup), if built
 };
 
 struct Field {

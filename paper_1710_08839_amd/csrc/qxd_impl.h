@@ -152,7 +152,16 @@ template <> struct St<QXD_BF16> {
     uint32_t v = p[i];
     return {bf2f(v & 0xffffu), bf2f(v >> 16)};
   }
-  QXD_HD static void st(pair_t *p, int64_t i, cx<float> z) { p[i] = f2bf(z.re) | (f2bf(z.im) << 16); }
+  QXD_HD static void st(pair_t *p, int64_t i, cx<float> z) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    // one packed conversion instruction of gfx950 (round to nearest even)
+    typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+    typedef float f32x2_t __attribute__((ext_vector_type(2)));
+    p[i] = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){z.re, z.im}, bf16x2_t));
+#else
+    p[i] = f2bf(z.re) | (f2bf(z.im) << 16);
+#endif
+  }
   QXD_HD static float ldr(const real_t *p, int64_t i) { return p[i]; }
   QXD_HD static void str(real_t *p, int64_t i, float v) { p[i] = v; }
 };
@@ -499,16 +508,13 @@ QXD_HD void store_spinor(const Spinor<P> &s, int64_t i, const cx<T> psi[4][3]) {
   using C = typename St<P>::comp_t;
   C f = (C)1;
   if constexpr (St<P>::scaled) {
+    // largest magnitude (fmax ignores a NaN operand, as the comparison did;
+    // one max with an abs modifier per component)
     T m = 0;
 #pragma unroll
     for (int a = 0; a < 4; a++)
 #pragma unroll
-      for (int c = 0; c < 3; c++) {
-        T r = psi[a][c].re < 0 ? -psi[a][c].re : psi[a][c].re;
-        T q = psi[a][c].im < 0 ? -psi[a][c].im : psi[a][c].im;
-        m = r > m ? r : m;
-        m = q > m ? q : m;
-      }
+      for (int c = 0; c < 3; c++) m = fmax(fmax(m, fabs(psi[a][c].re)), fabs(psi[a][c].im));
     *at32(s.scale, (uint32_t)j) = (float)m;
     f = m > 0 ? (C)(1.0f / (float)m) : (C)0;
   }

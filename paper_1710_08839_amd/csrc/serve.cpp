@@ -20,13 +20,15 @@
 // already held when the scheduler first saw it are not charged: they were
 // outside the free memory a default budget is taken from.
 //
-// Besides the budget, a request is admitted only while the device's free
-// memory, less what admitted work has still to allocate (slots and
-// operators), covers what the request will allocate plus a floor kept for
-// the runtime (kernels' private memory is allocated at dispatch, and a
-// dispatch that cannot get it ends the process) and other users of the
-// device.  Nothing else in the process is counted, so this check bounds what
-// the budget cannot see.
+// Besides the budget, right-hand sides are admitted only while the device's
+// free memory, less what admitted work has still to allocate (slots and
+// operators), covers what they will allocate plus a floor kept for the
+// runtime (kernels' private memory is allocated at dispatch, and a dispatch
+// that cannot get it ends the process) and other users of the device.
+// Nothing else in the process is counted, so this check bounds what the
+// budget cannot see.  A request whose right-hand sides do not all fit is
+// admitted in pieces, as many as fit at a time; it stays at the head of the
+// queue (later requests wait) until all of them are in.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -57,6 +59,8 @@ struct Req {
   double t_submit = 0, t_admit = 0;
   int remaining = 0;
   int status = QXD_OK;
+  std::string err;      // why the request failed (its first failure)
+  int next_rhs = 0;     // right-hand sides admitted so far (admission may come in pieces)
   int max_iters = 0;
   double max_res = 0;
   size_t op_bytes = 0;  // charged operator memory not yet built (cleared once built or done)
@@ -129,6 +133,7 @@ struct Worker {
       }
       if (!bs) continue;
       std::vector<Finished> fin;
+      std::string step_msg;  // why a failed step failed
       {
         qxd_field *f = proto.field;
         std::lock_guard<std::recursive_mutex> flk(f->mu);
@@ -141,12 +146,15 @@ struct Worker {
             held = (size_t)bs->capacity() * slot_b;
           }
           if (s != QXD_OK) {
+            const std::string msg = qxd_last_error();
+            std::lock_guard<std::mutex> lk(sv->mu);
             for (auto &x : take) {
               Finished e;
               e.slot = -1;
               e.tag = x.req;
               e.info = qxd_solve_info{s, 0, 0, 0.0, 0.0};
               fin.push_back(e);
+              if (x.req->err.empty()) x.req->err = msg;
             }
             take.clear();
           }
@@ -161,6 +169,8 @@ struct Worker {
             e.tag = x.req;
             e.info = qxd_solve_info{s, 0, 0, 0.0, 0.0};
             fin.push_back(e);
+            std::lock_guard<std::mutex> lk(sv->mu);
+            if (x.req->err.empty()) x.req->err = qxd_last_error();
           } else {
             built.push_back(x.req);
           }
@@ -178,9 +188,10 @@ struct Worker {
           if (s != QXD_OK) {
             // the batch cannot go on: every right-hand side in it ends with
             // the error, so their requests complete and stop() can join
+            step_msg = qxd_last_error();
             {
               std::lock_guard<std::mutex> lk(sv->mu);
-              sv->error = qxd_last_error();
+              sv->error = step_msg;
             }
             bs->abort_all(s);
           }
@@ -192,6 +203,7 @@ struct Worker {
         for (auto &x : fin) {
           Req *q = (Req *)x.tag;
           if (x.info.status != QXD_OK && q->status == QXD_OK) q->status = x.info.status;
+          if (x.info.status != QXD_OK && q->err.empty()) q->err = step_msg;
           if (x.info.inner_iters > q->max_iters) q->max_iters = x.info.inner_iters;
           if (x.info.true_resid > q->max_res) q->max_res = x.info.true_resid;
           sv->active_rhs--;
@@ -242,7 +254,8 @@ static void scheduler(qxd_serve *sv) {
       Req *q = sv->queue.front();
       qxd_field *f = q->r.field;
       const size_t slot_b = BatchSolver::slot_bytes(f, q->r.solver.inner_prec, q->r.solver);
-      const size_t op_b = f->pending_op_bytes_nowait(q->r.quark, q->r.solver.inner_prec);
+      const bool first = q->next_rhs == 0;
+      const size_t op_b = first ? f->pending_op_bytes_nowait(q->r.quark, q->r.solver.inner_prec) : 0;
       if (std::find_if(sv->fields.begin(), sv->fields.end(), [&](const std::pair<qxd_field *, size_t> &x) {
             return x.first == f;
           }) == sv->fields.end())
@@ -259,26 +272,47 @@ static void scheduler(qxd_serve *sv) {
         resident += now > fd.second ? now - fd.second : 0;
       }
       const size_t before = w0 ? w0->charge() : 0;
-      const size_t after = w0 ? std::max(w0->held, (size_t)(w0->admitted + q->r.nrhs) * slot_b)
-                              : (size_t)q->r.nrhs * slot_b;
-      // what admitted work has still to allocate, with this request
-      size_t to_alloc = sv->op_pending + op_b;
+      const size_t held0 = w0 ? w0->held : 0;
+      const int adm0 = w0 ? w0->admitted : 0;
+      // what admitted work of the other groups has still to allocate
+      size_t pend_base = sv->op_pending;
       for (auto &kv : sv->workers) {
         const Worker *w = kv.second.get();
-        const size_t need = (size_t)(w->admitted + (w == w0 ? q->r.nrhs : 0)) * w->slot_b;
-        to_alloc += need > w->held ? need - w->held : 0;
+        if (w == w0) continue;
+        const size_t need = (size_t)w->admitted * w->slot_b;
+        pend_base += need > w->held ? need - w->held : 0;
       }
-      if (!w0) to_alloc += (size_t)q->r.nrhs * slot_b;
       size_t dev_free = 0, dev_total = 0;
-      bool dev_ok = hipMemGetInfo(&dev_free, &dev_total) == hipSuccess;
-      dev_ok = dev_ok && dev_free >= to_alloc && dev_free - to_alloc >= device_floor(dev_total);
-      // one request always runs when no other work is charged, whatever the
-      // cached operators hold (if the device cannot hold it, its solve ends
-      // with QXD_ENOMEM)
-      bool fits = (work - before + after + op_b + resident <= sv->budget && dev_ok) || work == 0;
-      bool room = sv->max_active <= 0 || sv->active_rhs + q->r.nrhs <= sv->max_active || sv->active_rhs == 0;
-      if (!fits || !room) break;
-      sv->queue.pop_front();
+      const bool have_info = hipMemGetInfo(&dev_free, &dev_total) == hipSuccess;
+      // can k more right-hand sides of this request be admitted?
+      auto ok = [&](int k) {
+        const size_t need0 = (size_t)(adm0 + k) * slot_b;
+        const size_t after = std::max(held0, need0);
+        const size_t to_alloc = pend_base + (need0 > held0 ? need0 - held0 : 0) + op_b;
+        const bool budget_ok = work - before + after + op_b + resident <= sv->budget;
+        const bool dev_ok = have_info && dev_free >= to_alloc && dev_free - to_alloc >= device_floor(dev_total);
+        const bool room = sv->max_active <= 0 || sv->active_rhs + k <= sv->max_active;
+        return budget_ok && dev_ok && room;
+      };
+      // the most of its remaining right-hand sides that fit (the conditions
+      // only tighten as k grows); a request may be admitted in pieces, and
+      // holds back the later ones until all its right-hand sides are in
+      const int left = q->r.nrhs - q->next_rhs;
+      int k = 0;
+      for (int lo = 1, hi = left; lo <= hi;) {
+        const int mid = lo + (hi - lo) / 2;
+        if (ok(mid)) {
+          k = mid;
+          lo = mid + 1;
+        } else {
+          hi = mid - 1;
+        }
+      }
+      // one right-hand side always runs when no other work is charged,
+      // whatever the cached operators hold (if the device cannot hold it, it
+      // ends with QXD_ENOMEM)
+      if (k == 0 && work == 0 && sv->active_rhs == 0) k = 1;
+      if (k == 0) break;
       auto &w = sv->workers[gk];
       if (!w) {
         w.reset(new Worker());
@@ -297,14 +331,19 @@ static void scheduler(qxd_serve *sv) {
         w->bs = std::move(bs);
         w->th = std::thread([wp = w.get()] { wp->run(); });
       }
-      q->t_admit = now_s();
-      q->remaining = q->r.nrhs;
-      q->op_bytes = op_b;
-      sv->op_pending += op_b;
-      w->admitted += q->r.nrhs;
-      sv->active_rhs += q->r.nrhs;
-      for (int i = 0; i < q->r.nrhs; i++) w->inbox.push_back(Rhs{q, i});
+      if (first) {
+        q->t_admit = now_s();
+        q->remaining = q->r.nrhs;
+        q->op_bytes = op_b;
+        sv->op_pending += op_b;
+      }
+      w->admitted += k;
+      sv->active_rhs += k;
+      for (int i = 0; i < k; i++) w->inbox.push_back(Rhs{q, q->next_rhs + i});
+      q->next_rhs += k;
       sv->cv.notify_all();
+      if (q->next_rhs < q->r.nrhs) break;  // the rest waits for room
+      sv->queue.pop_front();
     }
     if (sv->stopping && sv->queue.empty()) break;
     sv->cv.wait_for(lk, std::chrono::milliseconds(20));
@@ -426,6 +465,11 @@ qxd_status qxd_serve_poll(qxd_ctx *ctx, uint64_t ticket, qxd_result *out) {
     return QXD_ENOTFOUND;
   }
   *out = it->second;
+  if (out->status != QXD_OK) {
+    auto rq = sv->reqs.find(ticket);
+    const std::string &why = rq != sv->reqs.end() ? rq->second->err : std::string();
+    set_error("request %llu failed: %s", (unsigned long long)ticket, why.empty() ? "(no message)" : why.c_str());
+  }
   sv->results.erase(it);
   sv->reqs.erase(ticket);
   return QXD_OK;

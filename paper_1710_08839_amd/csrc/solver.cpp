@@ -21,6 +21,7 @@
 
 #include "batch_solver.h"
 #include "blas.h"
+#include "dfl.h"
 #include "sap.h"
 #include "solver.h"
 
@@ -372,7 +373,8 @@ qxd_status sap_apply(Field *f, const Operator &op, int prec, int ncy, int nmr, v
 
 qxd_status solve(Field *f, const qxd_quark *quarks, int nquark, const qxd_solver &s, const double *eta_dev,
                  double *psi_dev, int nrhs, int use_guess, qxd_solve_info *info, hipStream_t st) {
-  if (!(s.tol > 0.0) || s.tol >= 1.0 || (s.kind != QXD_SOLVER_EO_GCR && s.kind != QXD_SOLVER_SAP_GCR) ||
+  if (!(s.tol > 0.0) || s.tol >= 1.0 ||
+      (s.kind != QXD_SOLVER_EO_GCR && s.kind != QXD_SOLVER_SAP_GCR && s.kind != QXD_SOLVER_DFL_SAP_GCR) ||
       s.inner_prec < QXD_F64 || s.inner_prec > QXD_BF16 || s.nkv < 0 || s.nkv > MAXV || s.ncy < 0 ||
       s.nmr < 0 || s.maxiter < 0 || s.max_outer < 0 || !(s.inner_tol >= 0.0 && s.inner_tol < 1.0)) {
     set_error("invalid solver parameters");
@@ -428,6 +430,10 @@ qxd_status solve(Field *f, const qxd_quark *quarks, int nquark, const qxd_solver
     }
     return worst;
   }
+  if (s.kind == QXD_SOLVER_DFL_SAP_GCR && s.inner_prec != QXD_F32) {
+    set_error("the deflated SAP-GCR runs with FP32 inner storage only");
+    return QXD_EINVAL;
+  }
   Ws w{f, st};
   size_t fb = spinor_bytes(QXD_F64, g.V);
   void *eta = w.get("solve_eta", fb), *psi = w.get("solve_psi", fb);
@@ -437,12 +443,20 @@ qxd_status solve(Field *f, const qxd_quark *quarks, int nquark, const qxd_solver
     const qxd_quark &q = quarks[r / per];
     Operator *op;
     CS(f->get_op(q, QXD_F64, &op, st));
+    if (s.kind == QXD_SOLVER_DFL_SAP_GCR) {
+      CS(f->get_op(q, QXD_F32, &op, st));
+      if (!op->dfl) {
+        set_error("no deflation subspace for this quark: call qxd_dfl_setup first");
+        return QXD_EINVAL;
+      }
+    }
     const double *src = eta_dev + (int64_t)r * 24 * g.V;
     double *dst = psi_dev + (int64_t)r * 24 * g.V;
     CK(launch_pack(QXD_F64, g, src, eta, 1, st));
     if (use_guess) CK(launch_pack(QXD_F64, g, dst, psi, 1, st));
     qxd_solve_info inf{};
-    qxd_status rs = eo_gcr(f, *op, s, eta, psi, use_guess, &inf, st);
+    qxd_status rs = s.kind == QXD_SOLVER_DFL_SAP_GCR ? dfl_solve(f, *op, s, eta, psi, use_guess, &inf, st)
+                                                     : eo_gcr(f, *op, s, eta, psi, use_guess, &inf, st);
     if (rs != QXD_OK && rs != QXD_ENOCONV && rs != QXD_EFLOAT) return rs;
     CK(launch_unpack(QXD_F64, g, psi, dst, 1, st));
     CK(hipStreamSynchronize(st));

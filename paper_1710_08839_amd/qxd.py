@@ -16,7 +16,7 @@ F64, F32, F16S, BF16 = 0, 1, 2, 3
 PREC = {"f64": F64, "f32": F32, "f16": F16S, "f16s": F16S, "bf16": BF16}
 OP_D, OP_DHAT, OP_HOP, OP_PAULI, OP_OOINV, OP_G5D, OP_DHAT_DAG, OP_NORMAL = 0, 1, 2, 3, 4, 5, 6, 7
 NATIVE = 1
-EO_GCR, SAP_GCR = 0, 1
+EO_GCR, SAP_GCR, DFL_SAP_GCR = 0, 1, 2
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ENOCONV", -4: "EFLOAT", -5: "EDEVICE",
           -6: "EBUSY", -7: "ENOTFOUND"}
 
@@ -48,6 +48,12 @@ class Solver(ctypes.Structure):
 class SolveInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("outer_iters", ctypes.c_int), ("inner_iters", ctypes.c_int),
                 ("true_resid", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+class DflParams(ctypes.Structure):
+    _fields_ = [("ns", ctypes.c_int), ("ninv", ctypes.c_int), ("ncy", ctypes.c_int), ("nmr", ctypes.c_int),
+                ("little_tol", ctypes.c_double), ("little_nkv", ctypes.c_int), ("little_maxiter", ctypes.c_int),
+                ("seed", ctypes.c_uint64)]
 
 
 class Request(ctypes.Structure):
@@ -84,6 +90,7 @@ SIGNATURES = {
                               _VP], _I),
     "qxd_rational_apply": ([_VP, ctypes.POINTER(Quark), _D, _VP, _VP, _I, _D, _I, _VP, _VP,
                             ctypes.POINTER(SolveInfo), _VP], _I),
+    "qxd_dfl_setup": ([_VP, ctypes.POINTER(Quark), ctypes.POINTER(DflParams), _VP, _VP], _I),
     "qxd_serve_start": ([_VP, _SZ, _I], _I),
     "qxd_serve_submit": ([_VP, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], _I),
     "qxd_serve_poll": ([_VP, ctypes.c_uint64, ctypes.POINTER(Result)], _I),
@@ -98,6 +105,10 @@ SIGNATURES = {
     "qxd_debug_stream": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, _I, ctypes.c_void_p], _I),
     "qxd_debug_step_graph_counts": ([ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], _I),
     "qxd_debug_get_dirac_variant": ([_VP, _I, ctypes.POINTER(_I)], _I),
+    "qxd_debug_dfl_basis": ([_VP, ctypes.POINTER(Quark), _I, _VP, _VP], _I),
+    "qxd_debug_dfl_little": ([_VP, ctypes.POINTER(Quark), ctypes.POINTER(_I), ctypes.POINTER(_I), _VP, _VP], _I),
+    "qxd_debug_dfl_precond": ([_VP, ctypes.POINTER(Quark), _D, _I, _I, _VP, _VP, _VP], _I),
+    "qxd_debug_dfl_stats": ([_VP, ctypes.POINTER(Quark), ctypes.POINTER(ctypes.c_int64)], _I),
 }
 
 _lib = None
@@ -148,6 +159,12 @@ def set_step_graphs(enable=True):
     """Replay batched SAP-GCR steps from captured HIP graphs (default) or
     issue every launch directly.  A testing hook."""
     _check(lib().qxd_debug_set_step_graphs(1 if enable else 0))
+
+
+def last_error():
+    """The calling thread's last error message of the library."""
+    m = lib().qxd_last_error()
+    return m.decode() if m else ""
 
 
 def fail_steps(n):
@@ -312,6 +329,43 @@ class Field:
         if check and st != 0:
             _check(st)
         return st, list(info)
+
+    def dfl_setup(self, q, ns=0, ninv=0, ncy=0, nmr=0, little_tol=0.0, little_nkv=0, little_maxiter=0, seed=0,
+                  init=None, stream=None):
+        """Build the local deflation subspace and little operator of quark q
+        (start fields: init, ns API-layout FP64 spinors on the device, or
+        random from seed)."""
+        p = DflParams(ns, ninv, ncy, nmr, little_tol, little_nkv, little_maxiter, seed)
+        _check(lib().qxd_dfl_setup(self.h, ctypes.byref(q), ctypes.byref(p), _ptr(init) if init is not None else None,
+                                   _stream(stream)))
+
+    def dfl_basis(self, q, k, out, stream=None):
+        """Basis field k of the deflation subspace into the API-layout FP64
+        spinor out (a testing hook)."""
+        _check(lib().qxd_debug_dfl_basis(self.h, ctypes.byref(q), int(k), _ptr(out), _stream(stream)))
+
+    def dfl_little(self, q):
+        """The little operator as a complex array [nblocks, 9, ns, ns] and the
+        neighbour table [nblocks, 9] (a testing hook)."""
+        ns, nb = _I(0), _I(0)
+        _check(lib().qxd_debug_dfl_little(self.h, ctypes.byref(q), ctypes.byref(ns), ctypes.byref(nb), None, None))
+        a = np.empty((nb.value, 9, ns.value, ns.value), dtype=np.complex128)
+        nbr = np.empty((nb.value, 9), dtype=np.int32)
+        _check(lib().qxd_debug_dfl_little(self.h, ctypes.byref(q), ctypes.byref(ns), ctypes.byref(nb),
+                                          a.ctypes.data, nbr.ctypes.data))
+        return a, nbr
+
+    def dfl_stats(self, q):
+        """(preconditioner applications, little GCR iterations, most in one
+        little solve) since the last call; a measurement hook."""
+        out = (ctypes.c_int64 * 3)()
+        _check(lib().qxd_debug_dfl_stats(self.h, ctypes.byref(q), out))
+        return tuple(out)
+
+    def dfl_precond(self, q, x, y, little_tol=0.0, ncy=4, nmr=4, stream=None):
+        """y = M_dfl x (API-layout FP64 spinors; a testing hook)."""
+        _check(lib().qxd_debug_dfl_precond(self.h, ctypes.byref(q), float(little_tol), int(ncy), int(nmr), _ptr(x),
+                                           _ptr(y), _stream(stream)))
 
     def sap_pair_pass_ms(self, q, prec, nmr=4, npair=1, reps=20, stream=None):
         """Average time (ms) of one colour pass of the paired SAP block

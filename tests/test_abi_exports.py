@@ -45,6 +45,11 @@ def test_header_parses():
     assert fns["qxd_debug_step_graph_counts"] == 2
     assert fns["qxd_debug_stream"] == 5
     assert fns["qxd_debug_serve_charges"] == 2
+    assert fns["qxd_dfl_setup"] == 5
+    assert fns["qxd_debug_dfl_basis"] == 5
+    assert fns["qxd_debug_dfl_little"] == 6
+    assert fns["qxd_debug_dfl_precond"] == 8
+    assert fns["qxd_debug_dfl_stats"] == 3
     assert fns["qxd_abi_version"] == 0
     assert fns["qxd_dirac_apply"] == 10
     assert fns["qxd_solve"] == 10
@@ -88,3 +93,4 @@ def test_library_loads_and_reports(libpath):
     assert lib.qxd_debug_fail_steps(0) == 0
     out = (ctypes.c_size_t * 4)()
     assert lib.qxd_debug_serve_charges(None, out) != 0
+    assert lib.qxd_dfl_setup(None, None, None, None, None) != 0

@@ -331,3 +331,41 @@ def test_serve_charges_drain(ctx, small):
     for e, o, op in zip(etas, outs, ops):
         x = to_host(e)[0]
         assert od.norm(x - op.apply(to_host(o)[0])) / od.norm(x) <= 1.05e-10
+
+
+def test_serve_admits_requests_in_pieces(ctx, small):
+    """With a budget that holds no solver slot at all, a request of three
+    right-hand sides is admitted one right-hand side at a time (each when no
+    other work is charged) and completes with every solution correct; the
+    request behind it waits until all three are in."""
+    import torch
+    from paper_1710_08839_amd import qxd
+    c = small
+    s = qxd.solver(kind=qxd.SAP_GCR, tol=1e-10, nkv=6, ncy=2, nmr=3, inner_prec=qxd.F32)
+    e3 = to_dev(np.stack([c.source(80 + j) for j in range(3)]))
+    e1 = to_dev(c.source(90)[None])
+    o3, o1 = torch.empty_like(e3), torch.empty_like(e1)
+    torch.cuda.synchronize()
+    ctx.serve_start(budget_bytes=1)
+    try:
+        t3 = ctx.serve_submit(c.field, c.quark, s, e3, o3, 3)
+        t1 = ctx.serve_submit(c.field, c.quark, s, e1, o1, 1)
+        done, t0 = {}, time.time()
+        while len(done) < 2 and time.time() - t0 < 60:
+            for t in (t3, t1):
+                if t not in done:
+                    r = ctx.serve_poll(t)
+                    if r is not None:
+                        done[t] = r
+            time.sleep(0.005)
+    finally:
+        ctx.serve_stop()
+    assert len(done) == 2 and done[t3].status == 0 and done[t1].status == 0
+    assert done[t3].nrhs == 3
+    # the second request was admitted only after the first one's last piece
+    assert done[t1].queue_s > 0
+    eh, oh = to_host(e3), to_host(o3)
+    for j in range(3):
+        assert od.norm(eh[j] - c.op.apply(oh[j])) / od.norm(eh[j]) <= 1.05e-10, j
+    x = to_host(e1)[0]
+    assert od.norm(x - c.op.apply(to_host(o1)[0])) / od.norm(x) <= 1.05e-10
