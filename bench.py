@@ -481,7 +481,7 @@ def single_rhs_64x32(f):
     return out
 
 
-def dfl_leg(f, ns=20, ninv=10, nkv=32):
+def dfl_leg(f, ns=20, ninv=20, nkv=32):
     """Locally deflated SAP-GCR on the 64 x 32^3 field of the D leg (q = -1/3,
     kappa 0.1365, csw 1.9), one Gaussian source: the deflation subspace's
     setup time, then the deflated solve and the plain SAP-GCR on the same
@@ -501,9 +501,11 @@ def dfl_leg(f, ns=20, ninv=10, nkv=32):
     setup_s = time.perf_counter() - t0
     dfl = single_solve(f, q, qxd.solver(kind=qxd.DFL_SAP_GCR, tol=1e-10, nkv=nkv, ncy=4, nmr=4,
                                         inner_prec=qxd.F32), eta)
+    st = f.dfl_stats(q)  # the warm-up and the timed solve
     log(f"64x32^3 deflated SAP-GCR: setup {setup_s:.2f} s, {dfl}")
     return {"setup_s": round(setup_s, 3), "deflated": dfl, "sap_gcr": sap,
-            "subspace": {"ns": ns, "ninv": ninv, "ncy": 4, "nmr": 4, "little_tol": 1e-2, "little_nkv": 24},
+            "subspace": {"ns": ns, "ninv": ninv, "ncy": 4, "nmr": 4, "little_tol": 1e-1, "little_nkv": 32},
+            "little": {"applications": st[0], "iterations": st[1], "max_per_solve": st[2]},
             "workload": "64x32^3 C*, q=-1/3, kappa=0.1365, csw=1.9, Gaussian source (seed 1003), tol 1e-10"}
 
 

@@ -267,10 +267,10 @@ typedef struct {
   int ns;             /* deflation fields, i.e. basis vectors per SAP block
                          (1..32) [20]                                          */
   int ninv;           /* SAP-smoothed inverse-iteration steps that refine the
-                         random start fields [10]                              */
+                         random start fields [20]                              */
   int ncy, nmr;       /* SAP cycles and MR steps of each such step [4, 4]      */
-  double little_tol;  /* relative residual of each little-system solve [1e-2] */
-  int little_nkv;     /* Krylov vectors of the little GCR (<= 64) [24]         */
+  double little_tol;  /* relative residual of each little-system solve [1e-1] */
+  int little_nkv;     /* Krylov vectors of the little GCR (<= 64) [32]         */
   int little_maxiter; /* iterations of one little solve [256]                  */
   uint64_t seed;      /* seed of the random start fields                       */
 } qxd_dfl_params;
@@ -291,7 +291,9 @@ typedef struct {
  *     its eight neighbours.
  * A later qxd_solve with QXD_SOLVER_DFL_SAP_GCR for this quark then uses the
  * preconditioner M_dfl r = V A^-1 V^dag r + M_sap (r - D V A^-1 V^dag r),
- * with A^-1 applied by block-Jacobi right-preconditioned GCR to little_tol.
+ * with A^-1 applied by GCR on the even-block Schur complement of A (blocks
+ * coloured as for SAP), right-preconditioned by the inverse diagonal blocks,
+ * to little_tol, with FP32 copies of the little matrices.
  * A new call for the same quark replaces the subspace.  The subspace lives
  * with the quark's operator in the field's operator cache (freed with it).
  * Needs SAP blocks of at most 256 sites that admit the two-colour

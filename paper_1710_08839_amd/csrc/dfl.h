@@ -11,7 +11,9 @@
 //   - little operator A = V^dag D V: per block its couplings to itself and,
 //     through each of its eight faces, to the block across;
 //   - preconditioner M_dfl r = V A^-1 V^dag r + M_sap (r - D V A^-1 V^dag r),
-//     A^-1 by GCR right-preconditioned with the inverse diagonal blocks.
+//     A^-1 by GCR on the even-block Schur complement A_ee - A_eo A_oo^-1 A_oe
+//     (blocks coloured as for SAP, so A_ee and A_oo are block diagonal),
+//     right-preconditioned with the inverse diagonal blocks A_ee^-1.
 #pragma once
 
 #include "host.h"
@@ -29,9 +31,12 @@ struct Dfl {
   DevBuf basis;            // ns FP32 native spinors; field k holds basis vector k of every block
   DevBuf a;                // little operator [nb][9][ns][ns] double2
   DevBuf ainv;             // inverses of the diagonal blocks A[b][0] [nb][ns][ns] double2
+  DevBuf at32, ait32;      // FP32 copies of a and ainv for the little solve, transposed per block
   DevBuf nbr;              // [nb][9] int: the block each slot couples to
+  DevBuf even, odd;        // the blocks of each SAP colour (neighbours have opposite colours)
+  int ne = 0, no = 0;
   // little GCR: Krylov vectors z_k (preconditioned) and w_k = A z_k, work vectors, scalars
-  DevBuf lz, lw, lx, lr, lb, lpart, lscal;
+  DevBuf lz, lw, lx, lr, lb, lt, lu, lpart, lscal;
   // counters since the last read: preconditioner applications, little GCR
   // iterations (total and the largest of one solve)
   int64_t applications = 0, little_iters = 0, little_max = 0;
@@ -63,12 +68,17 @@ hipError_t launch_dfl_diag(const Geom &g, const void *basis, size_t vbytes, int 
                            double2 *a, int *nbr, hipStream_t st);
 // ainv[b] = a[b][0]^-1 (Gauss-Jordan with partial pivoting); *bad counts singular blocks
 hipError_t launch_little_invert(int nb, int ns, const double2 *a, double2 *ainv, int *bad, hipStream_t st);
-// y = A x over all blocks
-hipError_t launch_little_apply(int nb, int ns, const double2 *a, const int *nbr, const double2 *x, double2 *y,
-                               hipStream_t st);
-// y[b] = ainv[b] x[b]
-hipError_t launch_little_jacobi(int nb, int ns, const double2 *ainv, const double2 *x, double2 *y,
-                                hipStream_t st);
+// FP32 copies of nmat ns x ns blocks, transposed within each block
+hipError_t launch_little_pack(int64_t nmat, int ns, const double2 *src, float2 *dst, hipStream_t st);
+// for the blocks b of `list`: y_b = (xa ? A[b][0] xa_b : (w ? w_b : 0)) -
+// sum_{d >= 1} A[b][d] xh[nbr[b][d]] (the couplings to the blocks across the
+// faces); at: the transposed FP32 copy of A
+hipError_t launch_lt_hop(const int *list, int nlist, int ns, const float2 *at, const int *nbr, const double2 *xa,
+                         const double2 *w, const double2 *xh, double2 *y, hipStream_t st);
+// for the blocks b of `list`: y_b = s ainv[b] x_b (x and y distinct); ait:
+// the transposed FP32 copy of the inverse diagonal blocks
+hipError_t launch_lt_jacobi(const int *list, int nlist, int ns, const float2 *ait, double s, const double2 *x,
+                            double2 *y, hipStream_t st);
 // out[2j..2j+1] = (W_j, x) for j < k, W_j = W + j * n (complex vectors of length n)
 hipError_t launch_lv_dots(const double2 *W, int k, int64_t n, const double2 *x, double *partial, double *out,
                           hipStream_t st);

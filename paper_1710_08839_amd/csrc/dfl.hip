@@ -335,38 +335,73 @@ __global__ void __launch_bounds__(DT) little_invert_kernel(int ns, const double2
   if (singular && threadIdx.x == 0) atomicAdd(bad, 1);
 }
 
-__global__ void __launch_bounds__(DT) little_apply_kernel(int nb, int ns, const double2 *a, const int *nbr,
-                                                          const double2 *x, double2 *y) {
+// The little solve reads FP32 copies of A and of the inverse diagonal blocks,
+// transposed within each ns x ns block (element (k, l) at l * ns + k), so
+// that the threads of consecutive rows k read consecutive words.
+__global__ void __launch_bounds__(DT) little_pack_kernel(int64_t nmat, int ns, const double2 *src, float2 *dst) {
   const int64_t t = (int64_t)blockIdx.x * DT + threadIdx.x;
-  if (t >= (int64_t)nb * ns) return;
-  const int blk = (int)(t / ns), k = (int)(t - (int64_t)blk * ns);
-  double re = 0.0, im = 0.0;
-  for (int d = 0; d < DFL_SLOTS; d++) {
-    const double2 *row = a + (((int64_t)blk * DFL_SLOTS + d) * ns + k) * ns;
-    const double2 *xv = x + (int64_t)nbr[blk * DFL_SLOTS + d] * ns;
-    for (int l = 0; l < ns; l++) {
-      const double2 m = row[l], v = xv[l];
-      re += m.x * v.x - m.y * v.y;
-      im += m.x * v.y + m.y * v.x;
-    }
-  }
-  y[t] = make_double2(re, im);
+  if (t >= nmat * ns * ns) return;
+  const int64_t m = t / (ns * ns);
+  const int e = (int)(t - m * ns * ns), k = e / ns, l = e - k * ns;
+  const double2 v = src[t];
+  dst[m * ns * ns + (int64_t)l * ns + k] = make_float2((float)v.x, (float)v.y);
 }
 
-__global__ void __launch_bounds__(DT) little_jacobi_kernel(int nb, int ns, const double2 *ainv, const double2 *x,
-                                                           double2 *y) {
+// y_b = (xa ? A[b][0] xa_b : (w ? w_b : 0)) - sum_{d >= 1} A[b][d] xh[nbr[b][d]]
+// for the blocks b of `list` (one thread per (block, row)); at: the
+// transposed FP32 copy of A
+__global__ void __launch_bounds__(DT) lt_hop_kernel(const int *list, int nlist, int ns, const float2 *at,
+                                                    const int *nbr, const double2 *xa, const double2 *w,
+                                                    const double2 *xh, double2 *y) {
   const int64_t t = (int64_t)blockIdx.x * DT + threadIdx.x;
-  if (t >= (int64_t)nb * ns) return;
-  const int blk = (int)(t / ns), k = (int)(t - (int64_t)blk * ns);
-  const double2 *row = ainv + ((int64_t)blk * ns + k) * ns;
+  if (t >= (int64_t)nlist * ns) return;
+  const int li = (int)(t / ns), k = (int)(t - (int64_t)li * ns);
+  const int blk = list[li];
+  double re = 0.0, im = 0.0;
+  if (xa) {
+    const float2 *col = at + ((int64_t)blk * DFL_SLOTS) * ns * ns + k;
+    const double2 *xv = xa + (int64_t)blk * ns;
+    for (int l = 0; l < ns; l++) {
+      const float2 m = col[(int64_t)l * ns];
+      const double2 v = xv[l];
+      re += (double)m.x * v.x - (double)m.y * v.y;
+      im += (double)m.x * v.y + (double)m.y * v.x;
+    }
+  } else if (w) {
+    re = w[(int64_t)blk * ns + k].x;
+    im = w[(int64_t)blk * ns + k].y;
+  }
+  for (int d = 1; d < DFL_SLOTS; d++) {
+    const float2 *col = at + ((int64_t)blk * DFL_SLOTS + d) * ns * ns + k;
+    const double2 *xv = xh + (int64_t)nbr[blk * DFL_SLOTS + d] * ns;
+    for (int l = 0; l < ns; l++) {
+      const float2 m = col[(int64_t)l * ns];
+      const double2 v = xv[l];
+      re -= (double)m.x * v.x - (double)m.y * v.y;
+      im -= (double)m.x * v.y + (double)m.y * v.x;
+    }
+  }
+  y[(int64_t)blk * ns + k] = make_double2(re, im);
+}
+
+// y_b = s ainv[b] x_b for the blocks b of `list` (x and y distinct); ait:
+// the transposed FP32 copy of the inverse diagonal blocks
+__global__ void __launch_bounds__(DT) lt_jacobi_kernel(const int *list, int nlist, int ns, const float2 *ait,
+                                                       double s, const double2 *x, double2 *y) {
+  const int64_t t = (int64_t)blockIdx.x * DT + threadIdx.x;
+  if (t >= (int64_t)nlist * ns) return;
+  const int li = (int)(t / ns), k = (int)(t - (int64_t)li * ns);
+  const int blk = list[li];
+  const float2 *col = ait + (int64_t)blk * ns * ns + k;
   const double2 *xv = x + (int64_t)blk * ns;
   double re = 0.0, im = 0.0;
   for (int l = 0; l < ns; l++) {
-    const double2 m = row[l], v = xv[l];
-    re += m.x * v.x - m.y * v.y;
-    im += m.x * v.y + m.y * v.x;
+    const float2 m = col[(int64_t)l * ns];
+    const double2 v = xv[l];
+    re += (double)m.x * v.x - (double)m.y * v.y;
+    im += (double)m.x * v.y + (double)m.y * v.x;
   }
-  y[t] = make_double2(re, im);
+  y[(int64_t)blk * ns + k] = make_double2(s * re, s * im);
 }
 
 // ---- little-vector reductions: LVG work-groups, partial sums per group ------
@@ -503,15 +538,20 @@ hipError_t launch_little_invert(int nb, int ns, const double2 *a, double2 *ainv,
   return hipGetLastError();
 }
 
-hipError_t launch_little_apply(int nb, int ns, const double2 *a, const int *nbr, const double2 *x, double2 *y,
-                               hipStream_t st) {
-  little_apply_kernel<<<grid_for((int64_t)nb * ns, DT), DT, 0, st>>>(nb, ns, a, nbr, x, y);
+hipError_t launch_little_pack(int64_t nmat, int ns, const double2 *src, float2 *dst, hipStream_t st) {
+  little_pack_kernel<<<grid_for(nmat * ns * ns, DT), DT, 0, st>>>(nmat, ns, src, dst);
   return hipGetLastError();
 }
 
-hipError_t launch_little_jacobi(int nb, int ns, const double2 *ainv, const double2 *x, double2 *y,
-                                hipStream_t st) {
-  little_jacobi_kernel<<<grid_for((int64_t)nb * ns, DT), DT, 0, st>>>(nb, ns, ainv, x, y);
+hipError_t launch_lt_hop(const int *list, int nlist, int ns, const float2 *at, const int *nbr, const double2 *xa,
+                         const double2 *w, const double2 *xh, double2 *y, hipStream_t st) {
+  lt_hop_kernel<<<grid_for((int64_t)nlist * ns, DT), DT, 0, st>>>(list, nlist, ns, at, nbr, xa, w, xh, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_lt_jacobi(const int *list, int nlist, int ns, const float2 *ait, double s, const double2 *x,
+                            double2 *y, hipStream_t st) {
+  lt_jacobi_kernel<<<grid_for((int64_t)nlist * ns, DT), DT, 0, st>>>(list, nlist, ns, ait, s, x, y);
   return hipGetLastError();
 }
 

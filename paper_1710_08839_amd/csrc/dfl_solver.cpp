@@ -56,18 +56,29 @@ SpinorArg full(const Geom &g, void *p) { return SpinorArg{p, g.V, 0, g.rd}; }
 // scalars of the little GCR on the device
 constexpr int LS_S = 0, LS_RR = 4, LS_DOTS = 8, LS_WN = 8 + 2 * 64, LS_N = LS_WN + 64 + 8;
 
-// x = A^-1 b approximately: GCR right-preconditioned by the inverse diagonal
-// blocks, with p_k = J r (z) and w_k = A z_k made A-orthogonal, x and r
-// updated at every step; stops at |r| <= tol |b| or maxiter iterations
+// x = A^-1 b approximately, on the even-block Schur complement
+//   Ahat = A_ee - A_eo A_oo^-1 A_oe,   Ahat x_e = b_e - A_eo A_oo^-1 b_o,
+//   x_o = A_oo^-1 (b_o - A_oe x_e),
+// by GCR right-preconditioned with A_ee^-1: z_k = A_ee^-1 r and w_k = Ahat z_k
+// made orthogonal to the earlier w, x and r updated at every step; stops at
+// |r| <= tol |b_e - A_eo A_oo^-1 b_o| or maxiter iterations.  Vectors are
+// full length (blocks of both colours); the odd entries of r, z, w stay 0.
 qxd_status little_solve(Dfl &d, const double2 *b, double2 *x, double tol, int *iters, hipStream_t st) {
   const int64_t n = (int64_t)d.nb * d.ns;
-  const int nkv = d.p.little_nkv;
+  const int nkv = d.p.little_nkv, ns = d.ns;
   double2 *Z = d.lz.as<double2>(), *W = d.lw.as<double2>(), *r = d.lr.as<double2>();
+  double2 *t = d.lt.as<double2>(), *u = d.lu.as<double2>();
   double *part = d.lpart.as<double>(), *sc = d.lscal.as<double>();
-  const double2 *A = d.a.as<double2>(), *Ai = d.ainv.as<double2>();
-  const int *nbr = d.nbr.as<int>();
-  DCK(hipMemsetAsync(x, 0, n * sizeof(double2), st));
-  DCK(hipMemcpyAsync(r, b, n * sizeof(double2), hipMemcpyDeviceToDevice, st));
+  const float2 *A = d.at32.as<float2>(), *Ai = d.ait32.as<float2>();
+  const int *nbr = d.nbr.as<int>(), *ev = d.even.as<int>(), *od = d.odd.as<int>();
+  const size_t vb = n * sizeof(double2);
+  DCK(hipMemsetAsync(x, 0, vb, st));
+  DCK(hipMemsetAsync(r, 0, vb, st));
+  DCK(hipMemsetAsync(Z, 0, vb * nkv, st));
+  DCK(hipMemsetAsync(W, 0, vb * nkv, st));
+  // r_e = b_e - A_eo A_oo^-1 b_o
+  DCK(launch_lt_jacobi(od, d.no, ns, Ai, 1.0, b, u, st));
+  DCK(launch_lt_hop(ev, d.ne, ns, A, nbr, nullptr, b, u, r, st));
   DCK(launch_lv_dot2(r, r, n, part, sc + LS_S, st));
   double bn2;
   DCS(fetch(&bn2, sc + LS_S, 1, st));
@@ -81,8 +92,11 @@ qxd_status little_solve(Dfl &d, const double2 *b, double2 *x, double tol, int *i
     while (!done && it < d.p.little_maxiter) {
       for (int k = 0; k < nkv && !done; k++) {
         double2 *zk = Z + (int64_t)k * n, *wk = W + (int64_t)k * n;
-        DCK(launch_little_jacobi(d.nb, d.ns, Ai, r, zk, st));
-        DCK(launch_little_apply(d.nb, d.ns, A, nbr, zk, wk, st));
+        DCK(launch_lt_jacobi(ev, d.ne, ns, Ai, 1.0, r, zk, st));
+        // w_e = A_ee z - A_eo u_o with u_o = A_oo^-1 A_oe z
+        DCK(launch_lt_hop(od, d.no, ns, A, nbr, nullptr, nullptr, zk, t, st));
+        DCK(launch_lt_jacobi(od, d.no, ns, Ai, -1.0, t, u, st));
+        DCK(launch_lt_hop(ev, d.ne, ns, A, nbr, zk, nullptr, u, wk, st));
         if (k > 0) {
           DCK(launch_lv_dots(W, k, n, wk, part, sc + LS_DOTS, st));
           DCK(launch_lv_maxpy(wk, W, k, n, sc + LS_DOTS, sc + LS_WN, st));
@@ -102,17 +116,20 @@ qxd_status little_solve(Dfl &d, const double2 *b, double2 *x, double tol, int *i
       }
     }
   }
+  // x_o = A_oo^-1 (b_o - A_oe x_e)
+  DCK(launch_lt_hop(od, d.no, ns, A, nbr, nullptr, b, x, t, st));
+  DCK(launch_lt_jacobi(od, d.no, ns, Ai, 1.0, t, x, st));
   if (iters) *iters = it;
   return QXD_OK;
 }
 
 qxd_status fill_params(qxd_dfl_params *p) {
   if (p->ns == 0) p->ns = 20;
-  if (p->ninv == 0) p->ninv = 10;
+  if (p->ninv == 0) p->ninv = 20;
   if (p->ncy == 0) p->ncy = 4;
   if (p->nmr == 0) p->nmr = 4;
-  if (p->little_tol == 0.0) p->little_tol = 1e-2;
-  if (p->little_nkv == 0) p->little_nkv = 24;
+  if (p->little_tol == 0.0) p->little_tol = 1e-1;
+  if (p->little_nkv == 0) p->little_nkv = 32;
   if (p->little_maxiter == 0) p->little_maxiter = 256;
   if (p->ns < 1 || p->ns > DFL_NSMAX || p->ninv < 0 || p->ncy < 1 || p->nmr < 0 || !(p->little_tol > 0.0) ||
       p->little_tol >= 1.0 || p->little_nkv < 1 || p->little_nkv > 64 || p->little_maxiter < 1) {
@@ -137,7 +154,8 @@ qxd_status op_with_dfl(Field *f, const qxd_quark &q, Operator **op, hipStream_t 
 }  // namespace
 
 size_t Dfl::bytes() const {
-  return basis.n + a.n + ainv.n + nbr.n + lz.n + lw.n + lx.n + lr.n + lb.n + lpart.n + lscal.n;
+  return basis.n + a.n + ainv.n + at32.n + ait32.n + nbr.n + even.n + odd.n + lz.n + lw.n + lx.n + lr.n + lb.n + lt.n + lu.n +
+         lpart.n + lscal.n;
 }
 
 qxd_status dfl_setup(Field *f, const qxd_quark &q, const qxd_dfl_params *pin, const double *init_api,
@@ -231,8 +249,34 @@ qxd_status dfl_setup(Field *f, const qxd_quark &q, const qxd_dfl_params *pin, co
     set_error("the little operator has %d singular diagonal blocks", nbad);
     return QXD_EFLOAT;
   }
+  DCK(d->at32.ensure((size_t)d->nb * DFL_SLOTS * nn * sizeof(float2)));
+  DCK(d->ait32.ensure((size_t)d->nb * nn * sizeof(float2)));
+  DCK(launch_little_pack((int64_t)d->nb * DFL_SLOTS, ns, d->a.as<double2>(), d->at32.as<float2>(), st));
+  DCK(launch_little_pack((int64_t)d->nb, ns, d->ainv.as<double2>(), d->ait32.as<float2>(), st));
+  // the blocks of each colour: the parity of the block coordinates, as for
+  // SAP (the two-colour check guarantees that neighbours differ)
+  {
+    std::vector<int> ev, od;
+    for (int b = 0; b < d->nb; b++) {
+      int c = b, sum = 0;
+      for (int m = 3; m >= 0; m--) {
+        sum += c % g.nb[m];
+        c /= g.nb[m];
+      }
+      (sum & 1 ? od : ev).push_back(b);
+    }
+    d->ne = (int)ev.size();
+    d->no = (int)od.size();
+    DCK(d->even.ensure(ev.size() * sizeof(int)));
+    DCK(d->odd.ensure(od.size() * sizeof(int)));
+    DCK(hipMemcpyAsync(d->even.p, ev.data(), ev.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    DCK(hipMemcpyAsync(d->odd.p, od.data(), od.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    DCK(hipStreamSynchronize(st));
+  }
   // little GCR workspace
   const size_t n = (size_t)d->nb * ns;
+  DCK(d->lt.ensure(n * sizeof(double2)));
+  DCK(d->lu.ensure(n * sizeof(double2)));
   DCK(d->lz.ensure((size_t)p.little_nkv * n * sizeof(double2)));
   DCK(d->lw.ensure((size_t)p.little_nkv * n * sizeof(double2)));
   DCK(d->lx.ensure(n * sizeof(double2)));
