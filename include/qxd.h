@@ -269,7 +269,7 @@ typedef struct {
   int ninv;           /* SAP-smoothed inverse-iteration steps that refine the
                          random start fields [20]                              */
   int ncy, nmr;       /* SAP cycles and MR steps of each such step [4, 4]      */
-  double little_tol;  /* relative residual of each little-system solve [1e-1] */
+  double little_tol;  /* relative residual of each little-system solve [0.2]  */
   int little_nkv;     /* Krylov vectors of the little GCR (<= 64) [32]         */
   int little_maxiter; /* iterations of one little solve [256]                  */
   uint64_t seed;      /* seed of the random start fields                       */

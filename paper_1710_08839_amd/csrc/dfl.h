@@ -23,6 +23,28 @@ namespace qxd {
 constexpr int DFL_NSMAX = 32;  // basis vectors per block
 constexpr int DFL_SLOTS = 9;   // couplings of a block: itself, then faces 2 mu + (0 fwd, 1 bwd)
 
+// Pinned host slots and events through which the little GCR reads the
+// residual norm of a step while the device already runs the next one.
+struct LittleSync {
+  double *host = nullptr;  // two slots
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  LittleSync() = default;
+  LittleSync(const LittleSync &) = delete;
+  LittleSync &operator=(const LittleSync &) = delete;
+  ~LittleSync() {
+    if (host) (void)hipHostFree(host);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  hipError_t init() {
+    hipError_t e = hipSuccess;
+    if (!host) e = hipHostMalloc((void **)&host, 2 * sizeof(double), hipHostMallocDefault);
+    for (int i = 0; i < 2 && e == hipSuccess; i++)
+      if (!ev[i]) e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+    return e;
+  }
+};
+
 struct Dfl {
   qxd_dfl_params p{};     // with the defaults filled in
   int ns = 0;
@@ -36,7 +58,8 @@ struct Dfl {
   DevBuf even, odd;        // the blocks of each SAP colour (neighbours have opposite colours)
   int ne = 0, no = 0;
   // little GCR: Krylov vectors z_k (preconditioned) and w_k = A z_k, work vectors, scalars
-  DevBuf lz, lw, lx, lr, lb, lt, lu, lpart, lscal;
+  DevBuf lz, lw, lx, lr, lb, lu, lpart, lscal;
+  LittleSync sync;
   // counters since the last read: preconditioner applications, little GCR
   // iterations (total and the largest of one solve)
   int64_t applications = 0, little_iters = 0, little_max = 0;
@@ -70,11 +93,14 @@ hipError_t launch_dfl_diag(const Geom &g, const void *basis, size_t vbytes, int 
 hipError_t launch_little_invert(int nb, int ns, const double2 *a, double2 *ainv, int *bad, hipStream_t st);
 // FP32 copies of nmat ns x ns blocks, transposed within each block
 hipError_t launch_little_pack(int64_t nmat, int ns, const double2 *src, float2 *dst, hipStream_t st);
-// for the blocks b of `list`: y_b = (xa ? A[b][0] xa_b : (w ? w_b : 0)) -
+// for the blocks b of `list`: h_b = (xa ? A[b][0] xa_b : (w ? w_b : 0)) -
 // sum_{d >= 1} A[b][d] xh[nbr[b][d]] (the couplings to the blocks across the
-// faces); at: the transposed FP32 copy of A
+// faces), y_b = h_b, or y_b = s ainv[b] h_b if ait is given; at, ait: the
+// transposed FP32 copies of A and of the inverse diagonal blocks.  y must not
+// overlap the entries of xa, w and xh the blocks of `list` read.
 hipError_t launch_lt_hop(const int *list, int nlist, int ns, const float2 *at, const int *nbr, const double2 *xa,
-                         const double2 *w, const double2 *xh, double2 *y, hipStream_t st);
+                         const double2 *w, const double2 *xh, const float2 *ait, double s, double2 *y,
+                         hipStream_t st);
 // for the blocks b of `list`: y_b = s ainv[b] x_b (x and y distinct); ait:
 // the transposed FP32 copy of the inverse diagonal blocks
 hipError_t launch_lt_jacobi(const int *list, int nlist, int ns, const float2 *ait, double s, const double2 *x,
@@ -88,9 +114,10 @@ hipError_t launch_lv_maxpy(double2 *x, const double2 *W, int k, int64_t n, const
 // s[0] = |w|^2, s[1..2] = (w, r)
 hipError_t launch_lv_dot2(const double2 *w, const double2 *r, int64_t n, double *partial, double *s,
                           hipStream_t st);
-// alpha = (s[1] + i s[2]) / s[0]: x += alpha z, r -= alpha w; out[0] = |r|^2
+// alpha = (s[1] + i s[2]) / s[0]: x += alpha z, r -= alpha w; *wn = s[0];
+// out[0] = |r|^2
 hipError_t launch_lv_update(double2 *x, const double2 *z, double2 *r, const double2 *w, int64_t n,
-                            const double *s, double *partial, double *out, hipStream_t st);
+                            const double *s, double *wn, double *partial, double *out, hipStream_t st);
 // partial-sum scratch of the little reductions (doubles)
 size_t lv_partial_doubles();
 

@@ -347,81 +347,136 @@ __global__ void __launch_bounds__(DT) little_pack_kernel(int64_t nmat, int ns, c
   dst[m * ns * ns + (int64_t)l * ns + k] = make_float2((float)v.x, (float)v.y);
 }
 
-// y_b = (xa ? A[b][0] xa_b : (w ? w_b : 0)) - sum_{d >= 1} A[b][d] xh[nbr[b][d]]
-// for the blocks b of `list` (one thread per (block, row)); at: the
-// transposed FP32 copy of A
-__global__ void __launch_bounds__(DT) lt_hop_kernel(const int *list, int nlist, int ns, const float2 *at,
-                                                    const int *nbr, const double2 *xa, const double2 *w,
-                                                    const double2 *xh, double2 *y) {
-  const int64_t t = (int64_t)blockIdx.x * DT + threadIdx.x;
-  if (t >= (int64_t)nlist * ns) return;
-  const int li = (int)(t / ns), k = (int)(t - (int64_t)li * ns);
-  const int blk = list[li];
+// Little products in column-streaming form: one work-group per block b of
+// `list`, made of G = blockDim.x / ns groups of ns threads.  The block's
+// transposed matrices are columns of ns FP32 complex numbers, column c of
+// slot d at c = d * ns + l holding A[b][d][k][l] for k = 0 .. ns-1; thread
+// (g, k) takes the columns c = g, g + G, ... for its row k, so that the
+// work-group reads the block's matrices front to back, and the G partial
+// sums of a row are added in the order g = 0 .. G-1.  The vector entries
+// the columns multiply are staged in LDS first.
+
+// h_b = (xa ? A[b][0] xa_b : (w ? w_b : 0)) - sum_{d >= 1} A[b][d] xh[nbr[b][d]];
+// y_b = h_b, or with INV y_b = s ainv[b] h_b (ait: the transposed FP32 copy
+// of the inverse diagonal blocks)
+template <bool DIAG, bool INV>
+__global__ void __launch_bounds__(DT) lt_hop_kernel(const int *list, int ns, const float2 *at, const int *nbr,
+                                                    const double2 *xa, const double2 *w, const double2 *xh,
+                                                    const float2 *ait, double s, double2 *y) {
+  __shared__ double2 xs[DFL_SLOTS * DFL_NSMAX];
+  __shared__ double2 red[DT];
+  const int blk = list[blockIdx.x];
+  const int G = blockDim.x / ns, g = threadIdx.x / ns, k = threadIdx.x - g * ns;
+  // column c multiplies xs[c]: xa_b for the diagonal slot, -xh at the block
+  // across face d for the others
+  for (int i = threadIdx.x; i < DFL_SLOTS * ns; i += blockDim.x) {
+    const int d = i / ns, l = i - d * ns;
+    double2 v = make_double2(0.0, 0.0);
+    if (d == 0) {
+      if (DIAG) v = xa[(int64_t)blk * ns + l];
+    } else {
+      v = xh[(int64_t)nbr[blk * DFL_SLOTS + d] * ns + l];
+      v.x = -v.x;
+      v.y = -v.y;
+    }
+    xs[i] = v;
+  }
+  __syncthreads();
+  const float2 *m = at + (int64_t)blk * DFL_SLOTS * ns * ns + k;
   double re = 0.0, im = 0.0;
-  if (xa) {
-    const float2 *col = at + ((int64_t)blk * DFL_SLOTS) * ns * ns + k;
-    const double2 *xv = xa + (int64_t)blk * ns;
-    for (int l = 0; l < ns; l++) {
-      const float2 m = col[(int64_t)l * ns];
-      const double2 v = xv[l];
-      re += (double)m.x * v.x - (double)m.y * v.y;
-      im += (double)m.x * v.y + (double)m.y * v.x;
-    }
-  } else if (w) {
-    re = w[(int64_t)blk * ns + k].x;
-    im = w[(int64_t)blk * ns + k].y;
+#pragma unroll 8
+  for (int c = (DIAG ? 0 : ns) + g; c < DFL_SLOTS * ns; c += G) {
+    const float2 a = m[(int64_t)c * ns];
+    const double2 v = xs[c];
+    re += (double)a.x * v.x - (double)a.y * v.y;
+    im += (double)a.x * v.y + (double)a.y * v.x;
   }
-  for (int d = 1; d < DFL_SLOTS; d++) {
-    const float2 *col = at + ((int64_t)blk * DFL_SLOTS + d) * ns * ns + k;
-    const double2 *xv = xh + (int64_t)nbr[blk * DFL_SLOTS + d] * ns;
-    for (int l = 0; l < ns; l++) {
-      const float2 m = col[(int64_t)l * ns];
-      const double2 v = xv[l];
-      re -= (double)m.x * v.x - (double)m.y * v.y;
-      im -= (double)m.x * v.y + (double)m.y * v.x;
+  red[threadIdx.x] = make_double2(re, im);
+  __syncthreads();
+  if (g == 0) {
+    double2 h = make_double2(0.0, 0.0);
+    if (!DIAG && w) h = w[(int64_t)blk * ns + k];
+    for (int q = 0; q < G; q++) {
+      h.x += red[q * ns + k].x;
+      h.y += red[q * ns + k].y;
+    }
+    if (INV)
+      xs[k] = h;  // every read of xs and red is done (the barrier above)
+    else
+      y[(int64_t)blk * ns + k] = h;
+  }
+  if (INV) {
+    __syncthreads();
+    const float2 *mi = ait + (int64_t)blk * ns * ns + k;
+    re = 0.0;
+    im = 0.0;
+    for (int c = g; c < ns; c += G) {
+      const float2 a = mi[(int64_t)c * ns];
+      const double2 v = xs[c];
+      re += (double)a.x * v.x - (double)a.y * v.y;
+      im += (double)a.x * v.y + (double)a.y * v.x;
+    }
+    red[threadIdx.x] = make_double2(re, im);
+    __syncthreads();
+    if (g == 0) {
+      double2 t = make_double2(0.0, 0.0);
+      for (int q = 0; q < G; q++) {
+        t.x += red[q * ns + k].x;
+        t.y += red[q * ns + k].y;
+      }
+      y[(int64_t)blk * ns + k] = make_double2(s * t.x, s * t.y);
     }
   }
-  y[(int64_t)blk * ns + k] = make_double2(re, im);
 }
 
 // y_b = s ainv[b] x_b for the blocks b of `list` (x and y distinct); ait:
 // the transposed FP32 copy of the inverse diagonal blocks
-__global__ void __launch_bounds__(DT) lt_jacobi_kernel(const int *list, int nlist, int ns, const float2 *ait,
-                                                       double s, const double2 *x, double2 *y) {
-  const int64_t t = (int64_t)blockIdx.x * DT + threadIdx.x;
-  if (t >= (int64_t)nlist * ns) return;
-  const int li = (int)(t / ns), k = (int)(t - (int64_t)li * ns);
-  const int blk = list[li];
-  const float2 *col = ait + (int64_t)blk * ns * ns + k;
-  const double2 *xv = x + (int64_t)blk * ns;
+__global__ void __launch_bounds__(DT) lt_jacobi_kernel(const int *list, int ns, const float2 *ait, double s,
+                                                       const double2 *x, double2 *y) {
+  __shared__ double2 xs[DFL_NSMAX];
+  __shared__ double2 red[DT];
+  const int blk = list[blockIdx.x];
+  const int G = blockDim.x / ns, g = threadIdx.x / ns, k = threadIdx.x - g * ns;
+  if (threadIdx.x < ns) xs[threadIdx.x] = x[(int64_t)blk * ns + threadIdx.x];
+  __syncthreads();
+  const float2 *m = ait + (int64_t)blk * ns * ns + k;
   double re = 0.0, im = 0.0;
-  for (int l = 0; l < ns; l++) {
-    const float2 m = col[(int64_t)l * ns];
-    const double2 v = xv[l];
-    re += (double)m.x * v.x - (double)m.y * v.y;
-    im += (double)m.x * v.y + (double)m.y * v.x;
+  for (int c = g; c < ns; c += G) {
+    const float2 a = m[(int64_t)c * ns];
+    const double2 v = xs[c];
+    re += (double)a.x * v.x - (double)a.y * v.y;
+    im += (double)a.x * v.y + (double)a.y * v.x;
   }
-  y[(int64_t)blk * ns + k] = make_double2(s * re, s * im);
+  red[threadIdx.x] = make_double2(re, im);
+  __syncthreads();
+  if (g == 0) {
+    double2 t = make_double2(0.0, 0.0);
+    for (int h = 0; h < G; h++) {
+      t.x += red[h * ns + k].x;
+      t.y += red[h * ns + k].y;
+    }
+    y[(int64_t)blk * ns + k] = make_double2(s * t.x, s * t.y);
+  }
 }
 
 // ---- little-vector reductions: LVG work-groups, partial sums per group ------
-__global__ void __launch_bounds__(DT) lv_dots_kernel(const double2 *W, int k, int64_t n, const double2 *x,
+// work-group (g, j): its share of (W_j, x)
+__global__ void __launch_bounds__(DT) lv_dots_kernel(const double2 *W, int64_t n, const double2 *x,
                                                      double *partial) {
   __shared__ double sh[NW];
-  for (int j = 0; j < k; j++) {
-    const double2 *wj = W + (int64_t)j * n;
-    double re = 0.0, im = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * DT + threadIdx.x; e < n; e += (int64_t)LVG * DT) {
-      const double2 u = wj[e], v = x[e];
-      re += u.x * v.x + u.y * v.y;
-      im += u.x * v.y - u.y * v.x;
-    }
-    re = wg_sum(re, sh);
-    im = wg_sum(im, sh);
-    if (threadIdx.x == 0) {
-      partial[(int64_t)(2 * j) * LVG + blockIdx.x] = re;
-      partial[(int64_t)(2 * j + 1) * LVG + blockIdx.x] = im;
-    }
+  const int j = blockIdx.y;
+  const double2 *wj = W + (int64_t)j * n;
+  double re = 0.0, im = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * DT + threadIdx.x; e < n; e += (int64_t)LVG * DT) {
+    const double2 u = wj[e], v = x[e];
+    re += u.x * v.x + u.y * v.y;
+    im += u.x * v.y - u.y * v.x;
+  }
+  re = wg_sum(re, sh);
+  im = wg_sum(im, sh);
+  if (threadIdx.x == 0) {
+    partial[(int64_t)(2 * j) * LVG + blockIdx.x] = re;
+    partial[(int64_t)(2 * j + 1) * LVG + blockIdx.x] = im;
   }
 }
 
@@ -468,9 +523,10 @@ __global__ void __launch_bounds__(DT) lv_maxpy_kernel(double2 *x, const double2 
 }
 
 __global__ void __launch_bounds__(DT) lv_update_kernel(double2 *x, const double2 *z, double2 *r, const double2 *w,
-                                                       int64_t n, const double *s, double *partial) {
+                                                       int64_t n, const double *s, double *wn, double *partial) {
   __shared__ double sh[NW];
   const double ar = s[1] / s[0], ai = s[2] / s[0];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *wn = s[0];
   double rr = 0.0;
   for (int64_t e = (int64_t)blockIdx.x * DT + threadIdx.x; e < n; e += (int64_t)LVG * DT) {
     const double2 zv = z[e], wv = w[e];
@@ -543,22 +599,40 @@ hipError_t launch_little_pack(int64_t nmat, int ns, const double2 *src, float2 *
   return hipGetLastError();
 }
 
+// work-group size of the column-streaming little products: a whole number
+// of ns-thread groups, at most DT threads
+static int lt_threads(int ns) { return (DT / ns) * ns; }
+
 hipError_t launch_lt_hop(const int *list, int nlist, int ns, const float2 *at, const int *nbr, const double2 *xa,
-                         const double2 *w, const double2 *xh, double2 *y, hipStream_t st) {
-  lt_hop_kernel<<<grid_for((int64_t)nlist * ns, DT), DT, 0, st>>>(list, nlist, ns, at, nbr, xa, w, xh, y);
+                         const double2 *w, const double2 *xh, const float2 *ait, double s, double2 *y,
+                         hipStream_t st) {
+  if (ns < 1 || ns > DFL_NSMAX) return hipErrorInvalidValue;
+  if (nlist < 1) return hipSuccess;
+  const int nt = lt_threads(ns);
+  if (xa && ait)
+    lt_hop_kernel<true, true><<<nlist, nt, 0, st>>>(list, ns, at, nbr, xa, w, xh, ait, s, y);
+  else if (xa)
+    lt_hop_kernel<true, false><<<nlist, nt, 0, st>>>(list, ns, at, nbr, xa, w, xh, ait, s, y);
+  else if (ait)
+    lt_hop_kernel<false, true><<<nlist, nt, 0, st>>>(list, ns, at, nbr, xa, w, xh, ait, s, y);
+  else
+    lt_hop_kernel<false, false><<<nlist, nt, 0, st>>>(list, ns, at, nbr, xa, w, xh, ait, s, y);
   return hipGetLastError();
 }
 
 hipError_t launch_lt_jacobi(const int *list, int nlist, int ns, const float2 *ait, double s, const double2 *x,
                             double2 *y, hipStream_t st) {
-  lt_jacobi_kernel<<<grid_for((int64_t)nlist * ns, DT), DT, 0, st>>>(list, nlist, ns, ait, s, x, y);
+  if (ns < 1 || ns > DFL_NSMAX) return hipErrorInvalidValue;
+  if (nlist < 1) return hipSuccess;
+  // about four columns per thread: a block's inverse is only ns x ns
+  lt_jacobi_kernel<<<nlist, ns * ((ns + 3) / 4), 0, st>>>(list, ns, ait, s, x, y);
   return hipGetLastError();
 }
 
 hipError_t launch_lv_dots(const double2 *W, int k, int64_t n, const double2 *x, double *partial, double *out,
                           hipStream_t st) {
   if (k < 1 || k > LV_MAXK) return hipErrorInvalidValue;
-  lv_dots_kernel<<<LVG, DT, 0, st>>>(W, k, n, x, partial);
+  lv_dots_kernel<<<dim3(LVG, k), DT, 0, st>>>(W, n, x, partial);
   lv_finish_kernel<<<2 * k, 64, 0, st>>>(partial, 2 * k, out);
   return hipGetLastError();
 }
@@ -578,8 +652,8 @@ hipError_t launch_lv_dot2(const double2 *w, const double2 *r, int64_t n, double 
 }
 
 hipError_t launch_lv_update(double2 *x, const double2 *z, double2 *r, const double2 *w, int64_t n, const double *s,
-                            double *partial, double *out, hipStream_t st) {
-  lv_update_kernel<<<LVG, DT, 0, st>>>(x, z, r, w, n, s, partial);
+                            double *wn, double *partial, double *out, hipStream_t st) {
+  lv_update_kernel<<<LVG, DT, 0, st>>>(x, z, r, w, n, s, wn, partial);
   lv_finish_kernel<<<1, 64, 0, st>>>(partial, 1, out);
   return hipGetLastError();
 }

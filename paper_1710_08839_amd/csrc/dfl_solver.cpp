@@ -63,11 +63,14 @@ constexpr int LS_S = 0, LS_RR = 4, LS_DOTS = 8, LS_WN = 8 + 2 * 64, LS_N = LS_WN
 // made orthogonal to the earlier w, x and r updated at every step; stops at
 // |r| <= tol |b_e - A_eo A_oo^-1 b_o| or maxiter iterations.  Vectors are
 // full length (blocks of both colours); the odd entries of r, z, w stay 0.
+// The host reads the residual norm of step j while step j + 1 is already
+// queued, so the device never waits for the host; the step queued past
+// convergence is kept (it only lowers the residual further).
 qxd_status little_solve(Dfl &d, const double2 *b, double2 *x, double tol, int *iters, hipStream_t st) {
   const int64_t n = (int64_t)d.nb * d.ns;
-  const int nkv = d.p.little_nkv, ns = d.ns;
+  const int nkv = d.p.little_nkv, ns = d.ns, maxiter = d.p.little_maxiter;
   double2 *Z = d.lz.as<double2>(), *W = d.lw.as<double2>(), *r = d.lr.as<double2>();
-  double2 *t = d.lt.as<double2>(), *u = d.lu.as<double2>();
+  double2 *u = d.lu.as<double2>();
   double *part = d.lpart.as<double>(), *sc = d.lscal.as<double>();
   const float2 *A = d.at32.as<float2>(), *Ai = d.ait32.as<float2>();
   const int *nbr = d.nbr.as<int>(), *ev = d.even.as<int>(), *od = d.odd.as<int>();
@@ -78,48 +81,53 @@ qxd_status little_solve(Dfl &d, const double2 *b, double2 *x, double tol, int *i
   DCK(hipMemsetAsync(W, 0, vb * nkv, st));
   // r_e = b_e - A_eo A_oo^-1 b_o
   DCK(launch_lt_jacobi(od, d.no, ns, Ai, 1.0, b, u, st));
-  DCK(launch_lt_hop(ev, d.ne, ns, A, nbr, nullptr, b, u, r, st));
+  DCK(launch_lt_hop(ev, d.ne, ns, A, nbr, nullptr, b, u, nullptr, 1.0, r, st));
   DCK(launch_lv_dot2(r, r, n, part, sc + LS_S, st));
   double bn2;
   DCS(fetch(&bn2, sc + LS_S, 1, st));
-  int it = 0;
   if (!isfinite(bn2)) {
     set_error("little system: right-hand side is NaN/Inf");
     return QXD_EFLOAT;
   }
+  // step j: Krylov slot j mod nkv (a restart every nkv steps); its |r|^2 goes
+  // to host slot j mod 2
+  auto step = [&](int j) -> qxd_status {
+    const int k = j % nkv;
+    double2 *zk = Z + (int64_t)k * n, *wk = W + (int64_t)k * n;
+    DCK(launch_lt_jacobi(ev, d.ne, ns, Ai, 1.0, r, zk, st));
+    // w_e = A_ee z - A_eo u_o with u_o = A_oo^-1 A_oe z (-A_oe z is what
+    // the hop makes)
+    DCK(launch_lt_hop(od, d.no, ns, A, nbr, nullptr, nullptr, zk, Ai, -1.0, u, st));
+    DCK(launch_lt_hop(ev, d.ne, ns, A, nbr, zk, nullptr, u, nullptr, 1.0, wk, st));
+    if (k > 0) {
+      DCK(launch_lv_dots(W, k, n, wk, part, sc + LS_DOTS, st));
+      DCK(launch_lv_maxpy(wk, W, k, n, sc + LS_DOTS, sc + LS_WN, st));
+      DCK(launch_lv_maxpy(zk, Z, k, n, sc + LS_DOTS, sc + LS_WN, st));
+    }
+    DCK(launch_lv_dot2(wk, r, n, part, sc + LS_S, st));
+    DCK(launch_lv_update(x, zk, r, wk, n, sc + LS_S, sc + LS_WN + k, part, sc + LS_RR, st));
+    DCK(hipMemcpyAsync(d.sync.host + (j & 1), sc + LS_RR, sizeof(double), hipMemcpyDeviceToHost, st));
+    DCK(hipEventRecord(d.sync.ev[j & 1], st));
+    return QXD_OK;
+  };
+  int launched = 0;
   if (bn2 > 0.0) {
-    bool done = false;
-    while (!done && it < d.p.little_maxiter) {
-      for (int k = 0; k < nkv && !done; k++) {
-        double2 *zk = Z + (int64_t)k * n, *wk = W + (int64_t)k * n;
-        DCK(launch_lt_jacobi(ev, d.ne, ns, Ai, 1.0, r, zk, st));
-        // w_e = A_ee z - A_eo u_o with u_o = A_oo^-1 A_oe z
-        DCK(launch_lt_hop(od, d.no, ns, A, nbr, nullptr, nullptr, zk, t, st));
-        DCK(launch_lt_jacobi(od, d.no, ns, Ai, -1.0, t, u, st));
-        DCK(launch_lt_hop(ev, d.ne, ns, A, nbr, zk, nullptr, u, wk, st));
-        if (k > 0) {
-          DCK(launch_lv_dots(W, k, n, wk, part, sc + LS_DOTS, st));
-          DCK(launch_lv_maxpy(wk, W, k, n, sc + LS_DOTS, sc + LS_WN, st));
-          DCK(launch_lv_maxpy(zk, Z, k, n, sc + LS_DOTS, sc + LS_WN, st));
-        }
-        DCK(launch_lv_dot2(wk, r, n, part, sc + LS_S, st));
-        DCK(hipMemcpyAsync(sc + LS_WN + k, sc + LS_S, sizeof(double), hipMemcpyDeviceToDevice, st));
-        DCK(launch_lv_update(x, zk, r, wk, n, sc + LS_S, part, sc + LS_RR, st));
-        double rr;
-        DCS(fetch(&rr, sc + LS_RR, 1, st));
-        it++;
-        if (!isfinite(rr)) {
-          set_error("little system: residual is NaN/Inf");
-          return QXD_EFLOAT;
-        }
-        if (rr <= tol * tol * bn2 || it >= d.p.little_maxiter) done = true;
+    DCS(step(launched++));
+    for (int j = 0;; j++) {
+      if (launched < maxiter) DCS(step(launched++));
+      DCK(hipEventSynchronize(d.sync.ev[j & 1]));
+      const double rr = d.sync.host[j & 1];
+      if (!isfinite(rr)) {
+        DCK(hipStreamSynchronize(st));
+        set_error("little system: residual is NaN/Inf");
+        return QXD_EFLOAT;
       }
+      if (rr <= tol * tol * bn2 || j + 1 >= launched) break;
     }
   }
   // x_o = A_oo^-1 (b_o - A_oe x_e)
-  DCK(launch_lt_hop(od, d.no, ns, A, nbr, nullptr, b, x, t, st));
-  DCK(launch_lt_jacobi(od, d.no, ns, Ai, 1.0, t, x, st));
-  if (iters) *iters = it;
+  DCK(launch_lt_hop(od, d.no, ns, A, nbr, nullptr, b, x, Ai, 1.0, x, st));
+  if (iters) *iters = launched;
   return QXD_OK;
 }
 
@@ -128,7 +136,7 @@ qxd_status fill_params(qxd_dfl_params *p) {
   if (p->ninv == 0) p->ninv = 20;
   if (p->ncy == 0) p->ncy = 4;
   if (p->nmr == 0) p->nmr = 4;
-  if (p->little_tol == 0.0) p->little_tol = 1e-1;
+  if (p->little_tol == 0.0) p->little_tol = 0.2;
   if (p->little_nkv == 0) p->little_nkv = 32;
   if (p->little_maxiter == 0) p->little_maxiter = 256;
   if (p->ns < 1 || p->ns > DFL_NSMAX || p->ninv < 0 || p->ncy < 1 || p->nmr < 0 || !(p->little_tol > 0.0) ||
@@ -154,7 +162,7 @@ qxd_status op_with_dfl(Field *f, const qxd_quark &q, Operator **op, hipStream_t 
 }  // namespace
 
 size_t Dfl::bytes() const {
-  return basis.n + a.n + ainv.n + at32.n + ait32.n + nbr.n + even.n + odd.n + lz.n + lw.n + lx.n + lr.n + lb.n + lt.n + lu.n +
+  return basis.n + a.n + ainv.n + at32.n + ait32.n + nbr.n + even.n + odd.n + lz.n + lw.n + lx.n + lr.n + lb.n + lu.n +
          lpart.n + lscal.n;
 }
 
@@ -275,7 +283,6 @@ qxd_status dfl_setup(Field *f, const qxd_quark &q, const qxd_dfl_params *pin, co
   }
   // little GCR workspace
   const size_t n = (size_t)d->nb * ns;
-  DCK(d->lt.ensure(n * sizeof(double2)));
   DCK(d->lu.ensure(n * sizeof(double2)));
   DCK(d->lz.ensure((size_t)p.little_nkv * n * sizeof(double2)));
   DCK(d->lw.ensure((size_t)p.little_nkv * n * sizeof(double2)));
@@ -284,6 +291,7 @@ qxd_status dfl_setup(Field *f, const qxd_quark &q, const qxd_dfl_params *pin, co
   DCK(d->lb.ensure(n * sizeof(double2)));
   DCK(d->lpart.ensure(lv_partial_doubles() * sizeof(double)));
   DCK(d->lscal.ensure(LS_N * sizeof(double)));
+  DCK(d->sync.init());
   op->dfl = d;
   return QXD_OK;
 }
