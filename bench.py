@@ -481,7 +481,7 @@ def single_rhs_64x32(f):
     return out
 
 
-def dfl_leg(f, ns=20, ninv=20, nkv=32):
+def dfl_leg(f, ns=16, ninv=30, nkv=32):
     """Locally deflated SAP-GCR on the 64 x 32^3 field of the D leg (q = -1/3,
     kappa 0.1365, csw 1.9), one Gaussian source: the deflation subspace's
     setup time, then the deflated solve and the plain SAP-GCR on the same

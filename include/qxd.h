@@ -265,9 +265,9 @@ qxd_status qxd_solve(qxd_field *field, const qxd_quark *quarks, int nquark,
  * Zero means the default given in brackets. */
 typedef struct {
   int ns;             /* deflation fields, i.e. basis vectors per SAP block
-                         (1..32) [20]                                          */
+                         (1..32) [16]                                          */
   int ninv;           /* SAP-smoothed inverse-iteration steps that refine the
-                         random start fields [20]                              */
+                         random start fields [30]                              */
   int ncy, nmr;       /* SAP cycles and MR steps of each such step [4, 4]      */
   double little_tol;  /* relative residual of each little-system solve [0.2]  */
   int little_nkv;     /* Krylov vectors of the little GCR (<= 64) [32]         */

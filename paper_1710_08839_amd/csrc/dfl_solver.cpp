@@ -132,8 +132,8 @@ qxd_status little_solve(Dfl &d, const double2 *b, double2 *x, double tol, int *i
 }
 
 qxd_status fill_params(qxd_dfl_params *p) {
-  if (p->ns == 0) p->ns = 20;
-  if (p->ninv == 0) p->ninv = 20;
+  if (p->ns == 0) p->ns = 16;
+  if (p->ninv == 0) p->ninv = 30;
   if (p->ncy == 0) p->ncy = 4;
   if (p->nmr == 0) p->nmr = 4;
   if (p->little_tol == 0.0) p->little_tol = 0.2;
