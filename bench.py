@@ -52,7 +52,8 @@ def site_bytes(prec, choice):
 # sources they were taken on (hash of the files below) and for the variant
 # the autotuner picked there (hop group + 16 LDS + 32 non-temporal + 64 mirror).
 KERNEL_FILES = ["dirac.hip", "dirac_site.h", "qxd_impl.h"]
-TRAFFIC = {("34a0479e4cb9cdce", 113): 8.126e9}
+TRAFFIC = {("34a0479e4cb9cdce", 113): 8.126e9, ("34a0479e4cb9cdce", 114): 8.125e9,
+           ("34a0479e4cb9cdce", 241): 8.128e9, ("34a0479e4cb9cdce", 242): 8.119e9}
 
 
 def kernel_hash():
