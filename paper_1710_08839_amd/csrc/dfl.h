@@ -32,6 +32,10 @@ struct LittleSync {
   LittleSync(const LittleSync &) = delete;
   LittleSync &operator=(const LittleSync &) = delete;
   ~LittleSync() {
+    // a copy into the slots may still be queued (a solve that stopped on an
+    // error): wait for the events recorded after the copies before freeing
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventSynchronize(e);
     if (host) (void)hipHostFree(host);
     for (hipEvent_t e : ev)
       if (e) (void)hipEventDestroy(e);
