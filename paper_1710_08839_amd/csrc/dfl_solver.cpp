@@ -205,19 +205,22 @@ qxd_status dfl_setup(Field *f, const qxd_quark &q, const qxd_dfl_params *pin, co
   for (int k = 0; k < ns; k++) {
     void *v = basis + (size_t)k * d->vbytes;
     for (int it = 0; it <= p.ninv; it++) {
+      void *src = v;  // the field to normalise into v: v itself, then M_sap v
       if (it > 0) {
         DCS(sap_apply(f, *op, QXD_F32, p.ncy, p.nmr, v, t32, st));
-        DCK(hipMemcpyAsync(v, t32, spinor_bytes(QXD_F32, g.V), hipMemcpyDeviceToDevice, st));
+        src = t32;
       }
-      DCK(blas_norm2<QXD_F32>(full(g, v), 0, g.V, (double *)partial, misc, st));
+      DCK(blas_norm2<QXD_F32>(full(g, src), 0, g.V, (double *)partial, misc, st));
       double n2;
       DCS(fetch(&n2, misc, 1, st));
       if (!(n2 > 0.0) || !isfinite(n2)) {
         set_error("deflation field %d vanished or is not finite in inverse iteration", k);
         return QXD_EFLOAT;
       }
-      DCK(blas_axpby<QXD_F32, QXD_F32>(full(g, v), 1.0 / sqrt(n2), full(g, v), 0.0, 0, g.V, (double *)partial,
-                                       nullptr, st));
+      // v = src / |src| (with a zero coefficient the old v is not read)
+      const double sc = 1.0 / sqrt(n2);
+      DCK(blas_axpby<QXD_F32, QXD_F32>(full(g, v), src == v ? sc : 0.0, full(g, src), src == v ? 0.0 : sc, 0,
+                                       g.V, (double *)partial, nullptr, st));
     }
   }
   // block orthonormalisation
