@@ -293,7 +293,9 @@ typedef struct {
  * preconditioner M_dfl r = V A^-1 V^dag r + M_sap (r - D V A^-1 V^dag r),
  * with A^-1 applied by GCR on the even-block Schur complement of A (blocks
  * coloured as for SAP), right-preconditioned by the inverse diagonal blocks,
- * to little_tol, with FP32 copies of the little matrices.
+ * to little_tol, with FP16 copies of the little matrices when little_tol is
+ * 1e-2 or more (the default) and FP32 copies otherwise (the inverse diagonal
+ * blocks in FP32 either way).
  * A new call for the same quark replaces the subspace.  The subspace lives
  * with the quark's operator in the field's operator cache (freed with it).
  * Needs SAP blocks of at most 256 sites that admit the two-colour

@@ -58,6 +58,7 @@ struct Dfl {
   DevBuf a;                // little operator [nb][9][ns][ns] double2
   DevBuf ainv;             // inverses of the diagonal blocks A[b][0] [nb][ns][ns] double2
   DevBuf at32, ait32;      // FP32 copies of a and ainv for the little solve, transposed per block
+  DevBuf at16;             // FP16 copy of a, transposed per block (little solves to a loose tolerance)
   DevBuf nbr;              // [nb][9] int: the block each slot couples to
   DevBuf even, odd;        // the blocks of each SAP colour (neighbours have opposite colours)
   int ne = 0, no = 0;
@@ -95,14 +96,18 @@ hipError_t launch_dfl_diag(const Geom &g, const void *basis, size_t vbytes, int 
                            double2 *a, int *nbr, hipStream_t st);
 // ainv[b] = a[b][0]^-1 (Gauss-Jordan with partial pivoting); *bad counts singular blocks
 hipError_t launch_little_invert(int nb, int ns, const double2 *a, double2 *ainv, int *bad, hipStream_t st);
-// FP32 copies of nmat ns x ns blocks, transposed within each block
-hipError_t launch_little_pack(int64_t nmat, int ns, const double2 *src, float2 *dst, hipStream_t st);
+// FP32 (MT = float2) or FP16 (MT = h2_t) copies of nmat ns x ns blocks,
+// transposed within each block
+template <class MT>
+hipError_t launch_little_pack(int64_t nmat, int ns, const double2 *src, MT *dst, hipStream_t st);
 // for the blocks b of `list`: h_b = (xa ? A[b][0] xa_b : (w ? w_b : 0)) -
 // sum_{d >= 1} A[b][d] xh[nbr[b][d]] (the couplings to the blocks across the
-// faces), y_b = h_b, or y_b = s ainv[b] h_b if ait is given; at, ait: the
-// transposed FP32 copies of A and of the inverse diagonal blocks.  y must not
-// overlap the entries of xa, w and xh the blocks of `list` read.
-hipError_t launch_lt_hop(const int *list, int nlist, int ns, const float2 *at, const int *nbr, const double2 *xa,
+// faces), y_b = h_b, or y_b = s ainv[b] h_b if ait is given; at: the
+// transposed FP32 (MT = float2) or FP16 (MT = h2_t) copy of A, ait: the
+// transposed FP32 copy of the inverse diagonal blocks.  y must not overlap
+// the entries of xa, w and xh the blocks of `list` read.
+template <class MT>
+hipError_t launch_lt_hop(const int *list, int nlist, int ns, const MT *at, const int *nbr, const double2 *xa,
                          const double2 *w, const double2 *xh, const float2 *ait, double s, double2 *y,
                          hipStream_t st);
 // for the blocks b of `list`: y_b = s ainv[b] x_b (x and y distinct); ait:

@@ -335,16 +335,24 @@ __global__ void __launch_bounds__(DT) little_invert_kernel(int ns, const double2
   if (singular && threadIdx.x == 0) atomicAdd(bad, 1);
 }
 
-// The little solve reads FP32 copies of A and of the inverse diagonal blocks,
-// transposed within each ns x ns block (element (k, l) at l * ns + k), so
-// that the threads of consecutive rows k read consecutive words.
-__global__ void __launch_bounds__(DT) little_pack_kernel(int64_t nmat, int ns, const double2 *src, float2 *dst) {
+// The little solve reads FP32 (or FP16) copies of A and FP32 copies of the
+// inverse diagonal blocks, transposed within each ns x ns block (element
+// (k, l) at l * ns + k), so that the threads of consecutive rows k read
+// consecutive words.
+__device__ __forceinline__ void to_mt(double2 v, float2 *d) { *d = make_float2((float)v.x, (float)v.y); }
+__device__ __forceinline__ void to_mt(double2 v, h2_t *d) {
+  h2_t h;
+  h.x = (_Float16)v.x;
+  h.y = (_Float16)v.y;
+  *d = h;
+}
+template <class MT>
+__global__ void __launch_bounds__(DT) little_pack_kernel(int64_t nmat, int ns, const double2 *src, MT *dst) {
   const int64_t t = (int64_t)blockIdx.x * DT + threadIdx.x;
   if (t >= nmat * ns * ns) return;
   const int64_t m = t / (ns * ns);
   const int e = (int)(t - m * ns * ns), k = e / ns, l = e - k * ns;
-  const double2 v = src[t];
-  dst[m * ns * ns + (int64_t)l * ns + k] = make_float2((float)v.x, (float)v.y);
+  to_mt(src[t], dst + m * ns * ns + (int64_t)l * ns + k);
 }
 
 // Little products in column-streaming form: one work-group per block b of
@@ -357,10 +365,11 @@ __global__ void __launch_bounds__(DT) little_pack_kernel(int64_t nmat, int ns, c
 // the columns multiply are staged in LDS first.
 
 // h_b = (xa ? A[b][0] xa_b : (w ? w_b : 0)) - sum_{d >= 1} A[b][d] xh[nbr[b][d]];
-// y_b = h_b, or with INV y_b = s ainv[b] h_b (ait: the transposed FP32 copy
-// of the inverse diagonal blocks)
-template <bool DIAG, bool INV>
-__global__ void __launch_bounds__(DT) lt_hop_kernel(const int *list, int ns, const float2 *at, const int *nbr,
+// y_b = h_b, or with INV y_b = s ainv[b] h_b (at: the transposed FP32 or
+// FP16 copy of A; ait: the transposed FP32 copy of the inverse diagonal
+// blocks)
+template <bool DIAG, bool INV, class MT>
+__global__ void __launch_bounds__(DT) lt_hop_kernel(const int *list, int ns, const MT *at, const int *nbr,
                                                     const double2 *xa, const double2 *w, const double2 *xh,
                                                     const float2 *ait, double s, double2 *y) {
   __shared__ double2 xs[DFL_SLOTS * DFL_NSMAX];
@@ -382,11 +391,11 @@ __global__ void __launch_bounds__(DT) lt_hop_kernel(const int *list, int ns, con
     xs[i] = v;
   }
   __syncthreads();
-  const float2 *m = at + (int64_t)blk * DFL_SLOTS * ns * ns + k;
+  const MT *m = at + (int64_t)blk * DFL_SLOTS * ns * ns + k;
   double re = 0.0, im = 0.0;
 #pragma unroll 8
   for (int c = (DIAG ? 0 : ns) + g; c < DFL_SLOTS * ns; c += G) {
-    const float2 a = m[(int64_t)c * ns];
+    const MT a = m[(int64_t)c * ns];
     const double2 v = xs[c];
     re += (double)a.x * v.x - (double)a.y * v.y;
     im += (double)a.x * v.y + (double)a.y * v.x;
@@ -594,31 +603,41 @@ hipError_t launch_little_invert(int nb, int ns, const double2 *a, double2 *ainv,
   return hipGetLastError();
 }
 
-hipError_t launch_little_pack(int64_t nmat, int ns, const double2 *src, float2 *dst, hipStream_t st) {
-  little_pack_kernel<<<grid_for(nmat * ns * ns, DT), DT, 0, st>>>(nmat, ns, src, dst);
+template <class MT>
+hipError_t launch_little_pack(int64_t nmat, int ns, const double2 *src, MT *dst, hipStream_t st) {
+  little_pack_kernel<MT><<<grid_for(nmat * ns * ns, DT), DT, 0, st>>>(nmat, ns, src, dst);
   return hipGetLastError();
 }
+template hipError_t launch_little_pack<float2>(int64_t, int, const double2 *, float2 *, hipStream_t);
+template hipError_t launch_little_pack<h2_t>(int64_t, int, const double2 *, h2_t *, hipStream_t);
 
 // work-group size of the column-streaming little products: a whole number
 // of ns-thread groups, at most DT threads
 static int lt_threads(int ns) { return (DT / ns) * ns; }
 
-hipError_t launch_lt_hop(const int *list, int nlist, int ns, const float2 *at, const int *nbr, const double2 *xa,
+template <class MT>
+hipError_t launch_lt_hop(const int *list, int nlist, int ns, const MT *at, const int *nbr, const double2 *xa,
                          const double2 *w, const double2 *xh, const float2 *ait, double s, double2 *y,
                          hipStream_t st) {
   if (ns < 1 || ns > DFL_NSMAX) return hipErrorInvalidValue;
   if (nlist < 1) return hipSuccess;
   const int nt = lt_threads(ns);
   if (xa && ait)
-    lt_hop_kernel<true, true><<<nlist, nt, 0, st>>>(list, ns, at, nbr, xa, w, xh, ait, s, y);
+    lt_hop_kernel<true, true, MT><<<nlist, nt, 0, st>>>(list, ns, at, nbr, xa, w, xh, ait, s, y);
   else if (xa)
-    lt_hop_kernel<true, false><<<nlist, nt, 0, st>>>(list, ns, at, nbr, xa, w, xh, ait, s, y);
+    lt_hop_kernel<true, false, MT><<<nlist, nt, 0, st>>>(list, ns, at, nbr, xa, w, xh, ait, s, y);
   else if (ait)
-    lt_hop_kernel<false, true><<<nlist, nt, 0, st>>>(list, ns, at, nbr, xa, w, xh, ait, s, y);
+    lt_hop_kernel<false, true, MT><<<nlist, nt, 0, st>>>(list, ns, at, nbr, xa, w, xh, ait, s, y);
   else
-    lt_hop_kernel<false, false><<<nlist, nt, 0, st>>>(list, ns, at, nbr, xa, w, xh, ait, s, y);
+    lt_hop_kernel<false, false, MT><<<nlist, nt, 0, st>>>(list, ns, at, nbr, xa, w, xh, ait, s, y);
   return hipGetLastError();
 }
+template hipError_t launch_lt_hop<float2>(const int *, int, int, const float2 *, const int *, const double2 *,
+                                          const double2 *, const double2 *, const float2 *, double, double2 *,
+                                          hipStream_t);
+template hipError_t launch_lt_hop<h2_t>(const int *, int, int, const h2_t *, const int *, const double2 *,
+                                        const double2 *, const double2 *, const float2 *, double, double2 *,
+                                        hipStream_t);
 
 hipError_t launch_lt_jacobi(const int *list, int nlist, int ns, const float2 *ait, double s, const double2 *x,
                             double2 *y, hipStream_t st) {

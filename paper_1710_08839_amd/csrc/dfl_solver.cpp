@@ -66,13 +66,15 @@ constexpr int LS_S = 0, LS_RR = 4, LS_DOTS = 8, LS_WN = 8 + 2 * 64, LS_N = LS_WN
 // The host reads the residual norm of step j while step j + 1 is already
 // queued, so the device never waits for the host; the step queued past
 // convergence is kept (it only lowers the residual further).
-qxd_status little_solve(Dfl &d, const double2 *b, double2 *x, double tol, int *iters, hipStream_t st) {
+template <class MT>
+qxd_status little_solve_t(Dfl &d, const MT *A, const double2 *b, double2 *x, double tol, int *iters,
+                          hipStream_t st) {
   const int64_t n = (int64_t)d.nb * d.ns;
   const int nkv = d.p.little_nkv, ns = d.ns, maxiter = d.p.little_maxiter;
   double2 *Z = d.lz.as<double2>(), *W = d.lw.as<double2>(), *r = d.lr.as<double2>();
   double2 *u = d.lu.as<double2>();
   double *part = d.lpart.as<double>(), *sc = d.lscal.as<double>();
-  const float2 *A = d.at32.as<float2>(), *Ai = d.ait32.as<float2>();
+  const float2 *Ai = d.ait32.as<float2>();
   const int *nbr = d.nbr.as<int>(), *ev = d.even.as<int>(), *od = d.odd.as<int>();
   const size_t vb = n * sizeof(double2);
   DCK(hipMemsetAsync(x, 0, vb, st));
@@ -131,6 +133,17 @@ qxd_status little_solve(Dfl &d, const double2 *b, double2 *x, double tol, int *i
   return QXD_OK;
 }
 
+// Little solves to a relative residual of at least HALF_LITTLE_TOL read the
+// FP16 copy of A (half the bytes of the two hops that dominate a step; its
+// 11-bit mantissa perturbs the little operator far below such a tolerance),
+// tighter ones the FP32 copy.
+constexpr double HALF_LITTLE_TOL = 1e-2;
+
+qxd_status little_solve(Dfl &d, const double2 *b, double2 *x, double tol, int *iters, hipStream_t st) {
+  if (tol >= HALF_LITTLE_TOL) return little_solve_t(d, d.at16.as<h2_t>(), b, x, tol, iters, st);
+  return little_solve_t(d, d.at32.as<float2>(), b, x, tol, iters, st);
+}
+
 qxd_status fill_params(qxd_dfl_params *p) {
   if (p->ns == 0) p->ns = 16;
   if (p->ninv == 0) p->ninv = 30;
@@ -162,8 +175,8 @@ qxd_status op_with_dfl(Field *f, const qxd_quark &q, Operator **op, hipStream_t 
 }  // namespace
 
 size_t Dfl::bytes() const {
-  return basis.n + a.n + ainv.n + at32.n + ait32.n + nbr.n + even.n + odd.n + lz.n + lw.n + lx.n + lr.n + lb.n + lu.n +
-         lpart.n + lscal.n;
+  return basis.n + a.n + ainv.n + at32.n + ait32.n + at16.n + nbr.n + even.n + odd.n + lz.n + lw.n + lx.n + lr.n +
+         lb.n + lu.n + lpart.n + lscal.n;
 }
 
 qxd_status dfl_setup(Field *f, const qxd_quark &q, const qxd_dfl_params *pin, const double *init_api,
@@ -262,7 +275,9 @@ qxd_status dfl_setup(Field *f, const qxd_quark &q, const qxd_dfl_params *pin, co
   }
   DCK(d->at32.ensure((size_t)d->nb * DFL_SLOTS * nn * sizeof(float2)));
   DCK(d->ait32.ensure((size_t)d->nb * nn * sizeof(float2)));
+  DCK(d->at16.ensure((size_t)d->nb * DFL_SLOTS * nn * sizeof(h2_t)));
   DCK(launch_little_pack((int64_t)d->nb * DFL_SLOTS, ns, d->a.as<double2>(), d->at32.as<float2>(), st));
+  DCK(launch_little_pack((int64_t)d->nb * DFL_SLOTS, ns, d->a.as<double2>(), d->at16.as<h2_t>(), st));
   DCK(launch_little_pack((int64_t)d->nb, ns, d->ainv.as<double2>(), d->ait32.as<float2>(), st));
   // the blocks of each colour: the parity of the block coordinates, as for
   // SAP (the two-colour check guarantees that neighbours differ)

@@ -110,6 +110,27 @@ def test_precond_matches_oracle(case, setup):
     assert rel(to_host(y), vc) < 5e-5
 
 
+@pytest.mark.parametrize("little_tol", [0.2, 1e-12], ids=["fp16-matrices", "fp32-matrices"])
+def test_precond_repeatable(case, setup, little_tol):
+    """Repeated applications of the deflated preconditioner to one vector
+    agree bit for bit (fixed-order reductions; the little GCR's stopping
+    step is decided on the same residual norms); with the default loose
+    little tolerance the little solve reads the FP16 copies of the little
+    matrices, with a tight one the FP32 copies."""
+    import torch
+    c = case
+    r = to_dev(c.source(903))
+    outs = []
+    for _ in range(3):
+        y = torch.empty_like(r)
+        c.field.dfl_precond(c.quark, r, y, little_tol=little_tol, ncy=NCY, nmr=NMR)
+        torch.cuda.synchronize()
+        outs.append(to_host(y))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    assert np.all(np.isfinite(outs[0]))
+
+
 @pytest.mark.parametrize("nkv", [8, 32])
 def test_deflated_solve(case, setup, nkv):
     import torch
