@@ -210,6 +210,43 @@ def test_time_boundaries(ctx, tbc, cf, cfp):
     assert od.norm(eta - c.op.apply(to_host(psi))) / od.norm(eta) <= 1.05e-10
 
 
+@pytest.mark.parametrize("ns", [1, 32], ids=["ns1", "ns32"])
+def test_smallest_and_largest_subspace(ctx, ns):
+    """The extreme subspace sizes (1 and the maximum 32 vectors per block) on
+    a 4^4 C* lattice with 2^4 blocks (192 components per block): the basis is
+    block-orthonormal, the little operator equals the oracle's V^dag D V on
+    the library's basis, and the deflated solve reaches the tolerance."""
+    import torch
+    from paper_1710_08839_amd import qxd
+    c = Case(ctx, (4, 4, 4, 4), cstar=1, q=-1 / 3, kappa=0.126, csw=1.3, seed=90 + ns, block=(2, 2, 2, 2))
+    c.field.dfl_setup(c.quark, ns=ns, ninv=2, ncy=2, nmr=3, seed=7)
+    out = torch.empty((1, c.V, 4, 3), dtype=torch.complex128, device="cuda")
+    basis = []
+    for k in range(ns):
+        c.field.dfl_basis(c.quark, k, out)
+        torch.cuda.synchronize()
+        basis.append(to_host(out)[0])
+    basis = np.array(basis)
+    blocks = osv.Blocks(c.lat, (2, 2, 2, 2))
+    for b in range(blocks.n_blocks):
+        v = basis[:, blocks.block_id == b].reshape(ns, -1)
+        assert np.max(np.abs(v.conj() @ v.T - np.eye(ns))) < 1e-5
+    a, nbr = c.field.dfl_little(c.quark)
+    nb = blocks.n_blocks
+    dense = np.zeros((nb * ns, nb * ns), dtype=complex)
+    for b in range(nb):
+        for d in range(9):
+            dense[b * ns:(b + 1) * ns, nbr[b, d] * ns:(nbr[b, d] + 1) * ns] += a[b, d]
+    ref = odf.little_operator(c.op, blocks, basis)
+    assert np.max(np.abs(dense - ref)) < 1e-12 * np.max(np.abs(ref))
+    eta = c.source(91)
+    psi = torch.empty_like(to_dev(eta))
+    st, info = c.field.solve(c.quark, qxd.solver(kind=qxd.DFL_SAP_GCR, tol=1e-10, nkv=8, ncy=2, nmr=3),
+                             to_dev(eta), psi)
+    assert st == 0
+    assert od.norm(eta - c.op.apply(to_host(psi))) / od.norm(eta) <= 1.05e-10
+
+
 def test_dfl_errors(case):
     import torch
     from paper_1710_08839_amd import qxd
