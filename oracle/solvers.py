@@ -226,6 +226,85 @@ def sap(op, blocks, rho, ncy, nmr, bops=None):
 
 
 # --------------------------------------------------------------------------
+# single blocks of lattices too large to build the whole operator
+# --------------------------------------------------------------------------
+def block_solve_at(lat, u_ext, a_ext, sites, r, nmr, kappa, q=0.0, csw=0.0, csw_u1=1.0, q_el=1.0 / 6.0):
+    """BlockOperator.solve for one block from the site formula: D_Lambda (D
+    on the block's sites with every hop that leaves the block dropped) as a
+    dense matrix over the block, built from the Pauli term at those sites and
+    the links between them, then the same even-odd MR steps.  sites: the
+    block's sites, r: the residual on them [n, 4, 3].  Returns v [n, 4, 3]."""
+    from .dirac import EYE4, GAMMA
+    from .fields import charge_hat, pauli_term
+    sites = np.asarray(sites)
+    n = len(sites)
+    pos = {int(x): i for i, x in enumerate(sites)}
+    qhat = charge_hat(q, q_el) if a_ext is not None else 0
+    p = pauli_term(lat, u_ext, a_ext, kappa, q if a_ext is not None else 0.0, csw, csw_u1, q_el, sites)
+    d = np.zeros((n, 12, n, 12), dtype=complex)
+    for i in range(n):
+        d[i, :, i, :] = p[i]
+
+    def link(x, mu):
+        w = u_ext[x, mu]
+        return w * np.exp(1j * qhat * a_ext[x, mu]) if qhat else w
+
+    for i, x in enumerate(sites):
+        for mu in range(4):
+            yf, yb = int(lat.fwd[mu][x]), int(lat.bwd[mu][x])
+            if yf in pos and not lat.frozen[x]:
+                d[i, :, pos[yf], :] += -0.5 * lat.sign[mu][x] * np.kron(EYE4 - GAMMA[mu], link(x, mu))
+            if yb in pos and not lat.frozen[yb]:
+                d[i, :, pos[yb], :] += -0.5 * lat.bsign[mu][x] * np.kron(EYE4 + GAMMA[mu],
+                                                                         np.conj(link(yb, mu)).T)
+    d = d.reshape(12 * n, 12 * n)
+    par = lat.parity[sites]
+    ie = (12 * np.nonzero(par == 0)[0][:, None] + np.arange(12)).reshape(-1)
+    io = (12 * np.nonzero(par == 1)[0][:, None] + np.arange(12)).reshape(-1)
+    dee, deo, doe = d[np.ix_(ie, ie)], d[np.ix_(ie, io)], d[np.ix_(io, ie)]
+    doo_inv = np.linalg.inv(d[np.ix_(io, io)])
+    rf = r.reshape(-1)
+    r_e, r_o = rf[ie], rf[io]
+    rho_e = r_e - deo @ (doo_inv @ r_o)
+    v_e = np.zeros_like(rho_e)
+    s_e = rho_e.copy()
+    for _ in range(nmr):
+        t = dee @ s_e - deo @ (doo_inv @ (doe @ s_e))
+        tt = np.real(np.vdot(t, t))
+        alpha = np.vdot(t, s_e) / tt if tt > 0 else 0.0
+        v_e = v_e + alpha * s_e
+        s_e = s_e - alpha * t
+    v = np.zeros(12 * n, dtype=complex)
+    v[ie] = v_e
+    v[io] = doo_inv @ (r_o - doe @ v_e)
+    return v.reshape(n, 4, 3)
+
+
+def sap_cycle_block_at(lat, u_ext, a_ext, blocks, r, b, nmr, kappa, q=0.0, csw=0.0, csw_u1=1.0, q_el=1.0 / 6.0):
+    """M_SAP r after one cycle (ncy = 1, from psi = 0), on the sites of block
+    b only, from the site formula: a colour-0 block holds its block solve of
+    r; a colour-1 block the block solve of r - D v0, where v0 holds the block
+    solves of r on the colour-0 blocks next to it (the only ones D v0 reaches
+    it from).  r: the residual on the whole lattice [V, 4, 3].  Returns
+    (sites of b, M_SAP r on them)."""
+    from .dirac import apply_at_sites
+    bid = blocks.block_id
+    sites = np.nonzero(bid == b)[0]
+    if blocks.colour[sites[0]] == 0:
+        return sites, block_solve_at(lat, u_ext, a_ext, sites, r[sites], nmr, kappa, q, csw, csw_u1, q_el)
+    nbrs = set()
+    for mu in range(4):
+        for nb in (lat.fwd[mu][sites], lat.bwd[mu][sites]):
+            nbrs.update(int(c) for c in np.unique(bid[nb]) if c != b)
+    v0 = np.zeros_like(r)
+    for c in sorted(nbrs):
+        sc = np.nonzero(bid == c)[0]
+        v0[sc] = block_solve_at(lat, u_ext, a_ext, sc, r[sc], nmr, kappa, q, csw, csw_u1, q_el)
+    rb = r[sites] - apply_at_sites(lat, u_ext, a_ext, v0, sites, kappa, q, csw, csw_u1, q_el)
+    return sites, block_solve_at(lat, u_ext, a_ext, sites, rb, nmr, kappa, q, csw, csw_u1, q_el)
+
+
+# --------------------------------------------------------------------------
 # flexible GCR with a variable right preconditioner
 # --------------------------------------------------------------------------
 def fgcr(apply_d, precond, b, tol, nkv=16, maxiter=1000, history=None):
