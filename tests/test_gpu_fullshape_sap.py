@@ -1,0 +1,66 @@
+"""The Schwarz preconditioner at the full 64 x 32^3 C* shape (4,194,304
+extended sites, 16,384 blocks of 4^4), in the launch configuration the
+benchmark times, against the oracle at sampled blocks: one cycle (ncy 1,
+nmr 4) from a Gaussian residual in every storage precision, compared on a
+colour-0 block of the mirror half (its block solve) and on two colour-1
+blocks whose faces cross the shifted C* boundaries, the time boundary and
+the boundary between the physical and mirror halves (block solves after the
+face update from the colour-0 blocks around them; oracle/solvers.py,
+sap_cycle_block_at), to the precision bars (1e-12 FP64, 1e-5 FP32, 1e-2
+FP16/BF16 storage)."""
+
+import numpy as np
+import pytest
+
+from gpu_common import rel, to_dev, to_host
+from oracle import Lattice
+from oracle import fields as of
+from oracle import solvers as osv
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-12, 1: 1e-5, 2: 1e-2, 3: 1e-2}
+
+
+def test_sap_full_shape_sampled_blocks():
+    import torch
+    from paper_1710_08839_amd import qxd, synth
+    ctx = qxd.Context(0)
+    dims = (64, 32, 32, 32)
+    kappa, q, csw = 0.1365, -1 / 3, 1.9
+    u, a = synth.gauge_field(dims, 20171002, 0.25, 0.15)
+    lat = Lattice(dims, cstar=3)
+    blocks = osv.Blocks(lat, (4, 4, 4, 4))
+    nb = blocks.nb
+
+    def bid(b0, b1, b2, b3):
+        return ((b0 * nb[1] + b1) * nb[2] + b2) * nb[3] + b3
+
+    # colour 0 in the mirror half; colour 1 with x3 forward across the shifted
+    # C* boundary and x0 backward across the time boundary; colour 1 with x1
+    # forward into the mirror half and x2 forward / x3 backward across the
+    # shifted boundaries
+    picks = [bid(5, 11, 3, 7), bid(0, 2, 4, 7), bid(9, 7, 7, 0)]
+    sites = {b: np.nonzero(blocks.block_id == b)[0] for b in picks}
+    r = synth.source(dims, 3, 1004)
+    f = qxd.Field(ctx, dims, u, a, cstar=3)
+    quark = qxd.quark(kappa, q, csw, 1.0)
+    rd = to_dev(r)
+    out = torch.empty_like(rd)
+    got = {}
+    for prec in (0, 1, 2, 3):
+        f.sap_apply(quark, prec, 1, 4, rd, out)
+        torch.cuda.synchronize()
+        oh = to_host(out)
+        got[prec] = {b: oh[s].copy() for b, s in sites.items()}
+        del oh
+    del rd, out
+    f.release()
+    ue, ae = of.extend_gauge(lat, u, a)
+    for b in picks:
+        s, expect = osv.sap_cycle_block_at(lat, ue, ae, blocks, r, b, 4, kappa, q, csw, 1.0)
+        assert np.array_equal(s, sites[b])
+        assert blocks.colour[s[0]] == (0 if b == picks[0] else 1)
+        for prec in (0, 1, 2, 3):
+            err = rel(got[prec][b], expect)
+            assert err < TOL[prec], (b, prec, err)
