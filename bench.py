@@ -754,8 +754,8 @@ def main():
         print(json.dumps(cpu_baseline_child(args.cpu_child)))
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not part "
-              f"of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library has no multi-GPU "
+              f"path", file=sys.stderr)
         sys.exit(2)
 
     import torch
