@@ -357,8 +357,9 @@ __global__ void __launch_bounds__(DT) little_pack_kernel(int64_t nmat, int ns, c
 
 // Little products in column-streaming form: one work-group per block b of
 // `list`, made of G = blockDim.x / ns groups of ns threads.  The block's
-// transposed matrices are columns of ns FP32 complex numbers, column c of
-// slot d at c = d * ns + l holding A[b][d][k][l] for k = 0 .. ns-1; thread
+// transposed matrices are columns of ns complex numbers (FP32 or FP16),
+// column c of slot d at c = d * ns + l holding A[b][d][k][l] for k = 0 ..
+// ns-1; thread
 // (g, k) takes the columns c = g, g + G, ... for its row k, so that the
 // work-group reads the block's matrices front to back, and the G partial
 // sums of a row are added in the order g = 0 .. G-1.  The vector entries
