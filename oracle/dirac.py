@@ -156,6 +156,31 @@ def apply_at_sites(lat, u_ext, a_ext, psi, sites, kappa, q=0.0, csw=0.0, csw_u1=
     return out - 0.5 * acc
 
 
+def schur_at_sites(lat, u_ext, a_ext, psi, sites, kappa, q=0.0, csw=0.0, csw_u1=1.0, q_el=1.0 / 6.0):
+    """(D^ psi_e)(x) = (D_ee psi_e - D_eo D_oo^-1 D_oe psi_e)(x) at the listed
+    even sites only (the odd entries of psi are not used), by the site
+    formula, for lattices too large to build the whole operator: D_oe psi_e
+    on the odd neighbours of the sites, D_oo^-1 there from the Pauli term at
+    those sites, then D_eo of the result at the sites."""
+    from .fields import pauli_term
+    sites = np.asarray(sites)
+    if np.any(lat.parity[sites] != 0):
+        raise ValueError("schur_at_sites takes even sites")
+    qq = q if a_ext is not None else 0.0
+    pe = psi.copy()
+    pe[lat.parity == 1] = 0
+    odd = np.unique(np.concatenate([lat.fwd[mu][sites] for mu in range(4)] + [lat.bwd[mu][sites] for mu in range(4)]))
+    # D psi_e on odd sites is D_oe psi_e (the Pauli term meets zeros there)
+    z = apply_at_sites(lat, u_ext, a_ext, pe, odd, kappa, qq, csw, csw_u1, q_el).reshape(-1, 12)
+    p_o = pauli_term(lat, u_ext, a_ext, kappa, qq, csw, csw_u1, q_el, odd)
+    t = np.zeros_like(psi)
+    t[odd] = np.linalg.solve(p_o, z[..., None])[..., 0].reshape(-1, 4, 3)
+    # D t on the even sites is D_eo t (t vanishes on even sites)
+    dt = apply_at_sites(lat, u_ext, a_ext, t, sites, kappa, qq, csw, csw_u1, q_el)
+    p_e = pauli_term(lat, u_ext, a_ext, kappa, qq, csw, csw_u1, q_el, sites)
+    return np.einsum("xij,xj->xi", p_e, pe[sites].reshape(-1, 12)).reshape(-1, 4, 3) - dt
+
+
 def dot(a, b):
     """(a, b) = sum conj(a) b over everything."""
     return np.vdot(a, b)

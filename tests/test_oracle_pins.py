@@ -514,6 +514,21 @@ def test_apply_at_sites_matches_full_operator():
     assert rel(got, op.apply(psi)[sites]) < 1e-14
 
 
+@pytest.mark.parametrize("time_bc", [0, 1], ids=["antiperiodic", "open"])
+def test_schur_at_sites_matches_full_operator(time_bc):
+    """The per-site evaluation of D^ used for huge lattices equals the whole
+    Schur complement at even sites, the sites at the C* and time boundaries
+    among them (the odd entries of the input are ignored)."""
+    lat = Lattice((4, 4, 4, 4), cstar=3, time_bc=time_bc)
+    ue, ae = random_field(lat, 93)
+    op = od.build_operator(lat, ue, ae, 0.13, q=-1 / 3, csw=1.9, csw_u1=1.2)
+    psi = rand_spinor(lat, 6)
+    even = np.nonzero(lat.parity == 0)[0]
+    sites = np.array([even[0], even[7], even[100], even[-1]])
+    got = od.schur_at_sites(lat, ue, ae, psi, sites, 0.13, q=-1 / 3, csw=1.9, csw_u1=1.2)
+    assert rel(got, op.apply_schur(op.restrict(psi, lat.even))[sites]) < 1e-13
+
+
 # ---------------------------------------------------------------------------
 # Open time boundary (Sec. 2 features list; the boundary term dD_b is only
 # named in Sec. 2.3).  Reading: the links across x0 = T-1 -> 0 do not exist,
