@@ -12,6 +12,9 @@ face update from the colour-0 blocks around them; oracle/solvers.py,
 sap_cycle_block_at), to the precision bars (1e-12 FP64, 1e-5 FP32, 1e-2
 FP16/BF16 storage).
 
+The even-odd Schur complement D^ (the half-lattice passes) at 64 x 32^3 at
+sampled even sites in every storage precision and kernel variant.
+
 The batched mixed-precision SAP-GCR at the full 48 x 24^3 C* shape and the
 deflated SAP-GCR at 64 x 32^3: the oracle's D at sampled sites leaves the
 residual bound of the solve."""
@@ -145,3 +148,43 @@ def test_deflated_solve_full_shape_residual():
     sites = np.sort(np.random.default_rng(19).choice(lat.V, 1024, replace=False))
     dpsi = od.apply_at_sites(lat, ue, ae, ph, sites, kappa, q=q, csw=csw, csw_u1=1.0)
     assert np.linalg.norm(eta[sites] - dpsi) <= 1.05e-10 * np.linalg.norm(eta)
+
+
+def test_schur_full_shape_sampled_sites():
+    """The even-odd Schur complement D^ (the two half-lattice passes) at the
+    full 64 x 32^3 C* shape in every storage precision, with the autotuned
+    kernel variant and with the mirror-fused and wavefront-uniform variants
+    forced, against the oracle's site formula at sampled even sites (the
+    first and last even sites among them)."""
+    import torch
+    from paper_1710_08839_amd import qxd, synth
+    from oracle import dirac as od
+    ctx = qxd.Context(0)
+    dims = (64, 32, 32, 32)
+    kappa, q, csw = 0.1365, -1 / 3, 1.9
+    u, a = synth.gauge_field(dims, 20171002, 0.25, 0.15)
+    f = qxd.Field(ctx, dims, u, a, cstar=3)
+    quark = qxd.quark(kappa, q, csw, 1.0)
+    x = synth.source(dims, 3, 1006)
+    lat = Lattice(dims, cstar=3)
+    even = np.nonzero(lat.parity == 0)[0]
+    sites = np.unique(np.concatenate([np.random.default_rng(23).choice(even, 64, replace=False),
+                                      [even[0], even[-1]]]))
+    xd = to_dev(x)
+    y = torch.empty_like(xd)
+    got = {}
+    try:
+        for prec in (0, 1, 2, 3):
+            for choice in (0, 113, 241):
+                qxd.set_dirac_variant(choice)
+                f.apply(quark, qxd.OP_DHAT, prec, xd, y)
+                torch.cuda.synchronize()
+                got[(prec, choice)] = to_host(y)[sites]
+    finally:
+        qxd.set_dirac_variant(0)
+    del xd, y
+    f.release()
+    ue, ae = of.extend_gauge(lat, u, a)
+    expect = od.schur_at_sites(lat, ue, ae, x, sites, kappa, q=q, csw=csw, csw_u1=1.0)
+    for (prec, choice), yh in got.items():
+        assert rel(yh, expect) < TOL[prec], (prec, choice, rel(yh, expect))
