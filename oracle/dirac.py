@@ -181,6 +181,21 @@ def schur_at_sites(lat, u_ext, a_ext, psi, sites, kappa, q=0.0, csw=0.0, csw_u1=
     return np.einsum("xij,xj->xi", p_e, pe[sites].reshape(-1, 12)).reshape(-1, 4, 3) - dt
 
 
+def normal_at_sites(lat, u_ext, a_ext, psi, sites, kappa, q=0.0, csw=0.0, csw_u1=1.0, q_el=1.0 / 6.0, mu=0.0):
+    """(X psi_e)(x) with X = D^dag D^ + mu^2 at the listed even sites only, by
+    the site formula (D^dag = g5 D^ g5 on even sites): D^ psi_e on the even
+    sites two hops around them, then D^ of g5 times that at the sites."""
+    sites = np.asarray(sites)
+    odd = np.unique(np.concatenate([lat.fwd[m][sites] for m in range(4)] + [lat.bwd[m][sites] for m in range(4)]))
+    near = np.unique(np.concatenate([sites] + [lat.fwd[m][odd] for m in range(4)] + [lat.bwd[m][odd] for m in range(4)]))
+    y = np.zeros_like(psi)
+    y[near] = schur_at_sites(lat, u_ext, a_ext, psi, near, kappa, q, csw, csw_u1, q_el)
+    g5y = np.einsum("st,xtc->xsc", GAMMA5, y)
+    out = np.einsum("st,xtc->xsc", GAMMA5,
+                    schur_at_sites(lat, u_ext, a_ext, g5y, sites, kappa, q, csw, csw_u1, q_el))
+    return out + mu * mu * psi[sites]
+
+
 def dot(a, b):
     """(a, b) = sum conj(a) b over everything."""
     return np.vdot(a, b)

@@ -529,6 +529,21 @@ def test_schur_at_sites_matches_full_operator(time_bc):
     assert rel(got, op.apply_schur(op.restrict(psi, lat.even))[sites]) < 1e-13
 
 
+def test_normal_at_sites_matches_full_operator():
+    """The per-site evaluation of X = D^dag D^ + mu^2 used for huge lattices
+    equals the whole normal operator of the multi-shift oracle at even sites
+    (the C* and time boundaries among them)."""
+    from oracle import rational as orat
+    lat = Lattice((4, 4, 4, 4), cstar=3, time_bc=0)
+    ue, ae = random_field(lat, 95)
+    op = od.build_operator(lat, ue, ae, 0.13, q=-1 / 3, csw=1.9, csw_u1=1.2)
+    psi = op.restrict(rand_spinor(lat, 8), lat.even)
+    even = np.nonzero(lat.parity == 0)[0]
+    sites = np.array([even[0], even[9], even[200], even[-1]])
+    got = od.normal_at_sites(lat, ue, ae, psi, sites, 0.13, q=-1 / 3, csw=1.9, csw_u1=1.2, mu=0.07)
+    assert rel(got, orat.NormalOperator(op, 0.07).apply(psi)[sites]) < 1e-13
+
+
 # ---------------------------------------------------------------------------
 # Open time boundary (Sec. 2 features list; the boundary term dD_b is only
 # named in Sec. 2.3).  Reading: the links across x0 = T-1 -> 0 do not exist,
