@@ -15,9 +15,9 @@ FP16/BF16 storage).
 The even-odd Schur complement D^ (the half-lattice passes) at 64 x 32^3 at
 sampled even sites in every storage precision and kernel variant.
 
-The batched mixed-precision SAP-GCR at the full 48 x 24^3 C* shape and the
-deflated SAP-GCR at 64 x 32^3: the oracle's D at sampled sites leaves the
-residual bound of the solve."""
+The batched mixed-precision SAP-GCR at the full 48 x 24^3 C* shape, the
+deflated SAP-GCR and the multi-shift CG at 64 x 32^3: the oracle's
+operators at sampled sites leave the residual bound of each solve."""
 
 import numpy as np
 import pytest
@@ -188,3 +188,40 @@ def test_schur_full_shape_sampled_sites():
     expect = od.schur_at_sites(lat, ue, ae, x, sites, kappa, q=q, csw=csw, csw_u1=1.0)
     for (prec, choice), yh in got.items():
         assert rel(yh, expect) < TOL[prec], (prec, choice, rel(yh, expect))
+
+
+def test_multishift_full_shape_residuals():
+    """Multi-shift CG at the full 64 x 32^3 C* shape on D^dag D^ of the
+    benchmark's operator (shifts 0.05, 0.2 and 0.8): for every shift the
+    oracle's X = D^dag D^ (site formula) at sampled even sites, the first
+    and last among them, leaves the residual bound of the solve,
+    |eta_e - (X + sigma) psi| over those sites <= 1.05e-10 |eta_e|."""
+    import torch
+    from paper_1710_08839_amd import qxd, synth
+    from oracle import dirac as od
+    ctx = qxd.Context(0)
+    dims = (64, 32, 32, 32)
+    kappa, q, csw = 0.1365, -1 / 3, 1.9
+    u, a = synth.gauge_field(dims, 20171002, 0.25, 0.15)
+    f = qxd.Field(ctx, dims, u, a, cstar=3)
+    quark = qxd.quark(kappa, q, csw, 1.0)
+    eta = synth.source(dims, 3, 1007)
+    shifts = np.array([0.05, 0.2, 0.8])
+    ed = to_dev(eta)
+    psi = torch.empty((len(shifts),) + tuple(ed.shape), dtype=ed.dtype, device="cuda")
+    st, info = f.multishift(quark, shifts, ed, psi, tol=1e-10)
+    assert st == 0
+    ph = to_host(psi)
+    del ed, psi
+    f.release()
+    lat = Lattice(dims, cstar=3)
+    ue, ae = of.extend_gauge(lat, u, a)
+    even = np.nonzero(lat.parity == 0)[0]
+    sites = np.unique(np.concatenate([np.random.default_rng(29).choice(even, 32, replace=False),
+                                      [even[0], even[-1]]]))
+    eta_e_norm = np.linalg.norm(eta[even])
+    for j, sg in enumerate(shifts):
+        xv = od.normal_at_sites(lat, ue, ae, ph[j], sites, kappa, q=q, csw=csw, csw_u1=1.0) + sg * ph[j][sites]
+        res = np.linalg.norm(eta[sites] - xv)
+        assert res <= 1.05e-10 * eta_e_norm, (j, res / eta_e_norm)
+        assert info[j].true_resid <= 1e-10
