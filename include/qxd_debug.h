@@ -38,6 +38,14 @@ qxd_status qxd_debug_set_dirac_variant(int choice);
  * launch directly instead (the results are the same bits); process-wide. */
 qxd_status qxd_debug_set_step_graphs(int enable);
 
+/* Classical Gram-Schmidt passes per step of the batched SAP-GCR (qxd_solve
+ * with QXD_SOLVER_SAP_GCR, and the serve loop): 1 (the default) orthogonalises
+ * the new direction chi_k = D phi_k once against the stored chi_l; 2 repeats
+ * the projection against the stored vectors and adds the second coefficients
+ * to the first (equal in exact arithmetic).  Applies to solvers created after
+ * the call; process-wide.  QXD_EINVAL for any other value. */
+qxd_status qxd_debug_set_gs_passes(int passes);
+
 /* Process-wide totals since load: step graphs captured, and step graphs
  * launched (each capture is launched once at once, then replayed while its
  * configuration repeats).  QXD_EINVAL if either pointer is NULL. */

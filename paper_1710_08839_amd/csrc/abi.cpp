@@ -426,6 +426,15 @@ qxd_status qxd_debug_set_step_graphs(int enable) {
   return QXD_OK;
 }
 
+qxd_status qxd_debug_set_gs_passes(int passes) {
+  if (passes != 1 && passes != 2) {
+    set_error("qxd_debug_set_gs_passes: passes must be 1 or 2");
+    return QXD_EINVAL;
+  }
+  set_gs_passes(passes);
+  return QXD_OK;
+}
+
 qxd_status qxd_debug_sap_pair_pass(qxd_field *field, const qxd_quark *quark, qxd_prec prec, int nmr, int npair,
                                    int reps, float *ms, void *stream) {
   if (!field || !quark || !ms || nmr < 0 || npair < 1 || reps < 1) {

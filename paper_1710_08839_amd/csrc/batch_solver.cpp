@@ -24,6 +24,9 @@
 
 namespace qxd {
 
+// Gram-Schmidt passes of batch solvers constructed from now on (1 or 2)
+std::atomic<int> g_gs_passes{1};
+
 namespace {
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -69,14 +72,15 @@ struct BatchSolver::Slot {
   void *sap_v() { return (char *)inner.p + 4 * fbP; }
   void *phi(int k) { return (char *)inner.p + (5 + k) * fbP; }
   void *chi(int nkv, int k) { return (char *)inner.p + (5 + nkv + k) * fbP; }
-  // scalars: amat[2*nkv*nkv], rec[3*nkv], coef[2*nkv], misc[8]
+  // scalars: amat[2*nkv*nkv], rec[3*nkv], coef[2*nkv], misc[8], ak2[2*nkv]
   double *amat() { return (double *)scal.p; }
   double *rec(int nkv) { return amat() + 2 * nkv * nkv; }
   double *coef(int nkv) { return rec(nkv) + 3 * nkv; }
   double *misc(int nkv) { return coef(nkv) + 2 * nkv; }
+  double *ak2(int nkv) { return misc(nkv) + 8; }
 };
 
-static size_t scal_doubles(int nkv) { return (size_t)2 * nkv * nkv + 3 * nkv + 2 * nkv + 8; }
+static size_t scal_doubles(int nkv) { return (size_t)2 * nkv * nkv + 3 * nkv + 2 * nkv + 8 + 2 * nkv; }
 
 BatchSolver::BatchSolver(Field *f, int prec, const qxd_solver &s, hipStream_t st)
     : f_(f), prec_(prec), s_(s), st_(st) {
@@ -85,6 +89,7 @@ BatchSolver::BatchSolver(Field *f, int prec, const qxd_solver &s, hipStream_t st
   ncy_ = s.ncy > 0 ? s.ncy : kDefaultNcy;
   nmr_ = s.nmr > 0 ? s.nmr : kDefaultNmr;
   inner_tol_ = s.inner_tol > 0 ? s.inner_tol : kDefaultInnerTol[prec >= QXD_F64 && prec <= QXD_BF16 ? prec : 0];
+  gs_passes_ = g_gs_passes.load();
 }
 
 BatchSolver::~BatchSolver() {
@@ -301,6 +306,7 @@ struct BImpl {
       hg[j].vstride_bytes = (int64_t)sl.fbP;
       hg[j].rho = (typename St<P>::pair_t *)sl.rho();
       hg[j].ak = sl.amat() + 2 * sl.k * nkv;
+      hg[j].ak2 = sl.ak2(nkv);
       hg[j].rec = sl.rec(nkv);
       hg[j].norm = norms + j;
       hg[j].k = sl.k;
@@ -323,7 +329,7 @@ struct BImpl {
                                     cy == 0 && c == 0, nmr, st));
         }
       BCK(launch_dirac_batch<P>(g, dslots.as<DSlot<P>>(), actbuf.as<int>(), n, 2, st));
-      BCK(blas_gs_batch<P>(gsslots.as<GsSlot<P>>(), n, g.V, g.rd, gspart.as<double>(), st));
+      BCK(blas_gs_batch<P>(gsslots.as<GsSlot<P>>(), n, g.V, g.rd, gspart.as<double>(), bs.gs_passes(), st));
       return QXD_OK;
     };
     const std::array<int64_t, 10> key{P, n, npair, (int64_t)ncy * 256 + nmr, (int64_t)(intptr_t)sslots.p,
@@ -349,6 +355,7 @@ std::atomic<int64_t> g_graph_captures{0}, g_graph_replays{0};
   }
 
 void set_step_graphs(bool on) { g_step_graphs.store(on); }
+void set_gs_passes(int passes) { g_gs_passes.store(passes); }
 void inject_step_failures(int n) { g_inject_failures.store(n > 0 ? n : 0); }
 void step_graph_counts(int64_t *captures, int64_t *replays) {
   *captures = g_graph_captures.load();

@@ -53,6 +53,8 @@ class BatchSolver {
   const qxd_solver &params() const { return s_; }
   int prec() const { return prec_; }
   Field *field() const { return f_; }
+  // classical Gram-Schmidt passes per step (1, or 2 with re-orthogonalisation)
+  int gs_passes() const { return gs_passes_; }
 
   struct Slot;  // one right-hand side in flight (batch_solver.cpp)
 
@@ -78,7 +80,7 @@ class BatchSolver {
   int prec_;
   qxd_solver s_;
   hipStream_t st_;
-  int nkv_, ncy_, nmr_;
+  int nkv_, ncy_, nmr_, gs_passes_ = 1;
   double inner_tol_;
   std::vector<std::unique_ptr<Slot>> slots_;
   std::vector<Finished> done_;
@@ -109,6 +111,9 @@ constexpr double kDefaultInnerTol[4] = {1e-6, 1e-5, 2e-2, 1e-2};
 
 // Process-wide switch for graph capture of the batched steps (testing hook).
 void set_step_graphs(bool on);
+// Gram-Schmidt passes (1 or 2) of batch solvers constructed from now on
+// (measurement hook).
+void set_gs_passes(int passes);
 // Make the next n batched steps of any solver fail before any launch
 // (testing hook for the error paths of qxd_solve and the serve loop).
 void inject_step_failures(int n);

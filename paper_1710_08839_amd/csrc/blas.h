@@ -69,6 +69,10 @@ hipError_t blas_norm2(SpinorArg x, int64_t first, int64_t count, double *partial
 // For each slot, with k = slot.k:
 //   ak_l = (chi_l, chi_k) / |chi_l|^2            (l < k; |chi_l|^2 = rec[3l])
 //   chi_k -= sum_l ak_l chi_l                     (stored in place)
+//   with passes = 2, once more (classical Gram-Schmidt with one
+//   re-orthogonalisation against the stored vectors):
+//     ak2_l = (chi_l, chi_k) / |chi_l|^2, chi_k -= sum_l ak2_l chi_l,
+//     ak_l += ak2_l
 //   rec[3k] = |chi_k|^2, rec[3k+1..2] = (chi_k, rho)
 //   rho -= (rec[3k+1..2] / rec[3k]) chi_k,  *norm = |rho|^2
 // Sums are FP64 over a grid fixed by the vector length, so a slot's results do
@@ -79,6 +83,7 @@ struct GsSlot {
   int64_t vstride_bytes;         // bytes from chi_l to chi_l+1
   typename St<P>::pair_t *rho;
   double *ak;                    // complex, l < k
+  double *ak2;                   // second-pass coefficients (complex, l < k)
   double *rec;                   // 3 per vector
   double *norm;                  // |rho|^2 out
   int k;
@@ -91,6 +96,6 @@ inline size_t gs_batch_partial_doubles(int n, int prec, int64_t nsites) {
 }
 template <int P>
 hipError_t blas_gs_batch(const GsSlot<P> *slots, int n, int64_t nsites, const RunDiv &rd, double *partial,
-                         hipStream_t st);
+                         int passes, hipStream_t st);
 
 }  // namespace qxd

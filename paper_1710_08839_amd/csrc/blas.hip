@@ -492,16 +492,17 @@ __global__ void __launch_bounds__(BT) gs_dot_kernel(const GsSlot<P> *slots, int6
   }
 }
 
-// chi_k -= sum_l ak_l chi_l; partial values 0..2 = |chi_k|^2, (chi_k, rho)
+// chi_k -= sum_l ak_l chi_l (second: ak2_l); partial values 0..2 = |chi_k|^2, (chi_k, rho)
 template <int P>
-__global__ void __launch_bounds__(BT) gs_axpy_kernel(const GsSlot<P> *slots, int64_t ng, double *partial) {
+__global__ void __launch_bounds__(BT) gs_axpy_kernel(const GsSlot<P> *slots, int64_t ng, double *partial, int second) {
   constexpr int W = VW<P>;
   __shared__ double sh[12];
   __shared__ double cfs[2 * MAXV];  // the coefficients ak, read once per work-group
   const GsSlot<P> s = slots[blockIdx.y];
   const int k = s.k, gx = gridDim.x;
   typename St<P>::pair_t *xk = vec_at(s, k);
-  for (int j = threadIdx.x; j < 2 * k; j += BT) cfs[j] = gld(s.ak, j);
+  const double *cf_src = second ? s.ak2 : s.ak;
+  for (int j = threadIdx.x; j < 2 * k; j += BT) cfs[j] = gld(cf_src, j);
   __syncthreads();
   double nn = 0.0, wr = 0.0, wi = 0.0;
   for (int64_t t = (int64_t)blockIdx.x * BT + threadIdx.x; t < ng; t += (int64_t)gx * BT) {
@@ -608,14 +609,16 @@ __global__ void __launch_bounds__(BT) gs_dot_site_kernel(const GsSlot<P> *slots,
 }
 
 template <int P>
-__global__ void __launch_bounds__(BT) gs_axpy_site_kernel(const GsSlot<P> *slots, int64_t nsites, RunDiv rd, double *partial) {
+__global__ void __launch_bounds__(BT) gs_axpy_site_kernel(const GsSlot<P> *slots, int64_t nsites, RunDiv rd, double *partial,
+                                                           int second) {
   __shared__ double sh[12];
   __shared__ double cfs[2 * MAXV];
   const GsSlot<P> s = slots[blockIdx.y];
   const int k = s.k, gx = gridDim.x;
   const Spinor<P> xk = vec_view(s, k, nsites, rd);
   const Spinor<P> rho = spinor_view<P>(s.rho, nsites, 0, rd);
-  for (int j = threadIdx.x; j < 2 * k; j += BT) cfs[j] = gld(s.ak, j);
+  const double *cf_src = second ? s.ak2 : s.ak;
+  for (int j = threadIdx.x; j < 2 * k; j += BT) cfs[j] = gld(cf_src, j);
   __syncthreads();
   double nn = 0.0, wr = 0.0, wi = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < nsites; i += (int64_t)gx * BT) {
@@ -679,14 +682,15 @@ __global__ void __launch_bounds__(BT) gs_update_site_kernel(const GsSlot<P> *slo
 
 // Per slot (one work-group each): add the partial sums of a phase in a fixed
 // order and write the results.  phase 0: ak_l = dot_l / rec[3l] (l < k);
-// phase 1: rec[3k..3k+2]; phase 2: *norm.
+// phase 1: rec[3k..3k+2]; phase 2: *norm; phase 3: ak2_l = dot_l / rec[3l]
+// and ak_l += ak2_l (l < k).
 template <int P>
 __global__ void __launch_bounds__(BT) gs_finish_kernel(const GsSlot<P> *slots, int gx, const double *partial, int phase) {
   constexpr int K = 16;
   __shared__ double sh[4 * K], res[K];
   const GsSlot<P> s = slots[blockIdx.x];
   const int k = s.k;
-  const int nval = phase == 0 ? 2 * k : (phase == 1 ? 3 : 1);
+  const int nval = (phase == 0 || phase == 3) ? 2 * k : (phase == 1 ? 3 : 1);
   const double *pp = partial + (int64_t)blockIdx.x * 2 * MAXV * gx;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int v0 = 0; v0 < nval; v0 += K) {
@@ -708,9 +712,13 @@ __global__ void __launch_bounds__(BT) gs_finish_kernel(const GsSlot<P> *slots, i
     __syncthreads();
     if ((int)threadIdx.x < m) {
       const int j = threadIdx.x, v = v0 + j;
-      if (phase == 0)
+      if (phase == 0) {
         gst(s.ak, v, res[j] / gld(s.rec, 3 * (v >> 1)));
-      else if (phase == 1)
+      } else if (phase == 3) {
+        const double a2 = res[j] / gld(s.rec, 3 * (v >> 1));
+        gst(s.ak2, v, a2);
+        gst(s.ak, v, gld(s.ak, v) + a2);
+      } else if (phase == 1)
         gst(s.rec, 3 * k + v, res[j]);
       else
         gst(s.norm, 0, res[j]);
@@ -915,14 +923,20 @@ unsigned gs_batch_grid(int prec, int64_t nsites) {
 
 template <int P>
 hipError_t blas_gs_batch(const GsSlot<P> *slots, int n, int64_t nsites, const RunDiv &rd, double *partial,
-                         hipStream_t st) {
+                         int passes, hipStream_t st) {
   if (n < 1) return hipSuccess;
+  if (passes != 1 && passes != 2) return hipErrorInvalidValue;
   const unsigned gx = gs_batch_grid(P, nsites);
   const dim3 grid(gx, (unsigned)n);
   if constexpr (St<P>::scaled) {
     gs_dot_site_kernel<P><<<grid, BT, 0, st>>>(slots, nsites, rd, partial);
     gs_finish_kernel<P><<<(unsigned)n, BT, 0, st>>>(slots, (int)gx, partial, 0);
-    gs_axpy_site_kernel<P><<<grid, BT, 0, st>>>(slots, nsites, rd, partial);
+    gs_axpy_site_kernel<P><<<grid, BT, 0, st>>>(slots, nsites, rd, partial, 0);
+    if (passes == 2) {
+      gs_dot_site_kernel<P><<<grid, BT, 0, st>>>(slots, nsites, rd, partial);
+      gs_finish_kernel<P><<<(unsigned)n, BT, 0, st>>>(slots, (int)gx, partial, 3);
+      gs_axpy_site_kernel<P><<<grid, BT, 0, st>>>(slots, nsites, rd, partial, 1);
+    }
     gs_finish_kernel<P><<<(unsigned)n, BT, 0, st>>>(slots, (int)gx, partial, 1);
     gs_update_site_kernel<P><<<grid, BT, 0, st>>>(slots, nsites, rd, partial);
     gs_finish_kernel<P><<<(unsigned)n, BT, 0, st>>>(slots, (int)gx, partial, 2);
@@ -930,7 +944,12 @@ hipError_t blas_gs_batch(const GsSlot<P> *slots, int n, int64_t nsites, const Ru
     const int64_t ng = nsites * 12 / VW<P>;
     gs_dot_kernel<P><<<grid, BT, 0, st>>>(slots, ng, partial);
     gs_finish_kernel<P><<<(unsigned)n, BT, 0, st>>>(slots, (int)gx, partial, 0);
-    gs_axpy_kernel<P><<<grid, BT, 0, st>>>(slots, ng, partial);
+    gs_axpy_kernel<P><<<grid, BT, 0, st>>>(slots, ng, partial, 0);
+    if (passes == 2) {
+      gs_dot_kernel<P><<<grid, BT, 0, st>>>(slots, ng, partial);
+      gs_finish_kernel<P><<<(unsigned)n, BT, 0, st>>>(slots, (int)gx, partial, 3);
+      gs_axpy_kernel<P><<<grid, BT, 0, st>>>(slots, ng, partial, 1);
+    }
     gs_finish_kernel<P><<<(unsigned)n, BT, 0, st>>>(slots, (int)gx, partial, 1);
     gs_update_kernel<P><<<grid, BT, 0, st>>>(slots, ng, partial);
     gs_finish_kernel<P><<<(unsigned)n, BT, 0, st>>>(slots, (int)gx, partial, 2);
@@ -938,7 +957,7 @@ hipError_t blas_gs_batch(const GsSlot<P> *slots, int n, int64_t nsites, const Ru
   return hipGetLastError();
 }
 #define QXD_INST(P)                                                                                       \
-  template hipError_t blas_gs_batch<P>(const GsSlot<P> *, int, int64_t, const RunDiv &, double *, hipStream_t);
+  template hipError_t blas_gs_batch<P>(const GsSlot<P> *, int, int64_t, const RunDiv &, double *, int, hipStream_t);
 QXD_INST(QXD_F64)
 QXD_INST(QXD_F32)
 QXD_INST(QXD_F16S)

@@ -98,6 +98,7 @@ SIGNATURES = {
     # testing hooks (include/qxd_debug.h)
     "qxd_debug_set_dirac_variant": ([_I], _I),
     "qxd_debug_set_step_graphs": ([_I], _I),
+    "qxd_debug_set_gs_passes": ([_I], _I),
     "qxd_debug_fail_steps": ([_I], _I),
     "qxd_debug_serve_charges": ([_VP, ctypes.POINTER(ctypes.c_size_t)], _I),
     "qxd_debug_sap_pair_pass": ([_VP, ctypes.POINTER(Quark), _I, _I, _I, _I, ctypes.POINTER(ctypes.c_float), _VP],
@@ -159,6 +160,13 @@ def set_step_graphs(enable=True):
     """Replay batched SAP-GCR steps from captured HIP graphs (default) or
     issue every launch directly.  A testing hook."""
     _check(lib().qxd_debug_set_step_graphs(1 if enable else 0))
+
+
+def set_gs_passes(passes=1):
+    """Classical Gram-Schmidt passes (1, or 2 with one re-orthogonalisation)
+    per step of batched SAP-GCR solvers created after the call.  A
+    measurement hook."""
+    _check(lib().qxd_debug_set_gs_passes(int(passes)))
 
 
 def last_error():

@@ -42,6 +42,7 @@ def test_header_parses():
     assert fns["qxd_debug_set_dirac_variant"] == 1
     assert fns["qxd_debug_get_dirac_variant"] == 3
     assert fns["qxd_debug_set_step_graphs"] == 1
+    assert fns["qxd_debug_set_gs_passes"] == 1
     assert fns["qxd_debug_step_graph_counts"] == 2
     assert fns["qxd_debug_stream"] == 5
     assert fns["qxd_debug_serve_charges"] == 2

@@ -144,13 +144,16 @@ _FGCR_REF = {}
 @pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 1e-5), (2, 1e-2), (3, 1e-2)],
                          ids=["f64", "f32", "f16s", "bf16"])
 @pytest.mark.parametrize("k", [1, 3, 8])
-def test_fgcr_steps_match_oracle(cstar_case, prec, tol, k):
+@pytest.mark.parametrize("passes", [1, 2], ids=["cgs", "cgs2"])
+def test_fgcr_steps_match_oracle(cstar_case, prec, tol, k, passes):
     """The iterate after k flexible-GCR steps (SAP preconditioner, one outer
     defect-correction step) equals the oracle's k-step FGCR on the same source
     to the bar of the inner precision: the per-step error of the mixed-
     precision solver against FP64.  The library orthogonalises by one
-    classical Gram-Schmidt pass with FP64 sums, the oracle by modified
-    Gram-Schmidt with normalised vectors; the two agree in exact arithmetic."""
+    classical Gram-Schmidt pass with FP64 sums (or two, the second against the
+    stored vectors with its coefficients added to the first), the oracle by
+    modified Gram-Schmidt with normalised vectors; they agree in exact
+    arithmetic."""
     import torch
     from paper_1710_08839_amd import qxd
     c = cstar_case
@@ -166,7 +169,11 @@ def test_fgcr_steps_match_oracle(cstar_case, prec, tol, k):
     psi = torch.empty_like(to_dev(eta))
     s = qxd.solver(kind=qxd.SAP_GCR, tol=1e-14, maxiter=k, nkv=8, ncy=2, nmr=4, inner_prec=prec,
                    inner_tol=1e-14, max_outer=1)
-    st, info = c.field.solve(c.quark, s, to_dev(eta), psi, check=False)
+    qxd.set_gs_passes(passes)
+    try:
+        st, info = c.field.solve(c.quark, s, to_dev(eta), psi, check=False)
+    finally:
+        qxd.set_gs_passes(1)
     assert st == -3 and info[0].inner_iters == k and info[0].outer_iters == 1
     err = rel(to_host(psi), ref)
     assert err < tol, err
@@ -203,3 +210,6 @@ def test_solve_errors(cstar_case):
     bad = qxd.quark(0.13, 0.25, 1.0, 1.0)  # q / q_el not an integer
     with pytest.raises(qxd.QxdError):
         c.field.solve(bad, qxd.solver(), to_dev(eta), psi)
+    for passes in (0, 3):
+        with pytest.raises(qxd.QxdError):
+            qxd.set_gs_passes(passes)
