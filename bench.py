@@ -505,7 +505,7 @@ def dfl_leg(f, ns=16, ninv=30, nkv=32):
     st = f.dfl_stats(q)  # the warm-up and the timed solve
     log(f"64x32^3 deflated SAP-GCR: setup {setup_s:.2f} s, {dfl}")
     return {"setup_s": round(setup_s, 3), "deflated": dfl, "sap_gcr": sap,
-            "subspace": {"ns": ns, "ninv": ninv, "ncy": 4, "nmr": 4, "little_tol": 0.2, "little_nkv": 32},
+            "subspace": {"ns": ns, "ninv": ninv, "ncy": 4, "nmr": 4, "little_tol": 0.2, "little_nkv": 48},
             "little": {"applications": st[0], "iterations": st[1], "max_per_solve": st[2]},
             "workload": "64x32^3 C*, q=-1/3, kappa=0.1365, csw=1.9, Gaussian source (seed 1003), tol 1e-10"}
 

@@ -270,7 +270,7 @@ typedef struct {
                          random start fields [30]                              */
   int ncy, nmr;       /* SAP cycles and MR steps of each such step [4, 4]      */
   double little_tol;  /* relative residual of each little-system solve [0.2]  */
-  int little_nkv;     /* Krylov vectors of the little GCR (<= 64) [32]         */
+  int little_nkv;     /* Krylov vectors of the little GCR (<= 64) [48]         */
   int little_maxiter; /* iterations of one little solve [256]                  */
   uint64_t seed;      /* seed of the random start fields                       */
 } qxd_dfl_params;

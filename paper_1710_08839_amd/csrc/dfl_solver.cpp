@@ -150,7 +150,7 @@ qxd_status fill_params(qxd_dfl_params *p) {
   if (p->ncy == 0) p->ncy = 4;
   if (p->nmr == 0) p->nmr = 4;
   if (p->little_tol == 0.0) p->little_tol = 0.2;
-  if (p->little_nkv == 0) p->little_nkv = 32;
+  if (p->little_nkv == 0) p->little_nkv = 48;
   if (p->little_maxiter == 0) p->little_maxiter = 256;
   if (p->ns < 1 || p->ns > DFL_NSMAX || p->ninv < 0 || p->ncy < 1 || p->nmr < 0 || !(p->little_tol > 0.0) ||
       p->little_tol >= 1.0 || p->little_nkv < 1 || p->little_nkv > 64 || p->little_maxiter < 1) {
