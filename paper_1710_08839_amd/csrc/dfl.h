@@ -23,10 +23,12 @@ namespace qxd {
 constexpr int DFL_NSMAX = 32;  // basis vectors per block
 constexpr int DFL_SLOTS = 9;   // couplings of a block: itself, then faces 2 mu + (0 fwd, 1 bwd)
 
-// Pinned host slots and events through which the little GCR reads the
-// residual norm of a step while the device already runs the next one.
+// Pinned host slots (mapped and coherent: the last kernel of a step writes
+// them) and events through which the little GCR reads the residual norm of a
+// step while the device already runs the next one.
 struct LittleSync {
   double *host = nullptr;  // two slots
+  double *dev = nullptr;   // their device address (mapped pinned memory)
   hipEvent_t ev[2] = {nullptr, nullptr};
   LittleSync() = default;
   LittleSync(const LittleSync &) = delete;
@@ -42,7 +44,10 @@ struct LittleSync {
   }
   hipError_t init() {
     hipError_t e = hipSuccess;
-    if (!host) e = hipHostMalloc((void **)&host, 2 * sizeof(double), hipHostMallocDefault);
+    if (!host) {
+      e = hipHostMalloc((void **)&host, 2 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent);
+      if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&dev, host, 0);
+    }
     for (int i = 0; i < 2 && e == hipSuccess; i++)
       if (!ev[i]) e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
     return e;
@@ -117,16 +122,19 @@ hipError_t launch_lt_jacobi(const int *list, int nlist, int ns, const float2 *ai
 // out[2j..2j+1] = (W_j, x) for j < k, W_j = W + j * n (complex vectors of length n)
 hipError_t launch_lv_dots(const double2 *W, int k, int64_t n, const double2 *x, double *partial, double *out,
                           hipStream_t st);
-// x -= sum_{j<k} (d[2j] + i d[2j+1]) / wn[j] * W_j
-hipError_t launch_lv_maxpy(double2 *x, const double2 *W, int k, int64_t n, const double *d, const double *wn,
-                           hipStream_t st);
-// s[0] = |w|^2, s[1..2] = (w, r)
+// x1 -= sum_{j<k} c_j W1_j and x2 -= sum_{j<k} c_j W2_j with
+// c_j = (d[2j] + i d[2j+1]) / wn[j]
+hipError_t launch_lv_maxpy2(double2 *x1, const double2 *W1, double2 *x2, const double2 *W2, int k, int64_t n,
+                            const double *d, const double *wn, hipStream_t st);
+// partial sums of s[0] = |w|^2, s[1..2] = (w, r) into the partial-sum
+// scratch, and, if s is given, their totals into s
 hipError_t launch_lv_dot2(const double2 *w, const double2 *r, int64_t n, double *partial, double *s,
                           hipStream_t st);
+// with s the totals of the partial sums launch_lv_dot2 left in `partial`:
 // alpha = (s[1] + i s[2]) / s[0]: x += alpha z, r -= alpha w; *wn = s[0];
-// out[0] = |r|^2
-hipError_t launch_lv_update(double2 *x, const double2 *z, double2 *r, const double2 *w, int64_t n,
-                            const double *s, double *wn, double *partial, double *out, hipStream_t st);
+// out[0] = |r|^2 (out may be the device address of mapped host memory)
+hipError_t launch_lv_update(double2 *x, const double2 *z, double2 *r, const double2 *w, int64_t n, double *wn,
+                            double *partial, double *out, hipStream_t st);
 // partial-sum scratch of the little reductions (doubles)
 size_t lv_partial_doubles();
 

@@ -518,23 +518,41 @@ __global__ void __launch_bounds__(64) lv_finish_kernel(const double *partial, in
   if (threadIdx.x == 0 && v < nval) out[v] = s;
 }
 
-__global__ void __launch_bounds__(DT) lv_maxpy_kernel(double2 *x, const double2 *W, int k, int64_t n,
-                                                      const double *d, const double *wn) {
+// the same multi-axpy on two vector sets: x1 -= sum_j c_j W1_j, x2 -= sum_j c_j W2_j
+__global__ void __launch_bounds__(DT) lv_maxpy2_kernel(double2 *x1, const double2 *W1, double2 *x2,
+                                                       const double2 *W2, int k, int64_t n, const double *d,
+                                                       const double *wn) {
   const int64_t e = (int64_t)blockIdx.x * DT + threadIdx.x;
   if (e >= n) return;
-  double2 v = x[e];
+  double2 v1 = x1[e], v2 = x2[e];
   for (int j = 0; j < k; j++) {
     const double cr = d[2 * j] / wn[j], ci = d[2 * j + 1] / wn[j];
-    const double2 u = W[(int64_t)j * n + e];
-    v.x -= cr * u.x - ci * u.y;
-    v.y -= cr * u.y + ci * u.x;
+    const double2 u1 = W1[(int64_t)j * n + e], u2 = W2[(int64_t)j * n + e];
+    v1.x -= cr * u1.x - ci * u1.y;
+    v1.y -= cr * u1.y + ci * u1.x;
+    v2.x -= cr * u2.x - ci * u2.y;
+    v2.y -= cr * u2.y + ci * u2.x;
   }
-  x[e] = v;
+  x1[e] = v1;
+  x2[e] = v2;
 }
 
+// the sums of lv_dot2_kernel's partials (as lv_finish_kernel adds them) are
+// formed by every work-group's first wavefront; the update's own partial
+// sums of |r|^2 go to rpart
 __global__ void __launch_bounds__(DT) lv_update_kernel(double2 *x, const double2 *z, double2 *r, const double2 *w,
-                                                       int64_t n, const double *s, double *wn, double *partial) {
+                                                       int64_t n, const double *spart, double *wn, double *rpart) {
   __shared__ double sh[NW];
+  __shared__ double s[3];
+  if (threadIdx.x < 64) {
+    for (int v = 0; v < 3; v++) {
+      double t = 0.0;
+      for (int gi = threadIdx.x; gi < LVG; gi += 64) t += spart[(int64_t)v * LVG + gi];
+      t = wave_sum(t);
+      if (threadIdx.x == 0) s[v] = t;
+    }
+  }
+  __syncthreads();
   const double ar = s[1] / s[0], ai = s[2] / s[0];
   if (blockIdx.x == 0 && threadIdx.x == 0) *wn = s[0];
   double rr = 0.0;
@@ -550,7 +568,7 @@ __global__ void __launch_bounds__(DT) lv_update_kernel(double2 *x, const double2
     rr += rv.x * rv.x + rv.y * rv.y;
   }
   rr = wg_sum(rr, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = rr;
+  if (threadIdx.x == 0) rpart[blockIdx.x] = rr;
 }
 
 bool fits(const Geom &g) { return 2 * g.Vbh <= DT; }
@@ -558,6 +576,7 @@ bool fits(const Geom &g) { return 2 * g.Vbh <= DT; }
 }  // namespace
 
 size_t lv_partial_doubles() { return (size_t)2 * LV_MAXK * LVG + 8; }
+static_assert(2 * LV_MAXK >= 4, "lv_update's partial sums follow lv_dot2's");
 
 hipError_t launch_dfl_random(const Geom &g, void *basis, size_t vbytes, int ns, uint64_t seed, hipStream_t st) {
   for (int k = 0; k < ns; k++)
@@ -657,24 +676,24 @@ hipError_t launch_lv_dots(const double2 *W, int k, int64_t n, const double2 *x, 
   return hipGetLastError();
 }
 
-hipError_t launch_lv_maxpy(double2 *x, const double2 *W, int k, int64_t n, const double *d, const double *wn,
-                           hipStream_t st) {
+hipError_t launch_lv_maxpy2(double2 *x1, const double2 *W1, double2 *x2, const double2 *W2, int k, int64_t n,
+                            const double *d, const double *wn, hipStream_t st) {
   if (k < 1) return hipSuccess;
-  lv_maxpy_kernel<<<grid_for(n, DT), DT, 0, st>>>(x, W, k, n, d, wn);
+  lv_maxpy2_kernel<<<grid_for(n, DT), DT, 0, st>>>(x1, W1, x2, W2, k, n, d, wn);
   return hipGetLastError();
 }
 
 hipError_t launch_lv_dot2(const double2 *w, const double2 *r, int64_t n, double *partial, double *s,
                           hipStream_t st) {
   lv_dot2_kernel<<<LVG, DT, 0, st>>>(w, r, n, partial);
-  lv_finish_kernel<<<3, 64, 0, st>>>(partial, 3, s);
+  if (s) lv_finish_kernel<<<3, 64, 0, st>>>(partial, 3, s);
   return hipGetLastError();
 }
 
-hipError_t launch_lv_update(double2 *x, const double2 *z, double2 *r, const double2 *w, int64_t n, const double *s,
-                            double *wn, double *partial, double *out, hipStream_t st) {
-  lv_update_kernel<<<LVG, DT, 0, st>>>(x, z, r, w, n, s, wn, partial);
-  lv_finish_kernel<<<1, 64, 0, st>>>(partial, 1, out);
+hipError_t launch_lv_update(double2 *x, const double2 *z, double2 *r, const double2 *w, int64_t n, double *wn,
+                            double *partial, double *out, hipStream_t st) {
+  lv_update_kernel<<<LVG, DT, 0, st>>>(x, z, r, w, n, partial, wn, partial + 3 * LVG);
+  lv_finish_kernel<<<1, 64, 0, st>>>(partial + 3 * LVG, 1, out);
   return hipGetLastError();
 }
 

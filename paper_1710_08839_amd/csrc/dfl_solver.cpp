@@ -54,7 +54,7 @@ qxd_status ws(Field *f, const char *name, size_t bytes, void **p) {
 SpinorArg full(const Geom &g, void *p) { return SpinorArg{p, g.V, 0, g.rd}; }
 
 // scalars of the little GCR on the device
-constexpr int LS_S = 0, LS_RR = 4, LS_DOTS = 8, LS_WN = 8 + 2 * 64, LS_N = LS_WN + 64 + 8;
+constexpr int LS_S = 0, LS_DOTS = 8, LS_WN = 8 + 2 * 64, LS_N = LS_WN + 64 + 8;
 
 // x = A^-1 b approximately, on the even-block Schur complement
 //   Ahat = A_ee - A_eo A_oo^-1 A_oe,   Ahat x_e = b_e - A_eo A_oo^-1 b_o,
@@ -103,12 +103,10 @@ qxd_status little_solve_t(Dfl &d, const MT *A, const double2 *b, double2 *x, dou
     DCK(launch_lt_hop(ev, d.ne, ns, A, nbr, zk, nullptr, u, nullptr, 1.0, wk, st));
     if (k > 0) {
       DCK(launch_lv_dots(W, k, n, wk, part, sc + LS_DOTS, st));
-      DCK(launch_lv_maxpy(wk, W, k, n, sc + LS_DOTS, sc + LS_WN, st));
-      DCK(launch_lv_maxpy(zk, Z, k, n, sc + LS_DOTS, sc + LS_WN, st));
+      DCK(launch_lv_maxpy2(wk, W, zk, Z, k, n, sc + LS_DOTS, sc + LS_WN, st));
     }
-    DCK(launch_lv_dot2(wk, r, n, part, sc + LS_S, st));
-    DCK(launch_lv_update(x, zk, r, wk, n, sc + LS_S, sc + LS_WN + k, part, sc + LS_RR, st));
-    DCK(hipMemcpyAsync(d.sync.host + (j & 1), sc + LS_RR, sizeof(double), hipMemcpyDeviceToHost, st));
+    DCK(launch_lv_dot2(wk, r, n, part, nullptr, st));
+    DCK(launch_lv_update(x, zk, r, wk, n, sc + LS_WN + k, part, d.sync.dev + (j & 1), st));
     DCK(hipEventRecord(d.sync.ev[j & 1], st));
     return QXD_OK;
   };
