@@ -66,8 +66,11 @@ struct Dfl {
   DevBuf at16;             // FP16 copy of a, transposed per block (little solves to a loose tolerance)
   DevBuf nbr;              // [nb][9] int: the block each slot couples to
   DevBuf even, odd;        // the blocks of each SAP colour (neighbours have opposite colours)
+  DevBuf vpos;             // [nb] int: a block's position in the little vectors (even blocks first)
+  DevBuf nbrv;             // [nb][9] int: vpos of the block each slot couples to
   int ne = 0, no = 0;
-  // little GCR: Krylov vectors z_k (preconditioned) and w_k = A z_k, work vectors, scalars
+  // little GCR: Krylov vectors z_k (preconditioned) and w_k = A z_k (even
+  // blocks only, ne * ns entries each), work vectors, scalars
   DevBuf lz, lw, lx, lr, lb, lu, lpart, lscal;
   LittleSync sync;
   // counters since the last read: preconditioner applications, little GCR
@@ -85,12 +88,16 @@ hipError_t launch_dfl_random(const Geom &g, void *basis, size_t vbytes, int ns, 
 // modified Gram-Schmidt of the ns restricted fields on every block, in place;
 // *bad counts blocks on which a field vanished
 hipError_t launch_dfl_ortho(const Geom &g, void *basis, size_t vbytes, int ns, int *bad, hipStream_t st);
-// c[b * ns + k] = (phi_{b,k}, r)_b for an FP32 native spinor r
+// Little vectors hold block b's ns entries at position vpos[b] (entries
+// vpos[b] * ns ... + ns - 1): the blocks of the first colour first, in the
+// order of their list, then those of the second, so that the Krylov vectors
+// of the even-block system are the first ne * ns entries.
+// c[vpos[b] * ns + k] = (phi_{b,k}, r)_b for an FP32 native spinor r
 hipError_t launch_dfl_restrict(const Geom &g, const void *basis, size_t vbytes, int ns, const void *r,
-                               double2 *c, hipStream_t st);
-// out = sum_{b,k} c[b * ns + k] phi_{b,k} (FP32 native spinor)
+                               const int *vpos, double2 *c, hipStream_t st);
+// out = sum_{b,k} c[vpos[b] * ns + k] phi_{b,k} (FP32 native spinor)
 hipError_t launch_dfl_prolong(const Geom &g, const void *basis, size_t vbytes, int ns, const double2 *c,
-                              void *out, hipStream_t st);
+                              const int *vpos, void *out, hipStream_t st);
 // face couplings of basis field l: a[b][1 + d][k][l] = (phi_{b,k}, H_d phi_l)_b for the
 // eight faces d of every block (H_d: the hops of D through that face), and nbr[b][1 + d]
 hipError_t launch_dfl_face(const Geom &g, const double2 *wl64, const void *basis, size_t vbytes, int ns, int l,
@@ -105,20 +112,22 @@ hipError_t launch_little_invert(int nb, int ns, const double2 *a, double2 *ainv,
 // transposed within each block
 template <class MT>
 hipError_t launch_little_pack(int64_t nmat, int ns, const double2 *src, MT *dst, hipStream_t st);
-// for the blocks b of `list`: h_b = (xa ? A[b][0] xa_b : (w ? w_b : 0)) -
-// sum_{d >= 1} A[b][d] xh[nbr[b][d]] (the couplings to the blocks across the
-// faces), y_b = h_b, or y_b = s ainv[b] h_b if ait is given; at: the
-// transposed FP32 (MT = float2) or FP16 (MT = h2_t) copy of A, ait: the
-// transposed FP32 copy of the inverse diagonal blocks.  y must not overlap
-// the entries of xa, w and xh the blocks of `list` read.
+// for the i-th block b = list[i] of `list`, whose little-vector entries are
+// at position v = vbase + i: h_v = (xa ? A[b][0] xa_v : (w ? w_v : 0)) -
+// sum_{d >= 1} A[b][d] xh[nbrv[b][d]] (the couplings to the blocks across the
+// faces; nbrv: their positions), y_v = h_v, or y_v = s ainv[b] h_v if ait is
+// given; at: the transposed FP32 (MT = float2) or FP16 (MT = h2_t) copy of A,
+// ait: the transposed FP32 copy of the inverse diagonal blocks.  y must not
+// overlap the entries of xa, w and xh the blocks of `list` read.
 template <class MT>
-hipError_t launch_lt_hop(const int *list, int nlist, int ns, const MT *at, const int *nbr, const double2 *xa,
-                         const double2 *w, const double2 *xh, const float2 *ait, double s, double2 *y,
-                         hipStream_t st);
-// for the blocks b of `list`: y_b = s ainv[b] x_b (x and y distinct); ait:
-// the transposed FP32 copy of the inverse diagonal blocks
-hipError_t launch_lt_jacobi(const int *list, int nlist, int ns, const float2 *ait, double s, const double2 *x,
-                            double2 *y, hipStream_t st);
+hipError_t launch_lt_hop(const int *list, int nlist, int vbase, int ns, const MT *at, const int *nbrv,
+                         const double2 *xa, const double2 *w, const double2 *xh, const float2 *ait, double s,
+                         double2 *y, hipStream_t st);
+// for the i-th block b = list[i] of `list`: y_v = s ainv[b] x_v with v =
+// vbase + i (x and y distinct); ait: the transposed FP32 copy of the inverse
+// diagonal blocks
+hipError_t launch_lt_jacobi(const int *list, int nlist, int vbase, int ns, const float2 *ait, double s,
+                            const double2 *x, double2 *y, hipStream_t st);
 // out[2j..2j+1] = (W_j, x) for j < k, W_j = W + j * n (complex vectors of length n)
 hipError_t launch_lv_dots(const double2 *W, int k, int64_t n, const double2 *x, double *partial, double *out,
                           hipStream_t st);

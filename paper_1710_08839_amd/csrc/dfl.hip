@@ -164,7 +164,7 @@ __device__ __forceinline__ void block_dots(const Geom &g, const void *basis, siz
 }
 
 __global__ void __launch_bounds__(DT) dfl_restrict_kernel(Geom g, const char *basis, size_t vbytes, int ns,
-                                                          const void *r, double *c) {
+                                                          const void *r, const int *vpos, double *c) {
   __shared__ double sh[NW * 2 * DFL_NSMAX];
   __shared__ double out[2 * DFL_NSMAX];
   const int blk = blockIdx.x;
@@ -176,19 +176,20 @@ __global__ void __launch_bounds__(DT) dfl_restrict_kernel(Geom g, const char *ba
   else
     zero_sp(h);
   block_dots(g, basis, vbytes, ns, on, i, h, sh, out);
-  if ((int)threadIdx.x < 2 * ns) c[(int64_t)blk * 2 * ns + threadIdx.x] = out[threadIdx.x];
+  if ((int)threadIdx.x < 2 * ns) c[(int64_t)vpos[blk] * 2 * ns + threadIdx.x] = out[threadIdx.x];
 }
 
 __global__ void __launch_bounds__(DT) dfl_prolong_kernel(Geom g, const char *basis, size_t vbytes, int ns,
-                                                         const double2 *c, void *out) {
+                                                         const double2 *c, const int *vpos, void *out) {
   const int64_t i = (int64_t)blockIdx.x * DT + threadIdx.x;
   if (i >= g.V) return;
   const int64_t r = i >= g.Vh ? i - g.Vh : i;
   const int blk = (int)g.rd.div((uint32_t)r);
+  const int64_t vb = vpos[blk];
   cx<double> acc[4][3];
   zero_sp(acc);
   for (int k = 0; k < ns; k++) {
-    const double2 ck = c[(int64_t)blk * ns + k];
+    const double2 ck = c[vb * ns + k];
     const cx<double> cc{ck.x, ck.y};
     cx<double> u[4][3];
     load_spinor<QXD_F32, double>(field_at(g, basis, vbytes, k), i, u);
@@ -370,12 +371,13 @@ __global__ void __launch_bounds__(DT) little_pack_kernel(int64_t nmat, int ns, c
 // FP16 copy of A; ait: the transposed FP32 copy of the inverse diagonal
 // blocks)
 template <bool DIAG, bool INV, class MT>
-__global__ void __launch_bounds__(DT) lt_hop_kernel(const int *list, int ns, const MT *at, const int *nbr,
-                                                    const double2 *xa, const double2 *w, const double2 *xh,
-                                                    const float2 *ait, double s, double2 *y) {
+__global__ void __launch_bounds__(DT) lt_hop_kernel(const int *list, int vbase, int ns, const MT *at,
+                                                    const int *nbrv, const double2 *xa, const double2 *w,
+                                                    const double2 *xh, const float2 *ait, double s, double2 *y) {
   __shared__ double2 xs[DFL_SLOTS * DFL_NSMAX];
   __shared__ double2 red[DT];
-  const int blk = list[blockIdx.x];
+  const int blk = list[blockIdx.x];               // the block (its matrices)
+  const int64_t vb = vbase + (int64_t)blockIdx.x;  // its entries in the little vectors
   const int G = blockDim.x / ns, g = threadIdx.x / ns, k = threadIdx.x - g * ns;
   // column c multiplies xs[c]: xa_b for the diagonal slot, -xh at the block
   // across face d for the others
@@ -383,9 +385,9 @@ __global__ void __launch_bounds__(DT) lt_hop_kernel(const int *list, int ns, con
     const int d = i / ns, l = i - d * ns;
     double2 v = make_double2(0.0, 0.0);
     if (d == 0) {
-      if (DIAG) v = xa[(int64_t)blk * ns + l];
+      if (DIAG) v = xa[vb * ns + l];
     } else {
-      v = xh[(int64_t)nbr[blk * DFL_SLOTS + d] * ns + l];
+      v = xh[(int64_t)nbrv[blk * DFL_SLOTS + d] * ns + l];
       v.x = -v.x;
       v.y = -v.y;
     }
@@ -405,7 +407,7 @@ __global__ void __launch_bounds__(DT) lt_hop_kernel(const int *list, int ns, con
   __syncthreads();
   if (g == 0) {
     double2 h = make_double2(0.0, 0.0);
-    if (!DIAG && w) h = w[(int64_t)blk * ns + k];
+    if (!DIAG && w) h = w[vb * ns + k];
     for (int q = 0; q < G; q++) {
       h.x += red[q * ns + k].x;
       h.y += red[q * ns + k].y;
@@ -413,7 +415,7 @@ __global__ void __launch_bounds__(DT) lt_hop_kernel(const int *list, int ns, con
     if (INV)
       xs[k] = h;  // every read of xs and red is done (the barrier above)
     else
-      y[(int64_t)blk * ns + k] = h;
+      y[vb * ns + k] = h;
   }
   if (INV) {
     __syncthreads();
@@ -434,20 +436,21 @@ __global__ void __launch_bounds__(DT) lt_hop_kernel(const int *list, int ns, con
         t.x += red[q * ns + k].x;
         t.y += red[q * ns + k].y;
       }
-      y[(int64_t)blk * ns + k] = make_double2(s * t.x, s * t.y);
+      y[vb * ns + k] = make_double2(s * t.x, s * t.y);
     }
   }
 }
 
 // y_b = s ainv[b] x_b for the blocks b of `list` (x and y distinct); ait:
 // the transposed FP32 copy of the inverse diagonal blocks
-__global__ void __launch_bounds__(DT) lt_jacobi_kernel(const int *list, int ns, const float2 *ait, double s,
-                                                       const double2 *x, double2 *y) {
+__global__ void __launch_bounds__(DT) lt_jacobi_kernel(const int *list, int vbase, int ns, const float2 *ait,
+                                                       double s, const double2 *x, double2 *y) {
   __shared__ double2 xs[DFL_NSMAX];
   __shared__ double2 red[DT];
   const int blk = list[blockIdx.x];
+  const int64_t vb = vbase + (int64_t)blockIdx.x;
   const int G = blockDim.x / ns, g = threadIdx.x / ns, k = threadIdx.x - g * ns;
-  if (threadIdx.x < ns) xs[threadIdx.x] = x[(int64_t)blk * ns + threadIdx.x];
+  if (threadIdx.x < ns) xs[threadIdx.x] = x[vb * ns + threadIdx.x];
   __syncthreads();
   const float2 *m = ait + (int64_t)blk * ns * ns + k;
   double re = 0.0, im = 0.0;
@@ -465,7 +468,7 @@ __global__ void __launch_bounds__(DT) lt_jacobi_kernel(const int *list, int ns, 
       t.x += red[h * ns + k].x;
       t.y += red[h * ns + k].y;
     }
-    y[(int64_t)blk * ns + k] = make_double2(s * t.x, s * t.y);
+    y[vb * ns + k] = make_double2(s * t.x, s * t.y);
   }
 }
 
@@ -590,16 +593,16 @@ hipError_t launch_dfl_ortho(const Geom &g, void *basis, size_t vbytes, int ns, i
   return hipGetLastError();
 }
 
-hipError_t launch_dfl_restrict(const Geom &g, const void *basis, size_t vbytes, int ns, const void *r, double2 *c,
-                               hipStream_t st) {
+hipError_t launch_dfl_restrict(const Geom &g, const void *basis, size_t vbytes, int ns, const void *r,
+                               const int *vpos, double2 *c, hipStream_t st) {
   if (!fits(g) || ns > DFL_NSMAX) return hipErrorInvalidValue;
-  dfl_restrict_kernel<<<g.nblocks, DT, 0, st>>>(g, (const char *)basis, vbytes, ns, r, (double *)c);
+  dfl_restrict_kernel<<<g.nblocks, DT, 0, st>>>(g, (const char *)basis, vbytes, ns, r, vpos, (double *)c);
   return hipGetLastError();
 }
 
-hipError_t launch_dfl_prolong(const Geom &g, const void *basis, size_t vbytes, int ns, const double2 *c, void *out,
-                              hipStream_t st) {
-  dfl_prolong_kernel<<<grid_for(g.V, DT), DT, 0, st>>>(g, (const char *)basis, vbytes, ns, c, out);
+hipError_t launch_dfl_prolong(const Geom &g, const void *basis, size_t vbytes, int ns, const double2 *c,
+                              const int *vpos, void *out, hipStream_t st) {
+  dfl_prolong_kernel<<<grid_for(g.V, DT), DT, 0, st>>>(g, (const char *)basis, vbytes, ns, c, vpos, out);
   return hipGetLastError();
 }
 
@@ -636,35 +639,35 @@ template hipError_t launch_little_pack<h2_t>(int64_t, int, const double2 *, h2_t
 static int lt_threads(int ns) { return (DT / ns) * ns; }
 
 template <class MT>
-hipError_t launch_lt_hop(const int *list, int nlist, int ns, const MT *at, const int *nbr, const double2 *xa,
-                         const double2 *w, const double2 *xh, const float2 *ait, double s, double2 *y,
-                         hipStream_t st) {
+hipError_t launch_lt_hop(const int *list, int nlist, int vbase, int ns, const MT *at, const int *nbrv,
+                         const double2 *xa, const double2 *w, const double2 *xh, const float2 *ait, double s,
+                         double2 *y, hipStream_t st) {
   if (ns < 1 || ns > DFL_NSMAX) return hipErrorInvalidValue;
   if (nlist < 1) return hipSuccess;
   const int nt = lt_threads(ns);
   if (xa && ait)
-    lt_hop_kernel<true, true, MT><<<nlist, nt, 0, st>>>(list, ns, at, nbr, xa, w, xh, ait, s, y);
+    lt_hop_kernel<true, true, MT><<<nlist, nt, 0, st>>>(list, vbase, ns, at, nbrv, xa, w, xh, ait, s, y);
   else if (xa)
-    lt_hop_kernel<true, false, MT><<<nlist, nt, 0, st>>>(list, ns, at, nbr, xa, w, xh, ait, s, y);
+    lt_hop_kernel<true, false, MT><<<nlist, nt, 0, st>>>(list, vbase, ns, at, nbrv, xa, w, xh, ait, s, y);
   else if (ait)
-    lt_hop_kernel<false, true, MT><<<nlist, nt, 0, st>>>(list, ns, at, nbr, xa, w, xh, ait, s, y);
+    lt_hop_kernel<false, true, MT><<<nlist, nt, 0, st>>>(list, vbase, ns, at, nbrv, xa, w, xh, ait, s, y);
   else
-    lt_hop_kernel<false, false, MT><<<nlist, nt, 0, st>>>(list, ns, at, nbr, xa, w, xh, ait, s, y);
+    lt_hop_kernel<false, false, MT><<<nlist, nt, 0, st>>>(list, vbase, ns, at, nbrv, xa, w, xh, ait, s, y);
   return hipGetLastError();
 }
-template hipError_t launch_lt_hop<float2>(const int *, int, int, const float2 *, const int *, const double2 *,
+template hipError_t launch_lt_hop<float2>(const int *, int, int, int, const float2 *, const int *, const double2 *,
                                           const double2 *, const double2 *, const float2 *, double, double2 *,
                                           hipStream_t);
-template hipError_t launch_lt_hop<h2_t>(const int *, int, int, const h2_t *, const int *, const double2 *,
+template hipError_t launch_lt_hop<h2_t>(const int *, int, int, int, const h2_t *, const int *, const double2 *,
                                         const double2 *, const double2 *, const float2 *, double, double2 *,
                                         hipStream_t);
 
-hipError_t launch_lt_jacobi(const int *list, int nlist, int ns, const float2 *ait, double s, const double2 *x,
-                            double2 *y, hipStream_t st) {
+hipError_t launch_lt_jacobi(const int *list, int nlist, int vbase, int ns, const float2 *ait, double s,
+                            const double2 *x, double2 *y, hipStream_t st) {
   if (ns < 1 || ns > DFL_NSMAX) return hipErrorInvalidValue;
   if (nlist < 1) return hipSuccess;
   // about four columns per thread: a block's inverse is only ns x ns
-  lt_jacobi_kernel<<<nlist, ns * ((ns + 3) / 4), 0, st>>>(list, ns, ait, s, x, y);
+  lt_jacobi_kernel<<<nlist, ns * ((ns + 3) / 4), 0, st>>>(list, vbase, ns, ait, s, x, y);
   return hipGetLastError();
 }
 

@@ -61,29 +61,29 @@ constexpr int LS_S = 0, LS_DOTS = 8, LS_WN = 8 + 2 * 64, LS_N = LS_WN + 64 + 8;
 //   x_o = A_oo^-1 (b_o - A_oe x_e),
 // by GCR right-preconditioned with A_ee^-1: z_k = A_ee^-1 r and w_k = Ahat z_k
 // made orthogonal to the earlier w, x and r updated at every step; stops at
-// |r| <= tol |b_e - A_eo A_oo^-1 b_o| or maxiter iterations.  Vectors are
-// full length (blocks of both colours); the odd entries of r, z, w stay 0.
+// |r| <= tol |b_e - A_eo A_oo^-1 b_o| or maxiter iterations.  In the little
+// vectors the even blocks come first (positions 0 .. ne - 1), so r, z, w
+// and the Gram-Schmidt work on the first ne * ns entries only; b, x and u
+// are full length.
 // The host reads the residual norm of step j while step j + 1 is already
 // queued, so the device never waits for the host; the step queued past
 // convergence is kept (it only lowers the residual further).
 template <class MT>
 qxd_status little_solve_t(Dfl &d, const MT *A, const double2 *b, double2 *x, double tol, int *iters,
                           hipStream_t st) {
-  const int64_t n = (int64_t)d.nb * d.ns;
-  const int nkv = d.p.little_nkv, ns = d.ns, maxiter = d.p.little_maxiter;
+  const int nkv = d.p.little_nkv, ns = d.ns, maxiter = d.p.little_maxiter, ne = d.ne;
+  const int64_t n = (int64_t)ne * ns;  // entries of the even blocks
   double2 *Z = d.lz.as<double2>(), *W = d.lw.as<double2>(), *r = d.lr.as<double2>();
   double2 *u = d.lu.as<double2>();
   double *part = d.lpart.as<double>(), *sc = d.lscal.as<double>();
   const float2 *Ai = d.ait32.as<float2>();
-  const int *nbr = d.nbr.as<int>(), *ev = d.even.as<int>(), *od = d.odd.as<int>();
-  const size_t vb = n * sizeof(double2);
-  DCK(hipMemsetAsync(x, 0, vb, st));
-  DCK(hipMemsetAsync(r, 0, vb, st));
-  DCK(hipMemsetAsync(Z, 0, vb * nkv, st));
-  DCK(hipMemsetAsync(W, 0, vb * nkv, st));
+  const int *nbrv = d.nbrv.as<int>(), *ev = d.even.as<int>(), *od = d.odd.as<int>();
+  // x starts at 0 (x_o is written at the end); r, z_k and w_k are written
+  // whole before they are read
+  DCK(hipMemsetAsync(x, 0, (size_t)d.nb * ns * sizeof(double2), st));
   // r_e = b_e - A_eo A_oo^-1 b_o
-  DCK(launch_lt_jacobi(od, d.no, ns, Ai, 1.0, b, u, st));
-  DCK(launch_lt_hop(ev, d.ne, ns, A, nbr, nullptr, b, u, nullptr, 1.0, r, st));
+  DCK(launch_lt_jacobi(od, d.no, ne, ns, Ai, 1.0, b, u, st));
+  DCK(launch_lt_hop(ev, ne, 0, ns, A, nbrv, nullptr, b, u, nullptr, 1.0, r, st));
   DCK(launch_lv_dot2(r, r, n, part, sc + LS_S, st));
   double bn2;
   DCS(fetch(&bn2, sc + LS_S, 1, st));
@@ -96,11 +96,11 @@ qxd_status little_solve_t(Dfl &d, const MT *A, const double2 *b, double2 *x, dou
   auto step = [&](int j) -> qxd_status {
     const int k = j % nkv;
     double2 *zk = Z + (int64_t)k * n, *wk = W + (int64_t)k * n;
-    DCK(launch_lt_jacobi(ev, d.ne, ns, Ai, 1.0, r, zk, st));
+    DCK(launch_lt_jacobi(ev, ne, 0, ns, Ai, 1.0, r, zk, st));
     // w_e = A_ee z - A_eo u_o with u_o = A_oo^-1 A_oe z (-A_oe z is what
     // the hop makes)
-    DCK(launch_lt_hop(od, d.no, ns, A, nbr, nullptr, nullptr, zk, Ai, -1.0, u, st));
-    DCK(launch_lt_hop(ev, d.ne, ns, A, nbr, zk, nullptr, u, nullptr, 1.0, wk, st));
+    DCK(launch_lt_hop(od, d.no, ne, ns, A, nbrv, nullptr, nullptr, zk, Ai, -1.0, u, st));
+    DCK(launch_lt_hop(ev, ne, 0, ns, A, nbrv, zk, nullptr, u, nullptr, 1.0, wk, st));
     if (k > 0) {
       DCK(launch_lv_dots(W, k, n, wk, part, sc + LS_DOTS, st));
       DCK(launch_lv_maxpy2(wk, W, zk, Z, k, n, sc + LS_DOTS, sc + LS_WN, st));
@@ -126,7 +126,7 @@ qxd_status little_solve_t(Dfl &d, const MT *A, const double2 *b, double2 *x, dou
     }
   }
   // x_o = A_oo^-1 (b_o - A_oe x_e)
-  DCK(launch_lt_hop(od, d.no, ns, A, nbr, nullptr, b, x, Ai, 1.0, x, st));
+  DCK(launch_lt_hop(od, d.no, ne, ns, A, nbrv, nullptr, b, x, Ai, 1.0, x, st));
   if (iters) *iters = launched;
   return QXD_OK;
 }
@@ -173,8 +173,8 @@ qxd_status op_with_dfl(Field *f, const qxd_quark &q, Operator **op, hipStream_t 
 }  // namespace
 
 size_t Dfl::bytes() const {
-  return basis.n + a.n + ainv.n + at32.n + ait32.n + at16.n + nbr.n + even.n + odd.n + lz.n + lw.n + lx.n + lr.n +
-         lb.n + lu.n + lpart.n + lscal.n;
+  return basis.n + a.n + ainv.n + at32.n + ait32.n + at16.n + nbr.n + even.n + odd.n + vpos.n + nbrv.n + lz.n + lw.n +
+         lx.n + lr.n + lb.n + lu.n + lpart.n + lscal.n;
 }
 
 qxd_status dfl_setup(Field *f, const qxd_quark &q, const qxd_dfl_params *pin, const double *init_api,
@@ -295,6 +295,24 @@ qxd_status dfl_setup(Field *f, const qxd_quark &q, const qxd_dfl_params *pin, co
     DCK(d->odd.ensure(od.size() * sizeof(int)));
     DCK(hipMemcpyAsync(d->even.p, ev.data(), ev.size() * sizeof(int), hipMemcpyHostToDevice, st));
     DCK(hipMemcpyAsync(d->odd.p, od.data(), od.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    // positions in the little vectors: the even blocks, then the odd ones;
+    // the neighbour table in those positions
+    std::vector<int> vpos(d->nb), nbr((size_t)d->nb * DFL_SLOTS), nbrv((size_t)d->nb * DFL_SLOTS);
+    for (int i = 0; i < d->ne; i++) vpos[ev[i]] = i;
+    for (int i = 0; i < d->no; i++) vpos[od[i]] = d->ne + i;
+    DCK(hipMemcpyAsync(nbr.data(), d->nbr.p, nbr.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+    DCK(hipStreamSynchronize(st));
+    for (size_t i = 0; i < nbr.size(); i++) {
+      if (nbr[i] < 0 || nbr[i] >= d->nb) {
+        set_error("little operator: neighbour table out of range");
+        return QXD_EDEVICE;
+      }
+      nbrv[i] = vpos[nbr[i]];
+    }
+    DCK(d->vpos.ensure(vpos.size() * sizeof(int)));
+    DCK(d->nbrv.ensure(nbrv.size() * sizeof(int)));
+    DCK(hipMemcpyAsync(d->vpos.p, vpos.data(), vpos.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    DCK(hipMemcpyAsync(d->nbrv.p, nbrv.data(), nbrv.size() * sizeof(int), hipMemcpyHostToDevice, st));
     DCK(hipStreamSynchronize(st));
   }
   // little GCR workspace
@@ -321,7 +339,7 @@ qxd_status dfl_precond(Field *f, Operator &op, double little_tol, int ncy, int n
   DCS(ws(f, "dfl_t", spinor_bytes(QXD_F32, g.V), &t));
   DCS(ws(f, "partial", blas_partial_doubles() * 8, &partial));
   // u = V A^-1 V^dag r
-  DCK(launch_dfl_restrict(g, d.basis.p, d.vbytes, d.ns, r32, d.lb.as<double2>(), st));
+  DCK(launch_dfl_restrict(g, d.basis.p, d.vbytes, d.ns, r32, d.vpos.as<int>(), d.lb.as<double2>(), st));
   int lit = 0;
   DCS(little_solve(d, d.lb.as<double2>(), d.lx.as<double2>(), little_tol > 0.0 ? little_tol : d.p.little_tol,
                    &lit, st));
@@ -329,7 +347,7 @@ qxd_status dfl_precond(Field *f, Operator &op, double little_tol, int ncy, int n
   d.applications++;
   d.little_iters += lit;
   if (lit > d.little_max) d.little_max = lit;
-  DCK(launch_dfl_prolong(g, d.basis.p, d.vbytes, d.ns, d.lx.as<double2>(), u, st));
+  DCK(launch_dfl_prolong(g, d.basis.p, d.vbytes, d.ns, d.lx.as<double2>(), d.vpos.as<int>(), u, st));
   // out = u + M_sap (r - D u)
   DCS(apply_native(f, op, 0.0, QXD_OP_D, QXD_F32, u, t, st));
   DCK(blas_axpby<QXD_F32, QXD_F32>(full(g, t), -1.0, full(g, r32), 1.0, 0, g.V, (double *)partial, nullptr, st));
