@@ -27,8 +27,11 @@ constexpr int DFL_SLOTS = 9;   // couplings of a block: itself, then faces 2 mu 
 // them) and events through which the little GCR reads the residual norm of a
 // step while the device already runs the next one.
 struct LittleSync {
-  double *host = nullptr;  // two slots
-  double *dev = nullptr;   // their device address (mapped pinned memory)
+  // host[0..1]: |r|^2 of a step, by step parity; host[2]: |r_0|^2 of the
+  // solve (host[3..4] the other sums of the same reduction)
+  static constexpr int NSLOT = 8;
+  double *host = nullptr;
+  double *dev = nullptr;  // their device address (mapped pinned memory)
   hipEvent_t ev[2] = {nullptr, nullptr};
   LittleSync() = default;
   LittleSync(const LittleSync &) = delete;
@@ -45,7 +48,7 @@ struct LittleSync {
   hipError_t init() {
     hipError_t e = hipSuccess;
     if (!host) {
-      e = hipHostMalloc((void **)&host, 2 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent);
+      e = hipHostMalloc((void **)&host, NSLOT * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent);
       if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&dev, host, 0);
     }
     for (int i = 0; i < 2 && e == hipSuccess; i++)
@@ -132,7 +135,7 @@ hipError_t launch_lt_jacobi(const int *list, int nlist, int vbase, int ns, const
 hipError_t launch_lv_dots(const double2 *W, int k, int64_t n, const double2 *x, double *partial, double *out,
                           hipStream_t st);
 // x1 -= sum_{j<k} c_j W1_j and x2 -= sum_{j<k} c_j W2_j with
-// c_j = (d[2j] + i d[2j+1]) / wn[j]
+// c_j = (d[2j] + i d[2j+1]) / wn[j] (0 if wn[j] = 0)
 hipError_t launch_lv_maxpy2(double2 *x1, const double2 *W1, double2 *x2, const double2 *W2, int k, int64_t n,
                             const double *d, const double *wn, hipStream_t st);
 // partial sums of s[0] = |w|^2, s[1..2] = (w, r) into the partial-sum
@@ -140,7 +143,7 @@ hipError_t launch_lv_maxpy2(double2 *x1, const double2 *W1, double2 *x2, const d
 hipError_t launch_lv_dot2(const double2 *w, const double2 *r, int64_t n, double *partial, double *s,
                           hipStream_t st);
 // with s the totals of the partial sums launch_lv_dot2 left in `partial`:
-// alpha = (s[1] + i s[2]) / s[0]: x += alpha z, r -= alpha w; *wn = s[0];
+// alpha = (s[1] + i s[2]) / s[0] (0 if s[0] = 0): x += alpha z, r -= alpha w; *wn = s[0];
 // out[0] = |r|^2 (out may be the device address of mapped host memory)
 hipError_t launch_lv_update(double2 *x, const double2 *z, double2 *r, const double2 *w, int64_t n, double *wn,
                             double *partial, double *out, hipStream_t st);

@@ -525,11 +525,20 @@ __global__ void __launch_bounds__(64) lv_finish_kernel(const double *partial, in
 __global__ void __launch_bounds__(DT) lv_maxpy2_kernel(double2 *x1, const double2 *W1, double2 *x2,
                                                        const double2 *W2, int k, int64_t n, const double *d,
                                                        const double *wn) {
+  // the coefficients, once per work-group; wn[j] = |w_j|^2 is 0 only for
+  // steps on a zero residual: no update
+  __shared__ double cf[2 * LV_MAXK];
+  for (int j = threadIdx.x; j < k; j += DT) {
+    const double q = wn[j];
+    cf[2 * j] = q != 0.0 ? d[2 * j] / q : 0.0;
+    cf[2 * j + 1] = q != 0.0 ? d[2 * j + 1] / q : 0.0;
+  }
+  __syncthreads();
   const int64_t e = (int64_t)blockIdx.x * DT + threadIdx.x;
   if (e >= n) return;
   double2 v1 = x1[e], v2 = x2[e];
   for (int j = 0; j < k; j++) {
-    const double cr = d[2 * j] / wn[j], ci = d[2 * j + 1] / wn[j];
+    const double cr = cf[2 * j], ci = cf[2 * j + 1];
     const double2 u1 = W1[(int64_t)j * n + e], u2 = W2[(int64_t)j * n + e];
     v1.x -= cr * u1.x - ci * u1.y;
     v1.y -= cr * u1.y + ci * u1.x;
@@ -556,7 +565,8 @@ __global__ void __launch_bounds__(DT) lv_update_kernel(double2 *x, const double2
     }
   }
   __syncthreads();
-  const double ar = s[1] / s[0], ai = s[2] / s[0];
+  // s[0] = |w|^2 is 0 only for a step on a zero residual: no update
+  const double ar = s[0] != 0.0 ? s[1] / s[0] : 0.0, ai = s[0] != 0.0 ? s[2] / s[0] : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) *wn = s[0];
   double rr = 0.0;
   for (int64_t e = (int64_t)blockIdx.x * DT + threadIdx.x; e < n; e += (int64_t)LVG * DT) {
@@ -682,6 +692,7 @@ hipError_t launch_lv_dots(const double2 *W, int k, int64_t n, const double2 *x, 
 hipError_t launch_lv_maxpy2(double2 *x1, const double2 *W1, double2 *x2, const double2 *W2, int k, int64_t n,
                             const double *d, const double *wn, hipStream_t st) {
   if (k < 1) return hipSuccess;
+  if (k > LV_MAXK) return hipErrorInvalidValue;
   lv_maxpy2_kernel<<<grid_for(n, DT), DT, 0, st>>>(x1, W1, x2, W2, k, n, d, wn);
   return hipGetLastError();
 }

@@ -54,7 +54,7 @@ qxd_status ws(Field *f, const char *name, size_t bytes, void **p) {
 SpinorArg full(const Geom &g, void *p) { return SpinorArg{p, g.V, 0, g.rd}; }
 
 // scalars of the little GCR on the device
-constexpr int LS_S = 0, LS_DOTS = 8, LS_WN = 8 + 2 * 64, LS_N = LS_WN + 64 + 8;
+constexpr int LS_DOTS = 8, LS_WN = 8 + 2 * 64, LS_N = LS_WN + 64 + 8;
 
 // x = A^-1 b approximately, on the even-block Schur complement
 //   Ahat = A_ee - A_eo A_oo^-1 A_oe,   Ahat x_e = b_e - A_eo A_oo^-1 b_o,
@@ -84,13 +84,9 @@ qxd_status little_solve_t(Dfl &d, const MT *A, const double2 *b, double2 *x, dou
   // r_e = b_e - A_eo A_oo^-1 b_o
   DCK(launch_lt_jacobi(od, d.no, ne, ns, Ai, 1.0, b, u, st));
   DCK(launch_lt_hop(ev, ne, 0, ns, A, nbrv, nullptr, b, u, nullptr, 1.0, r, st));
-  DCK(launch_lv_dot2(r, r, n, part, sc + LS_S, st));
-  double bn2;
-  DCS(fetch(&bn2, sc + LS_S, 1, st));
-  if (!isfinite(bn2)) {
-    set_error("little system: right-hand side is NaN/Inf");
-    return QXD_EFLOAT;
-  }
+  // |r_0|^2 goes to host slot 2; the host reads it after the first step
+  // (a zero residual makes every step a no-op)
+  DCK(launch_lv_dot2(r, r, n, part, d.sync.dev + 2, st));
   // step j: Krylov slot j mod nkv (a restart every nkv steps); its |r|^2 goes
   // to host slot j mod 2
   auto step = [&](int j) -> qxd_status {
@@ -111,19 +107,26 @@ qxd_status little_solve_t(Dfl &d, const MT *A, const double2 *b, double2 *x, dou
     return QXD_OK;
   };
   int launched = 0;
-  if (bn2 > 0.0) {
-    DCS(step(launched++));
-    for (int j = 0;; j++) {
-      if (launched < maxiter) DCS(step(launched++));
-      DCK(hipEventSynchronize(d.sync.ev[j & 1]));
-      const double rr = d.sync.host[j & 1];
-      if (!isfinite(rr)) {
+  double bn2 = 0.0;
+  DCS(step(launched++));
+  for (int j = 0;; j++) {
+    if (launched < maxiter) DCS(step(launched++));
+    DCK(hipEventSynchronize(d.sync.ev[j & 1]));
+    if (j == 0) {
+      bn2 = d.sync.host[2];
+      if (!isfinite(bn2)) {
         DCK(hipStreamSynchronize(st));
-        set_error("little system: residual is NaN/Inf");
+        set_error("little system: right-hand side is NaN/Inf");
         return QXD_EFLOAT;
       }
-      if (rr <= tol * tol * bn2 || j + 1 >= launched) break;
     }
+    const double rr = d.sync.host[j & 1];
+    if (!isfinite(rr)) {
+      DCK(hipStreamSynchronize(st));
+      set_error("little system: residual is NaN/Inf");
+      return QXD_EFLOAT;
+    }
+    if (rr <= tol * tol * bn2 || j + 1 >= launched) break;
   }
   // x_o = A_oo^-1 (b_o - A_oe x_e)
   DCK(launch_lt_hop(od, d.no, ne, ns, A, nbrv, nullptr, b, x, Ai, 1.0, x, st));

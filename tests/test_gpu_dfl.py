@@ -131,6 +131,19 @@ def test_precond_repeatable(case, setup, little_tol):
     assert np.all(np.isfinite(outs[0]))
 
 
+@pytest.mark.parametrize("little_tol", [0.2, 1e-12], ids=["fp16-matrices", "fp32-matrices"])
+def test_precond_of_zero(case, setup, little_tol):
+    """M_dfl 0 = 0 exactly: the little GCR's steps on a zero residual change
+    nothing (no division by a zero norm), the step queued past convergence
+    included, and the preconditioner leaves no stale values behind."""
+    import torch
+    c = case
+    y = torch.full_like(to_dev(c.source(904)), 7.0)
+    c.field.dfl_precond(c.quark, torch.zeros_like(y), y, little_tol=little_tol, ncy=NCY, nmr=NMR)
+    torch.cuda.synchronize()
+    assert not torch.any(y != 0).item()
+
+
 @pytest.mark.parametrize("nkv", [8, 32])
 def test_deflated_solve(case, setup, nkv):
     import torch
