@@ -8,6 +8,7 @@
 #include "blas.h"
 #include "dfl.h"
 #include "qxd_debug.h"
+#include "sap.h"
 #include "solver.h"
 
 namespace qxd {
@@ -216,25 +217,73 @@ qxd_status dfl_setup(Field *f, const qxd_quark &q, const qxd_dfl_params *pin, co
   }
   // SAP-smoothed inverse iteration: psi <- psi / |psi|, then ninv times
   // psi <- M_sap psi / |M_sap psi|
-  for (int k = 0; k < ns; k++) {
-    void *v = basis + (size_t)k * d->vbytes;
+  auto field = [&](int k) -> void * { return basis + (size_t)k * d->vbytes; };
+  // v_k = src / |src| (with a zero coefficient the old v_k is not read)
+  auto normalise = [&](int k, void *src) -> qxd_status {
+    void *v = field(k);
+    DCK(blas_norm2<QXD_F32>(full(g, src), 0, g.V, (double *)partial, misc, st));
+    double n2;
+    DCS(fetch(&n2, misc, 1, st));
+    if (!(n2 > 0.0) || !isfinite(n2)) {
+      set_error("deflation field %d vanished or is not finite in inverse iteration", k);
+      return QXD_EFLOAT;
+    }
+    const double sc = 1.0 / sqrt(n2);
+    DCK(blas_axpby<QXD_F32, QXD_F32>(full(g, v), src == v ? sc : 0.0, full(g, src), src == v ? 0.0 : sc, 0, g.V,
+                                     (double *)partial, nullptr, st));
+    return QXD_OK;
+  };
+  int k0 = 0;
+  if (ns > 1 && sap_quad_pairs_ok(QXD_F32, g)) {
+    // two fields at a time through the paired SAP block solver (links and
+    // Pauli rows staged once per block for both; per field the same
+    // arithmetic as sap_apply): slot k reads field k and writes t32 (k even)
+    // or t32b (k odd), with its own two work vectors
+    const size_t fb = spinor_bytes(QXD_F32, g.V);
+    void *t32b, *rv, *dslots, *dpairs;
+    DCS(ws(f, "dfl_t32b", fb, &t32b));
+    DCS(ws(f, "dfl_pair_rv", 4 * fb, &rv));
+    DCS(ws(f, "dfl_pair_slots", (size_t)ns * sizeof(SapSlot<QXD_F32>), &dslots));
+    DCS(ws(f, "dfl_pair_idx", (size_t)ns * sizeof(int), &dpairs));
+    const OpFields of = f->op_fields(*op, QXD_F32);
+    using PT = typename St<QXD_F32>::pair_t;
+    std::vector<SapSlot<QXD_F32>> hs(ns);
+    std::vector<int> hp(ns);
+    for (int k = 0; k < ns; k++) {
+      char *w = (char *)rv + (size_t)2 * (k & 1) * fb;
+      hs[k].op = SapOp<QXD_F32>{(const PT *)of.links, nullptr, 0, (const PT *)of.pauli, (const PT *)of.pinv};
+      hs[k].vec = SapVecs<QXD_F32>{spinor_view<QXD_F32>(field(k), g.V, 0, g), spinor_view<QXD_F32>(w, g.V, 0, g),
+                                   spinor_view<QXD_F32>(k & 1 ? t32b : t32, g.V, 0, g),
+                                   spinor_view<QXD_F32>(w + fb, g.V, 0, g)};
+      hp[k] = k;
+    }
+    DCK(hipMemcpyAsync(dslots, hs.data(), hs.size() * sizeof(SapSlot<QXD_F32>), hipMemcpyHostToDevice, st));
+    DCK(hipMemcpyAsync(dpairs, hp.data(), hp.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    DCK(hipStreamSynchronize(st));
+    const int *lists[2];
+    int nper;
+    DCS(sap_block_lists(f, lists, &nper));
+    for (; k0 + 1 < ns; k0 += 2) {
+      for (int it = 0; it <= p.ninv; it++) {
+        if (it > 0) {
+          for (int cy = 0; cy < p.ncy; cy++)
+            for (int c = 0; c < 2; c++)
+              DCK(launch_sapq_pairs<QXD_F32>(g, lists[c], nper, (const SapSlot<QXD_F32> *)dslots,
+                                             (const int *)dpairs + k0, 1, cy == 0, cy == 0 && c == 0, p.nmr, st));
+        }
+        DCS(normalise(k0, it > 0 ? t32 : field(k0)));
+        DCS(normalise(k0 + 1, it > 0 ? t32b : field(k0 + 1)));
+      }
+    }
+  }
+  for (int k = k0; k < ns; k++) {
     for (int it = 0; it <= p.ninv; it++) {
-      void *src = v;  // the field to normalise into v: v itself, then M_sap v
+      void *src = field(k);  // the field to normalise into v_k: v_k itself, then M_sap v_k
       if (it > 0) {
-        DCS(sap_apply(f, *op, QXD_F32, p.ncy, p.nmr, v, t32, st));
+        DCS(sap_apply(f, *op, QXD_F32, p.ncy, p.nmr, field(k), t32, st));
         src = t32;
       }
-      DCK(blas_norm2<QXD_F32>(full(g, src), 0, g.V, (double *)partial, misc, st));
-      double n2;
-      DCS(fetch(&n2, misc, 1, st));
-      if (!(n2 > 0.0) || !isfinite(n2)) {
-        set_error("deflation field %d vanished or is not finite in inverse iteration", k);
-        return QXD_EFLOAT;
-      }
-      // v = src / |src| (with a zero coefficient the old v is not read)
-      const double sc = 1.0 / sqrt(n2);
-      DCK(blas_axpby<QXD_F32, QXD_F32>(full(g, v), src == v ? sc : 0.0, full(g, src), src == v ? 0.0 : sc, 0,
-                                       g.V, (double *)partial, nullptr, st));
+      DCS(normalise(k, src));
     }
   }
   // block orthonormalisation
